@@ -1,0 +1,651 @@
+/*
+ * gosma_oracle.c -- plain FP64 CPU oracle for GOSMA (Campbell, Petersson,
+ * Kneip, Li, Gould: "The Alignment of the Spheres: Globally-Optimal Spherical
+ * Mixture Alignment for Camera Pose Estimation", arXiv:1812.01232).
+ *
+ * TEST INFRASTRUCTURE ONLY: the reference that the GPU library is checked
+ * against.  Loaded by the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark, never by the product path.  Shares no code with it.
+ *
+ * The code follows the paper's notation and order: the objective of Lemma 1
+ * (Section 4, eqs. 10-13) written with the Z(.) normaliser of eq. 2 in log
+ * space; the bounds of Theorem 1 (Section 5.2, eqs. 20-25) with the
+ * uncertainty angles of Lemmas 2-3; and Algorithm 1 (Section 6) without the
+ * local optimiser.  Where the paper leaves a step open the reading taken is
+ * stated in the comment of that step.
+ *
+ * Parity status:
+ *   oracle_log_Z, oracle_vmf_pdf, oracle_pn_pdf, oracle_qpn_kappa  -- pinned
+ *     (Fig. 3b table).
+ *   oracle_objective, oracle_S22                                   -- pinned
+ *     (sphere quadrature of the L2 distance, zero distance at the true pose,
+ *      closed-form single-pair values, invariances).
+ *   oracle_psi_t, oracle_psi_r                                     -- pinned
+ *     (brute-force angle sampling).
+ *   oracle_bounds_cube: ub pinned (= objective at the centre); lb value is
+ *     "parity unpinned" (the paper's proof appendix is missing); its validity
+ *     (lb <= sampled minimum) and convergence are pinned by brute force.
+ *   oracle_solve: pinned on small problems by a dense pose grid with local
+ *     polishing, and by recovery of the ground-truth pose.
+ */
+#include "gosma_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Section 3: normaliser, vMF, PN and qPN densities                   */
+/* ------------------------------------------------------------------ */
+
+/* log Z(x) for Z(x) = (e^x - e^-x) / x (eq. 2).  Written as
+ * x + log(1 - e^{-2x}) - log x so that it does not overflow; Z(0) = 2 is the
+ * limit at zero. */
+double oracle_log_Z(double x)
+{
+    if (x <= 0.0) return log(2.0);
+    return x + log(-expm1(-2.0 * x)) - log(x);
+}
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static double norm3(const double *a) { return sqrt(dot3(a, a)); }
+static void cross3(const double *a, const double *b, double *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+/* The angle between two vectors, atan2(|a x b|, a . b). */
+static double angle3(const double *a, const double *b)
+{
+    double c[3];
+    cross3(a, b, c);
+    return atan2(norm3(c), dot3(a, b));
+}
+
+/* vMF density, eq. 1. */
+double oracle_vmf_pdf(const double f[3], const double mu_hat[3], double kappa)
+{
+    return exp(kappa * dot3(mu_hat, f) - oracle_log_Z(kappa)) / (2.0 * M_PI);
+}
+
+/* Isotropic Projected Normal density, eq. 3, with rho = |mu|/sigma and
+ * alpha = rho mu.f/|mu|; the two exponentials are merged to avoid overflow. */
+double oracle_pn_pdf(const double f[3], const double mu[3], double sigma2)
+{
+    double nmu = norm3(mu);
+    double rho = nmu / sqrt(sigma2);
+    double alpha = rho * dot3(mu, f) / nmu;
+    double Phi = 0.5 * erfc(-alpha / sqrt(2.0));
+    double a = exp(-0.5 * rho * rho) * alpha / sqrt(2.0 * M_PI);
+    double b = Phi * exp(0.5 * (alpha * alpha - rho * rho)) * (1.0 + alpha * alpha);
+    return (a + b) / (2.0 * M_PI);
+}
+
+/* qPN concentration, eq. 4 / eq. 6: kappa = (|mu| / sigma)^2 + 1. */
+double oracle_qpn_kappa(const double mu[3], double sigma)
+{
+    double r = norm3(mu) / sigma;
+    return r * r + 1.0;
+}
+
+/* Rodrigues' formula R_r for an angle-axis vector r (Section 5.1). */
+void oracle_rodrigues(const double r[3], double R[9])
+{
+    double th = norm3(r);
+    for (int k = 0; k < 9; ++k) R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    if (th == 0.0) return;
+    double k[3] = {r[0] / th, r[1] / th, r[2] / th};
+    double Kx[9] = {0, -k[2], k[1], k[2], 0, -k[0], -k[1], k[0], 0};
+    double K2[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0;
+            for (int c = 0; c < 3; ++c) s += Kx[3 * a + c] * Kx[3 * c + b];
+            K2[3 * a + b] = s;
+        }
+    double s = sin(th), c = 1.0 - cos(th);
+    for (int q = 0; q < 9; ++q) R[q] += s * Kx[q] + c * K2[q];
+}
+
+static void matvec(const double R[9], const double v[3], double out[3])
+{
+    for (int a = 0; a < 3; ++a) out[a] = R[3 * a] * v[0] + R[3 * a + 1] * v[1] + R[3 * a + 2] * v[2];
+}
+static void matTvec(const double R[9], const double v[3], double out[3])
+{
+    for (int a = 0; a < 3; ++a) out[a] = R[a] * v[0] + R[3 + a] * v[1] + R[6 + a] * v[2];
+}
+
+/* ------------------------------------------------------------------ */
+/* Semantic classes (eq. 17): class weights phi_l = 1/|Lambda|, and   */
+/* mixture weights renormalised within each class.                    */
+/* ------------------------------------------------------------------ */
+
+static int label_of(const int32_t *lab, int i) { return lab ? lab[i] : 0; }
+
+static void class_weights(const oracle_problem *p, double *w1, double *w2)
+{
+    int L = p->n_labels > 0 ? p->n_labels : 1;
+    double *s1 = calloc((size_t)L, sizeof(double)), *s2 = calloc((size_t)L, sizeof(double));
+    for (int i = 0; i < p->M; ++i) s1[label_of(p->label1, i)] += p->phi1[i];
+    for (int j = 0; j < p->N; ++j) s2[label_of(p->label2, j)] += p->phi2[j];
+    for (int i = 0; i < p->M; ++i) {
+        double s = s1[label_of(p->label1, i)];
+        w1[i] = s > 0 ? p->phi1[i] / s : 0.0;
+    }
+    for (int j = 0; j < p->N; ++j) {
+        double s = s2[label_of(p->label2, j)];
+        w2[j] = s > 0 ? p->phi2[j] / s : 0.0;
+    }
+    free(s1);
+    free(s2);
+}
+
+static double class_weight(const oracle_problem *p) { return 1.0 / (p->n_labels > 0 ? p->n_labels : 1); }
+
+/* ------------------------------------------------------------------ */
+/* Lemma 1: the objective f(R, t), eqs. 10-13.                        */
+/* ------------------------------------------------------------------ */
+
+double oracle_objective(const oracle_problem *p, const double r[3], const double t[3], double *S11,
+                        double *S12)
+{
+    int M = p->M, N = p->N;
+    double R[9];
+    oracle_rodrigues(r, R);
+    double *w1 = malloc(sizeof(double) * M), *w2 = malloc(sizeof(double) * N);
+    double *u = malloc(sizeof(double) * 3 * M), *kap = malloc(sizeof(double) * M);
+    class_weights(p, w1, w2);
+    for (int i = 0; i < M; ++i) {
+        double d[3] = {p->mu[3 * i] - t[0], p->mu[3 * i + 1] - t[1], p->mu[3 * i + 2] - t[2]};
+        double n = norm3(d);
+        for (int a = 0; a < 3; ++a) u[3 * i + a] = d[a] / n;          /* (mu_1i - t)/|mu_1i - t| */
+        kap[i] = (n / p->sigma[i]) * (n / p->sigma[i]) + 1.0;           /* eq. 13 */
+    }
+    double phil = class_weight(p), s11 = 0, s12 = 0;
+    for (int i = 0; i < M; ++i) {
+        for (int k = 0; k < M; ++k) {
+            if (label_of(p->label1, i) != label_of(p->label1, k)) continue;
+            double v[3];
+            for (int a = 0; a < 3; ++a) v[a] = kap[i] * u[3 * i + a] + kap[k] * u[3 * k + a];
+            double K = norm3(v);                                           /* eq. 11 */
+            s11 += w1[i] * w1[k] * exp(oracle_log_Z(K) - oracle_log_Z(kap[i]) - oracle_log_Z(kap[k]));
+        }
+        double Ru[3];
+        matvec(R, u + 3 * i, Ru);
+        for (int j = 0; j < N; ++j) {
+            if (label_of(p->label1, i) != label_of(p->label2, j)) continue;
+            double v[3];
+            for (int a = 0; a < 3; ++a) v[a] = kap[i] * Ru[a] + p->kappa2[j] * p->dir2[3 * j + a];
+            double K = norm3(v);                                           /* eq. 12 */
+            s12 += w1[i] * w2[j] * exp(oracle_log_Z(K) - oracle_log_Z(kap[i]) - oracle_log_Z(p->kappa2[j]));
+        }
+    }
+    free(w1); free(w2); free(u); free(kap);
+    s11 *= phil;
+    s12 *= phil;
+    if (S11) *S11 = s11;
+    if (S12) *S12 = s12;
+    return s11 - 2.0 * s12;                                                 /* eq. 10, eq. 17 */
+}
+
+/* The constant S22 that eq. 10 drops from the L2 distance (eq. 15). */
+double oracle_S22(const oracle_problem *p)
+{
+    int N = p->N;
+    double *w1 = malloc(sizeof(double) * (p->M > 0 ? p->M : 1)), *w2 = malloc(sizeof(double) * N);
+    class_weights(p, w1, w2);
+    double s = 0;
+    for (int j = 0; j < N; ++j)
+        for (int k = 0; k < N; ++k) {
+            if (label_of(p->label2, j) != label_of(p->label2, k)) continue;
+            double v[3];
+            for (int a = 0; a < 3; ++a) v[a] = p->kappa2[j] * p->dir2[3 * j + a] + p->kappa2[k] * p->dir2[3 * k + a];
+            s += w2[j] * w2[k] * exp(oracle_log_Z(norm3(v)) - oracle_log_Z(p->kappa2[j]) - oracle_log_Z(p->kappa2[k]));
+        }
+    free(w1); free(w2);
+    return s * class_weight(p);
+}
+
+/* ------------------------------------------------------------------ */
+/* Lemmas 2 and 3: uncertainty angles                                 */
+/* ------------------------------------------------------------------ */
+
+/* Lemma 3 (translation uncertainty angle) with a guard.  The lemma takes
+ * the largest vertex angle max_v angle(p - v, p - t0), or pi when p lies in
+ * the cuboid.  The vertex maximum bounds every interior point only while it
+ * is at most pi/2 (the set of directions within such an angle of p - t0 is a
+ * convex cone, which then contains the convex hull of the p - v); beyond
+ * pi/2 this reading returns pi. */
+double oracle_psi_t(const double p[3], const double t0[3], const double tau[3])
+{
+    double c[3] = {p[0] - t0[0], p[1] - t0[1], p[2] - t0[2]};
+    if (fabs(c[0]) <= tau[0] && fabs(c[1]) <= tau[1] && fabs(c[2]) <= tau[2]) return M_PI;
+    double best = 0.0;
+    for (int v = 0; v < 8; ++v) {
+        double a[3];
+        for (int k = 0; k < 3; ++k) {
+            double s = ((v >> (2 - k)) & 1) ? 1.0 : -1.0;
+            a[k] = p[k] - (t0[k] + s * tau[k]);
+        }
+        double th = angle3(a, c);
+        if (th > best) best = th;
+    }
+    return best > 0.5 * M_PI ? M_PI : best;
+}
+
+/* Lemma 2 (rotation uncertainty angle).  The surface maximum of the lemma is
+ * not given in computable form; this reading bounds it with the angle-axis
+ * metric inequality angle(R_r p, R_s p) <= |r - s|, so for a cube with
+ * half-widths h the angle is at most min(|h|, pi).  The bound is symmetric
+ * under r -> -r and so also covers the inverse rotations used in eq. 25. */
+double oracle_psi_r(const double half[3])
+{
+    double h = norm3(half);
+    return h < M_PI ? h : M_PI;
+}
+
+/* ------------------------------------------------------------------ */
+/* Cubes: integer octree keys (level, ix, iy, iz) over a root box.    */
+/* ------------------------------------------------------------------ */
+
+void oracle_decode(uint64_t key, const double lo[3], const double hi[3], double centre[3], double half[3])
+{
+    int L = (int)((key >> 57) & 63);
+    uint64_t mask = (1ull << 19) - 1;
+    uint64_t idx[3] = {(key >> 38) & mask, (key >> 19) & mask, key & mask};
+    for (int k = 0; k < 3; ++k) {
+        half[k] = (hi[k] - lo[k]) / ldexp(1.0, L + 1);
+        centre[k] = lo[k] + (2.0 * (double)idx[k] + 1.0) * half[k];
+    }
+}
+
+/* K(a, b, theta) = sqrt(a^2 + b^2 + 2 a b cos theta), the form of eqs. 22-23. */
+static double Kab(double a, double b, double th) { return sqrt(fmax(a * a + b * b + 2.0 * a * b * cos(th), 0.0)); }
+
+/* The logarithm of one summand of eq. 21 for fixed concentrations a, b and
+ * angle theta: g = log Z(K) - log Z(a) - log Z(b). */
+static double g_term(double a, double b, double th)
+{
+    return oracle_log_Z(Kab(a, b, th)) - oracle_log_Z(a) - oracle_log_Z(b);
+}
+
+/* L(x) = d log Z(x) / dx = coth x - 1/x, with 0 <= L < 1 and
+ * 0 < L'(x) <= min(1/3, 1/x^2). */
+static double langevin(double x) { return x < 1e-6 ? x / 3.0 : 1.0 / tanh(x) - 1.0 / x; }
+
+/* dg/da = L(K) (a + b cos theta) / K - L(a). */
+static double g_da(double a, double b, double th)
+{
+    double K = Kab(a, b, th);
+    double LK_over_K = K < 1e-6 ? 1.0 / 3.0 : langevin(K) / K;
+    return LK_over_K * (a + b * cos(th)) - langevin(a);
+}
+
+/* The concentrations kappa_1i(t) in eq. 21 depend on t; the paper states that
+ * this dependence "can be optimized separately" and leaves the details to an
+ * appendix that is not available.  Reading used here: over the cube,
+ * kappa_1i(t) is relaxed to the interval [lo, hi] it takes there, and the
+ * extremum of the summand over the interval (or, for the S11 sum, over the
+ * box of two intervals) is bounded by a second-order expansion at the interval
+ * centre with a certified remainder.  With L as above:
+ *   d^2 log Z(K) / da^2 = L'(K) K_a^2 + L(K) K_aa,  K_a^2 <= 1,
+ *   K_aa = b^2 sin^2(theta) / K^3 >= 0,  L'(K) <= min(1/3, 1/K^2),
+ *   L(K) K_aa <= min(1/3, b^2 sin^2(theta) / K^3)  (as L(K) <= K/3, K >= b sin theta),
+ * and the Hessian of log Z(K(a, b)) is positive semi-definite (K is a norm
+ * of a linear function of (a, b) and log Z(K) is increasing and convex in
+ * K^2), so the Hessian of g is at least -max(L'(a), L'(b)) I. */
+
+/* S11 summand, i != i' (eq. 21, first sum), at angle A: a lower bound on
+ * min over a in [alo, ahi], b in [blo, bhi] of g(a, b, A):
+ *   g(c) - |g_a| h_a - |g_b| h_b - (lambda/2)(h_a^2 + h_b^2),
+ * lambda = max(min(1/3, 1/alo^2), min(1/3, 1/blo^2)). */
+static double s11_lower_log(double alo, double ahi, double blo, double bhi, double A)
+{
+    double ac = 0.5 * (alo + ahi), ha = 0.5 * (ahi - alo);
+    double bc = 0.5 * (blo + bhi), hb = 0.5 * (bhi - blo);
+    double lam = fmax(fmin(1.0 / 3.0, 1.0 / (alo * alo)), fmin(1.0 / 3.0, 1.0 / (blo * blo)));
+    return g_term(ac, bc, A) - fabs(g_da(ac, bc, A)) * ha - fabs(g_da(bc, ac, A)) * hb -
+           0.5 * lam * (ha * ha + hb * hb);
+}
+
+/* S12 summand (eq. 21, second sum) at angle B with b = kappa_2j fixed: the
+ * ratio Z(K)/(Z(a) Z(b)) maximised over a in [alo, ahi], bounded by the
+ * smaller of
+ *   exp(g(ac) + |g_a(ac)| h + (G/2) h^2),  G = min(1/3, 1/m^2) + min(1/3, (b sin B)^2/m^3),
+ *     m = max(K(ac) - h, b sin B) a lower bound on K over the interval (G = 2/3 if m = 0),
+ * and the value for perfectly aligned directions,
+ *   Z(a + b)/(Z(a) Z(b)) = a b (coth a + coth b) / (2 (a + b)) <= min(ahi, b)(coth alo + coth b)/2,
+ * which bounds every angle since Z increases and K <= a + b. */
+static double s12_upper_term(double alo, double ahi, double b, double B)
+{
+    double ac = 0.5 * (alo + ahi), h = 0.5 * (ahi - alo);
+    double bs = b * sin(B);
+    double m = fmax(Kab(ac, b, B) - h, bs);
+    double G = m > 0 ? fmin(1.0 / 3.0, 1.0 / (m * m)) + fmin(1.0 / 3.0, bs * bs / (m * m * m)) : 2.0 / 3.0;
+    double taylor = exp(g_term(ac, b, B) + fabs(g_da(ac, b, B)) * h + 0.5 * G * h * h);
+    double aligned = 0.5 * fmin(ahi, b) * (1.0 / tanh(alo) + 1.0 / tanh(b));
+    return fmin(taylor, aligned);
+}
+
+/* Test hooks for the two summand bounds above. */
+double oracle_s11_lower_log(double alo, double ahi, double blo, double bhi, double A)
+{
+    return s11_lower_log(alo, ahi, blo, bhi, A);
+}
+double oracle_s12_upper_term(double alo, double ahi, double b, double B)
+{
+    return s12_upper_term(alo, ahi, b, B);
+}
+
+static int cmp_desc(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x < y) - (x > y);
+}
+
+/* Theorem 1 bounds for one sub-cube C_r x C_t (Section 5.2). */
+int oracle_bounds_cube(const oracle_problem *p, const oracle_domain *d, uint64_t rkey, uint64_t tkey,
+                       oracle_bound *out)
+{
+    int M = p->M, N = p->N;
+    double r0[3], hr[3], t0[3], tau[3];
+    oracle_decode(rkey, d->r_lo, d->r_hi, r0, hr);
+    oracle_decode(tkey, d->t_lo, d->t_hi, t0, tau);
+    memset(out, 0, sizeof(*out));
+    out->ub = out->lb = INFINITY;
+
+    /* Rotation cubes are cells of the box circumscribing the radius-pi ball
+     * (Section 5.1); a cell with no point in the ball holds no rotation. */
+    double nearest[3];
+    for (int k = 0; k < 3; ++k) {
+        double lo = r0[k] - hr[k], hi = r0[k] + hr[k];
+        nearest[k] = lo > 0 ? lo : (hi < 0 ? hi : 0.0);
+    }
+    if (norm3(nearest) > M_PI) { out->status = 1; return 0; }
+
+    double *w1 = malloc(sizeof(double) * M), *w2 = malloc(sizeof(double) * N);
+    double *c = malloc(sizeof(double) * 3 * M), *klo = malloc(sizeof(double) * M),
+           *khi = malloc(sizeof(double) * M), *psit = malloc(sizeof(double) * M);
+    class_weights(p, w1, w2);
+
+    /* Per Gaussian: c_i = mu_1i - t0, the kappa interval over the cube and
+     * psi_t.  The translation domain excludes points closer than zeta to any
+     * mean (Section 5.1), so over feasible t the distance to mu_1i is at least
+     * max(zeta, dist(mu_1i, C_t)) and at most the largest vertex distance. */
+    int infeasible = 0, centre_infeasible = 0;
+    double phisum = 0, psit_mean = 0;
+    for (int i = 0; i < M; ++i) {
+        double dmin2 = 0, dmax2 = 0;
+        for (int k = 0; k < 3; ++k) {
+            c[3 * i + k] = p->mu[3 * i + k] - t0[k];
+            double e = fabs(c[3 * i + k]) - tau[k];
+            if (e > 0) dmin2 += e * e;
+            double f = fabs(c[3 * i + k]) + tau[k];
+            dmax2 += f * f;
+        }
+        double dmin = fmax(sqrt(dmin2), d->zeta), dmax = sqrt(dmax2);
+        if (dmax < d->zeta) infeasible = 1;
+        if (norm3(c + 3 * i) < d->zeta) centre_infeasible = 1;
+        double s2 = p->sigma[i] * p->sigma[i];
+        klo[i] = dmin * dmin / s2 + 1.0;
+        khi[i] = dmax * dmax / s2 + 1.0;
+        psit[i] = oracle_psi_t(p->mu + 3 * i, t0, tau);
+        phisum += p->phi1[i];
+        psit_mean += p->phi1[i] * psit[i];
+    }
+    psit_mean /= phisum;
+    out->psi_r = oracle_psi_r(hr);
+    out->psi_t_mean = psit_mean;
+    /* Branching rule: split the group with the larger angular uncertainty
+     * (Section 5.1), ties to rotation. */
+    out->split_rot = out->psi_r >= psit_mean;
+    if (infeasible) {
+        out->status = 2;
+        free(w1); free(w2); free(c); free(klo); free(khi); free(psit);
+        return 0;
+    }
+
+    /* Upper bound, eq. 20: the objective at the centre (+inf if the centre
+     * is not a feasible camera position). */
+    double R0[9];
+    oracle_rodrigues(r0, R0);
+    if (!centre_infeasible) {
+        double S11, S12;
+        out->ub = oracle_objective(p, r0, t0, &S11, &S12);
+        out->s11_ub = S11;
+        out->s12_ub = S12;
+        /* Largest S12 pair terms at the centre (features for queue ordering). */
+        double *terms = malloc(sizeof(double) * ((size_t)M * N + 8));
+        int nt = 0;
+        double phil = class_weight(p);
+        for (int i = 0; i < M; ++i) {
+            double n = norm3(c + 3 * i), u[3], Ru[3];
+            for (int k = 0; k < 3; ++k) u[k] = c[3 * i + k] / n;
+            matvec(R0, u, Ru);
+            double ki = (n / p->sigma[i]) * (n / p->sigma[i]) + 1.0;
+            for (int j = 0; j < N; ++j) {
+                if (label_of(p->label1, i) != label_of(p->label2, j)) continue;
+                double v[3];
+                for (int k = 0; k < 3; ++k) v[k] = ki * Ru[k] + p->kappa2[j] * p->dir2[3 * j + k];
+                terms[nt++] = phil * w1[i] * w2[j] *
+                              exp(oracle_log_Z(norm3(v)) - oracle_log_Z(ki) - oracle_log_Z(p->kappa2[j]));
+            }
+        }
+        qsort(terms, (size_t)nt, sizeof(double), cmp_desc);
+        for (int q = 0; q < 8; ++q) out->top8[q] = q < nt ? terms[q] : 0.0;
+        free(terms);
+    }
+
+    /* Lower bound, eq. 21 with the angles A (eq. 24) and B (eq. 25). */
+    double phil = class_weight(p), s11lo = 0, s12hi = 0;
+    for (int i = 0; i < M; ++i) {
+        for (int k = 0; k < M; ++k) {
+            if (label_of(p->label1, i) != label_of(p->label1, k)) continue;
+            double lg;
+            if (k == i) {
+                /* The angle between mu_1i - t and itself is exactly 0, so the
+                 * summand is Z(2 kappa)/Z(kappa)^2 = kappa coth(kappa)/2, which
+                 * increases with kappa: its minimum is at the lower end. */
+                lg = oracle_log_Z(2.0 * klo[i]) - 2.0 * oracle_log_Z(klo[i]);
+            } else {
+                double A = angle3(c + 3 * i, c + 3 * k) + psit[i] + psit[k];
+                if (A > M_PI) A = M_PI;
+                lg = s11_lower_log(klo[i], khi[i], klo[k], khi[k], A);
+            }
+            s11lo += w1[i] * w1[k] * exp(lg);
+        }
+        for (int j = 0; j < N; ++j) {
+            if (label_of(p->label1, i) != label_of(p->label2, j)) continue;
+            double Rinv_mu[3];
+            matTvec(R0, p->dir2 + 3 * j, Rinv_mu);                     /* R_{r0}^{-1} mu_2j */
+            double B = angle3(c + 3 * i, Rinv_mu) - psit[i] - out->psi_r;
+            if (B < 0) B = 0;
+            s12hi += w1[i] * w2[j] * s12_upper_term(klo[i], khi[i], p->kappa2[j], B);
+        }
+    }
+    out->s11_lo = phil * s11lo;
+    out->s12_hi = phil * s12hi;
+    out->lb = out->s11_lo - 2.0 * out->s12_hi;
+    free(w1); free(w2); free(c); free(klo); free(khi); free(psit);
+    return 0;
+}
+
+int oracle_eval_bounds(const oracle_problem *p, const oracle_domain *d, const uint64_t *rkeys,
+                       const uint64_t *tkeys, int64_t n, oracle_bound *out, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < n; ++q) oracle_bounds_cube(p, d, rkeys[q], tkeys[q], out + q);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 1 (Section 6) without the local optimiser.               */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    uint64_t rkey, tkey;
+    double lb, ub;
+    int split_rot;
+} node;
+
+/* Best-first priority: lowest lower bound, then lowest upper bound, then key. */
+static int node_less(const node *a, const node *b)
+{
+    if (a->lb != b->lb) return a->lb < b->lb;
+    if (a->ub != b->ub) return a->ub < b->ub;
+    if (a->rkey != b->rkey) return a->rkey < b->rkey;
+    return a->tkey < b->tkey;
+}
+
+typedef struct { node *v; int64_t n, cap; } heap;
+
+static void heap_push(heap *h, node x)
+{
+    if (h->n == h->cap) {
+        h->cap = h->cap ? 2 * h->cap : 1024;
+        h->v = realloc(h->v, sizeof(node) * (size_t)h->cap);
+    }
+    int64_t i = h->n++;
+    while (i > 0) {
+        int64_t par = (i - 1) / 2;
+        if (!node_less(&x, &h->v[par])) break;
+        h->v[i] = h->v[par];
+        i = par;
+    }
+    h->v[i] = x;
+}
+
+static node heap_pop(heap *h)
+{
+    node top = h->v[0], x = h->v[--h->n];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        const node *best = &x;
+        if (l < h->n && node_less(&h->v[l], best)) { m = l; best = &h->v[l]; }
+        if (r < h->n && node_less(&h->v[r], best)) { m = r; }
+        if (m == i) break;
+        h->v[i] = h->v[m];
+        i = m;
+    }
+    if (h->n > 0) h->v[i] = x;
+    return top;
+}
+
+static int key_level(uint64_t k) { return (int)((k >> 57) & 63); }
+
+/* The 8 children of a key: one level deeper, indices 2 i + bit. */
+static uint64_t child_key(uint64_t k, int c)
+{
+    uint64_t mask = (1ull << 19) - 1;
+    uint64_t L = (uint64_t)key_level(k) + 1;
+    uint64_t ix = 2 * ((k >> 38) & mask) + ((c >> 2) & 1);
+    uint64_t iy = 2 * ((k >> 19) & mask) + ((c >> 1) & 1);
+    uint64_t iz = 2 * (k & mask) + (c & 1);
+    return (L << 57) | (ix << 38) | (iy << 19) | iz;
+}
+
+static double now_s(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return ts.tv_sec + 1e-9 * ts.tv_nsec;
+}
+
+int oracle_solve(const oracle_problem *p, const oracle_domain *d, const oracle_opts *o, oracle_result *res)
+{
+    double t_start = now_s();
+    memset(res, 0, sizeof(*res));
+    double S22 = oracle_S22(p);
+    double eps_f = o->eps * S22;          /* tolerance on f for eps on (f + S22)/S22 */
+    int64_t k = o->batch_parents > 0 ? o->batch_parents : 1;
+    double dstar = INFINITY, floor_lb = INFINITY;
+    double best_r[3] = {0, 0, 0}, best_t[3] = {0, 0, 0};
+
+    heap Q = {0};
+    oracle_bound root;
+    oracle_bounds_cube(p, d, 0, 0, &root);
+    res->cubes = 1;
+    if (root.ub < dstar) {
+        dstar = root.ub;
+        oracle_decode(0, d->r_lo, d->r_hi, best_r, (double[3]){0});
+        oracle_decode(0, d->t_lo, d->t_hi, best_t, (double[3]){0});
+    }
+    if (root.status == 0) heap_push(&Q, (node){0, 0, root.lb, root.ub, root.split_rot});
+
+    node *par = malloc(sizeof(node) * (size_t)k);
+    uint64_t *rk = malloc(sizeof(uint64_t) * (size_t)(8 * k)), *tk = malloc(sizeof(uint64_t) * (size_t)(8 * k));
+    int64_t *parent_of = malloc(sizeof(int64_t) * (size_t)(8 * k));
+    oracle_bound *cb = malloc(sizeof(oracle_bound) * (size_t)(8 * k));
+    int status = 1;
+    double lb_global = INFINITY;
+    for (;;) {
+        if (Q.n == 0) { status = 1; lb_global = fmin(dstar, floor_lb); break; }
+        lb_global = fmin(Q.v[0].lb, floor_lb);          /* lowest lower bound in Q */
+        if (dstar - lb_global <= eps_f) { status = 0; break; }
+        if ((o->max_iters > 0 && res->iters >= o->max_iters) ||
+            (o->time_limit_s > 0 && now_s() - t_start > o->time_limit_s)) { status = 2; break; }
+        int64_t np = 0;
+        while (np < k && Q.n > 0) par[np++] = heap_pop(&Q);
+        int64_t nc = 0;
+        for (int64_t q = 0; q < np; ++q) {
+            int rot = par[q].split_rot;
+            if (rot && key_level(par[q].rkey) >= 19) rot = 0;
+            if (!rot && key_level(par[q].tkey) >= 19) rot = key_level(par[q].rkey) < 19;
+            if (key_level(par[q].rkey) >= 19 && key_level(par[q].tkey) >= 19) {
+                if (par[q].lb < floor_lb) floor_lb = par[q].lb;   /* unsplittable: keep its bound */
+                continue;
+            }
+            for (int ch = 0; ch < 8; ++ch) {
+                rk[nc] = rot ? child_key(par[q].rkey, ch) : par[q].rkey;
+                tk[nc] = rot ? par[q].tkey : child_key(par[q].tkey, ch);
+                parent_of[nc++] = q;
+            }
+        }
+        oracle_eval_bounds(p, d, rk, tk, nc, cb, o->nthreads);
+        res->cubes += nc;
+        /* Upper bounds first (the best child sets d*), then push every child
+         * whose lower bound, raised to its parent's, is below d*. */
+        int64_t best = -1;
+        for (int64_t q = 0; q < nc; ++q)
+            if (cb[q].status == 0 && cb[q].ub < dstar) { dstar = cb[q].ub; best = q; }
+        if (best >= 0) {
+            double h[3];
+            oracle_decode(rk[best], d->r_lo, d->r_hi, best_r, h);
+            oracle_decode(tk[best], d->t_lo, d->t_hi, best_t, h);
+        }
+        for (int64_t q = 0; q < nc; ++q) {
+            if (cb[q].status != 0) continue;
+            double lb = fmax(cb[q].lb, par[parent_of[q]].lb);
+            if (lb < dstar) heap_push(&Q, (node){rk[q], tk[q], lb, cb[q].ub, cb[q].split_rot});
+        }
+        if (Q.n > res->max_queue) res->max_queue = Q.n;
+        res->iters++;
+    }
+    res->status = status;
+    res->f_best = dstar;
+    res->lb_global = lb_global;
+    res->S22 = S22;
+    res->f_norm_best = (dstar + S22) / S22;
+    res->lb_norm = (lb_global + S22) / S22;
+    memcpy(res->r, best_r, sizeof best_r);
+    memcpy(res->t, best_t, sizeof best_t);
+    res->seconds = now_s() - t_start;
+    free(Q.v); free(par); free(rk); free(tk); free(parent_of); free(cb);
+    return 0;
+}

@@ -1,0 +1,160 @@
+"""Theorem 1 bounds of the oracle: validity and convergence by brute force.
+
+The lower-bound value is "parity unpinned" (the paper's proof appendix is not
+available), so these tests pin what can be pinned: each summand bound against
+dense brute-force optimisation over its interval, the whole lower bound
+against the minimum of the objective sampled inside the cube, the upper bound
+as the objective at the centre, and convergence as cubes shrink.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import scenes
+
+
+def _logZ(x):
+    x = np.asarray(x, dtype=np.float64)
+    xs = np.maximum(x, 1e-300)
+    return np.where(x <= 0, math.log(2.0), xs + np.log(-np.expm1(-2 * xs)) - np.log(xs))
+
+
+def _g(a, b, th):
+    K = np.sqrt(np.maximum(a * a + b * b + 2 * a * b * np.cos(th), 0))
+    return _logZ(K) - _logZ(a) - _logZ(b)
+
+
+def test_s12_upper_term_bounds_interval_maximum():
+    rng = np.random.default_rng(0)
+    for _ in range(3000):
+        a = math.exp(rng.uniform(0, math.log(3e4)))
+        b = math.exp(rng.uniform(0, math.log(3e4)))
+        w = 10 ** rng.uniform(-5, 0.5)
+        B = rng.uniform(0, math.pi) * rng.uniform() ** 3
+        grid = np.linspace(a, a * (1 + w), 401)
+        exact = np.exp(_g(grid, b, B)).max()
+        bound = oracle.s12_upper_term(a, a * (1 + w), b, B)
+        assert bound >= exact * (1 - 1e-12)
+        if w < 1e-3 and exact > 1e-6:
+            assert bound <= exact * (1 + 1e-2)   # tight for small intervals
+
+
+def test_s11_lower_log_bounds_box_minimum():
+    rng = np.random.default_rng(1)
+    for _ in range(1500):
+        a = math.exp(rng.uniform(0, math.log(3e4)))
+        b = math.exp(rng.uniform(0, math.log(3e4)))
+        wa = 10 ** rng.uniform(-5, 0)
+        wb = 10 ** rng.uniform(-5, 0)
+        A = rng.uniform(0, math.pi) * rng.uniform() ** 3
+        ga = np.linspace(a, a * (1 + wa), 41)[:, None]
+        gb = np.linspace(b, b * (1 + wb), 41)[None, :]
+        exact = _g(ga, gb, A).min()
+        bound = oracle.s11_lower_log(a, a * (1 + wa), b, b * (1 + wb), A)
+        assert bound <= exact + 1e-10 * (1 + abs(exact))
+
+
+def _key_containing(x, lo, hi, L):
+    idx = np.floor((np.asarray(x) - lo) / (hi - lo) * (2 ** L)).astype(int)
+    idx = np.clip(idx, 0, 2 ** L - 1)
+    return int(scenes.pack_key(L, idx[0], idx[1], idx[2]))
+
+
+def _sampled_min(P, sc, rk, tk, n, rng):
+    rc, rh = oracle.decode(rk, sc.r_lo, sc.r_hi)
+    tc, th = oracle.decode(tk, sc.t_lo, sc.t_hi)
+    best = math.inf
+    for q in range(n):
+        r = rc + rh * rng.uniform(-1, 1, 3)
+        t = tc + th * rng.uniform(-1, 1, 3)
+        if q < 64:   # corners and faces too
+            r = rc + rh * rng.choice([-1.0, 1.0], 3)
+            t = tc + th * rng.choice([-1.0, 1.0], 3)
+        if np.min(np.linalg.norm(sc.mu - t, axis=1)) < sc.zeta:
+            continue
+        best = min(best, P.objective(r, t)[0])
+    return best
+
+
+@pytest.mark.parametrize("seed,M,N,noise", [(31, 5, 5, 0.0), (32, 6, 8, 1.0), (33, 8, 6, 2.0)])
+def test_lower_bound_below_sampled_minimum(seed, M, N, noise):
+    """lb <= min f over >= 4096 feasible poses sampled in each cube, and
+    ub = f(centre), on random small cubes and on cubes around the true pose."""
+    sc = scenes.small_scene(M, N, seed=seed, noise_deg=noise, n_inliers=min(M, N) - 1)
+    P = oracle.OracleProblem(sc)
+    rng = np.random.default_rng(seed)
+    rk, tk = scenes.random_cubes(sc, 12, seed + 500, r_levels=(4, 8), t_levels=(2, 6))
+    keys = list(zip(rk.tolist(), tk.tolist()))
+    for Lr, Lt in [(5, 3), (7, 5), (9, 7), (11, 9)]:
+        keys.append((_key_containing(sc.r_gt, sc.r_lo, sc.r_hi, Lr), _key_containing(sc.t_gt, sc.t_lo, sc.t_hi, Lt)))
+    b = P.bounds([k[0] for k in keys], [k[1] for k in keys])
+    checked = 0
+    for q, (rkq, tkq) in enumerate(keys):
+        if b["status"][q] != 0:
+            continue
+        smin = _sampled_min(P, sc, rkq, tkq, 4096, rng)
+        if not math.isfinite(smin):
+            continue
+        assert b["lb"][q] <= smin + 1e-12 * abs(smin)
+        rc, _ = oracle.decode(rkq, sc.r_lo, sc.r_hi)
+        tc, _ = oracle.decode(tkq, sc.t_lo, sc.t_hi)
+        if math.isfinite(b["ub"][q]):
+            f, s11, s12 = P.objective(rc, tc)
+            assert b["ub"][q] == f
+            assert b["s11_ub"][q] == s11 and b["s12_ub"][q] == s12
+            assert b["lb"][q] <= b["ub"][q]
+        checked += 1
+    assert checked >= 8
+
+
+def test_bounds_converge_as_cubes_shrink():
+    """UB - LB -> 0 as the cube around a pose halves (the B&B requirement
+    stated at the start of Section 5)."""
+    sc = scenes.small_scene(8, 8, seed=85)
+    P = oracle.OracleProblem(sc)
+    S22 = P.S22()
+    gaps = []
+    for Lr, Lt in [(4, 2), (6, 4), (8, 6), (10, 8), (12, 10), (14, 12)]:
+        rk = _key_containing(sc.r_gt, sc.r_lo, sc.r_hi, Lr)
+        tk = _key_containing(sc.t_gt, sc.t_lo, sc.t_hi, Lt)
+        b = P.bounds([rk], [tk])
+        gaps.append((b["ub"][0] - b["lb"][0]) / S22)
+    assert all(g > 0 for g in gaps)
+    assert all(gaps[k + 1] < 0.6 * gaps[k] for k in range(len(gaps) - 1))
+    assert gaps[-1] < 2e-3
+
+
+def test_cube_status_edge_cases():
+    sc = scenes.cfg1_scene(0)
+    P = oracle.OracleProblem(sc)
+    # rotation cell [3pi/4, pi]^3: its nearest point to 0 has norm 3 sqrt(3) pi / 4 > pi
+    corner = int(scenes.pack_key(3, 7, 7, 7))
+    # translation cell that lies entirely within zeta of a Gaussian mean
+    sc2 = scenes.small_scene(4, 4, seed=1)
+    sc2.mu[0] = np.array([0.01, 0.02, -0.03])     # inside the translation domain
+    P2 = oracle.OracleProblem(sc2)
+    inner_t = _key_containing(sc2.mu[0], sc2.t_lo, sc2.t_hi, 6)
+    b = P.bounds([corner, 0], [0, 0])
+    assert b["status"][0] == 1 and math.isinf(b["lb"][0])
+    assert b["status"][1] == 0 and b["lb"][1] < b["ub"][1]
+    b2 = P2.bounds([0], [inner_t])
+    assert b2["status"][0] == 2 and math.isinf(b2["lb"][0])
+    # a cell that touches the ball is kept
+    touching = int(scenes.pack_key(1, 1, 1, 1))
+    assert P.bounds([touching], [0])["status"][0] == 0
+
+
+def test_top8_are_the_largest_pair_terms():
+    sc = scenes.cfg1_scene(0)
+    P = oracle.OracleProblem(sc)
+    rk, tk = scenes.random_cubes(sc, 20, 77)
+    b = P.bounds(rk, tk)
+    for q in range(20):
+        if b["status"][q] != 0 or not math.isfinite(b["ub"][q]):
+            continue
+        top = b["top8"][q]
+        assert np.all(np.diff(top) <= 0)
+        assert top.sum() <= b["s12_ub"][q] * (1 + 1e-12)
+        assert top[0] >= b["s12_ub"][q] / (sc.M * sc.N)

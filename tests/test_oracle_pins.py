@@ -1,0 +1,303 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: the
+numbers printed in Fig. 3b, a sphere quadrature of the L2 distance (Lemma 1's
+closed form), closed forms for single pairs, the zero distance at the true
+pose of a noise-free scene, invariances, and brute-force sampling for the
+uncertainty angles (Lemmas 2 and 3).
+"""
+import math
+from pathlib import Path
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import oracle
+from synth import scenes
+
+GOLDEN = Path(__file__).resolve().parent / "golden"
+
+
+def _Z(x):
+    """Z of eq. 2 in plain numpy (small arguments only)."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.where(x == 0, 2.0, 2.0 * np.sinh(x) / np.where(x == 0, 1.0, x))
+
+
+# --------------------------------------------------------------------------
+# Fig. 3b: qPN vs PN mean absolute error (Section 3)
+# --------------------------------------------------------------------------
+
+def test_fig3b_table_reproduced():
+    """The 100 printed MAE values (Fig. 3b) from eq. 1, eq. 3 and eq. 6.
+
+    The mean is over the angle between f and mu at 1 degree steps on
+    [0, 180] degrees.  This pins log Z, the vMF and PN densities and the qPN
+    concentration map; the caption's claim MAE < 0.01 for rho >= 1 is also
+    checked."""
+    rows = [l.split() for l in (GOLDEN / "fig3b_qpn_pn_mae.txt").read_text().splitlines()
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 100
+    worst = 0.0
+    for rho_s, mae_s in rows:
+        rho, mae = float(rho_s), float(mae_s)
+        mu = np.array([0.0, 0.0, rho])
+        kappa = oracle.qpn_kappa(mu, 1.0)
+        assert kappa == pytest.approx(rho * rho + 1.0, rel=1e-15)
+        errs = []
+        for deg in range(181):
+            th = math.radians(deg)
+            f = np.array([math.sin(th), 0.0, math.cos(th)])
+            errs.append(abs(oracle.vmf_pdf(f, mu / rho, kappa) - oracle.pn_pdf(f, mu, 1.0)))
+        m = float(np.mean(errs))
+        worst = max(worst, abs(m - mae) / mae)
+        if rho >= 1.0:
+            assert m < 0.01
+    assert worst < 1e-9
+
+
+def test_log_Z_values():
+    for x in [1e-8, 1e-3, 0.5, 1.0, 3.0, 20.0]:
+        assert oracle.log_Z(x) == pytest.approx(math.log(2 * math.sinh(x) / x), rel=1e-12, abs=1e-14)
+    assert oracle.log_Z(0.0) == pytest.approx(math.log(2.0))
+    # large arguments: Z overflows but log Z = x - log x + log(1 - e^-2x)
+    assert oracle.log_Z(5000.0) == pytest.approx(5000.0 - math.log(5000.0), rel=1e-15)
+
+
+def test_vmf_normalised():
+    """eq. 1 integrates to one over the sphere (Gauss-Legendre in cos theta)."""
+    u, w = np.polynomial.legendre.leggauss(200)
+    for kappa in [0.3, 4.0, 60.0]:
+        tot = 0.0
+        for ui, wi in zip(u, w):
+            f = np.array([math.sqrt(max(0.0, 1 - ui * ui)), 0.0, ui])
+            tot += wi * 2 * math.pi * oracle.vmf_pdf(f, np.array([0, 0, 1.0]), kappa)
+        assert tot == pytest.approx(1.0, rel=1e-10)
+
+
+# --------------------------------------------------------------------------
+# Lemma 1: the objective
+# --------------------------------------------------------------------------
+
+def _sphere_grid(n_theta=96, n_phi=192):
+    u, w = np.polynomial.legendre.leggauss(n_theta)
+    ph = (np.arange(n_phi) + 0.5) * 2 * math.pi / n_phi
+    U, PH = np.meshgrid(u, ph, indexing="ij")
+    s = np.sqrt(1 - U * U)
+    F = np.stack([s * np.cos(PH), s * np.sin(PH), U], axis=-1).reshape(-1, 3)
+    W = (w[:, None] * np.full(n_phi, 2 * math.pi / n_phi)[None, :]).reshape(-1)
+    return F, W
+
+
+def _mixture_density(F, dirs, kappas, weights):
+    out = np.zeros(F.shape[0])
+    for d, k, w in zip(dirs, kappas, weights):
+        out += w * np.exp(k * (F @ d)) / (2 * math.pi * _Z(k))
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_lemma1_matches_sphere_quadrature(seed):
+    """(f + S22) / (2 pi) equals the integral of (p1 - p2)^2 over S^2 (eq. 14-15).
+
+    p1 is the qPN mixture of the GMM transformed by T(theta_1, R, t) = R(mu - t)
+    and p2 the vMF mixture.  The rotation is built with scipy, independently
+    of the oracle's Rodrigues formula.  Concentrations are kept below 6 so the
+    quadrature converges."""
+    rng = np.random.default_rng(seed)
+    M, N = 4, 3
+    mu = rng.uniform(-1, 1, size=(M, 3))
+    mu[:, 2] += 2.0
+    t = rng.uniform(-0.3, 0.3, size=3)
+    sigma = np.linalg.norm(mu - t, axis=1) / rng.uniform(0.5, 2.0, size=M)
+    phi1 = rng.dirichlet(np.ones(M))
+    dir2 = rng.standard_normal((N, 3))
+    dir2 /= np.linalg.norm(dir2, axis=1, keepdims=True)
+    kappa2 = rng.uniform(0.5, 5.0, size=N)
+    phi2 = rng.dirichlet(np.ones(N))
+    r = rng.standard_normal(3)
+    r *= rng.uniform(0.2, 3.0) / np.linalg.norm(r)
+    sc = scenes.Scene(mu=mu, sigma=sigma, phi1=phi1, dir2=dir2, kappa2=kappa2, phi2=phi2, r_gt=r,
+                      R_gt=np.eye(3), t_gt=t, t_lo=-np.ones(3), t_hi=np.ones(3))
+    P = oracle.OracleProblem(sc)
+    f, s11, s12 = P.objective(r, t)
+    S22 = P.S22()
+    R = Rotation.from_rotvec(r).as_matrix()
+    d = mu - t
+    rho = np.linalg.norm(d, axis=1)
+    dirs1 = (d / rho[:, None]) @ R.T
+    kap1 = (rho / sigma) ** 2 + 1.0
+    F, W = _sphere_grid()
+    p1 = _mixture_density(F, dirs1, kap1, phi1)
+    p2 = _mixture_density(F, dir2, kappa2, phi2)
+    assert np.sum(W * (p1 - p2) ** 2) == pytest.approx((f + S22) / (2 * math.pi), rel=1e-9)
+    assert np.sum(W * p1 * p1) == pytest.approx(s11 / (2 * math.pi), rel=1e-9)
+    assert np.sum(W * p1 * p2) == pytest.approx(s12 / (2 * math.pi), rel=1e-9)
+    assert np.sum(W * p2 * p2) == pytest.approx(S22 / (2 * math.pi), rel=1e-9)
+
+
+def test_single_pair_closed_form():
+    """M = N = 1: f = Z(2k1)/Z(k1)^2 - 2 Z(|k1 R u + k2 v|)/(Z(k1) Z(k2)),
+    and the diagonal term Z(2k)/Z(k)^2 = k coth(k) / 2."""
+    rng = np.random.default_rng(5)
+    for _ in range(10):
+        mu = rng.uniform(-2, 2, size=(1, 3))
+        t = rng.uniform(-0.2, 0.2, size=3)
+        sigma = np.array([np.linalg.norm(mu[0] - t) / rng.uniform(0.5, 4.0)])
+        v = rng.standard_normal(3)
+        v /= np.linalg.norm(v)
+        k2 = rng.uniform(0.5, 20.0)
+        r = rng.standard_normal(3)
+        sc = scenes.Scene(mu=mu, sigma=sigma, phi1=np.ones(1), dir2=v[None], kappa2=np.array([k2]),
+                          phi2=np.ones(1), r_gt=r, R_gt=np.eye(3), t_gt=t, t_lo=-np.ones(3), t_hi=np.ones(3))
+        f, s11, s12 = oracle.OracleProblem(sc).objective(r, t)
+        d = mu[0] - t
+        k1 = (np.linalg.norm(d) / sigma[0]) ** 2 + 1
+        u = Rotation.from_rotvec(r).as_matrix() @ (d / np.linalg.norm(d))
+        K = np.linalg.norm(k1 * u + k2 * v)
+        assert s11 == pytest.approx(_Z(2 * k1) / _Z(k1) ** 2, rel=1e-12)
+        assert s11 == pytest.approx(k1 / math.tanh(k1) / 2, rel=1e-12)
+        assert s12 == pytest.approx(_Z(K) / (_Z(k1) * _Z(k2)), rel=1e-11)
+        assert f == pytest.approx(s11 - 2 * s12, rel=1e-11, abs=1e-12)
+
+
+@pytest.mark.parametrize("make", [lambda: scenes.cfg1_scene(0), lambda: scenes.cfg1_scene(1),
+                                  lambda: scenes.small_scene(8, 8, seed=3)])
+def test_zero_distance_at_true_pose(make):
+    """Noise-free scenes: the vMF mixture is the qPN projection of the GMM at
+    the true pose (eq. 8 with T), so d_L2 = 0 and f = -S22 there.  The scene's
+    rotation was built from a quaternion; the oracle uses Rodrigues on the
+    stored angle-axis vector."""
+    sc = make()
+    P = oracle.OracleProblem(sc)
+    f, s11, s12 = P.objective(sc.r_gt, sc.t_gt)
+    S22 = P.S22()
+    assert abs(f + S22) <= 1e-12 * S22
+    assert s11 == pytest.approx(S22, rel=1e-12)
+    assert s12 == pytest.approx(S22, rel=1e-12)
+    # and anywhere else the distance is positive
+    f2, _, _ = P.objective(sc.r_gt + 0.05, sc.t_gt)
+    assert f2 + S22 > 1e-4 * S22
+
+
+def test_rodrigues_matches_scipy():
+    rng = np.random.default_rng(11)
+    for _ in range(50):
+        r = rng.standard_normal(3) * rng.uniform(0, 3.2)
+        assert np.allclose(oracle.rodrigues(r), Rotation.from_rotvec(r).as_matrix(), atol=1e-14)
+    assert np.allclose(oracle.rodrigues(np.zeros(3)), np.eye(3))
+    assert np.allclose(oracle.rodrigues(np.array([1e-12, 0, 0])), Rotation.from_rotvec([1e-12, 0, 0]).as_matrix())
+
+
+def test_objective_invariances():
+    sc = scenes.cfg2_scene(0)
+    P = oracle.OracleProblem(sc)
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal(3)
+    t = np.array([0.1, -0.2, 0.3])
+    f, s11, s12 = P.objective(r, t)
+    # component permutation
+    p1 = rng.permutation(sc.M)
+    p2 = rng.permutation(sc.N)
+    sc2 = scenes.Scene(mu=sc.mu[p1], sigma=sc.sigma[p1], phi1=sc.phi1[p1], dir2=sc.dir2[p2],
+                       kappa2=sc.kappa2[p2], phi2=sc.phi2[p2], r_gt=sc.r_gt, R_gt=sc.R_gt, t_gt=sc.t_gt,
+                       t_lo=sc.t_lo, t_hi=sc.t_hi)
+    assert oracle.OracleProblem(sc2).objective(r, t)[0] == pytest.approx(f, rel=1e-12)
+    # S11 does not depend on the rotation
+    assert P.objective(r * 0.3 + 1.0, t)[1] == pytest.approx(s11, rel=1e-13)
+    # the same rotation written as an angle-axis vector outside the pi-ball
+    th = np.linalg.norm(r)
+    r_alt = r / th * (th - 2 * math.pi)
+    assert P.objective(r_alt, t)[0] == pytest.approx(f, rel=1e-12)
+
+
+def test_semantic_objective_is_class_weighted_sum():
+    """eq. 17: f = sum_l phi_l f_l with phi_l = 1/|Lambda| and each f_l the
+    Lemma 1 objective of the class-l mixtures (weights renormalised)."""
+    sc = scenes.small_scene(24, 20, seed=9, n_labels=3, noise_deg=1.0, n_inliers=15)
+    P = oracle.OracleProblem(sc)
+    r = np.array([0.3, -1.0, 0.4])
+    t = np.array([0.05, 0.1, -0.2])
+    f, s11, s12 = P.objective(r, t)
+    tot = 0.0
+    tot22 = 0.0
+    for l in range(3):
+        a = sc.label1 == l
+        b = sc.label2 == l
+        sub = scenes.Scene(mu=sc.mu[a], sigma=sc.sigma[a], phi1=sc.phi1[a], dir2=sc.dir2[b],
+                           kappa2=sc.kappa2[b], phi2=sc.phi2[b], r_gt=sc.r_gt, R_gt=sc.R_gt, t_gt=sc.t_gt,
+                           t_lo=sc.t_lo, t_hi=sc.t_hi)
+        Ps = oracle.OracleProblem(sub)
+        tot += Ps.objective(r, t)[0] / 3
+        tot22 += Ps.S22() / 3
+    assert f == pytest.approx(tot, rel=1e-12)
+    assert P.S22() == pytest.approx(tot22, rel=1e-12)
+    # one class equals the unlabelled problem
+    sc1 = scenes.small_scene(10, 10, seed=4)
+    sc1l = scenes.small_scene(10, 10, seed=4)
+    sc1l.label1 = np.zeros(10, np.int32)
+    sc1l.label2 = np.zeros(10, np.int32)
+    assert oracle.OracleProblem(sc1l).objective(r, t)[0] == pytest.approx(
+        oracle.OracleProblem(sc1).objective(r, t)[0], rel=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Lemmas 2 and 3: uncertainty angles, brute force
+# --------------------------------------------------------------------------
+
+def _ang(a, b):
+    return np.arctan2(np.linalg.norm(np.cross(a, b), axis=-1), np.sum(a * b, axis=-1))
+
+
+def test_psi_t_bounds_sampled_angles():
+    rng = np.random.default_rng(21)
+    unguarded_fail = 0
+    for trial in range(400):
+        t0 = rng.uniform(-1, 1, 3)
+        tau = rng.uniform(0.01, 0.5, 3)
+        p = t0 + rng.standard_normal(3) * rng.uniform(0.05, 1.5)
+        psi = oracle.psi_t(p, t0, tau)
+        ts = t0 + tau * rng.uniform(-1, 1, size=(2000, 3))
+        verts = t0 + tau * np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)])
+        faces = t0 + tau * np.clip(rng.uniform(-1.5, 1.5, size=(2000, 3)), -1, 1)
+        allt = np.concatenate([ts, verts, faces])
+        sampled = _ang(p - allt, np.broadcast_to(p - t0, allt.shape)).max()
+        assert sampled <= psi + 1e-12
+        vmax = _ang(p - verts, np.broadcast_to(p - t0, verts.shape)).max()
+        inside = np.all(np.abs(p - t0) <= tau)
+        if not inside and vmax <= math.pi / 2:
+            assert psi == pytest.approx(vmax, rel=1e-12)
+        if not inside and sampled > vmax + 1e-9:
+            unguarded_fail += 1
+            assert vmax > math.pi / 2      # the plain vertex maximum only fails beyond pi/2
+    assert oracle.psi_t(np.zeros(3), np.zeros(3), np.ones(3)) == pytest.approx(math.pi)
+
+
+def test_psi_r_bounds_sampled_angles():
+    rng = np.random.default_rng(22)
+    for trial in range(200):
+        r0 = rng.uniform(-math.pi, math.pi, 3)
+        h = np.full(3, rng.uniform(1e-3, 0.6))
+        psi = oracle.psi_r(h)
+        assert psi == pytest.approx(min(math.sqrt(3) * h[0], math.pi))
+        R0 = Rotation.from_rotvec(r0).as_matrix()
+        p = rng.standard_normal(3)
+        rs = r0 + h * rng.uniform(-1, 1, size=(500, 3))
+        Rs = Rotation.from_rotvec(rs).as_matrix()
+        a = _ang(Rs @ p, np.broadcast_to(R0 @ p, (500, 3)))
+        b = _ang(np.swapaxes(Rs, 1, 2) @ p, np.broadcast_to(R0.T @ p, (500, 3)))
+        assert a.max() <= psi + 1e-12
+        assert b.max() <= psi + 1e-12
+
+
+def test_decode_keys():
+    lo, hi = np.array([-1.0, -2.0, 0.0]), np.array([1.0, 2.0, 3.0])
+    for L in [0, 1, 5, 19]:
+        idx = [(1 << L) - 1, 0, (1 << L) // 2]
+        key = int(scenes.pack_key(L, *idx))
+        c, h = oracle.decode(key, lo, hi)
+        assert np.allclose(h, (hi - lo) / 2 ** (L + 1))
+        assert np.allclose(c, lo + (2 * np.array(idx) + 1) * h)
+        c2, h2 = scenes.cube_geometry(np.uint64(key), lo, hi)
+        assert np.allclose(c2, c) and np.allclose(h2, h)
