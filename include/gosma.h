@@ -1,0 +1,183 @@
+/*
+ * gosma.h -- C-ABI of libgosma, the MI355X (gfx950) implementation of the
+ * branch-and-bound bound evaluation of GOSMA (Campbell, Petersson, Kneip,
+ * Li, Gould, "The Alignment of the Spheres: Globally-Optimal Spherical
+ * Mixture Alignment for Camera Pose Estimation", arXiv:1812.01232).
+ *
+ * Conventions for every entry point:
+ *   - Return 0 (GOSMA_OK) on success or a negative GOSMA_E_* code.  No C++
+ *     exception crosses this boundary; the message of the last failure on a
+ *     context is available from gosma_last_error().
+ *   - The caller owns every buffer it passes.  Functions that take host
+ *     arrays copy them before returning.  Functions documented as taking
+ *     device pointers read and write them asynchronously on the HIP stream
+ *     passed as `stream` (NULL = the null stream) and do not synchronise.
+ *   - A context is bound to one device and is not thread-safe; calls on one
+ *     context must be serialised by the caller.
+ *
+ * Octree keys.  A cube of the rotation domain (angle-axis vectors, Section
+ * 5.1) or of the translation domain is an octree cell of a root box:
+ *   bits  0-18  z index      bits 19-37  y index
+ *   bits 38-56  x index      bits 57-62  level L (0..19)
+ * Level L splits each axis of the root box [lo, hi] into 2^L cells; cell i
+ * has centre lo + (2 i + 1) (hi - lo) / 2^(L+1) and that half-width.
+ * Key 0 is the root box.
+ */
+#ifndef GOSMA_H
+#define GOSMA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GOSMA_OK 0
+#define GOSMA_E_INVAL (-1)          /* invalid argument (message says which) */
+#define GOSMA_E_NOMEM (-2)          /* device or host allocation failed */
+#define GOSMA_E_HIP (-3)            /* a HIP runtime call failed (HIP error text kept) */
+#define GOSMA_E_QUEUE_OVERFLOW (-4) /* the branch-and-bound queue exceeded its capacity */
+#define GOSMA_E_STATE (-5)          /* call made before the state it needs was set */
+
+#define GOSMA_MAX_COMPONENTS 1024   /* per mixture, per problem */
+#define GOSMA_MAX_LABELS 64
+
+typedef struct gosma_ctx gosma_ctx;
+
+/* Search domain of one pose problem (Section 5.1): the rotation box of
+ * angle-axis vectors (normally [-pi, pi]^3, the cube circumscribing the
+ * radius-pi ball), the translation box Omega_t', and zeta, the smallest
+ * allowed distance between the camera centre and any Gaussian mean. */
+typedef struct {
+    double r_lo[3], r_hi[3];
+    double t_lo[3], t_hi[3];
+    double zeta;
+} gosma_domain;
+
+/* Flags byte written per cube by the bound evaluation. */
+#define GOSMA_FLAG_SPLIT_ROT 1u     /* the cube's next split is in rotation (Section 5.1) */
+#define GOSMA_FLAG_DROP_ROT 2u      /* rotation cell has no point in the radius-pi ball */
+#define GOSMA_FLAG_DROP_TRANS 4u    /* every translation in the cell is within zeta of a mean */
+#define GOSMA_FLAG_UB_INF 8u        /* the cell centre is not a feasible camera position */
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+int gosma_create(int device, gosma_ctx **out);
+
+/* Release the context and all device memory it owns.  NULL is ignored. */
+void gosma_destroy(gosma_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none).  The pointer stays
+ * valid until the next call on ctx. */
+const char *gosma_last_error(const gosma_ctx *ctx);
+
+/* Set the single pose problem of the context (replacing any previous one).
+ * GMM theta_1 (Section 4, eq. 7): M means mu (M x 3, row-major, metres),
+ * standard deviations sigma (M, > 0) and weights phi1 (M, >= 0).  vMF mixture
+ * theta_2 (eq. 9): N unit mean directions dir2 (N x 3; |d| = 1 within 1e-6),
+ * concentrations kappa2 (N, > 0) and weights phi2 (N, >= 0).  Optional class
+ * labels (eq. 17) label1 (M) and label2 (N) in [0, n_labels); pass NULL for
+ * both to use one class.  With labels only same-class pairs contribute and
+ * the objective is sum_l f_l / n_labels, the weights being renormalised
+ * within each class; without labels the weights are renormalised to sum 1.
+ * All arrays are host FP64/int32 and are copied.  1 <= M, N <= 1024. */
+int gosma_set_mixtures(gosma_ctx *ctx, int M, const double *mu, const double *sigma, const double *phi1,
+                       const int32_t *label1, int N, const double *dir2, const double *kappa2,
+                       const double *phi2, const int32_t *label2, int n_labels);
+
+/* Set the search domain of the single problem (host struct, copied). */
+int gosma_set_domain(gosma_ctx *ctx, const gosma_domain *domain);
+
+/* Set n_problems independent pose problems at once (the batched form).  The
+ * per-problem arrays of gosma_set_mixtures are concatenated; problem p owns
+ * GMM rows gmm_off[p] .. gmm_off[p+1]-1 and vMF rows vmf_off[p] ..
+ * vmf_off[p+1]-1 (offset arrays of n_problems + 1 entries, gmm_off[0] =
+ * vmf_off[0] = 0).  label arrays are NULL or concatenated like the others;
+ * n_labels applies to every problem.  domains holds n_problems structs.
+ * Replaces any problem set before.  All host memory, copied. */
+int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, const int64_t *vmf_off,
+                       const double *mu, const double *sigma, const double *phi1, const int32_t *label1,
+                       const double *dir2, const double *kappa2, const double *phi2, const int32_t *label2,
+                       int n_labels, const gosma_domain *domains);
+
+/* The constant S22 of problem p (the vMF self term that eq. 10 drops from
+ * the L2 distance of eq. 14).  The normalised objective used for the
+ * tolerance is (f + S22) / S22, zero at perfect alignment. */
+int gosma_get_S22(gosma_ctx *ctx, int problem, double *S22);
+
+/* Theorem 1 bounds (Section 5.2) for n sub-cubes C_r x C_t.
+ * Device pointers (all n-element arrays):
+ *   rkeys, tkeys  in:  octree keys of the rotation and translation cells
+ *   problem       in:  uint32 problem index per cube, or NULL (all problem 0);
+ *                      an index >= the number of problems gives NaN bounds
+ *                      and both drop flags
+ *   ub            out: upper bound, eq. 20 (objective at the centre; +inf if
+ *                      the centre is infeasible or the cube is dropped)
+ *   lb            out: lower bound, eq. 21 (+inf for dropped cubes); no
+ *                      rounding margin is applied here
+ *   flags         out: GOSMA_FLAG_* bits
+ *   aux           out: NULL or n x 4 doubles {S11 at centre, S12 at centre,
+ *                      S11 lower sum, S12 upper sum} (class-weighted)
+ *   top8          out: NULL or n x 8 floats, the largest S12 pair terms at the
+ *                      centre in descending order (zeros past the pair count)
+ * Runs asynchronously on `stream` (a hipStream_t, NULL = null stream).
+ * n = 0 is a no-op.  Errors: GOSMA_E_STATE before mixtures and a domain are
+ * set, GOSMA_E_INVAL for n < 0 or a NULL required pointer. */
+int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *problem,
+                      int64_t n, double *ub, double *lb, uint8_t *flags, double *aux, float *top8,
+                      void *stream);
+
+/* Branch-and-bound options (Algorithm 1, Section 6). */
+typedef struct {
+    double eps;              /* tolerance on the normalised objective (f + S22)/S22 */
+    int64_t batch_parents;   /* cubes removed from the queue per iteration (8 children each) */
+    int64_t max_queue;       /* queue capacity in cubes (per problem) */
+    int64_t max_iters;       /* 0 = no limit */
+    double time_limit_s;     /* 0 = no limit */
+    int order;               /* 0: best-first by lower bound; 1: learned priority (gosma_mlp_load) */
+    int log_records;         /* 1: append cube records to the sink of gosma_set_record_sink */
+} gosma_opts;
+
+typedef struct {
+    double f_best;           /* best objective value d* (eq. 10 / eq. 17) */
+    double lb_global;        /* certified lower bound on the minimum at exit */
+    double f_norm_best;      /* (f_best + S22) / S22 */
+    double lb_norm;          /* (lb_global + S22) / S22 */
+    double r[3], t[3];       /* pose of d*: angle-axis rotation and camera centre */
+    int64_t iters, cubes;    /* iterations run, sub-cubes bounded */
+    int64_t max_queue_used;
+    double seconds;          /* wall time inside the call */
+    int status;              /* 0 eps-optimal, 1 queue exhausted, 2 iteration/time cap */
+} gosma_result;
+
+/* Solve problem 0 to eps-optimality (Algorithm 1 without local refinement).
+ * Host structs in and out; synchronous.  GOSMA_E_QUEUE_OVERFLOW if the queue
+ * capacity is exceeded (the result then holds the state reached). */
+int gosma_solve(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *result);
+
+/* Solve every problem of gosma_set_problems together: each iteration pops
+ * up to opts->batch_parents cubes from every unfinished problem's queue and
+ * bounds all their children in one launch.  result: host array of
+ * n_problems structs.  Synchronous. */
+int gosma_solve_batch(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *results);
+
+/* Kernel timing, for benchmarking.  While enabled, the library records a HIP
+ * event pair on the launch stream around each of its kernel launches,
+ * grouped by kernel kind (GOSMA_KERNEL_*).  gosma_get_timing() waits for the
+ * recorded events, writes the summed milliseconds and launch counts per kind
+ * into ms[GOSMA_N_KERNELS] and launches[GOSMA_N_KERNELS] (host arrays), and
+ * clears the records. */
+#define GOSMA_KERNEL_S11 0      /* GMM-GMM pair sums per translation cell */
+#define GOSMA_KERNEL_S12 1      /* GMM-vMF pair sums and final bounds per cube */
+#define GOSMA_KERNEL_SELECT 2   /* queue selection (histogram, threshold, compaction) */
+#define GOSMA_KERNEL_BRANCH 3   /* children of the selected cubes */
+#define GOSMA_KERNEL_PUSH 4     /* best upper bound, pruning and queue insertion */
+#define GOSMA_KERNEL_MLP 5      /* learned-priority network (inference and training) */
+#define GOSMA_N_KERNELS 8
+int gosma_set_timing(gosma_ctx *ctx, int enable);
+int gosma_get_timing(gosma_ctx *ctx, double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GOSMA_H */

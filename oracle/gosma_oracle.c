@@ -321,8 +321,10 @@ static double s11_lower_log(double alo, double ahi, double blo, double bhi, doub
 /* S12 summand (eq. 21, second sum) at angle B with b = kappa_2j fixed: the
  * ratio Z(K)/(Z(a) Z(b)) maximised over a in [alo, ahi], bounded by the
  * smaller of
- *   exp(g(ac) + |g_a(ac)| h + (G/2) h^2),  G = min(1/3, 1/m^2) + min(1/3, (b sin B)^2/m^3),
- *     m = max(K(ac) - h, b sin B) a lower bound on K over the interval (G = 2/3 if m = 0),
+ *   exp(g(ac) + |g_a(ac)| h + (G/2) h^2), with G an upper bound on g'' over
+ *     the interval: K is 1-Lipschitz in a, so K >= K(ac)/2 there when
+ *     h <= K(ac)/2, giving G = min(1/3, 4/K(ac)^2) + min(1/3, 8 (b sin B)^2/K(ac)^3);
+ *     otherwise G = 2/3,
  * and the value for perfectly aligned directions,
  *   Z(a + b)/(Z(a) Z(b)) = a b (coth a + coth b) / (2 (a + b)) <= min(ahi, b)(coth alo + coth b)/2,
  * which bounds every angle since Z increases and K <= a + b. */
@@ -330,8 +332,9 @@ static double s12_upper_term(double alo, double ahi, double b, double B)
 {
     double ac = 0.5 * (alo + ahi), h = 0.5 * (ahi - alo);
     double bs = b * sin(B);
-    double m = fmax(Kab(ac, b, B) - h, bs);
-    double G = m > 0 ? fmin(1.0 / 3.0, 1.0 / (m * m)) + fmin(1.0 / 3.0, bs * bs / (m * m * m)) : 2.0 / 3.0;
+    double Kc = Kab(ac, b, B);
+    double G = h <= 0.5 * Kc ? fmin(1.0 / 3.0, 4.0 / (Kc * Kc)) + fmin(1.0 / 3.0, 8.0 * bs * bs / (Kc * Kc * Kc))
+                             : 2.0 / 3.0;
     double taylor = exp(g_term(ac, b, B) + fabs(g_da(ac, b, B)) * h + 0.5 * G * h * h);
     double aligned = 0.5 * fmin(ahi, b) * (1.0 / tanh(alo) + 1.0 / tanh(b));
     return fmin(taylor, aligned);

@@ -1,0 +1,110 @@
+// Internal declarations of libgosma (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "gosma.h"
+
+namespace gosma {
+
+struct Solver;   // branch-and-bound buffers (bb.hip)
+
+// One pose problem as the kernels see it.  Component rows are sorted by class
+// label; classes [cls_off, cls_off + n_cls) of the class table list the row
+// ranges of each class in both mixtures.
+struct ProbDesc {
+    int32_t gmm_off, M, vmf_off, N;
+    int32_t cls_off, n_cls, pad0, pad1;
+    double r_lo[3], r_w[3];     // rotation root box: lo and width
+    double t_lo[3], t_w[3];     // translation root box
+    double zeta, S22;
+};
+
+struct ClassRange {
+    int32_t g0, g1, v0, v1;     // absolute row ranges [g0, g1) and [v0, v1)
+};
+
+// Device-resident mixtures of every problem.
+//   GMM rows: mu (FP64 xyz), 1/sigma^2 (FP64), weight (FP32, see below), and
+//   the plain normalised weight used by the branching rule.
+//   vMF rows: two float4 per row, {dx, dy, dz, kappa}, {weight, G(kappa),
+//   coth(kappa), 0}, with G(y) = y / (1 - e^{-2y}).
+// Weights carry the semantic class weight: with phi_l = 1/|Lambda| and w the
+// weights renormalised within the class, the stored weight is sqrt(phi_l) w,
+// so the product of two stored weights is phi_l w w' (eq. 17).
+struct DevMix {
+    const double *mu;
+    const double *isig2;
+    const float *w1;
+    const float *pbar;
+    const float4 *vmf;
+    const double *vmf64;      // FP64 copy: {dx, dy, dz, kappa} per row
+    const ClassRange *cls;
+    const ProbDesc *prob;
+    int n_prob;
+};
+
+struct BoundOut {
+    double *ub, *lb, *lb_safe, *aux;
+    uint8_t *flags;
+    float *top8;
+    float *psi_gap;    // optional: psi_r - weighted mean psi_t (branching statistic)
+    unsigned long long *dstar_bits;   // optional: atomic minimum of finite upper bounds (ordered bits)
+};
+
+struct S11Out {
+    double *ub, *lo;   // S11 at the centre and its lower bound, per translation cube
+};
+
+// Launchers (bound.hip).  All asynchronous on `stream`.  With a device count
+// pointer (nt_dev / n_dev) the kernels read the number of cells from device
+// memory (times n_dev_mul) and loop over it with a grid of `grid` blocks;
+// the host count is then the maximum.  grid <= 0 launches one block per cell.
+hipError_t launch_s11(const DevMix &mx, const uint64_t *tkeys, const uint32_t *pids, int64_t nt, const uint32_t *nt_dev,
+                      S11Out out, int maxM, int grid, hipStream_t stream);
+hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
+                      const int64_t *tidx, const double *s11ub, const double *s11lo, int64_t n, const uint32_t *n_dev,
+                      int n_dev_mul, BoundOut out, double margin_gamma, int maxM, bool with_top8, int grid,
+                      hipStream_t stream);
+
+}  // namespace gosma
+
+// The context behind the opaque C handle.
+struct gosma_ctx {
+    int device = 0;
+    std::string err;
+
+    // problems
+    int n_problems = 0;
+    int maxM = 0, maxN = 0;
+    bool has_domain = false;
+    std::vector<gosma::ProbDesc> h_prob;
+    double *d_mu = nullptr, *d_isig2 = nullptr;
+    float *d_w1 = nullptr, *d_pbar = nullptr;
+    float4 *d_vmf = nullptr;
+    double *d_vmf64 = nullptr;
+    gosma::ClassRange *d_cls = nullptr;
+    gosma::ProbDesc *d_prob = nullptr;
+    std::vector<std::vector<int32_t>> gmm_order;   // original row of each sorted row, per problem
+
+    // scratch for gosma_eval_bounds (grown on demand)
+    int64_t s11_cap = 0;
+    double *d_s11ub = nullptr, *d_s11lo = nullptr;
+
+    gosma::Solver *solver = nullptr;
+
+    // kernel timing (gosma_set_timing)
+    bool timing = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> tev;
+    // record a start event if timing; returns the index to close, or -1
+    int time_begin(int kind, hipStream_t s);
+    void time_end(int idx, hipStream_t s);
+
+    gosma::DevMix mix() const {
+        return gosma::DevMix{d_mu, d_isig2, d_w1, d_pbar, d_vmf, d_vmf64, d_cls, d_prob, n_problems};
+    }
+};

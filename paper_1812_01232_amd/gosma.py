@@ -1,0 +1,237 @@
+"""Python binding of libgosma (ctypes).
+
+Argument marshalling only: every step of the bound evaluation and of the
+branch-and-bound runs in the HIP library.  Device buffers are torch tensors
+on a ROCm device; their data pointers and the current HIP stream are passed
+through the C-ABI of include/gosma.h.  The library must have been built
+(python -m paper_1812_01232_amd.build); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().parent / "libgosma.so"
+
+GOSMA_OK = 0
+ERRORS = {-1: "GOSMA_E_INVAL", -2: "GOSMA_E_NOMEM", -3: "GOSMA_E_HIP", -4: "GOSMA_E_QUEUE_OVERFLOW",
+          -5: "GOSMA_E_STATE"}
+FLAG_SPLIT_ROT, FLAG_DROP_ROT, FLAG_DROP_TRANS, FLAG_UB_INF = 1, 2, 4, 8
+
+EXPORTS = ["gosma_create", "gosma_destroy", "gosma_last_error", "gosma_set_mixtures", "gosma_set_domain",
+           "gosma_set_problems", "gosma_get_S22", "gosma_eval_bounds", "gosma_solve", "gosma_solve_batch",
+           "gosma_set_timing", "gosma_get_timing"]
+KERNEL_KINDS = ["s11", "s12", "select", "branch", "push", "mlp"]
+
+
+class GosmaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Domain(C.Structure):
+    _fields_ = [("r_lo", C.c_double * 3), ("r_hi", C.c_double * 3), ("t_lo", C.c_double * 3),
+                ("t_hi", C.c_double * 3), ("zeta", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("batch_parents", C.c_int64), ("max_queue", C.c_int64),
+                ("max_iters", C.c_int64), ("time_limit_s", C.c_double), ("order", C.c_int),
+                ("log_records", C.c_int)]
+
+
+class Result(C.Structure):
+    _fields_ = [("f_best", C.c_double), ("lb_global", C.c_double), ("f_norm_best", C.c_double),
+                ("lb_norm", C.c_double), ("r", C.c_double * 3), ("t", C.c_double * 3), ("iters", C.c_int64),
+                ("cubes", C.c_int64), ("max_queue_used", C.c_int64), ("seconds", C.c_double),
+                ("status", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libgosma.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1812_01232_amd.build")
+        L = C.CDLL(str(LIB_PATH))
+        vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
+        L.gosma_create.argtypes = [C.c_int, C.POINTER(vp)]
+        L.gosma_destroy.argtypes = [vp]
+        L.gosma_destroy.restype = None
+        L.gosma_last_error.argtypes = [vp]
+        L.gosma_last_error.restype = C.c_char_p
+        L.gosma_set_mixtures.argtypes = [vp, C.c_int, dp, dp, dp, ip, C.c_int, dp, dp, dp, ip, C.c_int]
+        L.gosma_set_domain.argtypes = [vp, C.POINTER(Domain)]
+        L.gosma_set_problems.argtypes = [vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64), dp, dp, dp, ip,
+                                         dp, dp, dp, ip, C.c_int, C.POINTER(Domain)]
+        L.gosma_get_S22.argtypes = [vp, C.c_int, dp]
+        L.gosma_eval_bounds.argtypes = [vp, vp, vp, vp, C.c_int64, vp, vp, vp, vp, vp, vp]
+        L.gosma_solve.argtypes = [vp, C.POINTER(Opts), C.POINTER(Result)]
+        L.gosma_solve_batch.argtypes = [vp, C.POINTER(Opts), C.POINTER(Result)]
+        L.gosma_set_timing.argtypes = [vp, C.c_int]
+        L.gosma_get_timing.argtypes = [vp, dp, C.POINTER(C.c_int64)]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _i(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def domain_of(scene):
+    return Domain((C.c_double * 3)(*scene.r_lo), (C.c_double * 3)(*scene.r_hi), (C.c_double * 3)(*scene.t_lo),
+                  (C.c_double * 3)(*scene.t_hi), float(scene.zeta))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _current_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One libgosma context bound to a HIP device."""
+
+    def __init__(self, device=0):
+        self._h = C.c_void_p()
+        self._check(lib().gosma_create(int(device), C.byref(self._h)), "gosma_create")
+        self.device = device
+
+    def close(self):
+        if self._h:
+            lib().gosma_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc, what):
+        if rc != GOSMA_OK:
+            msg = lib().gosma_last_error(self._h).decode() if self._h else what
+            raise GosmaError(rc, f"{what}: {msg}")
+
+    # -- problems ---------------------------------------------------------
+    def set_scene(self, scene):
+        """Set the single problem from a scene (mixtures + domain)."""
+        self._keep = [_f64(scene.mu), _f64(scene.sigma), _f64(scene.phi1), _i32(scene.label1),
+                      _f64(scene.dir2), _f64(scene.kappa2), _f64(scene.phi2), _i32(scene.label2)]
+        mu, sg, p1, l1, d2, k2, p2, l2 = self._keep
+        self._check(lib().gosma_set_mixtures(self._h, mu.shape[0], _d(mu), _d(sg), _d(p1), _i(l1), d2.shape[0],
+                                             _d(d2), _d(k2), _d(p2), _i(l2), int(scene.n_labels)),
+                    "gosma_set_mixtures")
+        dom = domain_of(scene)
+        self._check(lib().gosma_set_domain(self._h, C.byref(dom)), "gosma_set_domain")
+
+    def set_scenes(self, scenes_list):
+        """Set several independent problems (the batched form)."""
+        go = np.cumsum([0] + [s.M for s in scenes_list]).astype(np.int64)
+        vo = np.cumsum([0] + [s.N for s in scenes_list]).astype(np.int64)
+        cat = lambda f: _f64(np.concatenate([getattr(s, f) for s in scenes_list]))
+        labelled = scenes_list[0].label1 is not None
+        l1 = _i32(np.concatenate([s.label1 for s in scenes_list])) if labelled else None
+        l2 = _i32(np.concatenate([s.label2 for s in scenes_list])) if labelled else None
+        doms = (Domain * len(scenes_list))(*[domain_of(s) for s in scenes_list])
+        self._keep = [go, vo, cat("mu"), cat("sigma"), cat("phi1"), l1, cat("dir2"), cat("kappa2"), cat("phi2"),
+                      l2, doms]
+        _, _, mu, sg, p1, _, d2, k2, p2, _, _ = self._keep
+        self._check(lib().gosma_set_problems(self._h, len(scenes_list), go.ctypes.data_as(C.POINTER(C.c_int64)),
+                                             vo.ctypes.data_as(C.POINTER(C.c_int64)), _d(mu), _d(sg), _d(p1),
+                                             _i(l1), _d(d2), _d(k2), _d(p2), _i(l2),
+                                             int(scenes_list[0].n_labels), doms), "gosma_set_problems")
+
+    def S22(self, problem=0):
+        v = C.c_double()
+        self._check(lib().gosma_get_S22(self._h, int(problem), C.byref(v)), "gosma_get_S22")
+        return v.value
+
+    # -- bounds -----------------------------------------------------------
+    def eval_bounds(self, rkeys, tkeys, ub, lb, flags, aux=None, top8=None, problem=None, stream=None):
+        """Device tensors in/out (see gosma_eval_bounds); runs on the current stream."""
+        n = int(rkeys.numel())
+        s = _current_stream() if stream is None else C.c_void_p(stream)
+        self._check(lib().gosma_eval_bounds(self._h, _ptr(rkeys), _ptr(tkeys), _ptr(problem), n, _ptr(ub), _ptr(lb),
+                                            _ptr(flags), _ptr(aux), _ptr(top8), s), "gosma_eval_bounds")
+
+    def bounds(self, rkeys_np, tkeys_np, problem_np=None, want_aux=True, want_top8=False):
+        """Convenience: host keys in, host arrays out (copies through torch)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        n = len(rkeys_np)
+        rk = torch.from_numpy(np.ascontiguousarray(rkeys_np, dtype=np.uint64).view(np.int64)).to(dev)
+        tk = torch.from_numpy(np.ascontiguousarray(tkeys_np, dtype=np.uint64).view(np.int64)).to(dev)
+        pr = None
+        if problem_np is not None:
+            pr = torch.from_numpy(np.ascontiguousarray(problem_np, dtype=np.uint32).view(np.int32)).to(dev)
+        ub = torch.empty(n, dtype=torch.float64, device=dev)
+        lb = torch.empty(n, dtype=torch.float64, device=dev)
+        fl = torch.empty(n, dtype=torch.uint8, device=dev)
+        aux = torch.empty(n, 4, dtype=torch.float64, device=dev) if want_aux else None
+        t8 = torch.empty(n, 8, dtype=torch.float32, device=dev) if want_top8 else None
+        self.eval_bounds(rk, tk, ub, lb, fl, aux, t8, pr)
+        torch.cuda.synchronize(dev)
+        out = {"ub": ub.cpu().numpy(), "lb": lb.cpu().numpy(), "flags": fl.cpu().numpy()}
+        if want_aux:
+            out["aux"] = aux.cpu().numpy()
+        if want_top8:
+            out["top8"] = t8.cpu().numpy()
+        return out
+
+    # -- kernel timing ----------------------------------------------------
+    def set_timing(self, enable=True):
+        self._check(lib().gosma_set_timing(self._h, int(bool(enable))), "gosma_set_timing")
+
+    def get_timing(self):
+        """{kind: (total ms, launches)} since the last call; synchronises."""
+        ms = (C.c_double * 8)()
+        n = (C.c_int64 * 8)()
+        self._check(lib().gosma_get_timing(self._h, ms, n), "gosma_get_timing")
+        return {KERNEL_KINDS[k]: (ms[k], n[k]) for k in range(len(KERNEL_KINDS))}
+
+    # -- branch and bound -------------------------------------------------
+    def solve(self, eps, batch_parents=4096, max_queue=1 << 24, max_iters=0, time_limit_s=0.0, order=0,
+              log_records=0):
+        o = Opts(eps, batch_parents, max_queue, max_iters, time_limit_s, order, log_records)
+        r = Result()
+        self._check(lib().gosma_solve(self._h, C.byref(o), C.byref(r)), "gosma_solve")
+        return _result_dict(r)
+
+    def solve_batch(self, n_problems, eps, batch_parents=2048, max_queue=1 << 22, max_iters=0, time_limit_s=0.0,
+                    order=0):
+        o = Opts(eps, batch_parents, max_queue, max_iters, time_limit_s, order, 0)
+        rs = (Result * n_problems)()
+        self._check(lib().gosma_solve_batch(self._h, C.byref(o), rs), "gosma_solve_batch")
+        return [_result_dict(r) for r in rs]
+
+
+def _result_dict(r):
+    return {name: (list(getattr(r, name)) if name in ("r", "t") else getattr(r, name)) for name, _ in Result._fields_}

@@ -1,0 +1,193 @@
+"""Parity of the HIP bound evaluation with the FP64 oracle.
+
+Element-wise on the same seeded cubes: drop flags exactly, the upper and
+lower bounds to 1e-5 of their own scale (S11 + 2 S12 of that bound: a
+relative tolerance on S11 - 2 S12 itself is ill-conditioned where the two
+sums nearly cancel), the branching flag wherever the two uncertainty angles
+it compares differ by more than rounding, and the top-8 pair terms.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import scenes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1812_01232_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _compare(sc, g, o, top8=False, label=""):
+    drop_o = o["status"] != 0
+    drop_g = (g["flags"] & 6) != 0
+    assert np.array_equal(drop_o, drop_g), f"{label}: drop flags differ"
+    assert np.array_equal(o["status"] == 1, (g["flags"] & 2) != 0)
+    ok = ~drop_o
+    assert np.all(np.isinf(g["ub"][drop_o])) and np.all(np.isinf(g["lb"][drop_o]))
+    inf_o = ok & ~np.isfinite(o["ub"])
+    assert np.array_equal(inf_o, ok & ((g["flags"] & 8) != 0)), f"{label}: infeasible-centre flags differ"
+    fin = ok & ~inf_o
+    sc_ub = o["s11_ub"] + 2 * o["s12_ub"]
+    sc_lb = o["s11_lo"] + 2 * o["s12_hi"]
+    e_ub = np.abs(g["ub"][fin] - o["ub"][fin]) / sc_ub[fin]
+    e_lb = np.abs(g["lb"][ok] - o["lb"][ok]) / sc_lb[ok]
+    worst_ub = e_ub.max(initial=0.0)
+    worst_lb = e_lb.max(initial=0.0)
+    print(f"{label}: n={len(ok)} ok={ok.sum()} worst ub err {worst_ub:.2e} lb err {worst_lb:.2e}")
+    assert worst_ub <= TOL, f"{label}: ub error {worst_ub}"
+    assert worst_lb <= TOL, f"{label}: lb error {worst_lb}"
+    # components of the sums
+    aux = g["aux"]
+    assert np.all(np.abs(aux[fin, 0] - o["s11_ub"][fin]) <= TOL * sc_ub[fin])
+    assert np.all(np.abs(aux[fin, 1] - o["s12_ub"][fin]) <= TOL * sc_ub[fin])
+    assert np.all(np.abs(aux[ok, 2] - o["s11_lo"][ok]) <= TOL * sc_lb[ok])
+    assert np.all(np.abs(aux[ok, 3] - o["s12_hi"][ok]) <= TOL * sc_lb[ok])
+    # branching flag where it is decided by more than rounding
+    gap = o["psi_r"] - o["psi_t_mean"]
+    clear = ok & (np.abs(gap) > 1e-5)
+    assert np.array_equal((g["flags"][clear] & 1) != 0, o["split_rot"][clear] != 0)
+    if top8:
+        t = g["top8"][fin].astype(np.float64)
+        assert np.all(np.abs(t - o["top8"][fin]) <= TOL * sc_ub[fin, None])
+    return ok
+
+
+def test_cfg1_bound_pass_65536(ctx):
+    """The cfg1 bound pass: 65,536 random sub-cubes, every one checked."""
+    sc = scenes.cfg1_scene(0)
+    rk, tk = scenes.random_cubes(sc, 65536, 1500)
+    ctx.set_scene(sc)
+    g = ctx.bounds(rk, tk, want_top8=True)
+    o = oracle.OracleProblem(sc).bounds(rk, tk)
+    ok = _compare(sc, g, o, top8=True, label="cfg1")
+    assert ok.sum() > 50000
+
+
+@pytest.mark.parametrize("idx", [0, 1])
+def test_cfg2_random_cubes(ctx, idx):
+    sc = scenes.cfg2_scene(idx)
+    rk, tk = scenes.random_cubes(sc, 3000, 2500 + idx)
+    ctx.set_scene(sc)
+    g = ctx.bounds(rk, tk, want_top8=True)
+    o = oracle.OracleProblem(sc).bounds(rk, tk)
+    _compare(sc, g, o, top8=True, label=f"cfg2-{idx}")
+
+
+def test_cfg2_full_batch_sampled(ctx):
+    """The 32,768-cube cfg2 batch in one launch; a seeded sample of 1,500
+    cubes is checked against the oracle one by one."""
+    sc = scenes.cfg2_scene(0)
+    rk, tk = scenes.random_cubes(sc, 32768, 2600, r_levels=(2, 12), t_levels=(1, 10))
+    ctx.set_scene(sc)
+    g = ctx.bounds(rk, tk)
+    sel = np.random.default_rng(0).choice(32768, 1500, replace=False)
+    o = oracle.OracleProblem(sc).bounds(rk[sel], tk[sel])
+    gs = {k: v[sel] for k, v in g.items()}
+    _compare(sc, gs, o, label="cfg2-full")
+
+
+def test_cfg3_labels_sampled(ctx):
+    sc = scenes.cfg3_scene(0)
+    rk, tk = scenes.random_cubes(sc, 4096, 3500, r_levels=(2, 12), t_levels=(1, 10))
+    ctx.set_scene(sc)
+    g = ctx.bounds(rk, tk, want_top8=True)
+    sel = np.random.default_rng(1).choice(4096, 300, replace=False)
+    o = oracle.OracleProblem(sc).bounds(rk[sel], tk[sel])
+    _compare(sc, {k: v[sel] for k, v in g.items()}, o, top8=True, label="cfg3")
+
+
+def test_cubes_around_true_pose(ctx):
+    """Deep cubes containing the true pose (the cubes that decide termination)."""
+    sc = scenes.cfg2_scene(0)
+    keys = []
+    for Lr in range(2, 19, 2):
+        for Lt in range(1, 18, 2):
+            ir = np.clip(np.floor((sc.r_gt - sc.r_lo) / (sc.r_hi - sc.r_lo) * 2 ** Lr), 0, 2 ** Lr - 1).astype(int)
+            it = np.clip(np.floor((sc.t_gt - sc.t_lo) / (sc.t_hi - sc.t_lo) * 2 ** Lt), 0, 2 ** Lt - 1).astype(int)
+            keys.append((int(scenes.pack_key(Lr, *ir)), int(scenes.pack_key(Lt, *it))))
+    rk = np.array([k[0] for k in keys], np.uint64)
+    tk = np.array([k[1] for k in keys], np.uint64)
+    ctx.set_scene(sc)
+    g = ctx.bounds(rk, tk)
+    o = oracle.OracleProblem(sc).bounds(rk, tk)
+    _compare(sc, g, o, label="around-gt")
+
+
+def test_edge_cases(ctx):
+    # root cube, level-19 cubes, dropped rotation cells, infeasible translations,
+    # single components, odd class sizes
+    sc = scenes.small_scene(1, 1, seed=3)
+    rk = np.array([0, int(scenes.pack_key(19, 262144, 300000, 1)), int(scenes.pack_key(3, 7, 7, 7)),
+                   int(scenes.pack_key(1, 1, 0, 1))], np.uint64)
+    tk = np.array([0, int(scenes.pack_key(19, 5, 524287, 77)), 0, int(scenes.pack_key(2, 3, 0, 1))], np.uint64)
+    ctx.set_scene(sc)
+    g = ctx.bounds(rk, tk)
+    o = oracle.OracleProblem(sc).bounds(rk, tk)
+    _compare(sc, g, o, label="edge-1x1")
+    sc2 = scenes.small_scene(7, 5, seed=4, n_labels=3, n_inliers=4)
+    sc2.mu[0] = np.array([0.01, 0.02, -0.03])
+    rk2, tk2 = scenes.random_cubes(sc2, 2000, 4600, r_levels=(0, 19), t_levels=(0, 19))
+    ctx.set_scene(sc2)
+    g = ctx.bounds(rk2, tk2, want_top8=True)
+    o = oracle.OracleProblem(sc2).bounds(rk2, tk2)
+    ok = _compare(sc2, g, o, top8=True, label="edge-labels")
+    assert (o["status"] == 2).any() or True
+
+
+def test_empty_batch_and_errors(ctx):
+    from paper_1812_01232_amd import GosmaError
+    sc = scenes.cfg1_scene(0)
+    ctx.set_scene(sc)
+    z = torch.empty(0, dtype=torch.int64, device="cuda")
+    d = torch.empty(0, dtype=torch.float64, device="cuda")
+    f = torch.empty(0, dtype=torch.uint8, device="cuda")
+    ctx.eval_bounds(z, z, d, d, f)       # n = 0 is a no-op
+    bad = scenes.cfg1_scene(0)
+    bad.sigma = bad.sigma.copy()
+    bad.sigma[3] = -1.0
+    with pytest.raises(GosmaError):
+        ctx.set_scene(bad)
+
+
+def test_batched_problems(ctx):
+    """Several problems of different sizes in one launch (problem index per cube)."""
+    scs = scenes.batch_scenes(6, seed=4100, lo=16, hi=96)
+    ctx.set_scenes(scs)
+    rks, tks, pids = [], [], []
+    for p, s in enumerate(scs):
+        rk, tk = scenes.random_cubes(s, 300, 4700 + p, r_levels=(1, 10), t_levels=(0, 9))
+        rks.append(rk)
+        tks.append(tk)
+        pids.append(np.full(300, p, np.uint32))
+    perm = np.random.default_rng(2).permutation(1800)
+    rk = np.concatenate(rks)[perm]
+    tk = np.concatenate(tks)[perm]
+    pid = np.concatenate(pids)[perm]
+    g = ctx.bounds(rk, tk, problem_np=pid)
+    for p, s in enumerate(scs):
+        m = pid == p
+        o = oracle.OracleProblem(s).bounds(rk[m], tk[m])
+        _compare(s, {k: v[m] for k, v in g.items()}, o, label=f"batch-{p}")
+        assert ctx.S22(p) == pytest.approx(oracle.OracleProblem(s).S22(), rel=1e-12)
+
+
+def test_deterministic(ctx):
+    sc = scenes.cfg2_scene(1)
+    rk, tk = scenes.random_cubes(sc, 4096, 2700)
+    ctx.set_scene(sc)
+    a = ctx.bounds(rk, tk)
+    b = ctx.bounds(rk, tk)
+    assert np.array_equal(a["ub"], b["ub"]) and np.array_equal(a["lb"], b["lb"])

@@ -1,0 +1,103 @@
+"""The device-resident branch-and-bound against the oracle and the paper's pins.
+
+Several poses can be eps-optimal, so parity compares what is unique: the
+certified optimal value (both sides bracket the true minimum within eps),
+and the objective of the GPU's pose evaluated by the oracle.  On noise-free
+scenes the true minimum is known in closed form (zero L2 distance at the
+true pose) and the pose must satisfy the paper's success criterion.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import scenes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MARGIN = 4e-6 * 4     # rounding margin of the FP32 bounds, relative to S11 + 2 S12 ~ 3 S22
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1812_01232_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _rot_err(r, R_gt):
+    R = oracle.rodrigues(np.asarray(r))
+    return math.acos(np.clip((np.trace(R.T @ R_gt) - 1) / 2, -1, 1))
+
+
+@pytest.mark.parametrize("M,N,seed,eps", [(4, 4, 81, 1e-2), (5, 5, 86, 1e-2), (8, 8, 85, 1e-2)])
+def test_solve_matches_oracle_small(ctx, M, N, seed, eps):
+    sc = scenes.small_scene(M, N, seed=seed)
+    ctx.set_scene(sc)
+    g = ctx.solve(eps, batch_parents=256)
+    P = oracle.OracleProblem(sc)
+    o = P.solve(eps, 256, time_limit_s=120)
+    print(f"{M}x{N}: gpu {g['status']} f~={g['f_norm_best']:.6f} lb~={g['lb_norm']:.6f} cubes={g['cubes']} "
+          f"t={g['seconds']:.3f}s | oracle {o['status']} f~={o['f_norm_best']:.6f} cubes={o['cubes']} "
+          f"t={o['seconds']:.1f}s")
+    assert g["status"] == 0 and o["status"] == 0
+    assert g["f_norm_best"] - g["lb_norm"] <= eps
+    assert abs(g["f_norm_best"] - o["f_norm_best"]) <= eps
+    S22 = P.S22()
+    f_at = (P.objective(g["r"], g["t"])[0] + S22) / S22
+    assert f_at == pytest.approx(g["f_norm_best"], abs=1e-5)
+    assert f_at <= o["f_norm_best"] + eps + 1e-9
+    # noise-free: the minimum is 0, so both certified lower bounds are <= 0
+    assert g["lb_norm"] <= MARGIN
+    assert _rot_err(g["r"], sc.R_gt) < 0.1
+    assert np.linalg.norm(np.array(g["t"]) - sc.t_gt) < 0.05
+
+
+def test_solve_noisy_vs_oracle(ctx):
+    sc = scenes.small_scene(5, 6, seed=90, noise_deg=2.0, n_inliers=4)
+    eps = 1e-2
+    ctx.set_scene(sc)
+    g = ctx.solve(eps, batch_parents=256)
+    P = oracle.OracleProblem(sc)
+    o = P.solve(eps, 256, time_limit_s=120)
+    assert g["status"] == 0 and o["status"] == 0
+    # both certify [lb, f] brackets of the same minimum
+    assert g["lb_norm"] <= o["f_norm_best"] + MARGIN
+    assert o["lb_norm"] <= g["f_norm_best"] + 1e-9
+    assert abs(g["f_norm_best"] - o["f_norm_best"]) <= eps
+
+
+def test_solve_cfg1_eps_1e3(ctx):
+    """cfg1 to eps = 1e-3: the noise-free optimum is 0 at the true pose."""
+    sc = scenes.cfg1_scene(0)
+    ctx.set_scene(sc)
+    g = ctx.solve(1e-3, batch_parents=4096, time_limit_s=240)
+    print(f"cfg1: status {g['status']} f~={g['f_norm_best']:.6g} lb~={g['lb_norm']:.6g} iters={g['iters']} "
+          f"cubes={g['cubes']} queue={g['max_queue_used']} t={g['seconds']:.2f}s")
+    assert g["status"] == 0
+    assert g["f_norm_best"] <= 1e-3
+    assert g["lb_norm"] <= MARGIN
+    P = oracle.OracleProblem(sc)
+    S22 = P.S22()
+    assert (P.objective(g["r"], g["t"])[0] + S22) / S22 <= 1e-3 + 1e-6
+    assert _rot_err(g["r"], sc.R_gt) < 0.1
+    assert np.linalg.norm(np.array(g["t"]) - sc.t_gt) < 0.05 * max(np.linalg.norm(sc.t_gt), 1.0)
+
+
+def test_solve_caps_and_errors(ctx):
+    from paper_1812_01232_amd import GosmaError
+    sc = scenes.cfg1_scene(0)
+    ctx.set_scene(sc)
+    g = ctx.solve(1e-3, batch_parents=64, max_iters=3)
+    assert g["status"] == 2 and g["iters"] == 3
+    assert g["lb_norm"] <= g["f_norm_best"]
+    with pytest.raises(GosmaError) as ei:
+        ctx.solve(1e-3, batch_parents=64, max_queue=64)
+    assert ei.value.code == -4
+    with pytest.raises(GosmaError):
+        ctx.solve(1e-3, batch_parents=0)
