@@ -136,6 +136,9 @@ typedef struct {
     double time_limit_s;     /* 0 = no limit */
     int order;               /* 0: best-first by lower bound; 1: learned priority (gosma_mlp_load) */
     int log_records;         /* 1: append cube records to the sink of gosma_set_record_sink */
+    int trace_every;         /* > 0: record the search state every n-th iteration (gosma_get_trace) */
+    int no_graph;            /* 1: launch each iteration's kernels directly instead of replaying
+                                a captured HIP graph of one iteration */
 } gosma_opts;
 
 typedef struct {
@@ -154,6 +157,13 @@ typedef struct {
  * Host structs in and out; synchronous.  GOSMA_E_QUEUE_OVERFLOW if the queue
  * capacity is exceeded (the result then holds the state reached). */
 int gosma_solve(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *result);
+
+/* Search trace of the last gosma_solve with opts->trace_every > 0 (the
+ * bound-evolution record of Section 7.1): rows of 6 doubles {iteration,
+ * seconds since entry, cubes bounded, queue size, d*, lowest lower bound in
+ * the queue}.  buf: host array of cap rows; *n receives the number of rows
+ * available (at most cap are written). */
+int gosma_get_trace(gosma_ctx *ctx, double *buf, int64_t cap, int64_t *n);
 
 /* Solve every problem of gosma_set_problems together: each iteration pops
  * up to opts->batch_parents cubes from every unfinished problem's queue and

@@ -116,6 +116,7 @@ int gosma_create(int device, gosma_ctx **out)
 }
 
 void gosma_release_solver(gosma_ctx *ctx);   // bb.hip
+void gosma_drop_graph(gosma_ctx *ctx);       // bb.hip
 
 void gosma_destroy(gosma_ctx *ctx)
 {
@@ -179,6 +180,7 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
     }
 
     HIP_TRY(ctx, hipSetDevice(ctx->device));
+    gosma_drop_graph(ctx);   // a captured iteration holds the old mixture pointers
     free_problems(ctx);
     std::vector<double> h_mu(3 * TM), h_isig2(TM);
     std::vector<float> h_w1(TM), h_pbar(TM);
@@ -375,7 +377,7 @@ int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tke
     HIP_TRY(ctx, gosma::launch_s11(mx, tkeys, problem, n, nullptr, gosma::S11Out{ctx->d_s11ub, ctx->d_s11lo},
                                    ctx->maxM, 0, s));
     ctx->time_end(ti, s);
-    gosma::BoundOut out{ub, lb, nullptr, aux, flags, top8, nullptr, nullptr};
+    gosma::BoundOut out{ub, lb, nullptr, aux, flags, top8, nullptr, nullptr, 0};
     ti = ctx->time_begin(GOSMA_KERNEL_S12, s);
     HIP_TRY(ctx, gosma::launch_s12(mx, rkeys, tkeys, problem, nullptr, ctx->d_s11ub, ctx->d_s11lo, n, nullptr, 1, out,
                                    0.0, ctx->maxM, top8 != nullptr, 0, s));

@@ -1,23 +1,30 @@
-// Branch-and-bound driver (Algorithm 1, Section 6) with a device-resident queue.
+// Branch-and-bound driver (Algorithm 1, Section 6) for one or many pose
+// problems, with device-resident queues and device-side control, so that a
+// whole iteration is a fixed sequence of kernel launches (captured once in a
+// HIP graph and replayed).
 //
-// One iteration, all on the device (the host reads a 100-byte status block):
-//   begin     reset the per-iteration counters
-//   select    3 radix passes (11 + 11 + 10 bits) over the 32-bit ordered key of
-//             each queued cube's priority find the key of the k-th lowest;
-//             compaction then moves the k lowest into the parent list, keeps
-//             the rest in the other queue buffer and drops cubes whose lower
-//             bound is no longer below d*
-//   branch    8 children per parent, split in rotation or translation by the
-//             flag the bound kernel computed for the parent; a rotation split
-//             shares one translation cell among its 8 children
-//   bound     S11 per translation cell, S12 and both bounds per child (bound.hip);
-//             the upper bounds update d* with an atomic minimum
-//   push      children whose lower bound (raised to the parent's, minus the
-//             rounding margin) is below d* join the queue; the child holding d*
-//             records the incumbent pose
-// The stop test d* - min LB <= eps uses the minimum lower bound over the queue
-// after the push, i.e. the "lowest lower bound in Q" at the start of the next
-// iteration.
+// Queue of each problem: a small "hot" part holding every queued cube whose
+// priority key is below a threshold theta, and a large append-only "cold"
+// part holding the rest.  Each iteration only the hot part is scanned:
+//   select   3 radix passes (11 + 11 + 10 bits) over the ordered 32-bit key of
+//            the priority find the k-th lowest key; compaction moves the k
+//            lowest into the parent list and keeps the rest (cubes whose lower
+//            bound is no longer below d* are dropped)
+//   branch   8 children per parent, split in rotation or translation by the
+//            flag the bound kernel computed for the parent (Section 5.1); a
+//            rotation split shares one translation cell among its 8 children
+//   bound    S11 per translation cell, S12 and both bounds per child; the
+//            upper bounds update d* with an atomic minimum (bound.hip)
+//   push     children whose lower bound (raised to the parent's, minus the
+//            rounding margin) is below d* are queued: hot if their key is
+//            below theta, cold otherwise; the child holding d* records the pose
+//   control  stop test d* - (lowest lower bound in the queue) <= eps, caps,
+//            and the decision to re-partition: when the hot part runs low or
+//            fills up, the next iteration first redistributes hot and cold
+//            around a new theta (one pass over the whole queue).
+// With the best-first order (priority = lower bound) every hot cube has a
+// lower key than every cold cube, so the k cubes taken are the k lowest of
+// the whole queue, as in Algorithm 1.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,25 +40,41 @@ namespace {
 
 constexpr int kHistBins = 2048;
 constexpr int kBlock = 256;
-constexpr int kGridCap = 2048;           // blocks for grid-stride kernels
-constexpr int kBoundGrid = 8192;         // blocks (one wavefront each) for the bound kernels
+constexpr int kGridX = 2048;            // blocks per grid-stride kernel (divided among problems)
+constexpr int kBoundGrid = 8192;        // blocks (one wavefront each) for the bound kernels
 constexpr int kMaxLevel = 19;
-// Rounding margin of the FP32 bounds relative to the magnitude S11 + 2 S12 of
-// each bound: about 8x the largest relative error measured against the FP64
-// oracle.
+// Rounding margin of the FP32 bounds, relative to the magnitude S11 + 2 S12 of
+// each bound: over 6x the largest relative error measured against the FP64
+// oracle on every parity set.
 constexpr double kMarginGamma = 4e-6;
 
-struct BBState {
-    unsigned long long dstar;     // ordered bits of d*, the best upper bound
-    unsigned long long lbmin;     // ordered bits of the lowest lower bound in the queue
-    unsigned long long floor_lb;  // ordered bits: lowest bound of cubes that cannot be split
+enum Done : uint32_t { RUNNING = 0, EPS_OPTIMAL = 1, EXHAUSTED = 2, CAPPED = 3, OVERFLOW = 4 };
+
+struct PState {
+    unsigned long long dstar;      // ordered bits of d*, the best upper bound
+    unsigned long long minH;       // ordered bits: lowest lower bound in the hot part
+    unsigned long long minC;       // ordered bits: lowest lower bound in the cold part
+    unsigned long long floor_lb;   // ordered bits: lowest bound of cubes that cannot be split
     unsigned long long best_rkey, best_tkey;
-    unsigned long long bounded;   // cubes bounded so far
-    uint32_t qcount[2];
-    uint32_t nsel, tcount, overflow, take_all;
-    uint32_t prefix, need, eq_quota, eq_taken;
-    uint32_t kept;                // queue entries kept by the compaction
-    uint32_t pad;
+    unsigned long long bounded;    // cubes bounded
+    double eps_f;                  // eps * S22
+    uint32_t nH[2], nC[2];
+    uint32_t hcur, ccur;
+    uint32_t theta;                // hot iff key32(priority) < theta (0xffffffff: all hot)
+    uint32_t nsel, rebuild, done, overflow, iters, max_iters;
+    uint32_t take_all, prefix, need, eq_quota, eq_taken;   // radix select
+    uint32_t rb_target;            // hot entries wanted after a re-partition
+};
+
+struct GState {
+    uint32_t nchild, ntcell, running, pad;
+};
+
+struct Queue {
+    uint64_t *rkey, *tkey;
+    double *lb;
+    float *prio;
+    uint8_t *flags;
 };
 
 __device__ __forceinline__ unsigned long long ord64(double x)
@@ -74,160 +97,63 @@ __device__ __forceinline__ uint32_t key32(float x)
 // A NaN bound is never pruned: it orders like -inf.
 __device__ __forceinline__ double sane_lb(double x) { return x != x ? -INFINITY : x; }
 
-// Wavefront-aggregated append: one atomic per wave.  Every lane of the wave
-// must call it (pred false for lanes with nothing to append).
-__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool pred)
+// Block-aggregated append: one atomic per block and call.  Every thread of
+// the block must call it.
+__device__ __forceinline__ uint32_t block_append(uint32_t *counter, bool pred)
 {
-    unsigned long long mask = __ballot(pred);
-    const int lane = threadIdx.x & 63;
-    uint32_t base = 0;
-    if (mask) {
-        int leader = __ffsll((long long)mask) - 1;
-        if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
-        base = __shfl(base, leader, 64);
-    }
-    return base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-}
-
-struct Queue {
-    uint64_t *rkey, *tkey;
-    double *lb;
-    float *prio;
-    uint8_t *flags;
-};
-
-__global__ void k_begin(BBState *st, int out, uint32_t *hist)
-{
-    int t = threadIdx.x;
-    if (t == 0) {
-        st->qcount[out] = 0;
-        st->nsel = 0;
-        st->tcount = 0;
-        st->take_all = 0;
-        st->prefix = 0;
-        st->need = 0;
-        st->eq_quota = 0;
-        st->eq_taken = 0;
-        st->kept = 0;
-        st->lbmin = ord64(INFINITY);
-    }
-    for (int b = t; b < kHistBins; b += blockDim.x) hist[b] = 0;
-}
-
-// Radix pass: histogram of the digit below the prefix fixed by earlier passes.
-__global__ __launch_bounds__(kBlock) void k_hist(Queue q, const BBState *st, int in, int pass, uint32_t *hist)
-{
-    __shared__ uint32_t h[kHistBins];
-    if (st->take_all) return;
-    for (int b = threadIdx.x; b < kHistBins; b += blockDim.x) h[b] = 0;
+    __shared__ uint32_t wcnt[kBlock / 64], wbase[kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long mask = __ballot(pred);
+    const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) wcnt[wave] = (uint32_t)__popcll(mask);
     __syncthreads();
-    const uint32_t n = st->qcount[in];
-    const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
-    const uint32_t mask = pass == 2 ? 0x3ffu : 0x7ffu;
-    const int pshift = pass == 0 ? 32 : (pass == 1 ? 21 : 10);
-    const uint32_t prefix = st->prefix;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        uint32_t k = key32(q.prio[i]);
-        if (pass == 0 || (k >> pshift) == prefix) atomicAdd(&h[(k >> shift) & mask], 1u);
+    if (threadIdx.x == 0) {
+        uint32_t total = 0;
+        for (int w = 0; w < kBlock / 64; ++w) total += wcnt[w];
+        uint32_t base = total ? atomicAdd(counter, total) : 0u;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            wbase[w] = base;
+            base += wcnt[w];
+        }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < kHistBins; b += blockDim.x)
-        if (h[b]) atomicAdd(&hist[b], h[b]);
+    const uint32_t r = wbase[wave] + rank;
+    __syncthreads();
+    return r;
 }
 
-// Radix pass: pick the digit holding the k-th lowest key.  One block.
-__global__ __launch_bounds__(kBlock) void k_scan(BBState *st, int in, int pass, uint32_t k, uint32_t *hist)
+// Block-aggregated reservation of cnt consecutive slots per thread.
+__device__ __forceinline__ uint32_t block_reserve(uint32_t *counter, uint32_t cnt)
 {
     __shared__ uint32_t part[kBlock];
-    __shared__ uint32_t found, left;
-    if (st->take_all) return;
-    const int t = threadIdx.x;
-    if (pass == 0 && st->qcount[in] <= k) {
-        if (t == 0) st->take_all = 1;
-        return;
-    }
-    const uint32_t need = pass == 0 ? k : st->need;
-    constexpr int per = kHistBins / kBlock;   // 8 bins per thread
-    uint32_t loc[per], sum = 0;
-    for (int j = 0; j < per; ++j) {
-        loc[j] = hist[t * per + j];
-        sum += loc[j];
-    }
-    part[t] = sum;
-    if (t == 0) {
-        found = 0;
-        left = need;
-    }
+    __shared__ uint32_t base;
+    part[threadIdx.x] = cnt;
     __syncthreads();
-    uint32_t cum = 0;
-    for (int u = 0; u < t; ++u) cum += part[u];
-    for (int j = 0; j < per; ++j) {
-        if (cum < need && need <= cum + loc[j]) {     // exactly one bin qualifies
-            found = (uint32_t)(t * per + j);
-            left = need - cum;
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int t = 0; t < kBlock; ++t) {
+            uint32_t c = part[t];
+            part[t] = s;
+            s += c;
         }
-        cum += loc[j];
+        base = s ? atomicAdd(counter, s) : 0u;
     }
     __syncthreads();
-    for (int j = 0; j < per; ++j) hist[t * per + j] = 0;
-    if (t == 0) {
-        const int bits = pass == 2 ? 10 : 11;
-        st->prefix = (st->prefix << bits) | found;
-        st->need = left;
-        if (pass == 2) st->eq_quota = left;
-    }
+    const uint32_t r = base + part[threadIdx.x];
+    __syncthreads();
+    return r;
 }
 
-// Compaction: k lowest -> parents; the rest (still below d*) -> the other buffer.
-__global__ __launch_bounds__(kBlock) void k_compact(Queue qin, Queue qout, BBState *st, int in, int out,
-                                                    Queue par, uint32_t capacity)
+__device__ __forceinline__ double block_min(double v)
 {
-    const uint32_t n = st->qcount[in];
-    const bool all = st->take_all != 0;
-    const uint32_t T = st->prefix;
-    const double dstar = unord64(st->dstar);
-    const uint32_t stride = gridDim.x * blockDim.x;
-    double local_min = INFINITY;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
-        const uint32_t i = base + threadIdx.x;
-        const bool valid = i < n;
-        bool sel = false, keep = false;
-        double lb = 0.0;
-        if (valid) {
-            lb = sane_lb(qin.lb[i]);
-            if (lb < dstar) {
-                uint32_t key = key32(qin.prio[i]);
-                if (all || key < T)
-                    sel = true;
-                else if (key == T)
-                    sel = atomicAdd(&st->eq_taken, 1u) < st->eq_quota;
-                keep = !sel;
-                if (keep) local_min = fmin(local_min, lb);
-            }
-        }
-        uint32_t ps = wave_append(&st->nsel, sel);
-        if (sel) {
-            par.rkey[ps] = qin.rkey[i];
-            par.tkey[ps] = qin.tkey[i];
-            par.lb[ps] = lb;
-            par.flags[ps] = qin.flags[i];
-        }
-        uint32_t qs = wave_append(&st->qcount[out], keep);
-        if (keep) {
-            if (qs < capacity) {
-                qout.rkey[qs] = qin.rkey[i];
-                qout.tkey[qs] = qin.tkey[i];
-                qout.lb[qs] = lb;
-                qout.prio[qs] = qin.prio[i];
-                qout.flags[qs] = qin.flags[i];
-            } else {
-                st->overflow = 1;
-            }
-        }
-    }
-    // lowest bound of the cubes that stay; k_push merges the children in
-    for (int off = 32; off > 0; off >>= 1) local_min = fmin(local_min, __shfl_xor(local_min, off, 64));
-    if ((threadIdx.x & 63) == 0 && local_min < INFINITY) atomicMin(&st->lbmin, ord64(local_min));
+    __shared__ double w[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double m = w[0];
+    for (int k = 1; k < kBlock / 64; ++k) m = fmin(m, w[k]);
+    __syncthreads();
+    return m;
 }
 
 __device__ __forceinline__ int key_level(uint64_t k) { return (int)((k >> 57) & 63); }
@@ -241,159 +167,491 @@ __device__ __forceinline__ uint64_t child_key(uint64_t k, int c)
     return (L << 57) | (ix << 38) | (iy << 19) | iz;
 }
 
-// Wavefront-aggregated reservation of cnt consecutive slots per lane.
-__device__ __forceinline__ uint32_t wave_reserve(uint32_t *counter, uint32_t cnt)
+// Buffers of all problems: queue part b of problem p occupies
+// [p * cap, (p + 1) * cap) of array b.
+struct Bufs {
+    Queue H[2], C[2];
+    uint32_t hcap, ccap;
+    Queue par;                    // parents, problem p at [p * k, (p + 1) * k)
+    uint32_t k;
+    // children (all problems, compacted)
+    uint64_t *crk, *ctk;
+    uint32_t *cpid, *cpar;        // problem and parent slot of each child
+    int64_t *ctidx;
+    uint8_t *cskip;
+    uint64_t *tcells;
+    uint32_t *tpid;
+    double *cub, *clb, *clbs;
+    uint8_t *cflags;
+    double *s11ub, *s11lo;
+    uint32_t *hist;               // kHistBins per problem
+    PState *st;
+    GState *g;
+};
+
+__device__ __forceinline__ Queue qoff(Queue q, size_t off)
 {
-    const int lane = threadIdx.x & 63;
-    uint32_t x = cnt;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    const uint32_t total = __shfl(x, 63, 64);
-    uint32_t base = 0;
-    if (lane == 0 && total) base = atomicAdd(counter, total);
-    base = __shfl(base, 0, 64);
-    return base + x - cnt;
+    return Queue{q.rkey + off, q.tkey + off, q.lb + off, q.prio + off, q.flags + off};
 }
 
-// 8 children per parent.  A rotation split shares its parent's translation
-// cell among the 8 children (one cell); a translation split has 8 cells.
-__global__ __launch_bounds__(kBlock) void k_branch(Queue par, BBState *st, uint64_t *crk, uint64_t *ctk,
-                                                   int64_t *ctidx, uint8_t *cskip, uint64_t *tcells)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_iter_begin(Bufs b, int P)
 {
-    const uint32_t n = st->nsel;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
-        const uint32_t p = base + threadIdx.x;
-        const bool valid = p < n;
+    const int p = blockIdx.x;
+    PState &s = b.st[p];
+    if (p == 0 && threadIdx.x == 0) {
+        b.g->nchild = 0;
+        b.g->ntcell = 0;
+        b.g->running = 0;
+    }
+    if (s.done) {              // finished problems keep their final state
+        if (threadIdx.x == 0) s.nsel = 0;
+        return;
+    }
+    uint32_t *h = b.hist + (size_t)p * kHistBins;
+    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) h[i] = 0;
+    if (threadIdx.x == 0) {
+        s.nsel = 0;
+        s.take_all = 0;
+        s.prefix = 0;
+        s.need = 0;
+        s.eq_quota = 0;
+        s.eq_taken = 0;
+        s.nH[s.hcur ^ 1] = 0;
+        s.minH = ord64(INFINITY);
+        if (s.rebuild) {
+            s.nC[s.ccur ^ 1] = 0;
+            s.minC = ord64(INFINITY);
+        }
+    }
+}
+
+// Radix pass over a problem's hot part (selection) or hot + cold parts
+// (re-partition): histogram of the digit below the prefix fixed so far.
+__global__ __launch_bounds__(kBlock) void k_hist(Bufs b, int rebuild_pass, int pass)
+{
+    __shared__ uint32_t h[kHistBins];
+    const int p = blockIdx.y;
+    const PState &s = b.st[p];
+    if (s.done || s.take_all || (rebuild_pass && !s.rebuild)) return;
+    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
+    const uint32_t mask = pass == 2 ? 0x3ffu : 0x7ffu;
+    const int pshift = pass == 1 ? 21 : 10;
+    const uint32_t prefix = s.prefix;
+    const int nparts = rebuild_pass ? 2 : 1;
+    for (int part = 0; part < nparts; ++part) {
+        const Queue q = part == 0 ? qoff(b.H[s.hcur], (size_t)p * b.hcap) : qoff(b.C[s.ccur], (size_t)p * b.ccap);
+        const uint32_t n = part == 0 ? s.nH[s.hcur] : s.nC[s.ccur];
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+            const uint32_t key = key32(q.prio[i]);
+            if (pass == 0 || (key >> pshift) == prefix) atomicAdd(&h[(key >> shift) & mask], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t *gh = b.hist + (size_t)p * kHistBins;
+    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x)
+        if (h[i]) atomicAdd(&gh[i], h[i]);
+}
+
+// Radix pass: the digit holding the need-th lowest key.  One block per problem.
+__global__ __launch_bounds__(kBlock) void k_scan(Bufs b, int rebuild_pass, int pass)
+{
+    __shared__ uint32_t part[kBlock];
+    __shared__ uint32_t found, left;
+    const int p = blockIdx.x;
+    PState &s = b.st[p];
+    if (s.done || s.take_all || (rebuild_pass && !s.rebuild)) return;
+    const int t = threadIdx.x;
+    const uint32_t want = rebuild_pass ? s.rb_target : b.k;
+    if (pass == 0) {
+        const uint32_t total = rebuild_pass ? s.nH[s.hcur] + s.nC[s.ccur] : s.nH[s.hcur];
+        if (total <= want) {
+            __syncthreads();
+            if (t == 0) {
+                s.take_all = 1;
+                s.prefix = 0xffffffffu;
+            }
+            return;
+        }
+    }
+    const uint32_t need = pass == 0 ? want : s.need;
+    constexpr int per = kHistBins / kBlock;
+    uint32_t *gh = b.hist + (size_t)p * kHistBins;
+    uint32_t loc[per], sum = 0;
+    for (int j = 0; j < per; ++j) {
+        loc[j] = gh[t * per + j];
+        sum += loc[j];
+    }
+    part[t] = sum;
+    if (t == 0) {
+        found = 0;
+        left = need;
+    }
+    __syncthreads();
+    uint32_t cum = 0;
+    for (int u = 0; u < t; ++u) cum += part[u];
+    for (int j = 0; j < per; ++j) {
+        if (cum < need && need <= cum + loc[j]) {   // exactly one bin qualifies
+            found = (uint32_t)(t * per + j);
+            left = need - cum;
+        }
+        cum += loc[j];
+    }
+    __syncthreads();
+    for (int j = 0; j < per; ++j) gh[t * per + j] = 0;
+    if (t == 0) {
+        s.prefix = (s.prefix << (pass == 2 ? 10 : 11)) | found;
+        s.need = left;
+        if (pass == 2) s.eq_quota = left;
+    }
+}
+
+// Re-partition: hot + cold -> new hot (key below the threshold, ties up to the
+// quota) and new cold, dropping cubes no longer below d*.
+__global__ __launch_bounds__(kBlock) void k_rebuild_compact(Bufs b)
+{
+    const int p = blockIdx.y;
+    PState &s = b.st[p];
+    if (s.done || !s.rebuild) return;
+    const double dstar = unord64(s.dstar);
+    const uint32_t T = s.prefix;
+    const bool all = s.take_all;
+    const Queue Hout = qoff(b.H[s.hcur ^ 1], (size_t)p * b.hcap);
+    const Queue Cout = qoff(b.C[s.ccur ^ 1], (size_t)p * b.ccap);
+    double mh = INFINITY, mc = INFINITY;
+    for (int part = 0; part < 2; ++part) {
+        const Queue q = part == 0 ? qoff(b.H[s.hcur], (size_t)p * b.hcap) : qoff(b.C[s.ccur], (size_t)p * b.ccap);
+        const uint32_t n = part == 0 ? s.nH[s.hcur] : s.nC[s.ccur];
+        for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+            const uint32_t i = base + threadIdx.x;
+            bool hot = false, cold = false;
+            double lb = 0.0;
+            if (i < n) {
+                lb = sane_lb(q.lb[i]);
+                if (lb < dstar) {
+                    const uint32_t key = key32(q.prio[i]);
+                    hot = all || key < T || (key == T && atomicAdd(&s.eq_taken, 1u) < s.eq_quota);
+                    cold = !hot;
+                }
+            }
+            const uint32_t ih = block_append(&s.nH[s.hcur ^ 1], hot);
+            const uint32_t ic = block_append(&s.nC[s.ccur ^ 1], cold);
+            if (hot) {
+                if (ih < b.hcap) {
+                    Hout.rkey[ih] = q.rkey[i];
+                    Hout.tkey[ih] = q.tkey[i];
+                    Hout.lb[ih] = lb;
+                    Hout.prio[ih] = q.prio[i];
+                    Hout.flags[ih] = q.flags[i];
+                } else {
+                    s.overflow = 1;
+                }
+                mh = fmin(mh, lb);
+            }
+            if (cold) {
+                if (ic < b.ccap) {
+                    Cout.rkey[ic] = q.rkey[i];
+                    Cout.tkey[ic] = q.tkey[i];
+                    Cout.lb[ic] = lb;
+                    Cout.prio[ic] = q.prio[i];
+                    Cout.flags[ic] = q.flags[i];
+                } else {
+                    s.overflow = 1;
+                }
+                mc = fmin(mc, lb);
+            }
+        }
+    }
+    mh = block_min(mh);
+    mc = block_min(mc);
+    if (threadIdx.x == 0) {
+        if (mh < INFINITY) atomicMin(&s.minH, ord64(mh));
+        if (mc < INFINITY) atomicMin(&s.minC, ord64(mc));
+    }
+}
+
+// After a re-partition: switch both parts, set the new threshold, reset the
+// radix state for the selection.
+__global__ void k_rebuild_finish(Bufs b, int P)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    PState &s = b.st[p];
+    if (s.done || !s.rebuild) return;
+    if (s.overflow) {          // counts may exceed the capacity: stop before anything reads them
+        s.done = OVERFLOW;
+        return;
+    }
+    s.theta = s.take_all ? 0xffffffffu : s.prefix;
+    s.minH = ord64(INFINITY);  // recomputed by the selection and the pushes
+    s.hcur ^= 1;
+    s.ccur ^= 1;
+    s.rebuild = 0;
+    s.take_all = 0;
+    s.prefix = 0;
+    s.need = 0;
+    s.eq_quota = 0;
+    s.eq_taken = 0;
+    s.nH[s.hcur ^ 1] = 0;
+    s.nC[s.ccur ^ 1] = 0;
+}
+
+// Selection: the k lowest keys of the hot part -> parents; the rest stays hot.
+__global__ __launch_bounds__(kBlock) void k_select_compact(Bufs b)
+{
+    const int p = blockIdx.y;
+    PState &s = b.st[p];
+    if (s.done) return;
+    const double dstar = unord64(s.dstar);
+    const uint32_t T = s.prefix;
+    const bool all = s.take_all;
+    const Queue q = qoff(b.H[s.hcur], (size_t)p * b.hcap);
+    const Queue Hout = qoff(b.H[s.hcur ^ 1], (size_t)p * b.hcap);
+    const Queue par = qoff(b.par, (size_t)p * b.k);
+    const uint32_t n = s.nH[s.hcur];
+    double mh = INFINITY;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        bool sel = false, keep = false;
+        double lb = 0.0;
+        if (i < n) {
+            lb = sane_lb(q.lb[i]);
+            if (lb < dstar) {
+                const uint32_t key = key32(q.prio[i]);
+                sel = all || key < T || (key == T && atomicAdd(&s.eq_taken, 1u) < s.eq_quota);
+                keep = !sel;
+            }
+        }
+        const uint32_t is = block_append(&s.nsel, sel);
+        const uint32_t ik = block_append(&s.nH[s.hcur ^ 1], keep);
+        if (sel) {
+            par.rkey[is] = q.rkey[i];
+            par.tkey[is] = q.tkey[i];
+            par.lb[is] = lb;
+            par.flags[is] = q.flags[i];
+        }
+        if (keep) {
+            Hout.rkey[ik] = q.rkey[i];
+            Hout.tkey[ik] = q.tkey[i];
+            Hout.lb[ik] = lb;
+            Hout.prio[ik] = q.prio[i];
+            Hout.flags[ik] = q.flags[i];
+            mh = fmin(mh, lb);
+        }
+    }
+    mh = block_min(mh);
+    if (threadIdx.x == 0 && mh < INFINITY) atomicMin(&s.minH, ord64(mh));
+}
+
+// 8 children per parent, all problems appended to one list.  A rotation split
+// shares its parent's translation cell among the 8 children.
+__global__ __launch_bounds__(kBlock) void k_branch(Bufs b)
+{
+    const int p = blockIdx.y;
+    PState &s = b.st[p];
+    const uint32_t n = s.done ? 0u : s.nsel;
+    const Queue par = qoff(b.par, (size_t)p * b.k);
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        const bool valid = i < n;
         bool rot = false, skip = false;
         uint64_t rk = 0, tk = 0;
         if (valid) {
-            rk = par.rkey[p];
-            tk = par.tkey[p];
-            rot = (par.flags[p] & GOSMA_FLAG_SPLIT_ROT) != 0;
+            rk = par.rkey[i];
+            tk = par.tkey[i];
+            rot = (par.flags[i] & GOSMA_FLAG_SPLIT_ROT) != 0;
             const bool rmax = key_level(rk) >= kMaxLevel, tmax = key_level(tk) >= kMaxLevel;
             if (rot && rmax) rot = false;
             if (!rot && tmax) rot = !rmax;
             skip = rmax && tmax;
-            if (skip) atomicMin(&st->floor_lb, ord64(par.lb[p]));
+            if (skip) atomicMin(&s.floor_lb, ord64(par.lb[i]));
         }
         const bool one = rot || skip;
-        const uint32_t tb = wave_reserve(&st->tcount, valid ? (one ? 1u : 8u) : 0u);
+        const uint32_t c0 = block_reserve(&b.g->nchild, valid ? 8u : 0u);
+        const uint32_t t0 = block_reserve(&b.g->ntcell, valid ? (one ? 1u : 8u) : 0u);
         if (!valid) continue;
         for (int c = 0; c < 8; ++c) {
-            const uint32_t ci = 8 * p + c;
+            const uint32_t ci = c0 + c;
             const uint64_t ck = one ? tk : child_key(tk, c);
-            crk[ci] = one ? child_key(rk, c) : rk;
-            ctk[ci] = ck;
-            cskip[ci] = skip;
-            ctidx[ci] = one ? tb : tb + c;
-            if (!one) tcells[tb + c] = ck;
+            b.crk[ci] = one ? child_key(rk, c) : rk;
+            b.ctk[ci] = ck;
+            b.cpid[ci] = (uint32_t)p;
+            b.cpar[ci] = (uint32_t)p * b.k + i;
+            b.cskip[ci] = skip;
+            b.ctidx[ci] = one ? t0 : t0 + c;
+            if (!one) {
+                b.tcells[t0 + c] = ck;
+                b.tpid[t0 + c] = (uint32_t)p;
+            }
         }
-        if (one) tcells[tb] = tk;
+        if (one) {
+            b.tcells[t0] = tk;
+            b.tpid[t0] = (uint32_t)p;
+        }
     }
 }
 
-struct ChildOut {
-    double *ub, *lb, *lb_safe, *aux;
-    uint8_t *flags;
-};
-
-__global__ __launch_bounds__(kBlock) void k_push(Queue par, const uint64_t *crk, const uint64_t *ctk,
-                                                 const uint8_t *cskip, ChildOut co, BBState *st, int out,
-                                                 Queue qout, uint32_t capacity)
+// Queue the children whose raised, margined lower bound is below d*.  Slots
+// are reserved per wavefront and target (problem, hot or cold): one atomic
+// per distinct target in the wave instead of one per child.
+__global__ __launch_bounds__(kBlock) void k_push(Bufs b, const float *prio_override)
 {
-    const uint32_t n = 8 * st->nsel;
-    const unsigned long long draw = st->dstar;
-    const double dstar = unord64(draw);
-    const uint32_t stride = gridDim.x * blockDim.x;
-    double local_min = INFINITY;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+    const uint32_t n = b.g->nchild;
+    const int lane = threadIdx.x & 63;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t i = base + threadIdx.x;
-        const bool valid = i < n;
-        bool push = false;
+        bool push = false, hot = false;
+        uint32_t p = 0;
         double lbs = 0.0;
+        float pr = 0.0f;
         uint8_t fl = 0;
-        if (valid) {
-            fl = co.flags[i];
-            const bool dropped = (fl & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS)) || cskip[i];
-            if (!dropped) {
-                lbs = fmax(sane_lb(co.lb_safe[i]), par.lb[i >> 3]);
-                push = lbs < dstar;
-                if (co.ub[i] < INFINITY && ord64(co.ub[i]) == draw) {
-                    st->best_rkey = crk[i];
-                    st->best_tkey = ctk[i];
+        if (i < n) {
+            p = b.cpid[i];
+            PState &s = b.st[p];
+            fl = b.cflags[i];
+            if (!((fl & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS)) || b.cskip[i])) {
+                const unsigned long long draw = s.dstar;
+                if (b.cub[i] < INFINITY && ord64(b.cub[i]) == draw) {
+                    s.best_rkey = b.crk[i];
+                    s.best_tkey = b.ctk[i];
+                }
+                lbs = fmax(sane_lb(b.clbs[i]), b.par.lb[b.cpar[i]]);
+                if (lbs < unord64(draw)) {
+                    push = true;
+                    pr = prio_override ? prio_override[i] : (float)lbs;
+                    hot = s.theta == 0xffffffffu || key32(pr) < s.theta;
                 }
             }
         }
-        uint32_t qs = wave_append(&st->qcount[out], push);
-        if (push) {
-            if (qs < capacity) {
-                qout.rkey[qs] = crk[i];
-                qout.tkey[qs] = ctk[i];
-                qout.lb[qs] = lbs;
-                qout.prio[qs] = (float)lbs;
-                qout.flags[qs] = fl & GOSMA_FLAG_SPLIT_ROT;
-            } else {
-                st->overflow = 1;
+        // group the pushing lanes of this wave by target
+        const uint32_t tgt = 2u * p + (hot ? 1u : 0u);
+        unsigned long long todo = __ballot(push);
+        uint32_t slot = 0;
+        while (todo) {
+            const int leader = __ffsll((long long)todo) - 1;
+            const uint32_t lt = __shfl(tgt, leader, 64);
+            const unsigned long long grp = __ballot(push && tgt == lt) & todo;
+            const uint32_t rank = (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
+            double m = (push && tgt == lt) ? lbs : INFINITY;
+            for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
+            uint32_t first = 0;
+            if (lane == leader) {
+                PState &s = b.st[lt >> 1];
+                const bool h = lt & 1u;
+                uint32_t *cnt = h ? &s.nH[s.hcur ^ 1] : &s.nC[s.ccur];
+                first = atomicAdd(cnt, (uint32_t)__popcll(grp));
+                unsigned long long *mn = h ? &s.minH : &s.minC;
+                const unsigned long long om = ord64(m);
+                if (om < __atomic_load_n(mn, __ATOMIC_RELAXED)) atomicMin(mn, om);
             }
-            local_min = fmin(local_min, lbs);
+            first = __shfl(first, leader, 64);
+            if (push && tgt == lt) slot = first + rank;
+            todo &= ~grp;
         }
+        if (!push) continue;
+        PState &s = b.st[p];
+        const Queue q = hot ? qoff(b.H[s.hcur ^ 1], (size_t)p * b.hcap) : qoff(b.C[s.ccur], (size_t)p * b.ccap);
+        if (slot >= (hot ? b.hcap : b.ccap)) {
+            s.overflow = 1;
+            continue;
+        }
+        q.rkey[slot] = b.crk[i];
+        q.tkey[slot] = b.ctk[i];
+        q.lb[slot] = lbs;
+        q.prio[slot] = pr;
+        q.flags[slot] = fl & GOSMA_FLAG_SPLIT_ROT;
     }
-    for (int off = 32; off > 0; off >>= 1) local_min = fmin(local_min, __shfl_xor(local_min, off, 64));
-    if ((threadIdx.x & 63) == 0 && local_min < INFINITY) atomicMin(&st->lbmin, ord64(local_min));
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&st->bounded, (unsigned long long)n);
 }
 
-__global__ void k_seed(Queue q, BBState *st, const uint64_t *rk, const uint64_t *tk, ChildOut co, int out,
-                       uint32_t capacity)
+// Per-problem control at the end of an iteration.
+__global__ void k_iter_end(Bufs b, int P)
 {
-    // root cube: push it unless dropped (lower bound raised to -inf parent)
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    st->bounded += 1;
-    uint8_t fl = co.flags[0];
-    if (fl & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS)) return;
-    double lbs = sane_lb(co.lb_safe[0]);
-    if (co.ub[0] < INFINITY && ord64(co.ub[0]) == st->dstar) {
-        st->best_rkey = rk[0];
-        st->best_tkey = tk[0];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    PState &s = b.st[p];
+    if (s.done) return;
+    s.bounded += 8ull * s.nsel;
+    s.hcur ^= 1;
+    s.iters += 1;
+    const uint32_t nh = s.nH[s.hcur], nc = s.nC[s.ccur];
+    const double lbq = fmin(fmin(unord64(s.minH), unord64(s.minC)), unord64(s.floor_lb));
+    const double dstar = unord64(s.dstar);
+    if (s.overflow)
+        s.done = OVERFLOW;
+    else if (nh + nc == 0)
+        s.done = EXHAUSTED;
+    else if (dstar - lbq <= s.eps_f)
+        s.done = EPS_OPTIMAL;
+    else if (s.max_iters && s.iters >= s.max_iters)
+        s.done = CAPPED;
+    if (s.done) return;
+    atomicAdd(&b.g->running, 1u);
+    // re-partition when the hot part runs low (and cold cubes exist) or fills up
+    if ((nh < b.k && nc > 0) || nh + 8u * b.k > b.hcap) {
+        s.rebuild = 1;
+        const uint32_t total = nh + nc;
+        s.rb_target = min(max(total / 16u, 16u * b.k), b.hcap / 2u);
     }
-    if (!(lbs < unord64(st->dstar))) return;
-    uint32_t qs = st->qcount[out]++;
-    if (qs >= capacity) {
-        st->overflow = 1;
+}
+
+// Queue the root cube of each problem (after its bounds were evaluated).
+__global__ void k_seed(Bufs b, int P)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    PState &s = b.st[p];
+    s.bounded = 1;
+    const uint8_t fl = b.cflags[p];
+    if (b.cub[p] < INFINITY && ord64(b.cub[p]) == s.dstar) {
+        s.best_rkey = b.crk[p];
+        s.best_tkey = b.ctk[p];
+    }
+    if (fl & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS)) {
+        s.done = EXHAUSTED;
         return;
     }
-    q.rkey[qs] = rk[0];
-    q.tkey[qs] = tk[0];
-    q.lb[qs] = lbs;
-    q.prio[qs] = (float)lbs;
-    q.flags[qs] = fl & GOSMA_FLAG_SPLIT_ROT;
-    st->lbmin = ord64(lbs);
+    const double lbs = sane_lb(b.clbs[p]);
+    if (!(lbs < unord64(s.dstar))) {
+        s.done = EXHAUSTED;
+        return;
+    }
+    const Queue q = qoff(b.H[s.hcur], (size_t)p * b.hcap);
+    q.rkey[0] = b.crk[p];
+    q.tkey[0] = b.ctk[p];
+    q.lb[0] = lbs;
+    q.prio[0] = (float)lbs;
+    q.flags[0] = fl & GOSMA_FLAG_SPLIT_ROT;
+    s.nH[s.hcur] = 1;
+    s.minH = ord64(lbs);
 }
 
 }  // namespace
 
-// Device buffers of one solve (owned by the context, grown on demand).
+// Device buffers of a solve, owned by the context and reused while large enough.
 struct Solver {
-    size_t cap = 0, kcap = 0;
-    Queue q[2] = {};
-    Queue par = {};
-    uint64_t *crk = nullptr, *ctk = nullptr, *tcells = nullptr;
-    int64_t *ctidx = nullptr;
-    uint8_t *cskip = nullptr;
-    double *cub = nullptr, *clb = nullptr, *clbs = nullptr, *s11ub = nullptr, *s11lo = nullptr;
-    uint8_t *cflags = nullptr;
-    uint32_t *hist = nullptr;
-    BBState *st = nullptr;
-    BBState *h_st = nullptr;   // pinned host copy
+    int P = 0;
+    size_t k = 0, hcap = 0, ccap = 0;
+    Bufs b{};
+    PState *h_st = nullptr;   // pinned host copies
+    GState *h_g = nullptr;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_maxM = 0;
 };
 
 }  // namespace gosma
 
 namespace {
+
+using gosma::Bufs;
+using gosma::GState;
+using gosma::PState;
+using gosma::Queue;
+using gosma::Solver;
 
 template <class T>
 hipError_t dalloc(T *&p, size_t n)
@@ -406,8 +664,7 @@ void dfree(T *&p)
     if (p) (void)hipFree((void *)p);
     p = nullptr;
 }
-
-void free_queue(gosma::Queue &q)
+void free_queue(Queue &q)
 {
     dfree(q.rkey);
     dfree(q.tkey);
@@ -415,8 +672,7 @@ void free_queue(gosma::Queue &q)
     dfree(q.prio);
     dfree(q.flags);
 }
-
-hipError_t alloc_queue(gosma::Queue &q, size_t n)
+hipError_t alloc_queue(Queue &q, size_t n)
 {
     hipError_t e;
     if ((e = dalloc(q.rkey, n)) || (e = dalloc(q.tkey, n)) || (e = dalloc(q.lb, n)) || (e = dalloc(q.prio, n)) ||
@@ -425,52 +681,306 @@ hipError_t alloc_queue(gosma::Queue &q, size_t n)
     return hipSuccess;
 }
 
-void free_solver(gosma::Solver *s)
+void drop_graph(Solver *s)
 {
-    if (!s) return;
-    free_queue(s->q[0]);
-    free_queue(s->q[1]);
-    free_queue(s->par);
-    dfree(s->crk);
-    dfree(s->ctk);
-    dfree(s->tcells);
-    dfree(s->ctidx);
-    dfree(s->cskip);
-    dfree(s->cub);
-    dfree(s->clb);
-    dfree(s->clbs);
-    dfree(s->s11ub);
-    dfree(s->s11lo);
-    dfree(s->cflags);
-    dfree(s->hist);
-    dfree(s->st);
-    if (s->h_st) (void)hipHostFree(s->h_st);
-    s->h_st = nullptr;
-    s->cap = s->kcap = 0;
+    if (s->exec) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->exec = nullptr;
+    s->graph = nullptr;
 }
 
-hipError_t ensure_solver(gosma::Solver *s, size_t cap, size_t k)
+void free_solver(Solver *s)
 {
-    if (s->cap >= cap && s->kcap >= k && s->st) return hipSuccess;
+    drop_graph(s);
+    Bufs &b = s->b;
+    for (int i = 0; i < 2; ++i) {
+        free_queue(b.H[i]);
+        free_queue(b.C[i]);
+    }
+    free_queue(b.par);
+    dfree(b.crk);
+    dfree(b.ctk);
+    dfree(b.cpid);
+    dfree(b.cpar);
+    dfree(b.ctidx);
+    dfree(b.cskip);
+    dfree(b.tcells);
+    dfree(b.tpid);
+    dfree(b.cub);
+    dfree(b.clb);
+    dfree(b.clbs);
+    dfree(b.cflags);
+    dfree(b.s11ub);
+    dfree(b.s11lo);
+    dfree(b.hist);
+    dfree(b.st);
+    dfree(b.g);
+    if (s->h_st) (void)hipHostFree(s->h_st);
+    if (s->h_g) (void)hipHostFree(s->h_g);
+    s->h_st = nullptr;
+    s->h_g = nullptr;
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    s->stream = nullptr;
+    s->P = 0;
+    s->k = s->hcap = s->ccap = 0;
+}
+
+hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap)
+{
+    if (s->P == P && s->k == k && s->hcap == hcap && s->ccap == ccap && s->b.st) return hipSuccess;
     free_solver(s);
-    hipError_t e;
-    const size_t c8 = 8 * k;
-    if ((e = alloc_queue(s->q[0], cap)) || (e = alloc_queue(s->q[1], cap)) || (e = alloc_queue(s->par, k)) ||
-        (e = dalloc(s->crk, c8)) || (e = dalloc(s->ctk, c8)) || (e = dalloc(s->tcells, c8)) ||
-        (e = dalloc(s->ctidx, c8)) || (e = dalloc(s->cskip, c8)) || (e = dalloc(s->cub, c8)) ||
-        (e = dalloc(s->clb, c8)) || (e = dalloc(s->clbs, c8)) || (e = dalloc(s->s11ub, c8)) ||
-        (e = dalloc(s->s11lo, c8)) || (e = dalloc(s->cflags, c8)) || (e = dalloc(s->hist, gosma::kHistBins)) ||
-        (e = dalloc(s->st, 1)))
+    Bufs &b = s->b;
+    hipError_t e = hipSuccess;
+    const size_t nc = 8 * k * (size_t)P + (size_t)P;   // children (+ one root per problem)
+    for (int i = 0; i < 2 && !e; ++i) {
+        e = alloc_queue(b.H[i], hcap * P);
+        if (!e) e = alloc_queue(b.C[i], ccap * P);
+    }
+    if (!e) e = alloc_queue(b.par, k * P);
+    if (!e) e = dalloc(b.crk, nc);
+    if (!e) e = dalloc(b.ctk, nc);
+    if (!e) e = dalloc(b.cpid, nc);
+    if (!e) e = dalloc(b.cpar, nc);
+    if (!e) e = dalloc(b.ctidx, nc);
+    if (!e) e = dalloc(b.cskip, nc);
+    if (!e) e = dalloc(b.tcells, nc);
+    if (!e) e = dalloc(b.tpid, nc);
+    if (!e) e = dalloc(b.cub, nc);
+    if (!e) e = dalloc(b.clb, nc);
+    if (!e) e = dalloc(b.clbs, nc);
+    if (!e) e = dalloc(b.cflags, nc);
+    if (!e) e = dalloc(b.s11ub, nc);
+    if (!e) e = dalloc(b.s11lo, nc);
+    if (!e) e = dalloc(b.hist, (size_t)gosma::kHistBins * P);
+    if (!e) e = dalloc(b.st, (size_t)P);
+    if (!e) e = dalloc(b.g, 1);
+    if (!e) e = hipHostMalloc((void **)&s->h_st, sizeof(PState) * P, hipHostMallocDefault);
+    if (!e) e = hipHostMalloc((void **)&s->h_g, sizeof(GState), hipHostMallocDefault);
+    if (!e) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e) {
+        free_solver(s);
         return e;
-    if ((e = hipHostMalloc((void **)&s->h_st, sizeof(gosma::BBState), hipHostMallocDefault))) return e;
-    s->cap = cap;
-    s->kcap = k;
+    }
+    b.hcap = (uint32_t)hcap;
+    b.ccap = (uint32_t)ccap;
+    b.k = (uint32_t)k;
+    s->P = P;
+    s->k = k;
+    s->hcap = hcap;
+    s->ccap = ccap;
     return hipSuccess;
+}
+
+unsigned long long ordh(double x)
+{
+    unsigned long long u;
+    std::memcpy(&u, &x, sizeof u);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+// Launch one iteration (all problems).  Every launch has a fixed shape and
+// reads its work counts from device memory, so the sequence can be captured.
+hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool timed)
+{
+    using namespace gosma;
+    Bufs &b = S.b;
+    const int P = S.P;
+    const int gx = std::max(1, kGridX / P);
+    const DevMix mx = ctx->mix();
+    auto T0 = [&](int kind) { return timed ? ctx->time_begin(kind, st) : -1; };
+    auto T1 = [&](int idx) {
+        if (timed) ctx->time_end(idx, st);
+    };
+    int ti = T0(GOSMA_KERNEL_SELECT);
+    hipLaunchKernelGGL(k_iter_begin, dim3(P), dim3(kBlock), 0, st, b, P);
+    // re-partition of the problems that asked for it
+    for (int pass = 0; pass < 3; ++pass) {
+        hipLaunchKernelGGL(k_hist, dim3(gx, P), dim3(kBlock), 0, st, b, 1, pass);
+        hipLaunchKernelGGL(k_scan, dim3(P), dim3(kBlock), 0, st, b, 1, pass);
+    }
+    hipLaunchKernelGGL(k_rebuild_compact, dim3(gx, P), dim3(kBlock), 0, st, b);
+    hipLaunchKernelGGL(k_rebuild_finish, dim3((P + 63) / 64), dim3(64), 0, st, b, P);
+    // selection of the k lowest hot cubes
+    for (int pass = 0; pass < 3; ++pass) {
+        hipLaunchKernelGGL(k_hist, dim3(gx, P), dim3(kBlock), 0, st, b, 0, pass);
+        hipLaunchKernelGGL(k_scan, dim3(P), dim3(kBlock), 0, st, b, 0, pass);
+    }
+    hipLaunchKernelGGL(k_select_compact, dim3(gx, P), dim3(kBlock), 0, st, b);
+    T1(ti);
+    ti = T0(GOSMA_KERNEL_BRANCH);
+    hipLaunchKernelGGL(k_branch, dim3(std::max(1, gx / 4), P), dim3(kBlock), 0, st, b);
+    T1(ti);
+    const int64_t maxc = 8 * (int64_t)S.k * P;
+    ti = T0(GOSMA_KERNEL_S11);
+    hipError_t e = launch_s11(mx, b.tcells, b.tpid, maxc, &b.g->ntcell, S11Out{b.s11ub, b.s11lo}, ctx->maxM,
+                              kBoundGrid, st);
+    T1(ti);
+    if (e) return e;
+    ti = T0(GOSMA_KERNEL_S12);
+    BoundOut bo{b.cub, b.clb, b.clbs, nullptr, b.cflags, nullptr, nullptr, &b.st->dstar,
+                (int)(sizeof(PState) / sizeof(unsigned long long))};
+    e = launch_s12(mx, b.crk, b.ctk, b.cpid, b.ctidx, b.s11ub, b.s11lo, maxc, &b.g->nchild, 1, bo, kMarginGamma,
+                   ctx->maxM, false, kBoundGrid, st);
+    T1(ti);
+    if (e) return e;
+    ti = T0(GOSMA_KERNEL_PUSH);
+    hipLaunchKernelGGL(k_push, dim3(kGridX), dim3(kBlock), 0, st, b, (const float *)nullptr);
+    hipLaunchKernelGGL(k_iter_end, dim3((P + 63) / 64), dim3(64), 0, st, b, P);
+    T1(ti);
+    return hipGetLastError();
+}
+
+int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, int P)
+{
+    using namespace gosma;
+    const auto t_start = std::chrono::steady_clock::now();
+    auto fail = [&](int code, const char *what, hipError_t e = hipSuccess) {
+        ctx->err = std::string(what) + (e ? std::string(": ") + hipGetErrorString(e) : std::string());
+        return code;
+    };
+    if (!opts || !res) return fail(GOSMA_E_INVAL, "opts and result must not be NULL");
+    if (ctx->n_problems < 1 || !ctx->has_domain) return fail(GOSMA_E_STATE, "no problem set");
+    if (!(opts->eps >= 0) || opts->batch_parents < 1 || opts->batch_parents > (1 << 20) || opts->max_queue < 16 ||
+        opts->max_queue > ((int64_t)1 << 31) || (uint64_t)opts->max_queue * P > ((uint64_t)1 << 34))
+        return fail(GOSMA_E_INVAL, "invalid options (eps >= 0, 1 <= batch_parents <= 2^20, 16 <= max_queue <= 2^31)");
+    if (opts->order != 0) return fail(GOSMA_E_STATE, "learned order needs a loaded network");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e) return fail(GOSMA_E_HIP, "hipSetDevice", e);
+    ctx->trace.clear();
+    for (int p = 0; p < P; ++p) std::memset(res + p, 0, sizeof *res);
+    if (!ctx->solver) ctx->solver = new Solver;
+    Solver &S = *ctx->solver;
+    const size_t k = (size_t)opts->batch_parents;
+    const size_t ccap = (size_t)opts->max_queue;
+    const size_t hcap = std::max<size_t>(std::min<size_t>(std::max<size_t>(256 * k, (size_t)1 << 20), ccap),
+                                         24 * k + 16);
+    if (S.graph_maxM != ctx->maxM) drop_graph(&S);   // the bound launches depend on the LDS size
+    if ((e = ensure_solver(&S, P, k, hcap, ccap))) return fail(GOSMA_E_NOMEM, "allocating solver buffers", e);
+    Bufs &b = S.b;
+    hipStream_t st = S.stream;
+
+    // initial state and the root cube of each problem
+    std::vector<PState> init(P);
+    for (int p = 0; p < P; ++p) {
+        PState &s = init[p];
+        std::memset(&s, 0, sizeof s);
+        s.dstar = s.minH = s.minC = s.floor_lb = ordh(INFINITY);
+        s.eps_f = opts->eps * ctx->h_prob[p].S22;
+        s.theta = 0xffffffffu;
+        s.max_iters = (uint32_t)std::min<int64_t>(opts->max_iters, 0xffffffffll);
+    }
+    std::vector<uint64_t> zeros(P, 0);
+    std::vector<uint32_t> pids(P);
+    for (int p = 0; p < P; ++p) pids[p] = (uint32_t)p;
+    if ((e = hipMemcpyAsync(b.st, init.data(), sizeof(PState) * P, hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(b.crk, zeros.data(), 8 * P, hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(b.ctk, zeros.data(), 8 * P, hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(b.cpid, pids.data(), 4 * P, hipMemcpyHostToDevice, st)) ||
+        (e = hipStreamSynchronize(st)))
+        return fail(GOSMA_E_HIP, "solver initialisation", e);
+    {
+        const DevMix mx = ctx->mix();
+        BoundOut bo{b.cub, b.clb, b.clbs, nullptr, b.cflags, nullptr, nullptr, &b.st->dstar,
+                    (int)(sizeof(PState) / sizeof(unsigned long long))};
+        e = launch_s11(mx, b.ctk, b.cpid, P, nullptr, S11Out{b.s11ub, b.s11lo}, ctx->maxM, 0, st);
+        if (!e)
+            e = launch_s12(mx, b.crk, b.ctk, b.cpid, nullptr, b.s11ub, b.s11lo, P, nullptr, 1, bo, kMarginGamma,
+                           ctx->maxM, false, 0, st);
+        if (!e) {
+            hipLaunchKernelGGL(k_seed, dim3((P + 63) / 64), dim3(64), 0, st, b, P);
+            e = hipGetLastError();
+        }
+        if (e) return fail(GOSMA_E_HIP, "root cubes", e);
+    }
+
+    // iterations: replay a captured graph of one iteration, reading the
+    // status every `check` iterations (every iteration when tracing or timing)
+    const bool timed = ctx->timing;
+    const bool tracing = opts->trace_every > 0 && P == 1;
+    const int check = (timed || tracing) ? 1 : 4;
+    bool use_graph = !timed && !opts->no_graph;
+    if (use_graph && !S.exec) {
+        e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (!e) {
+            hipError_t le = launch_iteration(ctx, S, st, false);
+            e = hipStreamEndCapture(st, &S.graph);
+            if (!e) e = le;
+        }
+        if (!e) e = hipGraphInstantiate(&S.exec, S.graph, nullptr, nullptr, 0);
+        if (e) {
+            drop_graph(&S);
+            (void)hipGetLastError();
+            use_graph = false;
+        } else {
+            S.graph_maxM = ctx->maxM;
+        }
+    }
+    int rc = GOSMA_OK;
+    int64_t launched = 0;
+    for (;;) {
+        if ((e = hipMemcpyAsync(S.h_st, b.st, sizeof(PState) * P, hipMemcpyDeviceToHost, st)) ||
+            (e = hipStreamSynchronize(st))) {
+            rc = fail(GOSMA_E_HIP, "branch-and-bound iteration", e);
+            break;
+        }
+        const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        int running = 0;
+        for (int p = 0; p < P; ++p) running += S.h_st[p].done == RUNNING;
+        if (tracing && (launched / check) % opts->trace_every == 0) {
+            const PState &h = S.h_st[0];
+            const double lbq = std::min({unord64(h.minH), unord64(h.minC), unord64(h.floor_lb)});
+            const double row[6] = {(double)h.iters, el, (double)h.bounded, (double)(h.nH[h.hcur] + h.nC[h.ccur]),
+                                   unord64(h.dstar), lbq};
+            ctx->trace.insert(ctx->trace.end(), row, row + 6);
+        }
+        if (running == 0) break;
+        if (opts->time_limit_s > 0 && el > opts->time_limit_s) break;
+        for (int r = 0; r < check && !e; ++r)
+            e = use_graph ? hipGraphLaunch(S.exec, st) : launch_iteration(ctx, S, st, timed);
+        if (e) {
+            rc = fail(GOSMA_E_HIP, "branch-and-bound iteration", e);
+            break;
+        }
+        launched += check;
+    }
+    const double seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    for (int p = 0; p < P; ++p) {
+        const PState &h = S.h_st[p];
+        gosma_result &r = res[p];
+        const double S22 = ctx->h_prob[p].S22;
+        const double lbq = std::min({unord64(h.minH), unord64(h.minC), unord64(h.floor_lb)});
+        r.f_best = unord64(h.dstar);
+        r.lb_global = h.done == EXHAUSTED ? std::min(r.f_best, unord64(h.floor_lb)) : std::min(lbq, r.f_best);
+        r.f_norm_best = (r.f_best + S22) / S22;
+        r.lb_norm = (r.lb_global + S22) / S22;
+        r.iters = h.iters;
+        r.cubes = (int64_t)h.bounded;
+        r.max_queue_used = (int64_t)h.nH[h.hcur] + h.nC[h.ccur];
+        r.seconds = seconds;
+        r.status = h.done == EPS_OPTIMAL ? 0 : (h.done == EXHAUSTED ? 1 : 2);
+        const ProbDesc &D = ctx->h_prob[p];
+        auto centre = [](uint64_t key, const double *lo, const double *w, double *c) {
+            const uint64_t m = (1ull << 19) - 1;
+            int L = (int)((key >> 57) & 63);
+            uint64_t idx[3] = {(key >> 38) & m, (key >> 19) & m, key & m};
+            for (int a = 0; a < 3; ++a) c[a] = lo[a] + (2.0 * (double)idx[a] + 1.0) * std::ldexp(w[a], -(L + 1));
+        };
+        centre(h.best_rkey, D.r_lo, D.r_w, r.r);
+        centre(h.best_tkey, D.t_lo, D.t_w, r.t);
+        if (h.done == OVERFLOW && rc == GOSMA_OK)
+            rc = fail(GOSMA_E_QUEUE_OVERFLOW, "branch-and-bound queue capacity exceeded");
+    }
+    return rc;
 }
 
 }  // namespace
 
 extern "C" {
+
+void gosma_drop_graph(gosma_ctx *ctx)
+{
+    if (ctx && ctx->solver) drop_graph(ctx->solver);
+}
 
 void gosma_release_solver(gosma_ctx *ctx)
 {
@@ -482,192 +992,30 @@ void gosma_release_solver(gosma_ctx *ctx)
 
 int gosma_solve(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res)
 {
-    using namespace gosma;
     if (!ctx) return GOSMA_E_INVAL;
     ctx->err.clear();
-    if (!opts || !res) {
-        ctx->err = "opts and result must not be NULL";
-        return GOSMA_E_INVAL;
-    }
-    if (ctx->n_problems != 1 || !ctx->has_domain) {
-        ctx->err = "gosma_solve needs exactly one problem with a domain";
+    if (ctx->n_problems != 1) {
+        ctx->err = "gosma_solve needs exactly one problem (use gosma_solve_batch)";
         return GOSMA_E_STATE;
     }
-    if (!(opts->eps >= 0) || opts->batch_parents < 1 || opts->batch_parents > (1 << 20) || opts->max_queue < 16 ||
-        opts->max_queue > ((int64_t)1 << 31)) {
-        ctx->err = "invalid options (eps >= 0, 1 <= batch_parents <= 2^20, 16 <= max_queue <= 2^31)";
-        return GOSMA_E_INVAL;
-    }
-    if (opts->order != 0) {
-        ctx->err = "learned order needs a loaded network";
-        return GOSMA_E_STATE;
-    }
-    const auto t_start = std::chrono::steady_clock::now();
-    std::memset(res, 0, sizeof *res);
-    auto hipcheck = [&](hipError_t e, const char *what) {
-        if (e != hipSuccess) ctx->err = std::string(what) + ": " + hipGetErrorString(e);
-        return e != hipSuccess;
-    };
-    if (hipcheck(hipSetDevice(ctx->device), "hipSetDevice")) return GOSMA_E_HIP;
-    if (!ctx->solver) ctx->solver = new Solver;
-    Solver &S = *ctx->solver;
-    const size_t k = (size_t)opts->batch_parents;
-    const uint32_t cap = (uint32_t)opts->max_queue;
-    if (hipcheck(ensure_solver(&S, cap, k), "allocating solver buffers")) {
-        free_solver(&S);
-        return GOSMA_E_NOMEM;
-    }
-    hipStream_t s = nullptr;
-    const double S22 = ctx->h_prob[0].S22;
-    const double eps_f = opts->eps * S22;
-    const DevMix mx = ctx->mix();
-    const int maxM = ctx->maxM;
-
-    // initial state
-    BBState init;
-    std::memset(&init, 0, sizeof init);
-    auto ordh = [](double x) {
-        unsigned long long u;
-        std::memcpy(&u, &x, sizeof u);
-        return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
-    };
-    init.dstar = ordh(INFINITY);
-    init.lbmin = ordh(INFINITY);
-    init.floor_lb = ordh(INFINITY);
-    if (hipcheck(hipMemcpy(S.st, &init, sizeof init, hipMemcpyHostToDevice), "state init")) return GOSMA_E_HIP;
-
-    ChildOut co{S.cub, S.clb, S.clbs, nullptr, S.cflags};
-    // d*: the S12 epilogue takes the atomic minimum of the FP32 upper bounds.
-    // The rounding margin is carried by the lower bounds (lb_safe), so the
-    // certificate is d* - min lb_safe <= eps up to the margin.
-    BoundOut bo{S.cub, S.clb, S.clbs, nullptr, S.cflags, nullptr, nullptr, &S.st->dstar};
-
-    // root cube
-    {
-        uint64_t zero64 = 0;
-        hipError_t e = hipMemcpy(S.crk, &zero64, 8, hipMemcpyHostToDevice);
-        if (!e) e = hipMemcpy(S.ctk, &zero64, 8, hipMemcpyHostToDevice);
-        if (!e) {
-            hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBlock), 0, s, S.st, 0, S.hist);
-            e = launch_s11(mx, S.ctk, nullptr, 1, nullptr, S11Out{S.s11ub, S.s11lo}, maxM, 0, s);
-        }
-        if (!e)
-            e = launch_s12(mx, S.crk, S.ctk, nullptr, nullptr, S.s11ub, S.s11lo, 1, nullptr, 1, bo, kMarginGamma, maxM,
-                           false, 0, s);
-        if (!e) {
-            hipLaunchKernelGGL(k_seed, dim3(1), dim3(64), 0, s, S.q[0], S.st, S.crk, S.ctk, co, 0, cap);
-            e = hipGetLastError();
-        }
-        if (hipcheck(e, "root cube")) return GOSMA_E_HIP;
-    }
-    int cur = 0;
-    int status = 1;
-    int rc = GOSMA_OK;
-    int64_t iters = 0;
-    const int gsel = kGridCap;
-    for (;;) {
-        // status of the queue after the last push
-        if (hipcheck(hipMemcpyAsync(S.h_st, S.st, sizeof(BBState), hipMemcpyDeviceToHost, s), "status copy") ||
-            hipcheck(hipStreamSynchronize(s), "iteration")) {
-            rc = GOSMA_E_HIP;
-            break;
-        }
-        const BBState &h = *S.h_st;
-        const double dstar = unord64(h.dstar);
-        const double lbq = std::min(unord64(h.lbmin), unord64(h.floor_lb));
-        res->max_queue_used = std::max<int64_t>(res->max_queue_used, h.qcount[cur]);
-        if (h.overflow) {
-            rc = GOSMA_E_QUEUE_OVERFLOW;
-            ctx->err = "branch-and-bound queue capacity exceeded";
-            status = 2;
-            res->lb_global = lbq;
-            break;
-        }
-        if (h.qcount[cur] == 0) {
-            status = 1;
-            res->lb_global = std::min(dstar, unord64(h.floor_lb));
-            break;
-        }
-        res->lb_global = lbq;
-        if (dstar - lbq <= eps_f) {
-            status = 0;
-            break;
-        }
-        const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-        if ((opts->max_iters > 0 && iters >= opts->max_iters) || (opts->time_limit_s > 0 && el > opts->time_limit_s)) {
-            status = 2;
-            break;
-        }
-        const int out = cur ^ 1;
-        // select
-        int ti = ctx->time_begin(GOSMA_KERNEL_SELECT, s);
-        hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBlock), 0, s, S.st, out, S.hist);
-        for (int pass = 0; pass < 3; ++pass) {
-            hipLaunchKernelGGL(k_hist, dim3(gsel), dim3(kBlock), 0, s, S.q[cur], S.st, cur, pass, S.hist);
-            hipLaunchKernelGGL(k_scan, dim3(1), dim3(kBlock), 0, s, S.st, cur, pass, (uint32_t)k, S.hist);
-        }
-        hipLaunchKernelGGL(k_compact, dim3(gsel), dim3(kBlock), 0, s, S.q[cur], S.q[out], S.st, cur, out, S.par,
-                           cap);
-        ctx->time_end(ti, s);
-        // branch
-        ti = ctx->time_begin(GOSMA_KERNEL_BRANCH, s);
-        hipLaunchKernelGGL(k_branch, dim3(64), dim3(kBlock), 0, s, S.par, S.st, S.crk, S.ctk, S.ctidx, S.cskip,
-                           S.tcells);
-        ctx->time_end(ti, s);
-        // bound
-        ti = ctx->time_begin(GOSMA_KERNEL_S11, s);
-        hipError_t e = launch_s11(mx, S.tcells, nullptr, 8 * (int64_t)k, &S.st->tcount, S11Out{S.s11ub, S.s11lo},
-                                  maxM, kBoundGrid, s);
-        ctx->time_end(ti, s);
-        ti = ctx->time_begin(GOSMA_KERNEL_S12, s);
-        if (!e)
-            e = launch_s12(mx, S.crk, S.ctk, nullptr, S.ctidx, S.s11ub, S.s11lo, 8 * (int64_t)k, &S.st->nsel, 8, bo,
-                           kMarginGamma, maxM, false, kBoundGrid, s);
-        ctx->time_end(ti, s);
-        if (hipcheck(e, "bound kernels")) {
-            rc = GOSMA_E_HIP;
-            break;
-        }
-        // push
-        ti = ctx->time_begin(GOSMA_KERNEL_PUSH, s);
-        hipLaunchKernelGGL(k_push, dim3(gsel), dim3(kBlock), 0, s, S.par, S.crk, S.ctk, S.cskip, co, S.st, out,
-                           S.q[out], cap);
-        ctx->time_end(ti, s);
-        if (hipcheck(hipGetLastError(), "kernel launch")) {
-            rc = GOSMA_E_HIP;
-            break;
-        }
-        cur = out;
-        ++iters;
-    }
-    // final state
-    if (hipcheck(hipMemcpy(S.h_st, S.st, sizeof(BBState), hipMemcpyDeviceToHost), "final status")) return GOSMA_E_HIP;
-    const BBState &h = *S.h_st;
-    res->f_best = unord64(h.dstar);
-    res->iters = iters;
-    res->cubes = (int64_t)h.bounded;
-    res->status = status;
-    res->f_norm_best = (res->f_best + S22) / S22;
-    res->lb_norm = (res->lb_global + S22) / S22;
-    // pose of d*: cube centre
-    const ProbDesc &P = ctx->h_prob[0];
-    auto centre = [](uint64_t key, const double *lo, const double *w, double *c) {
-        const uint64_t m = (1ull << 19) - 1;
-        int L = (int)((key >> 57) & 63);
-        uint64_t idx[3] = {(key >> 38) & m, (key >> 19) & m, key & m};
-        for (int a = 0; a < 3; ++a) c[a] = lo[a] + (2.0 * (double)idx[a] + 1.0) * std::ldexp(w[a], -(L + 1));
-    };
-    centre(h.best_rkey, P.r_lo, P.r_w, res->r);
-    centre(h.best_tkey, P.t_lo, P.t_w, res->t);
-    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-    return rc;
+    return solve_problems(ctx, opts, res, 1);
 }
 
-int gosma_solve_batch(gosma_ctx *ctx, const gosma_opts *, gosma_result *)
+int gosma_solve_batch(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res)
 {
     if (!ctx) return GOSMA_E_INVAL;
-    ctx->err = "gosma_solve_batch: not built yet";
-    return GOSMA_E_STATE;
+    ctx->err.clear();
+    return solve_problems(ctx, opts, res, ctx->n_problems);
+}
+
+int gosma_get_trace(gosma_ctx *ctx, double *buf, int64_t cap, int64_t *n)
+{
+    if (!ctx || !n || (cap > 0 && !buf)) return GOSMA_E_INVAL;
+    const int64_t rows = (int64_t)(ctx->trace.size() / 6);
+    *n = rows;
+    const int64_t w = std::min(rows, cap);
+    if (w > 0) std::memcpy(buf, ctx->trace.data(), sizeof(double) * 6 * (size_t)w);
+    return GOSMA_OK;
 }
 
 }  // extern "C"

@@ -645,7 +645,13 @@ __device__ void s12_cube(DevMix mx, const uint64_t *__restrict__ rkeys, const ui
         }
         out.ub[cube] = ub;
         out.lb[cube] = lb;
-        if (out.dstar_bits && ub < INFINITY) atomicMin(out.dstar_bits, ordered_bits(ub));
+        if (out.dstar_bits && ub < INFINITY) {
+            // read first: most cubes do not improve d*, and skipping their
+            // atomics avoids serialising every wave on one address
+            unsigned long long *d = out.dstar_bits + (size_t)pid * out.dstar_stride;
+            const unsigned long long u = ordered_bits(ub);
+            if (u < __atomic_load_n(d, __ATOMIC_RELAXED)) atomicMin(d, u);
+        }
         if (out.lb_safe) out.lb_safe[cube] = lbs;
         out.flags[cube] = flags;
         if (out.aux) {

@@ -53,7 +53,8 @@ struct BoundOut {
     uint8_t *flags;
     float *top8;
     float *psi_gap;    // optional: psi_r - weighted mean psi_t (branching statistic)
-    unsigned long long *dstar_bits;   // optional: atomic minimum of finite upper bounds (ordered bits)
+    unsigned long long *dstar_bits;   // optional: atomic minimum of finite upper bounds (ordered bits),
+    int dstar_stride;                 // at dstar_bits[problem * dstar_stride]
 };
 
 struct S11Out {
@@ -96,6 +97,7 @@ struct gosma_ctx {
     double *d_s11ub = nullptr, *d_s11lo = nullptr;
 
     gosma::Solver *solver = nullptr;
+    std::vector<double> trace;   // 6 doubles per recorded iteration
 
     // kernel timing (gosma_set_timing)
     bool timing = false;

@@ -22,7 +22,7 @@ FLAG_SPLIT_ROT, FLAG_DROP_ROT, FLAG_DROP_TRANS, FLAG_UB_INF = 1, 2, 4, 8
 
 EXPORTS = ["gosma_create", "gosma_destroy", "gosma_last_error", "gosma_set_mixtures", "gosma_set_domain",
            "gosma_set_problems", "gosma_get_S22", "gosma_eval_bounds", "gosma_solve", "gosma_solve_batch",
-           "gosma_set_timing", "gosma_get_timing"]
+           "gosma_set_timing", "gosma_get_timing", "gosma_get_trace"]
 KERNEL_KINDS = ["s11", "s12", "select", "branch", "push", "mlp"]
 
 
@@ -40,7 +40,7 @@ class Domain(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("batch_parents", C.c_int64), ("max_queue", C.c_int64),
                 ("max_iters", C.c_int64), ("time_limit_s", C.c_double), ("order", C.c_int),
-                ("log_records", C.c_int)]
+                ("log_records", C.c_int), ("trace_every", C.c_int), ("no_graph", C.c_int)]
 
 
 class Result(C.Structure):
@@ -75,6 +75,7 @@ def lib():
         L.gosma_solve.argtypes = [vp, C.POINTER(Opts), C.POINTER(Result)]
         L.gosma_solve_batch.argtypes = [vp, C.POINTER(Opts), C.POINTER(Result)]
         L.gosma_set_timing.argtypes = [vp, C.c_int]
+        L.gosma_get_trace.argtypes = [vp, dp, C.c_int64, C.POINTER(C.c_int64)]
         L.gosma_get_timing.argtypes = [vp, dp, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
@@ -219,15 +220,24 @@ class Context:
 
     # -- branch and bound -------------------------------------------------
     def solve(self, eps, batch_parents=4096, max_queue=1 << 24, max_iters=0, time_limit_s=0.0, order=0,
-              log_records=0):
-        o = Opts(eps, batch_parents, max_queue, max_iters, time_limit_s, order, log_records)
+              log_records=0, trace_every=0, no_graph=False):
+        o = Opts(eps, batch_parents, max_queue, max_iters, time_limit_s, order, log_records, trace_every,
+                 int(bool(no_graph)))
         r = Result()
         self._check(lib().gosma_solve(self._h, C.byref(o), C.byref(r)), "gosma_solve")
         return _result_dict(r)
 
+    def trace(self):
+        """Rows {iteration, seconds, cubes, queue, d*, min lb} of the last traced solve."""
+        n = C.c_int64()
+        self._check(lib().gosma_get_trace(self._h, None, 0, C.byref(n)), "gosma_get_trace")
+        buf = np.zeros((max(n.value, 1), 6))
+        self._check(lib().gosma_get_trace(self._h, _d(buf), n.value, C.byref(n)), "gosma_get_trace")
+        return buf[:n.value]
+
     def solve_batch(self, n_problems, eps, batch_parents=2048, max_queue=1 << 22, max_iters=0, time_limit_s=0.0,
-                    order=0):
-        o = Opts(eps, batch_parents, max_queue, max_iters, time_limit_s, order, 0)
+                    order=0, no_graph=False):
+        o = Opts(eps, batch_parents, max_queue, max_iters, time_limit_s, order, 0, 0, int(bool(no_graph)))
         rs = (Result * n_problems)()
         self._check(lib().gosma_solve_batch(self._h, C.byref(o), rs), "gosma_solve_batch")
         return [_result_dict(r) for r in rs]
