@@ -171,6 +171,52 @@ int gosma_get_trace(gosma_ctx *ctx, double *buf, int64_t cap, int64_t *n);
  * n_problems structs.  Synchronous. */
 int gosma_solve_batch(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *results);
 
+/* ------------------------------------------------------------------ */
+/* Learned queue order (not part of the paper's method).               */
+/* ------------------------------------------------------------------ */
+/* A small network, 20 -> 128 -> 128 -> 128 -> 1 with GELU activations,
+ * bf16 weights and FP32 accumulation, predicts for a queued cube how much
+ * the lower bound of its children will exceed its own (in units of S22).
+ * With gosma_opts.order = 1 the queue is ordered by the cube's normalised
+ * lower bound plus that prediction; pruning and the stop test still use the
+ * exact bounds, so the result keeps its eps certificate.
+ *
+ * Features of a cube (20 floats): rotation centre / pi (3); translation
+ * centre mapped to [-1, 1] over the domain box (3); rotation level / 19;
+ * translation level / 19; |rotation half-widths| / pi; |translation
+ * half-widths| / |domain half-widths|; upper and lower bound normalised as
+ * (f + S22) / S22 (clamped to [-10, 10]); the 8 largest S12 pair terms at
+ * the centre / S22.  A training record is the 20 features of a cube followed
+ * by the target: the smallest normalised lower bound of its children minus
+ * its own.
+ * Parameters (GOSMA_MLP_PARAMS floats, row-major): W1 [128 x 20], b1 [128],
+ * W2 [128 x 128], b2, W3 [128 x 128], b3, W4 [1 x 128], b4 [1]. */
+#define GOSMA_MLP_FEATURES 20
+#define GOSMA_MLP_RECORD 21
+#define GOSMA_MLP_PARAMS 35841
+
+/* Random initialisation (He normal weights, zero biases), deterministic per seed. */
+int gosma_mlp_init(gosma_ctx *ctx, uint64_t seed);
+/* Set / read the parameters (host FP32 arrays of GOSMA_MLP_PARAMS). */
+int gosma_mlp_set_params(gosma_ctx *ctx, const float *params);
+int gosma_mlp_get_params(gosma_ctx *ctx, float *params);
+/* Inference: x device n x 20 features, y device n outputs; async on stream. */
+int gosma_mlp_predict(gosma_ctx *ctx, const float *x, int64_t n, float *y, void *stream);
+/* Mean squared error over n device records (n x 21) and its gradient with
+ * respect to the parameters (host array of GOSMA_MLP_PARAMS).  Synchronous. */
+int gosma_mlp_loss_grad(gosma_ctx *ctx, const float *records, int64_t n, double *loss, float *grad);
+/* Train with Adam on n device records: `epochs` passes in minibatches of
+ * `batch` records, shuffled per epoch with `seed`.  loss_per_epoch: NULL or a
+ * host array of `epochs` floats.  Synchronous. */
+int gosma_mlp_train(gosma_ctx *ctx, const float *records, int64_t n, int epochs, int batch, float lr,
+                    uint64_t seed, float *loss_per_epoch);
+/* Record sink of the branch-and-bound (gosma_opts.log_records = 1): when a
+ * cube is split and its children bounded, one record is appended to
+ * `records` (device, capacity x GOSMA_MLP_RECORD floats) and *count (device
+ * uint64) is advanced; records past the capacity are counted but not
+ * written.  The caller owns both buffers and zeroes *count. */
+int gosma_set_record_sink(gosma_ctx *ctx, float *records, int64_t capacity, unsigned long long *count);
+
 /* Kernel timing, for benchmarking.  While enabled, the library records a HIP
  * event pair on the launch stream around each of its kernel launches,
  * grouped by kernel kind (GOSMA_KERNEL_*).  gosma_get_timing() waits for the

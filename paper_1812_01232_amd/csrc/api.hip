@@ -117,6 +117,7 @@ int gosma_create(int device, gosma_ctx **out)
 
 void gosma_release_solver(gosma_ctx *ctx);   // bb.hip
 void gosma_drop_graph(gosma_ctx *ctx);       // bb.hip
+void gosma_release_mlp(gosma_ctx *ctx);      // mlp.hip
 
 void gosma_destroy(gosma_ctx *ctx)
 {
@@ -126,6 +127,7 @@ void gosma_destroy(gosma_ctx *ctx)
     dfree(ctx->d_s11ub);
     dfree(ctx->d_s11lo);
     gosma_release_solver(ctx);
+    gosma_release_mlp(ctx);
     delete ctx;
 }
 
@@ -382,6 +384,21 @@ int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tke
     HIP_TRY(ctx, gosma::launch_s12(mx, rkeys, tkeys, problem, nullptr, ctx->d_s11ub, ctx->d_s11lo, n, nullptr, 1, out,
                                    0.0, ctx->maxM, top8 != nullptr, 0, s));
     ctx->time_end(ti, s);
+    return GOSMA_OK;
+}
+
+int gosma_set_record_sink(gosma_ctx *ctx, float *records, int64_t capacity, unsigned long long *count)
+{
+    if (!ctx) return GOSMA_E_INVAL;
+    ctx->err.clear();
+    if (capacity < 0 || (capacity > 0 && !records) || (records && !count)) {
+        ctx->err = "record sink: records and count must both be set, capacity >= 0";
+        return GOSMA_E_INVAL;
+    }
+    gosma_drop_graph(ctx);    // a captured iteration holds the old sink
+    ctx->rec_sink = records;
+    ctx->rec_cap = capacity;
+    ctx->rec_count = count;
     return GOSMA_OK;
 }
 

@@ -75,6 +75,7 @@ struct Queue {
     double *lb;
     float *prio;
     uint8_t *flags;
+    float *ubn, *t8;   // record logging only: normalised upper bound and top-8 pair terms
 };
 
 __device__ __forceinline__ unsigned long long ord64(double x)
@@ -96,31 +97,6 @@ __device__ __forceinline__ uint32_t key32(float x)
 }
 // A NaN bound is never pruned: it orders like -inf.
 __device__ __forceinline__ double sane_lb(double x) { return x != x ? -INFINITY : x; }
-
-// Block-aggregated append: one atomic per block and call.  Every thread of
-// the block must call it.
-__device__ __forceinline__ uint32_t block_append(uint32_t *counter, bool pred)
-{
-    __shared__ uint32_t wcnt[kBlock / 64], wbase[kBlock / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const unsigned long long mask = __ballot(pred);
-    const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-    if (lane == 0) wcnt[wave] = (uint32_t)__popcll(mask);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t total = 0;
-        for (int w = 0; w < kBlock / 64; ++w) total += wcnt[w];
-        uint32_t base = total ? atomicAdd(counter, total) : 0u;
-        for (int w = 0; w < kBlock / 64; ++w) {
-            wbase[w] = base;
-            base += wcnt[w];
-        }
-    }
-    __syncthreads();
-    const uint32_t r = wbase[wave] + rank;
-    __syncthreads();
-    return r;
-}
 
 // Block-aggregated reservation of cnt consecutive slots per thread.
 __device__ __forceinline__ uint32_t block_reserve(uint32_t *counter, uint32_t cnt)
@@ -187,11 +163,98 @@ struct Bufs {
     uint32_t *hist;               // kHistBins per problem
     PState *st;
     GState *g;
+    // learned order / record logging
+    float *ctop8;                 // children: 8 largest S12 pair terms
+    float *cfeat, *cpred, *cprio; // children: features, network output, priority
+    uint32_t *pchild;             // first child of each parent slot
+    const ProbDesc *prob;
+    float *rec;                   // record sink
+    unsigned long long *rec_count;
+    uint64_t rec_cap;
 };
 
 __device__ __forceinline__ Queue qoff(Queue q, size_t off)
 {
-    return Queue{q.rkey + off, q.tkey + off, q.lb + off, q.prio + off, q.flags + off};
+    return Queue{q.rkey + off, q.tkey + off, q.lb + off, q.prio + off, q.flags + off,
+                 q.ubn ? q.ubn + off : nullptr, q.t8 ? q.t8 + 8 * off : nullptr};
+}
+__device__ __forceinline__ void copy_payload(const Queue &dst, uint32_t d, const Queue &src, uint32_t i)
+{
+    if (dst.ubn) {
+        dst.ubn[d] = src.ubn[i];
+        for (int k = 0; k < 8; ++k) dst.t8[8 * d + k] = src.t8[8 * i + k];
+    }
+}
+
+// Tiled two-way partition of the index range [0, n): classify(i) returns 0
+// (drop), 1 (output A) or 2 (output B); writeA(i, slot) / writeB(i, slot)
+// store the element.  Each block handles tiles of kBlock * kPer elements with
+// one atomic per output per tile; element e of a tile is i = base + e * kBlock
+// + thread, so reads and writes stay coalesced.  All threads must call it.
+constexpr int kPer = 16;
+
+template <class Classify, class WriteA, class WriteB>
+__device__ __forceinline__ void partition_tiles(uint32_t n, uint32_t *cntA, uint32_t *cntB, Classify classify,
+                                                WriteA writeA, WriteB writeB)
+{
+    __shared__ uint32_t wa[kBlock / 64], wb[kBlock / 64], tileA, tileB;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (uint32_t base = blockIdx.x * kBlock * kPer; base < n; base += gridDim.x * kBlock * kPer) {
+        uint32_t ma = 0, mb = 0;
+        for (int e = 0; e < kPer; ++e) {
+            const uint32_t i = base + e * kBlock + threadIdx.x;
+            const int c = i < n ? classify(i) : 0;
+            if (c == 1) ma |= 1u << e;
+            if (c == 2) mb |= 1u << e;
+        }
+        // tile totals -> one atomic per output
+        uint32_t ca = (uint32_t)__popc(ma), cb = (uint32_t)__popc(mb);
+        for (int off = 32; off > 0; off >>= 1) {
+            ca += __shfl_xor(ca, off, 64);
+            cb += __shfl_xor(cb, off, 64);
+        }
+        if (lane == 0) {
+            wa[wave] = ca;
+            wb[wave] = cb;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t ta = 0, tb = 0;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                ta += wa[w];
+                tb += wb[w];
+            }
+            tileA = ta ? atomicAdd(cntA, ta) : 0u;
+            tileB = tb ? atomicAdd(cntB, tb) : 0u;
+        }
+        __syncthreads();
+        uint32_t ra = tileA, rb = tileB;
+        for (int e = 0; e < kPer; ++e) {
+            const bool fa = (ma >> e) & 1u, fb = (mb >> e) & 1u;
+            const unsigned long long ba = __ballot(fa), bb = __ballot(fb);
+            if (lane == 0) {
+                wa[wave] = (uint32_t)__popcll(ba);
+                wb[wave] = (uint32_t)__popcll(bb);
+            }
+            __syncthreads();
+            uint32_t pa = ra, pb = rb, sa = 0, sb = 0;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                if (w < wave) {
+                    pa += wa[w];
+                    pb += wb[w];
+                }
+                sa += wa[w];
+                sb += wb[w];
+            }
+            const uint32_t i = base + e * kBlock + threadIdx.x;
+            const unsigned long long lt = (1ull << lane) - 1ull;
+            if (fa) writeA(i, pa + (uint32_t)__popcll(ba & lt));
+            if (fb) writeB(i, pb + (uint32_t)__popcll(bb & lt));
+            ra += sa;
+            rb += sb;
+            __syncthreads();
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -245,9 +308,27 @@ __global__ __launch_bounds__(kBlock) void k_hist(Bufs b, int rebuild_pass, int p
     for (int part = 0; part < nparts; ++part) {
         const Queue q = part == 0 ? qoff(b.H[s.hcur], (size_t)p * b.hcap) : qoff(b.C[s.ccur], (size_t)p * b.ccap);
         const uint32_t n = part == 0 ? s.nH[s.hcur] : s.nC[s.ccur];
-        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-            const uint32_t key = key32(q.prio[i]);
-            if (pass == 0 || (key >> pshift) == prefix) atomicAdd(&h[(key >> shift) & mask], 1u);
+        const int lane = threadIdx.x & 63;
+        for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+            const uint32_t i = base + threadIdx.x;
+            uint32_t bin = 0;
+            bool m = false;
+            if (i < n) {
+                const uint32_t key = key32(q.prio[i]);
+                m = pass == 0 || (key >> pshift) == prefix;
+                bin = (key >> shift) & mask;
+            }
+            // keys cluster: when every counted lane of the wave hits one bin,
+            // add the count once instead of serialising 64 LDS atomics
+            const unsigned long long all = __ballot(m);
+            if (!all) continue;
+            const int leader = __ffsll((long long)all) - 1;
+            const uint32_t lb = __shfl(bin, leader, 64);
+            if (__ballot(m && bin == lb) == all) {
+                if (lane == leader) atomicAdd(&h[lb], (uint32_t)__popcll(all));
+            } else if (m) {
+                atomicAdd(&h[bin], 1u);
+            }
         }
     }
     __syncthreads();
@@ -321,49 +402,34 @@ __global__ __launch_bounds__(kBlock) void k_rebuild_compact(Bufs b)
     const bool all = s.take_all;
     const Queue Hout = qoff(b.H[s.hcur ^ 1], (size_t)p * b.hcap);
     const Queue Cout = qoff(b.C[s.ccur ^ 1], (size_t)p * b.ccap);
+    const uint32_t hcap = b.hcap, ccap = b.ccap;
     double mh = INFINITY, mc = INFINITY;
     for (int part = 0; part < 2; ++part) {
         const Queue q = part == 0 ? qoff(b.H[s.hcur], (size_t)p * b.hcap) : qoff(b.C[s.ccur], (size_t)p * b.ccap);
         const uint32_t n = part == 0 ? s.nH[s.hcur] : s.nC[s.ccur];
-        for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-            const uint32_t i = base + threadIdx.x;
-            bool hot = false, cold = false;
-            double lb = 0.0;
-            if (i < n) {
-                lb = sane_lb(q.lb[i]);
-                if (lb < dstar) {
-                    const uint32_t key = key32(q.prio[i]);
-                    hot = all || key < T || (key == T && atomicAdd(&s.eq_taken, 1u) < s.eq_quota);
-                    cold = !hot;
-                }
+        auto classify = [&](uint32_t i) -> int {
+            const double lb = sane_lb(q.lb[i]);
+            if (!(lb < dstar)) return 0;
+            const uint32_t key = key32(q.prio[i]);
+            return (all || key < T || (key == T && atomicAdd(&s.eq_taken, 1u) < s.eq_quota)) ? 1 : 2;
+        };
+        auto move = [&](const Queue &o, uint32_t cap, uint32_t i, uint32_t slot, double &mn) {
+            const double lb = sane_lb(q.lb[i]);
+            mn = fmin(mn, lb);
+            if (slot >= cap) {
+                s.overflow = 1;
+                return;
             }
-            const uint32_t ih = block_append(&s.nH[s.hcur ^ 1], hot);
-            const uint32_t ic = block_append(&s.nC[s.ccur ^ 1], cold);
-            if (hot) {
-                if (ih < b.hcap) {
-                    Hout.rkey[ih] = q.rkey[i];
-                    Hout.tkey[ih] = q.tkey[i];
-                    Hout.lb[ih] = lb;
-                    Hout.prio[ih] = q.prio[i];
-                    Hout.flags[ih] = q.flags[i];
-                } else {
-                    s.overflow = 1;
-                }
-                mh = fmin(mh, lb);
-            }
-            if (cold) {
-                if (ic < b.ccap) {
-                    Cout.rkey[ic] = q.rkey[i];
-                    Cout.tkey[ic] = q.tkey[i];
-                    Cout.lb[ic] = lb;
-                    Cout.prio[ic] = q.prio[i];
-                    Cout.flags[ic] = q.flags[i];
-                } else {
-                    s.overflow = 1;
-                }
-                mc = fmin(mc, lb);
-            }
-        }
+            o.rkey[slot] = q.rkey[i];
+            o.tkey[slot] = q.tkey[i];
+            o.lb[slot] = lb;
+            o.prio[slot] = q.prio[i];
+            o.flags[slot] = q.flags[i];
+            copy_payload(o, slot, q, i);
+        };
+        partition_tiles(n, &s.nH[s.hcur ^ 1], &s.nC[s.ccur ^ 1], classify,
+                        [&](uint32_t i, uint32_t slot) { move(Hout, hcap, i, slot, mh); },
+                        [&](uint32_t i, uint32_t slot) { move(Cout, ccap, i, slot, mc); });
     }
     mh = block_min(mh);
     mc = block_min(mc);
@@ -411,37 +477,32 @@ __global__ __launch_bounds__(kBlock) void k_select_compact(Bufs b)
     const Queue q = qoff(b.H[s.hcur], (size_t)p * b.hcap);
     const Queue Hout = qoff(b.H[s.hcur ^ 1], (size_t)p * b.hcap);
     const Queue par = qoff(b.par, (size_t)p * b.k);
-    const uint32_t n = s.nH[s.hcur];
     double mh = INFINITY;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-        const uint32_t i = base + threadIdx.x;
-        bool sel = false, keep = false;
-        double lb = 0.0;
-        if (i < n) {
-            lb = sane_lb(q.lb[i]);
-            if (lb < dstar) {
-                const uint32_t key = key32(q.prio[i]);
-                sel = all || key < T || (key == T && atomicAdd(&s.eq_taken, 1u) < s.eq_quota);
-                keep = !sel;
-            }
-        }
-        const uint32_t is = block_append(&s.nsel, sel);
-        const uint32_t ik = block_append(&s.nH[s.hcur ^ 1], keep);
-        if (sel) {
-            par.rkey[is] = q.rkey[i];
-            par.tkey[is] = q.tkey[i];
-            par.lb[is] = lb;
-            par.flags[is] = q.flags[i];
-        }
-        if (keep) {
-            Hout.rkey[ik] = q.rkey[i];
-            Hout.tkey[ik] = q.tkey[i];
-            Hout.lb[ik] = lb;
-            Hout.prio[ik] = q.prio[i];
-            Hout.flags[ik] = q.flags[i];
+    auto classify = [&](uint32_t i) -> int {
+        const double lb = sane_lb(q.lb[i]);
+        if (!(lb < dstar)) return 0;
+        const uint32_t key = key32(q.prio[i]);
+        return (all || key < T || (key == T && atomicAdd(&s.eq_taken, 1u) < s.eq_quota)) ? 1 : 2;
+    };
+    partition_tiles(
+        s.nH[s.hcur], &s.nsel, &s.nH[s.hcur ^ 1], classify,
+        [&](uint32_t i, uint32_t slot) {
+            par.rkey[slot] = q.rkey[i];
+            par.tkey[slot] = q.tkey[i];
+            par.lb[slot] = sane_lb(q.lb[i]);
+            par.flags[slot] = q.flags[i];
+            copy_payload(par, slot, q, i);
+        },
+        [&](uint32_t i, uint32_t slot) {
+            const double lb = sane_lb(q.lb[i]);
+            Hout.rkey[slot] = q.rkey[i];
+            Hout.tkey[slot] = q.tkey[i];
+            Hout.lb[slot] = lb;
+            Hout.prio[slot] = q.prio[i];
+            Hout.flags[slot] = q.flags[i];
+            copy_payload(Hout, slot, q, i);
             mh = fmin(mh, lb);
-        }
-    }
+        });
     mh = block_min(mh);
     if (threadIdx.x == 0 && mh < INFINITY) atomicMin(&s.minH, ord64(mh));
 }
@@ -473,6 +534,7 @@ __global__ __launch_bounds__(kBlock) void k_branch(Bufs b)
         const uint32_t c0 = block_reserve(&b.g->nchild, valid ? 8u : 0u);
         const uint32_t t0 = block_reserve(&b.g->ntcell, valid ? (one ? 1u : 8u) : 0u);
         if (!valid) continue;
+        b.pchild[(size_t)p * b.k + i] = c0;
         for (int c = 0; c < 8; ++c) {
             const uint32_t ci = c0 + c;
             const uint64_t ck = one ? tk : child_key(tk, c);
@@ -563,6 +625,92 @@ __global__ __launch_bounds__(kBlock) void k_push(Bufs b, const float *prio_overr
         q.lb[slot] = lbs;
         q.prio[slot] = pr;
         q.flags[slot] = fl & GOSMA_FLAG_SPLIT_ROT;
+        if (q.ubn) {
+            const double S22 = b.prob[p].S22;
+            q.ubn[slot] = (float)fmin(fmax((b.cub[i] + S22) / S22, -10.0), 10.0);
+            for (int k = 0; k < 8; ++k) q.t8[8 * slot + k] = b.ctop8[8 * (size_t)i + k];
+        }
+    }
+}
+
+// Features of a cube for the queue-ordering network (layout documented in
+// include/gosma.h): geometry from the keys, normalised bounds, top-8 terms.
+__device__ void cube_features(const ProbDesc &P, uint64_t rk, uint64_t tk, double ubn, double lbn,
+                              const float *t8, float *f)
+{
+    const uint64_t m = (1ull << 19) - 1;
+    const int Lr = key_level(rk), Lt = key_level(tk);
+    const uint64_t ir[3] = {(rk >> 38) & m, (rk >> 19) & m, rk & m};
+    const uint64_t it[3] = {(tk >> 38) & m, (tk >> 19) & m, tk & m};
+    double hr2 = 0.0, ht2 = 0.0, hd2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double hr = ldexp(P.r_w[a], -(Lr + 1)), ht = ldexp(P.t_w[a], -(Lt + 1));
+        const double rc = P.r_lo[a] + (2.0 * (double)ir[a] + 1.0) * hr;
+        const double tc = P.t_lo[a] + (2.0 * (double)it[a] + 1.0) * ht;
+        f[a] = (float)(rc / 3.14159265358979323846);
+        f[3 + a] = (float)(2.0 * (tc - P.t_lo[a]) / P.t_w[a] - 1.0);
+        hr2 += hr * hr;
+        ht2 += ht * ht;
+        hd2 += 0.25 * P.t_w[a] * P.t_w[a];
+    }
+    f[6] = (float)Lr / 19.0f;
+    f[7] = (float)Lt / 19.0f;
+    f[8] = (float)(sqrt(hr2) / 3.14159265358979323846);
+    f[9] = (float)sqrt(ht2 / hd2);
+    f[10] = (float)fmin(fmax(ubn, -10.0), 10.0);
+    f[11] = (float)fmin(fmax(lbn, -10.0), 10.0);
+    for (int k = 0; k < 8; ++k) f[12 + k] = (float)(t8[k] / P.S22);
+}
+
+// Features of every bounded child (input of the learned priority).
+__global__ __launch_bounds__(kBlock) void k_child_features(Bufs b)
+{
+    const uint32_t n = b.g->nchild;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const ProbDesc &P = b.prob[b.cpid[i]];
+        const double lbs = fmax(sane_lb(b.clbs[i]), b.par.lb[b.cpar[i]]);
+        cube_features(P, b.crk[i], b.ctk[i], (b.cub[i] + P.S22) / P.S22, (lbs + P.S22) / P.S22,
+                      b.ctop8 + 8 * (size_t)i, b.cfeat + (size_t)GOSMA_MLP_FEATURES * i);
+    }
+}
+
+// Learned priority: the cube's normalised lower bound plus the predicted rise
+// of its children's; the plain order where the prediction is not finite.
+__global__ __launch_bounds__(kBlock) void k_learned_prio(Bufs b)
+{
+    const uint32_t n = b.g->nchild;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float lbn = b.cfeat[(size_t)GOSMA_MLP_FEATURES * i + 11];
+        const float y = b.cpred[i];
+        b.cprio[i] = isfinite(y) ? lbn + fmaxf(y, 0.0f) : lbn;
+    }
+}
+
+// Training records: for each parent split this iteration, its features (as
+// queued) and the lowest normalised lower bound of its children minus its own.
+__global__ __launch_bounds__(kBlock) void k_log_records(Bufs b, int P)
+{
+    const int p = blockIdx.y;
+    if (p >= P) return;
+    const PState &s = b.st[p];
+    const uint32_t n = s.done ? 0u : s.nsel;
+    const ProbDesc &D = b.prob[p];
+    const Queue par = qoff(b.par, (size_t)p * b.k);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t c0 = b.pchild[(size_t)p * b.k + i];
+        double best = INFINITY;
+        for (int c = 0; c < 8; ++c) {
+            const uint32_t ci = c0 + c;
+            if ((b.cflags[ci] & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS)) || b.cskip[ci]) continue;
+            best = fmin(best, fmax(sane_lb(b.clbs[ci]), par.lb[i]));
+        }
+        if (!(best < INFINITY)) continue;
+        const unsigned long long slot = atomicAdd(b.rec_count, 1ull);
+        if (slot >= b.rec_cap) continue;
+        float *r = b.rec + slot * GOSMA_MLP_RECORD;
+        const double lbn = (par.lb[i] + D.S22) / D.S22;
+        cube_features(D, par.rkey[i], par.tkey[i], par.ubn[i], lbn, par.t8 + 8 * (size_t)i, r);
+        r[GOSMA_MLP_FEATURES] = (float)fmin((best + D.S22) / D.S22 - (double)r[11], 10.0);
     }
 }
 
@@ -624,6 +772,11 @@ __global__ void k_seed(Bufs b, int P)
     q.lb[0] = lbs;
     q.prio[0] = (float)lbs;
     q.flags[0] = fl & GOSMA_FLAG_SPLIT_ROT;
+    if (q.ubn) {
+        const double S22 = b.prob[p].S22;
+        q.ubn[0] = (float)fmin(fmax((b.cub[p] + S22) / S22, -10.0), 10.0);
+        for (int k = 0; k < 8; ++k) q.t8[k] = b.ctop8[8 * (size_t)p + k];
+    }
     s.nH[s.hcur] = 1;
     s.minH = ord64(lbs);
 }
@@ -641,6 +794,8 @@ struct Solver {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_maxM = 0;
+    bool payload = false, learned = false;   // buffers present / captured mode
+    int graph_mode = -1;
 };
 
 }  // namespace gosma
@@ -671,13 +826,16 @@ void free_queue(Queue &q)
     dfree(q.lb);
     dfree(q.prio);
     dfree(q.flags);
+    dfree(q.ubn);
+    dfree(q.t8);
 }
-hipError_t alloc_queue(Queue &q, size_t n)
+hipError_t alloc_queue(Queue &q, size_t n, bool payload)
 {
     hipError_t e;
     if ((e = dalloc(q.rkey, n)) || (e = dalloc(q.tkey, n)) || (e = dalloc(q.lb, n)) || (e = dalloc(q.prio, n)) ||
         (e = dalloc(q.flags, n)))
         return e;
+    if (payload && ((e = dalloc(q.ubn, n)) || (e = dalloc(q.t8, 8 * n)))) return e;
     return hipSuccess;
 }
 
@@ -715,6 +873,11 @@ void free_solver(Solver *s)
     dfree(b.hist);
     dfree(b.st);
     dfree(b.g);
+    dfree(b.ctop8);
+    dfree(b.cfeat);
+    dfree(b.cpred);
+    dfree(b.cprio);
+    dfree(b.pchild);
     if (s->h_st) (void)hipHostFree(s->h_st);
     if (s->h_g) (void)hipHostFree(s->h_g);
     s->h_st = nullptr;
@@ -725,18 +888,25 @@ void free_solver(Solver *s)
     s->k = s->hcap = s->ccap = 0;
 }
 
-hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap)
+hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap, bool payload)
 {
-    if (s->P == P && s->k == k && s->hcap == hcap && s->ccap == ccap && s->b.st) return hipSuccess;
+    if (s->P == P && s->k == k && s->hcap == hcap && s->ccap == ccap && s->b.st && s->payload == payload)
+        return hipSuccess;
     free_solver(s);
     Bufs &b = s->b;
+    b = Bufs{};
     hipError_t e = hipSuccess;
     const size_t nc = 8 * k * (size_t)P + (size_t)P;   // children (+ one root per problem)
     for (int i = 0; i < 2 && !e; ++i) {
-        e = alloc_queue(b.H[i], hcap * P);
-        if (!e) e = alloc_queue(b.C[i], ccap * P);
+        e = alloc_queue(b.H[i], hcap * P, payload);
+        if (!e) e = alloc_queue(b.C[i], ccap * P, payload);
     }
-    if (!e) e = alloc_queue(b.par, k * P);
+    if (!e) e = alloc_queue(b.par, k * P, payload);
+    if (!e) e = dalloc(b.ctop8, 8 * nc);
+    if (!e) e = dalloc(b.cfeat, (size_t)GOSMA_MLP_FEATURES * nc);
+    if (!e) e = dalloc(b.cpred, nc);
+    if (!e) e = dalloc(b.cprio, nc);
+    if (!e) e = dalloc(b.pchild, k * P);
     if (!e) e = dalloc(b.crk, nc);
     if (!e) e = dalloc(b.ctk, nc);
     if (!e) e = dalloc(b.cpid, nc);
@@ -764,6 +934,7 @@ hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap)
     b.hcap = (uint32_t)hcap;
     b.ccap = (uint32_t)ccap;
     b.k = (uint32_t)k;
+    s->payload = payload;
     s->P = P;
     s->k = k;
     s->hcap = hcap;
@@ -780,7 +951,7 @@ unsigned long long ordh(double x)
 
 // Launch one iteration (all problems).  Every launch has a fixed shape and
 // reads its work counts from device memory, so the sequence can be captured.
-hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool timed)
+hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool timed, bool learned, bool logging)
 {
     using namespace gosma;
     Bufs &b = S.b;
@@ -817,14 +988,24 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     T1(ti);
     if (e) return e;
     ti = T0(GOSMA_KERNEL_S12);
-    BoundOut bo{b.cub, b.clb, b.clbs, nullptr, b.cflags, nullptr, nullptr, &b.st->dstar,
+    const bool top8 = learned || logging;
+    BoundOut bo{b.cub, b.clb, b.clbs, nullptr, b.cflags, top8 ? b.ctop8 : nullptr, nullptr, &b.st->dstar,
                 (int)(sizeof(PState) / sizeof(unsigned long long))};
     e = launch_s12(mx, b.crk, b.ctk, b.cpid, b.ctidx, b.s11ub, b.s11lo, maxc, &b.g->nchild, 1, bo, kMarginGamma,
-                   ctx->maxM, false, kBoundGrid, st);
+                   ctx->maxM, top8, kBoundGrid, st);
     T1(ti);
     if (e) return e;
+    if (logging) hipLaunchKernelGGL(k_log_records, dim3(std::max(1, gx / 8), P), dim3(kBlock), 0, st, b, P);
+    if (learned) {
+        ti = T0(GOSMA_KERNEL_MLP);
+        hipLaunchKernelGGL(k_child_features, dim3(kGridX / 2), dim3(kBlock), 0, st, b);
+        e = mlp_predict(*ctx->mlp, b.cfeat, maxc, &b.g->nchild, b.cpred, 512, st);
+        if (e) return e;
+        hipLaunchKernelGGL(k_learned_prio, dim3(kGridX / 2), dim3(kBlock), 0, st, b);
+        T1(ti);
+    }
     ti = T0(GOSMA_KERNEL_PUSH);
-    hipLaunchKernelGGL(k_push, dim3(kGridX), dim3(kBlock), 0, st, b, (const float *)nullptr);
+    hipLaunchKernelGGL(k_push, dim3(kGridX), dim3(kBlock), 0, st, b, learned ? (const float *)b.cprio : nullptr);
     hipLaunchKernelGGL(k_iter_end, dim3((P + 63) / 64), dim3(64), 0, st, b, P);
     T1(ti);
     return hipGetLastError();
@@ -843,7 +1024,10 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
     if (!(opts->eps >= 0) || opts->batch_parents < 1 || opts->batch_parents > (1 << 20) || opts->max_queue < 16 ||
         opts->max_queue > ((int64_t)1 << 31) || (uint64_t)opts->max_queue * P > ((uint64_t)1 << 34))
         return fail(GOSMA_E_INVAL, "invalid options (eps >= 0, 1 <= batch_parents <= 2^20, 16 <= max_queue <= 2^31)");
-    if (opts->order != 0) return fail(GOSMA_E_STATE, "learned order needs a loaded network");
+    const bool learned = opts->order == 1, logging = opts->log_records != 0;
+    if (opts->order != 0 && opts->order != 1) return fail(GOSMA_E_INVAL, "order must be 0 (best-first) or 1 (learned)");
+    if (learned && !ctx->mlp_ready()) return fail(GOSMA_E_STATE, "learned order needs a network (gosma_mlp_init/set_params)");
+    if (logging && !ctx->rec_sink) return fail(GOSMA_E_STATE, "record logging needs gosma_set_record_sink");
     hipError_t e = hipSetDevice(ctx->device);
     if (e) return fail(GOSMA_E_HIP, "hipSetDevice", e);
     ctx->trace.clear();
@@ -854,9 +1038,15 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
     const size_t ccap = (size_t)opts->max_queue;
     const size_t hcap = std::max<size_t>(std::min<size_t>(std::max<size_t>(256 * k, (size_t)1 << 20), ccap),
                                          24 * k + 16);
-    if (S.graph_maxM != ctx->maxM) drop_graph(&S);   // the bound launches depend on the LDS size
-    if ((e = ensure_solver(&S, P, k, hcap, ccap))) return fail(GOSMA_E_NOMEM, "allocating solver buffers", e);
+    const int mode = (learned ? 1 : 0) | (logging ? 2 : 0);
+    if (S.graph_maxM != ctx->maxM || S.graph_mode != mode) drop_graph(&S);   // launches depend on both
+    if ((e = ensure_solver(&S, P, k, hcap, ccap, logging)))
+        return fail(GOSMA_E_NOMEM, "allocating solver buffers", e);
     Bufs &b = S.b;
+    b.prob = ctx->d_prob;
+    b.rec = ctx->rec_sink;
+    b.rec_count = ctx->rec_count;
+    b.rec_cap = (uint64_t)ctx->rec_cap;
     hipStream_t st = S.stream;
 
     // initial state and the root cube of each problem
@@ -880,12 +1070,12 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         return fail(GOSMA_E_HIP, "solver initialisation", e);
     {
         const DevMix mx = ctx->mix();
-        BoundOut bo{b.cub, b.clb, b.clbs, nullptr, b.cflags, nullptr, nullptr, &b.st->dstar,
+        BoundOut bo{b.cub, b.clb, b.clbs, nullptr, b.cflags, b.ctop8, nullptr, &b.st->dstar,
                     (int)(sizeof(PState) / sizeof(unsigned long long))};
         e = launch_s11(mx, b.ctk, b.cpid, P, nullptr, S11Out{b.s11ub, b.s11lo}, ctx->maxM, 0, st);
         if (!e)
             e = launch_s12(mx, b.crk, b.ctk, b.cpid, nullptr, b.s11ub, b.s11lo, P, nullptr, 1, bo, kMarginGamma,
-                           ctx->maxM, false, 0, st);
+                           ctx->maxM, true, 0, st);
         if (!e) {
             hipLaunchKernelGGL(k_seed, dim3((P + 63) / 64), dim3(64), 0, st, b, P);
             e = hipGetLastError();
@@ -902,7 +1092,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
     if (use_graph && !S.exec) {
         e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (!e) {
-            hipError_t le = launch_iteration(ctx, S, st, false);
+            hipError_t le = launch_iteration(ctx, S, st, false, learned, logging);
             e = hipStreamEndCapture(st, &S.graph);
             if (!e) e = le;
         }
@@ -913,6 +1103,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
             use_graph = false;
         } else {
             S.graph_maxM = ctx->maxM;
+            S.graph_mode = mode;
         }
     }
     int rc = GOSMA_OK;
@@ -936,7 +1127,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         if (running == 0) break;
         if (opts->time_limit_s > 0 && el > opts->time_limit_s) break;
         for (int r = 0; r < check && !e; ++r)
-            e = use_graph ? hipGraphLaunch(S.exec, st) : launch_iteration(ctx, S, st, timed);
+            e = use_graph ? hipGraphLaunch(S.exec, st) : launch_iteration(ctx, S, st, timed, learned, logging);
         if (e) {
             rc = fail(GOSMA_E_HIP, "branch-and-bound iteration", e);
             break;

@@ -12,6 +12,7 @@
 namespace gosma {
 
 struct Solver;   // branch-and-bound buffers (bb.hip)
+struct Mlp;      // queue-ordering network (mlp.hip)
 
 // One pose problem as the kernels see it.  Component rows are sorted by class
 // label; classes [cls_off, cls_off + n_cls) of the class table list the row
@@ -72,6 +73,10 @@ hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *t
                       int n_dev_mul, BoundOut out, double margin_gamma, int maxM, bool with_top8, int grid,
                       hipStream_t stream);
 
+struct Mlp;
+hipError_t mlp_predict(const Mlp &m, const float *X, int64_t n, const uint32_t *n_dev, float *y, int grid,
+                       hipStream_t s);
+
 }  // namespace gosma
 
 // The context behind the opaque C handle.
@@ -97,6 +102,11 @@ struct gosma_ctx {
     double *d_s11ub = nullptr, *d_s11lo = nullptr;
 
     gosma::Solver *solver = nullptr;
+    gosma::Mlp *mlp = nullptr;
+    float *rec_sink = nullptr;               // gosma_set_record_sink
+    int64_t rec_cap = 0;
+    unsigned long long *rec_count = nullptr;
+    bool mlp_ready() const;
     std::vector<double> trace;   // 6 doubles per recorded iteration
 
     // kernel timing (gosma_set_timing)
