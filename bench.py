@@ -1,21 +1,25 @@
-"""Benchmark: GOSMA sub-cube bounds per second at 64 x 64 components on one GPU.
+"""Benchmark: sub-cube bounds per second of the GOSMA branch-and-bound at
+64 x 64 components on one MI355X, and time to the eps-optimum with the plain
+best-first queue order against the learned order.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--solve]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-solve]
 
-A step is one pass of the hot path over one 32,768-cube batch of the
-64 x 64 workload (the paper-like scene: 45 projected inliers with 1 degree
-noise + 19 outliers, translation domain [-1, 1]^3 m, full rotation ball):
-for every cube the translation-cell pair sums (S11), the GMM-vMF pair sums
-(S12) and both bounds of Theorem 1.  Inputs are resident in HBM before the
-timed region.  `value` is cube-bounds/s.  With --solve the line also carries
-the time to the eps-optimum of the branch-and-bound, plain best-first
-against the learned queue order.
+Workload (64 x 64, the paper-like scene): 64 Gaussians in a 10 x 10 x 3 m
+room; 45 projected inliers with 1 degree noise + 19 outlier directions;
+translation domain [-1, 1]^3 m, full rotation ball; 4,096 parents popped per
+iteration, i.e. 32,768 sub-cubes bounded per step.
 
-The line carries the roofline of the dominant kernel (GMM-vMF pair sums):
-algorithmic VALU issue slots per launch (op model in the design doc) divided by
-its average launch time measured with HIP events on its own stream, against
-the issue rate of the chip, and the FP64 CPU oracle timed on a bounded sample
-of the same batch on the host's cores.
+A step is one iteration of the search: select the k lowest-bound cubes,
+branch, bound every child (translation-cell sums, GMM-vMF sums, both bounds
+of Theorem 1), update d*, prune and push.  `value` = cubes bounded per second
+over K steps after W warmup steps of the same search, inputs resident in HBM.
+
+Also reported: the bound kernels alone on a 32,768-cube batch, with the
+roofline of the dominant kernel (GMM-vMF pair sums) from its HIP-event launch
+times and the op model in the design doc; the FP64 CPU oracle's own search rate on
+the host's cores; time to eps on the 16 x 16 scene; and time to eps on fresh
+64 x 64 scenes with plain and learned queue order (network trained on records
+logged by the search itself).
 """
 from __future__ import annotations
 
@@ -31,54 +35,148 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Op model (VALU issue slots; a transcendental = 4 slots, everything else 1).
-# Per GMM-vMF pair, upper + lower summand; per unique GMM-GMM pair, both.
 S12_PLAIN, S12_TRANS = 90, 8
-S11_PLAIN, S11_TRANS = 85, 8
 TRANS_SLOTS = 4
 S12_SLOTS = S12_PLAIN + TRANS_SLOTS * S12_TRANS
-S11_SLOTS = S11_PLAIN + TRANS_SLOTS * S11_TRANS
 S12_FLOPS = S12_PLAIN + S12_TRANS + 20      # FMAs counted twice (20 per pair)
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9            # CUs x SIMDs x lanes x clock
 PEAK_FP32_TFLOPS = 157.3
-BATCH = 32768
+BATCH_PARENTS = 4096
+BATCH = 8 * BATCH_PARENTS
 
 
-def bench_batch(scene, n, seed):
-    """A batch shaped like the B&B's: cells from a range of octree levels."""
+def host_cores():
+    try:
+        return min(16, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return min(16, os.cpu_count() or 1)
+
+
+def search_rate(ctx, steps, warmup):
+    """Cubes bounded per second over `steps` iterations of the search after
+    `warmup` iterations, on the product path (captured iteration graph, status
+    read back every few iterations).  Two searches from the root, of `warmup`
+    and `warmup + steps` iterations; the rate is the difference of their
+    bounded-cube counts over the difference of their wall times."""
+    total = warmup + steps
+    kw = dict(batch_parents=BATCH_PARENTS, max_queue=1 << 27)
+    ctx.solve(1e-9, max_iters=warmup, **kw)            # captures the iteration graph
+    a = ctx.solve(1e-9, max_iters=warmup, **kw)
+    b = ctx.solve(1e-9, max_iters=total, **kw)
+    assert a["iters"] == warmup and b["iters"] == total, (a["iters"], b["iters"])
+    dt = b["seconds"] - a["seconds"]
+    cubes = b["cubes"] - a["cubes"]
+    # per-kernel split of the same iterations (direct launches with HIP events)
+    ctx.get_timing()
+    ctx.set_timing(True)
+    ctx.solve(1e-9, max_iters=total, **kw)
+    ctx.set_timing(False)
+    kt = ctx.get_timing()
+    return cubes / dt, dt / steps * 1e3, kt, b, b["max_queue_used"]
+
+
+def kernel_rate(ctx, scene, reps):
+    """Bound kernels alone on one 32,768-cube batch (cells across levels 2-12 / 1-10)."""
+    import torch
     from synth import scenes
-    return scenes.random_cubes(scene, n, seed, r_levels=(2, 12), t_levels=(1, 10))
+    dev = torch.device("cuda", 0)
+    rk_np, tk_np = scenes.random_cubes(scene, BATCH, 2600, r_levels=(2, 12), t_levels=(1, 10))
+    rk = torch.from_numpy(rk_np.view(np.int64)).to(dev)
+    tk = torch.from_numpy(tk_np.view(np.int64)).to(dev)
+    ub = torch.empty(BATCH, dtype=torch.float64, device=dev)
+    lb = torch.empty(BATCH, dtype=torch.float64, device=dev)
+    fl = torch.empty(BATCH, dtype=torch.uint8, device=dev)
+    for _ in range(2):
+        ctx.eval_bounds(rk, tk, ub, lb, fl)
+    torch.cuda.synchronize()
+    ctx.get_timing()
+    ctx.set_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.eval_bounds(rk, tk, ub, lb, fl)
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.set_timing(False)
+    kt = ctx.get_timing()
+    live = int(((fl.cpu().numpy() & 6) == 0).sum())
+    return BATCH * reps / (e0.elapsed_time(e1) / 1e3), kt, live, rk_np, tk_np
 
 
-def cpu_baseline(scene, rk, tk, budget_s=15.0):
+def cpu_baseline(scene, budget_s=15.0):
+    """The FP64 oracle's own branch-and-bound on the same scene, bounded in time."""
     import oracle
     P = oracle.OracleProblem(scene)
-    try:
-        cores = min(16, len(os.sched_getaffinity(0)))
-    except AttributeError:
-        cores = min(16, os.cpu_count() or 1)
-    probe = 256
-    t = time.perf_counter()
-    P.bounds(rk[:probe], tk[:probe], nthreads=cores)
-    rate = probe / (time.perf_counter() - t)
-    n = int(min(len(rk), max(probe, rate * budget_s)))
-    t = time.perf_counter()
-    P.bounds(rk[:n], tk[:n], nthreads=cores)
-    dt = time.perf_counter() - t
-    return {"value": n / dt, "unit": "cube-bounds/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n} cubes of the timed 64x64 batch (FP64, OpenMP over cubes, {dt:.1f} s)"}
+    cores = host_cores()
+    r = P.solve(1e-9, BATCH_PARENTS, time_limit_s=budget_s, nthreads=cores)
+    return {"value": r["cubes"] / r["seconds"], "unit": "cube-bounds/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle best-first search on the same 64x64 scene and batch size, stopped after "
+                      f"{r['seconds']:.1f} s ({r['cubes']} cubes, {r['iters']} iterations)"}
+
+
+def learned_comparison(ctx, n_eval, eps, records_cap, epochs, time_cap):
+    """Log records from searches, train the network on them, then time to eps
+    with plain and learned order on fresh 64x64 scenes."""
+    import torch
+    from synth import scenes
+    dev = torch.device("cuda", 0)
+    recs = torch.zeros((records_cap, 21), dtype=torch.float32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    ctx.set_record_sink(recs, cnt)
+    t0 = time.perf_counter()
+    i = 0
+    while int(cnt.item()) < records_cap and i < 12:
+        for sc in (scenes.cfg1_scene(10 + i), scenes.cfg2_scene(10 + i)):
+            ctx.set_scene(sc)
+            ctx.solve(eps, batch_parents=BATCH_PARENTS, max_queue=1 << 26, time_limit_s=6, log_records=1)
+        i += 1
+    ctx.set_record_sink(None, None)
+    n = min(int(cnt.item()), records_cap)
+    collect_s = time.perf_counter() - t0
+    g = torch.Generator(device=dev)
+    g.manual_seed(0)
+    perm = torch.randperm(n, device=dev, generator=g)
+    ntr = int(0.95 * n)
+    tr, te = recs[perm[:ntr]].contiguous(), recs[perm[ntr:]].contiguous()
+    ctx.mlp_init(0)
+    t0 = time.perf_counter()
+    hist = ctx.mlp_train(records=tr, epochs=epochs, batch=4096, lr=1e-3, seed=1)
+    train_s = time.perf_counter() - t0
+    yp = ctx.mlp_predict(te[:, :20].cpu().numpy())
+    yt = te[:, 20].cpu().numpy()
+    out = {"records": n, "collect_s": collect_s, "train_s": train_s, "train_loss": [float(h) for h in hist],
+           "heldout_mae": float(np.mean(np.abs(yp - yt))), "heldout_mae_mean_predictor": float(np.mean(np.abs(yt - yt.mean()))),
+           "eps": eps, "scenes": []}
+    for k in range(n_eval):
+        sc = scenes.cfg2_scene(seed=5000 + k)
+        ctx.set_scene(sc)
+        row = {"seed": 5000 + k}
+        for name, kw in (("plain", {}), ("learned", {"order": 1, "learned_window": eps})):
+            r = ctx.solve(eps, batch_parents=BATCH_PARENTS, max_queue=1 << 27, time_limit_s=time_cap, **kw)
+            row[name] = {"status": r["status"], "seconds": r["seconds"], "cubes": r["cubes"],
+                         "f_norm": r["f_norm_best"], "lb_norm": r["lb_norm"]}
+        out["scenes"].append(row)
+    for name in ("plain", "learned"):
+        t = np.array([s[name]["seconds"] for s in out["scenes"]])
+        out[f"{name}_median_s"] = float(np.median(t))
+        out[f"{name}_iqr_s"] = [float(np.percentile(t, 25)), float(np.percentile(t, 75))]
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--solve", action="store_true")
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-eps runs")
+    ap.add_argument("--learned-scenes", type=int, default=3)
+    ap.add_argument("--records", type=int, default=1_000_000)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU split is design-only "
-                                   "(see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; how the search would shard over "
+                                   "several GPUs is described in DESIGN.md", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
@@ -86,51 +184,25 @@ def main():
     from synth import scenes
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda", 0)
     scene = scenes.cfg2_scene(0)
-    rk_np, tk_np = bench_batch(scene, BATCH, 2600)
     ctx = Context(0)
     ctx.set_scene(scene)
-    rk = torch.from_numpy(rk_np.view(np.int64)).to(dev)
-    tk = torch.from_numpy(tk_np.view(np.int64)).to(dev)
-    ub = torch.empty(BATCH, dtype=torch.float64, device=dev)
-    lb = torch.empty(BATCH, dtype=torch.float64, device=dev)
-    fl = torch.empty(BATCH, dtype=torch.uint8, device=dev)
-
-    def step():
-        ctx.eval_bounds(rk, tk, ub, lb, fl)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.get_timing()
-    ctx.set_timing(True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    ctx.set_timing(False)
-    kt = ctx.get_timing()
-    total_ms = e0.elapsed_time(e1)
-    ms_step = total_ms / args.steps
-    flags = fl.cpu().numpy()
-    live = int(((flags & 6) == 0).sum())
     M, N = scene.M, scene.N
-    pairs = live * (M * N + M * (M + 1) // 2) * 2
-    value = BATCH * args.steps / (total_ms / 1e3)
 
+    # whole hot path: the search itself
+    torch.cuda.synchronize()
+    value, ms_step, kt_search, r_search, queue = search_rate(ctx, args.steps, args.warmup)
+    torch.cuda.synchronize()
+
+    # bound kernels alone + roofline of the GMM-vMF pair kernel
+    krate, kt, live, rk_np, tk_np = kernel_rate(ctx, scene, 10)
     s12_ms, s12_n = kt["s12"]
-    s11_ms, s11_n = kt["s11"]
     s12_avg_s = s12_ms / s12_n / 1e3
-    slots = live * M * N * S12_SLOTS
-    achieved = slots / s12_avg_s / 1e12
+    achieved = live * M * N * S12_SLOTS / s12_avg_s / 1e12
     peak = PEAK_SLOTS / 1e12
+
     rec = {
-        "metric": "sub-cube bounds/s at 64x64 comps",
+        "metric": "sub-cube bounds/s at 64x64 comps; time-to-eps-optimum plain vs learned order",
         "value": value,
         "unit": "cube-bounds/s",
         "n_gpus": 1,
@@ -142,18 +214,29 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "64x64 paper-like scene (45 noisy inliers + 19 outliers), 32768-cube batch",
-                   "M": M, "N": N, "batch_cubes": BATCH, "live_cubes": live},
-        "pair_terms_per_s": pairs * args.steps / (total_ms / 1e3),
-        "kernels_ms_per_launch": {"s12": s12_ms / s12_n, "s11": s11_ms / s11_n},
+        "config": {"workload": "64x64 paper-like scene (45 noisy inliers + 19 outliers), branch-and-bound with "
+                               "4096 parents = 32768 sub-cubes per step",
+                   "M": M, "N": N, "batch_cubes": BATCH, "queue_after_steps": queue},
+        "pair_terms_per_s": value * (M * N + M * (M - 1) // 2) * 2,
+        "search_kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt_search.items() if v[1]},
+        "bound_kernels_only": {"cube_bounds_per_s": krate, "live_cubes": live,
+                               "ms_per_launch": {"s12": s12_ms / s12_n, "s11": kt["s11"][0] / kt["s11"][1]}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "k_s12 (GMM-vMF pair sums)",
+                     "frac": achieved / peak, "traffic": None, "kernel": "k_s12 (GMM-vMF pair sums)",
                      "fp32_tflops": live * M * N * S12_FLOPS / s12_avg_s / 1e12,
                      "fp32_peak_tflops": PEAK_FP32_TFLOPS},
     }
+    if not args.no_solve:
+        sc1 = scenes.cfg1_scene(0)
+        ctx.set_scene(sc1)
+        r1 = ctx.solve(1e-3, batch_parents=BATCH_PARENTS, max_queue=1 << 28, time_limit_s=120)
+        rec["time_to_eps_16x16"] = {"eps": 1e-3, "status": r1["status"], "seconds": r1["seconds"],
+                                    "cubes": r1["cubes"], "f_norm": r1["f_norm_best"], "lb_norm": r1["lb_norm"]}
+        if args.learned_scenes > 0:
+            rec["time_to_eps_64x64_plain_vs_learned"] = learned_comparison(
+                ctx, args.learned_scenes, 1e-2, args.records, 4, 60)
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(scene, rk_np, tk_np)
+        rec["cpu_baseline"] = cpu_baseline(scene)
     ctx.close()
     print(json.dumps(rec), flush=True)
 

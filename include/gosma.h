@@ -139,6 +139,8 @@ typedef struct {
     int trace_every;         /* > 0: record the search state every n-th iteration (gosma_get_trace) */
     int no_graph;            /* 1: launch each iteration's kernels directly instead of replaying
                                 a captured HIP graph of one iteration */
+    double learned_window;   /* order = 1: the predicted rise added to a cube's normalised lower
+                                bound is clamped to [0, learned_window]; <= 0: not clamped */
 } gosma_opts;
 
 typedef struct {

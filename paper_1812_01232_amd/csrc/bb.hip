@@ -676,13 +676,14 @@ __global__ __launch_bounds__(kBlock) void k_child_features(Bufs b)
 
 // Learned priority: the cube's normalised lower bound plus the predicted rise
 // of its children's; the plain order where the prediction is not finite.
-__global__ __launch_bounds__(kBlock) void k_learned_prio(Bufs b)
+__global__ __launch_bounds__(kBlock) void k_learned_prio(Bufs b, float window)
 {
     const uint32_t n = b.g->nchild;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const float lbn = b.cfeat[(size_t)GOSMA_MLP_FEATURES * i + 11];
         const float y = b.cpred[i];
-        b.cprio[i] = isfinite(y) ? lbn + fmaxf(y, 0.0f) : lbn;
+        const float rise = window > 0.0f ? fminf(fmaxf(y, 0.0f), window) : fmaxf(y, 0.0f);
+        b.cprio[i] = isfinite(y) ? lbn + rise : lbn;
     }
 }
 
@@ -794,8 +795,9 @@ struct Solver {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_maxM = 0;
-    bool payload = false, learned = false;   // buffers present / captured mode
-    int graph_mode = -1;
+    bool payload = false;     // logging payload buffers present
+    int graph_mode = -1;      // captured mode: learned | logging
+    float graph_window = 0.0f;
 };
 
 }  // namespace gosma
@@ -951,7 +953,8 @@ unsigned long long ordh(double x)
 
 // Launch one iteration (all problems).  Every launch has a fixed shape and
 // reads its work counts from device memory, so the sequence can be captured.
-hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool timed, bool learned, bool logging)
+hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool timed, bool learned, bool logging,
+                            float window)
 {
     using namespace gosma;
     Bufs &b = S.b;
@@ -1001,7 +1004,7 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
         hipLaunchKernelGGL(k_child_features, dim3(kGridX / 2), dim3(kBlock), 0, st, b);
         e = mlp_predict(*ctx->mlp, b.cfeat, maxc, &b.g->nchild, b.cpred, 512, st);
         if (e) return e;
-        hipLaunchKernelGGL(k_learned_prio, dim3(kGridX / 2), dim3(kBlock), 0, st, b);
+        hipLaunchKernelGGL(k_learned_prio, dim3(kGridX / 2), dim3(kBlock), 0, st, b, window);
         T1(ti);
     }
     ti = T0(GOSMA_KERNEL_PUSH);
@@ -1038,8 +1041,10 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
     const size_t ccap = (size_t)opts->max_queue;
     const size_t hcap = std::max<size_t>(std::min<size_t>(std::max<size_t>(256 * k, (size_t)1 << 20), ccap),
                                          24 * k + 16);
+    const float window = (float)opts->learned_window;
     const int mode = (learned ? 1 : 0) | (logging ? 2 : 0);
-    if (S.graph_maxM != ctx->maxM || S.graph_mode != mode) drop_graph(&S);   // launches depend on both
+    if (S.graph_maxM != ctx->maxM || S.graph_mode != mode || S.graph_window != window)
+        drop_graph(&S);   // the captured launches depend on these
     if ((e = ensure_solver(&S, P, k, hcap, ccap, logging)))
         return fail(GOSMA_E_NOMEM, "allocating solver buffers", e);
     Bufs &b = S.b;
@@ -1092,7 +1097,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
     if (use_graph && !S.exec) {
         e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (!e) {
-            hipError_t le = launch_iteration(ctx, S, st, false, learned, logging);
+            hipError_t le = launch_iteration(ctx, S, st, false, learned, logging, window);
             e = hipStreamEndCapture(st, &S.graph);
             if (!e) e = le;
         }
@@ -1104,6 +1109,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         } else {
             S.graph_maxM = ctx->maxM;
             S.graph_mode = mode;
+            S.graph_window = window;
         }
     }
     int rc = GOSMA_OK;
@@ -1127,7 +1133,8 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         if (running == 0) break;
         if (opts->time_limit_s > 0 && el > opts->time_limit_s) break;
         for (int r = 0; r < check && !e; ++r)
-            e = use_graph ? hipGraphLaunch(S.exec, st) : launch_iteration(ctx, S, st, timed, learned, logging);
+            e = use_graph ? hipGraphLaunch(S.exec, st)
+                          : launch_iteration(ctx, S, st, timed, learned, logging, window);
         if (e) {
             rc = fail(GOSMA_E_HIP, "branch-and-bound iteration", e);
             break;

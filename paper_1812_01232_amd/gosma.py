@@ -22,7 +22,10 @@ FLAG_SPLIT_ROT, FLAG_DROP_ROT, FLAG_DROP_TRANS, FLAG_UB_INF = 1, 2, 4, 8
 
 EXPORTS = ["gosma_create", "gosma_destroy", "gosma_last_error", "gosma_set_mixtures", "gosma_set_domain",
            "gosma_set_problems", "gosma_get_S22", "gosma_eval_bounds", "gosma_solve", "gosma_solve_batch",
-           "gosma_set_timing", "gosma_get_timing", "gosma_get_trace"]
+           "gosma_set_timing", "gosma_get_timing", "gosma_get_trace", "gosma_mlp_init", "gosma_mlp_set_params",
+           "gosma_mlp_get_params", "gosma_mlp_predict", "gosma_mlp_loss_grad", "gosma_mlp_train",
+           "gosma_set_record_sink"]
+MLP_FEATURES, MLP_RECORD, MLP_PARAMS = 20, 21, 35841
 KERNEL_KINDS = ["s11", "s12", "select", "branch", "push", "mlp"]
 
 
@@ -40,7 +43,8 @@ class Domain(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("batch_parents", C.c_int64), ("max_queue", C.c_int64),
                 ("max_iters", C.c_int64), ("time_limit_s", C.c_double), ("order", C.c_int),
-                ("log_records", C.c_int), ("trace_every", C.c_int), ("no_graph", C.c_int)]
+                ("log_records", C.c_int), ("trace_every", C.c_int), ("no_graph", C.c_int),
+                ("learned_window", C.c_double)]
 
 
 class Result(C.Structure):
@@ -76,6 +80,14 @@ def lib():
         L.gosma_solve_batch.argtypes = [vp, C.POINTER(Opts), C.POINTER(Result)]
         L.gosma_set_timing.argtypes = [vp, C.c_int]
         L.gosma_get_trace.argtypes = [vp, dp, C.c_int64, C.POINTER(C.c_int64)]
+        fp = C.POINTER(C.c_float)
+        L.gosma_mlp_init.argtypes = [vp, C.c_uint64]
+        L.gosma_mlp_set_params.argtypes = [vp, fp]
+        L.gosma_mlp_get_params.argtypes = [vp, fp]
+        L.gosma_mlp_predict.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.gosma_mlp_loss_grad.argtypes = [vp, vp, C.c_int64, dp, fp]
+        L.gosma_mlp_train.argtypes = [vp, vp, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_uint64, fp]
+        L.gosma_set_record_sink.argtypes = [vp, vp, C.c_int64, vp]
         L.gosma_get_timing.argtypes = [vp, dp, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
@@ -207,6 +219,60 @@ class Context:
             out["top8"] = t8.cpu().numpy()
         return out
 
+    # -- queue-ordering network -------------------------------------------
+    def mlp_init(self, seed=0):
+        self._check(lib().gosma_mlp_init(self._h, int(seed)), "gosma_mlp_init")
+
+    def mlp_set_params(self, theta):
+        p = np.ascontiguousarray(theta, dtype=np.float32)
+        assert p.size == MLP_PARAMS
+        self._check(lib().gosma_mlp_set_params(self._h, p.ctypes.data_as(C.POINTER(C.c_float))), "gosma_mlp_set_params")
+
+    def mlp_get_params(self):
+        p = np.zeros(MLP_PARAMS, dtype=np.float32)
+        self._check(lib().gosma_mlp_get_params(self._h, p.ctypes.data_as(C.POINTER(C.c_float))), "gosma_mlp_get_params")
+        return p
+
+    def _dev(self, a):
+        import torch
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.device("cuda", self.device))
+
+    def mlp_predict(self, X):
+        import torch
+        x = self._dev(X)
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        self._check(lib().gosma_mlp_predict(self._h, _ptr(x), x.shape[0], _ptr(y), _current_stream()),
+                    "gosma_mlp_predict")
+        torch.cuda.synchronize(x.device)
+        return y.cpu().numpy().astype(np.float64)
+
+    def mlp_loss_grad(self, X, t):
+        import torch
+        rec = self._dev(np.concatenate([np.asarray(X), np.asarray(t)[:, None]], axis=1))
+        torch.cuda.synchronize(rec.device)
+        loss = C.c_double()
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        self._check(lib().gosma_mlp_loss_grad(self._h, _ptr(rec), rec.shape[0], C.byref(loss),
+                                              g.ctypes.data_as(C.POINTER(C.c_float))), "gosma_mlp_loss_grad")
+        return loss.value, g.astype(np.float64)
+
+    def mlp_train(self, X=None, t=None, records=None, epochs=10, batch=4096, lr=1e-3, seed=0):
+        """Train on records (device tensor n x 21) or on host arrays X, t."""
+        import torch
+        if records is None:
+            records = self._dev(np.concatenate([np.asarray(X), np.asarray(t)[:, None]], axis=1))
+        torch.cuda.synchronize(records.device)
+        hist = np.zeros(max(int(epochs), 1), dtype=np.float32)
+        self._check(lib().gosma_mlp_train(self._h, _ptr(records), int(records.shape[0]), int(epochs), int(batch),
+                                          float(lr), int(seed), hist.ctypes.data_as(C.POINTER(C.c_float))),
+                    "gosma_mlp_train")
+        return hist.astype(np.float64)
+
+    def set_record_sink(self, records, count):
+        """records: device float32 tensor [capacity, 21]; count: device int64 tensor [1] (zeroed)."""
+        cap = 0 if records is None else int(records.shape[0])
+        self._check(lib().gosma_set_record_sink(self._h, _ptr(records), cap, _ptr(count)), "gosma_set_record_sink")
+
     # -- kernel timing ----------------------------------------------------
     def set_timing(self, enable=True):
         self._check(lib().gosma_set_timing(self._h, int(bool(enable))), "gosma_set_timing")
@@ -220,9 +286,9 @@ class Context:
 
     # -- branch and bound -------------------------------------------------
     def solve(self, eps, batch_parents=4096, max_queue=1 << 24, max_iters=0, time_limit_s=0.0, order=0,
-              log_records=0, trace_every=0, no_graph=False):
+              log_records=0, trace_every=0, no_graph=False, learned_window=0.0):
         o = Opts(eps, batch_parents, max_queue, max_iters, time_limit_s, order, log_records, trace_every,
-                 int(bool(no_graph)))
+                 int(bool(no_graph)), float(learned_window))
         r = Result()
         self._check(lib().gosma_solve(self._h, C.byref(o), C.byref(r)), "gosma_solve")
         return _result_dict(r)
@@ -236,8 +302,9 @@ class Context:
         return buf[:n.value]
 
     def solve_batch(self, n_problems, eps, batch_parents=2048, max_queue=1 << 22, max_iters=0, time_limit_s=0.0,
-                    order=0, no_graph=False):
-        o = Opts(eps, batch_parents, max_queue, max_iters, time_limit_s, order, 0, 0, int(bool(no_graph)))
+                    order=0, no_graph=False, learned_window=0.0):
+        o = Opts(eps, batch_parents, max_queue, max_iters, time_limit_s, order, 0, 0, int(bool(no_graph)),
+                 float(learned_window))
         rs = (Result * n_problems)()
         self._check(lib().gosma_solve_batch(self._h, C.byref(o), rs), "gosma_solve_batch")
         return [_result_dict(r) for r in rs]

@@ -134,3 +134,30 @@ def test_batch_solve_matches_single(ctx):
         assert abs(many["cubes"] - one["cubes"]) <= 0.02 * one["cubes"]
         assert abs(many["f_norm_best"] - one["f_norm_best"]) <= 1e-2
         assert many["lb_norm"] <= one["f_norm_best"] and one["lb_norm"] <= many["f_norm_best"]
+
+
+def test_learned_order_keeps_certificate_and_logs_records(ctx):
+    """With the learned queue order the result is still eps-certified; record
+    logging writes finite features and non-negative targets."""
+    sc = scenes.small_scene(6, 6, seed=88)
+    ctx.set_scene(sc)
+    plain = ctx.solve(1e-2, batch_parents=256)
+    recs = torch.zeros((200000, 21), dtype=torch.float32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ctx.set_record_sink(recs, cnt)
+    logged = ctx.solve(1e-2, batch_parents=256, log_records=1)
+    n = int(cnt.item())
+    assert n > 1000
+    R = recs[:min(n, 200000)].cpu().numpy()
+    assert np.all(np.isfinite(R))
+    assert np.all(R[:, 20] >= -1e-6)
+    assert abs(logged["cubes"] - plain["cubes"]) <= 0.02 * plain["cubes"]
+    ctx.mlp_init(0)
+    ctx.mlp_train(records=recs[:min(n, 200000)], epochs=3, batch=1024, lr=1e-3)
+    learned = ctx.solve(1e-2, batch_parents=256, order=1, learned_window=1e-2, max_queue=1 << 26,
+                        time_limit_s=120)
+    assert learned["status"] == 0
+    assert learned["f_norm_best"] - learned["lb_norm"] <= 1e-2
+    assert abs(learned["f_norm_best"] - plain["f_norm_best"]) <= 1e-2
+    assert learned["lb_norm"] <= plain["f_norm_best"] and plain["lb_norm"] <= learned["f_norm_best"]
+    ctx.set_record_sink(None, None)
