@@ -80,7 +80,9 @@ const char *gosma_last_error(const gosma_ctx *ctx);
  * both to use one class.  With labels only same-class pairs contribute and
  * the objective is sum_l f_l / n_labels, the weights being renormalised
  * within each class; without labels the weights are renormalised to sum 1.
- * All arrays are host FP64/int32 and are copied.  1 <= M, N <= 1024. */
+ * All arrays are host FP64/int32 and are copied.  1 <= M, N <= 1024, and
+ * 64 M + 32 N + 1024 bytes must fit in one block's LDS (GOSMA_E_INVAL
+ * otherwise; 160 KB on gfx950). */
 int gosma_set_mixtures(gosma_ctx *ctx, int M, const double *mu, const double *sigma, const double *phi1,
                        const int32_t *label1, int N, const double *dir2, const double *kappa2,
                        const double *phi2, const int32_t *label2, int n_labels);
@@ -218,6 +220,42 @@ int gosma_mlp_train(gosma_ctx *ctx, const float *records, int64_t n, int epochs,
  * uint64) is advanced; records past the capacity are counted but not
  * written.  The caller owns both buffers and zeroes *count. */
 int gosma_set_record_sink(gosma_ctx *ctx, float *records, int64_t capacity, unsigned long long *count);
+
+/* ------------------------------------------------------------------ */
+/* Launch shapes of the bound kernels.                                  */
+/* ------------------------------------------------------------------ */
+/* Each bound kernel gives one cell (a translation cell for the GMM-GMM sums,
+ * a rotation x translation cube for the GMM-vMF sums and the bounds) to one
+ * block of 64 * waves threads, which stages the cell's per-component values
+ * in LDS and shares its pair sums; a grid of `blocks` blocks walks the
+ * cells.  Results agree between shapes up to FP64 summation order. */
+typedef struct {
+    int32_t waves;    /* 1, 2 or 4 */
+    int32_t blocks;   /* >= 1 */
+} gosma_tile;
+
+typedef struct {
+    gosma_tile s11;   /* GMM-GMM sums (GOSMA_KERNEL_S11) */
+    gosma_tile s12;   /* GMM-vMF sums and bounds (GOSMA_KERNEL_S12) */
+} gosma_tiles;
+
+/* Current shapes (host struct out).  gosma_set_problems resets them to a
+ * default chosen from the largest M and N. */
+int gosma_get_tiles(gosma_ctx *ctx, gosma_tiles *out);
+/* Set the shapes (host struct in).  GOSMA_E_INVAL for waves outside
+ * {1, 2, 4} or blocks < 1. */
+int gosma_set_tiles(gosma_ctx *ctx, const gosma_tiles *tiles);
+/* Autotuner: draws n_cubes random cubes of the current problems (levels 2-10
+ * in rotation, 1-8 in translation, inside the rotation ball; deterministic
+ * per seed), times every candidate shape of both kernels on them with HIP
+ * events (waves 1, 2, 4 x grids of 2048, 4096, 8192, 16384 waves; one
+ * warm-up and three timed launches each), and keeps the fastest.  rows:
+ * NULL or a host array of cap x 4 doubles receiving {kernel (GOSMA_KERNEL_S11
+ * or GOSMA_KERNEL_S12), waves, blocks, ms per launch} per candidate; *n_rows
+ * (if not NULL) receives the number of candidates.  chosen: NULL or the
+ * shapes kept.  Synchronous; allocates and frees its own device buffers. */
+int gosma_autotune(gosma_ctx *ctx, int64_t n_cubes, uint64_t seed, double *rows, int64_t cap, int64_t *n_rows,
+                   gosma_tiles *chosen);
 
 /* Kernel timing, for benchmarking.  While enabled, the library records a HIP
  * event pair on the launch stream around each of its kernel launches,

@@ -296,8 +296,10 @@ static double g_da(double a, double b, double th)
  * appendix that is not available.  Reading used here: over the cube,
  * kappa_1i(t) is relaxed to the interval [lo, hi] it takes there, and the
  * extremum of the summand over the interval (or, for the S11 sum, over the
- * box of two intervals) is bounded by a second-order expansion at the interval
- * centre with a certified remainder.  With L as above:
+ * box of two intervals) is bounded with certified second-order remainders:
+ * for the S11 minimum an expansion at the box centre, for the S12 maximum the
+ * exact end values of the convex part K - a - b and expansions of the rest at
+ * the interval ends.  With L as above:
  *   d^2 log Z(K) / da^2 = L'(K) K_a^2 + L(K) K_aa,  K_a^2 <= 1,
  *   K_aa = b^2 sin^2(theta) / K^3 >= 0,  L'(K) <= min(1/3, 1/K^2),
  *   L(K) K_aa <= min(1/3, b^2 sin^2(theta) / K^3)  (as L(K) <= K/3, K >= b sin theta),
@@ -319,25 +321,43 @@ static double s11_lower_log(double alo, double ahi, double blo, double bhi, doub
 }
 
 /* S12 summand (eq. 21, second sum) at angle B with b = kappa_2j fixed: the
- * ratio Z(K)/(Z(a) Z(b)) maximised over a in [alo, ahi], bounded by the
- * smaller of
- *   exp(g(ac) + |g_a(ac)| h + (G/2) h^2), with G an upper bound on g'' over
- *     the interval: K is 1-Lipschitz in a, so K >= K(ac)/2 there when
- *     h <= K(ac)/2, giving G = min(1/3, 4/K(ac)^2) + min(1/3, 8 (b sin B)^2/K(ac)^3);
- *     otherwise G = 2/3,
- * and the value for perfectly aligned directions,
+ * ratio Z(K)/(Z(a) Z(b)) maximised over a in [alo, ahi].  Split
+ *   g(a) = log Z(K) - log Z(a) - log Z(b) = x(a) + phi(a),
+ *   x(a) = K(a) - a - b,   phi(a) = l(K(a)) - l(a) - l(b),   l(y) = log Z(y) - y.
+ * x is convex in a (K is the norm of a u + b v for unit vectors u, v at angle
+ * B).  phi has phi'' = L'(K) K_a^2 + (L(K) - 1) K_aa - L'(a) <= min(1/3, 1/K^2)
+ * (the last two terms are <= 0), so with Kmin the smallest K on the interval
+ * (at an end, or b sin B where a = -b cos B lies inside) and G =
+ * min(1/3, 1/Kmin^2), a second-order expansion of phi at either end e gives
+ *   g(a) <= x(a) + phi(e) + phi'(e)(a - e) + G (a - e)^2 / 2,
+ * a convex function of a whose maximum is at one of the two ends.  The bound
+ * is the smaller of the two expansions and of the value for perfectly aligned
+ * directions,
  *   Z(a + b)/(Z(a) Z(b)) = a b (coth a + coth b) / (2 (a + b)) <= min(ahi, b)(coth alo + coth b)/2,
  * which bounds every angle since Z increases and K <= a + b. */
+static double ell(double y) { return oracle_log_Z(y) - y; }
+
 static double s12_upper_term(double alo, double ahi, double b, double B)
 {
-    double ac = 0.5 * (alo + ahi), h = 0.5 * (ahi - alo);
-    double bs = b * sin(B);
-    double Kc = Kab(ac, b, B);
-    double G = h <= 0.5 * Kc ? fmin(1.0 / 3.0, 4.0 / (Kc * Kc)) + fmin(1.0 / 3.0, 8.0 * bs * bs / (Kc * Kc * Kc))
-                             : 2.0 / 3.0;
-    double taylor = exp(g_term(ac, b, B) + fabs(g_da(ac, b, B)) * h + 0.5 * G * h * h);
-    double aligned = 0.5 * fmin(ahi, b) * (1.0 / tanh(alo) + 1.0 / tanh(b));
-    return fmin(taylor, aligned);
+    const double h = 0.5 * (ahi - alo), c = cos(B);
+    const double K1 = Kab(alo, b, B), K2 = Kab(ahi, b, B);
+    /* K - a - b = (K^2 - (a + b)^2) / (K + a + b), with 1 - cos B = 2 sin^2(B/2) */
+    const double sh = sin(0.5 * B), chord2 = 4.0 * sh * sh;
+    const double x1 = -alo * b * chord2 / (K1 + alo + b), x2 = -ahi * b * chord2 / (K2 + ahi + b);
+    const double phi1 = ell(K1) - ell(alo) - ell(b), phi2 = ell(K2) - ell(ahi) - ell(b);
+    /* phi'(a) = (L(K) - 1) K_a - (L(a) - 1), K_a = (a + b cos B) / K */
+    const double Ka1 = K1 > 0.0 ? (alo + b * c) / K1 : 0.0, Ka2 = K2 > 0.0 ? (ahi + b * c) / K2 : 0.0;
+    const double d1 = (langevin(K1) - 1.0) * Ka1 - (langevin(alo) - 1.0);
+    const double d2 = (langevin(K2) - 1.0) * Ka2 - (langevin(ahi) - 1.0);
+    const double astar = -b * c;
+    const double Kmin = (astar > alo && astar < ahi) ? b * sin(B) : fmin(K1, K2);
+    const double G = Kmin > 0.0 ? fmin(1.0 / 3.0, 1.0 / (Kmin * Kmin)) : 1.0 / 3.0;
+    const double q = 2.0 * G * h * h;    /* G (a - e)^2 / 2 at the far end, a - e = 2h */
+    const double from_lo = phi1 + fmax(x1, x2 + 2.0 * d1 * h + q);
+    const double from_hi = phi2 + fmax(x2, x1 - 2.0 * d2 * h + q);
+    const double expansion = exp(fmin(from_lo, from_hi));
+    const double aligned = 0.5 * fmin(ahi, b) * (1.0 / tanh(alo) + 1.0 / tanh(b));
+    return fmin(expansion, aligned);
 }
 
 /* Test hooks for the two summand bounds above. */

@@ -13,7 +13,7 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libgosma.so"
-SOURCES = ["api.hip", "bound.hip", "bb.hip", "mlp.hip"]
+SOURCES = ["api.hip", "bound.hip", "bb.hip", "mlp.hip", "tune.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # gfx950 only; packed FP32 instructions are disabled for all device code.

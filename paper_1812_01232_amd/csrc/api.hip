@@ -37,6 +37,14 @@ int hip_fail(gosma_ctx *ctx, hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
     } while (0)
 
+// Launch shape used until gosma_set_tiles or gosma_autotune: more waves per
+// cell for larger pair counts, and about 8,192 waves in the grid.
+gosma::Tile default_tile(int64_t pairs)
+{
+    const int w = pairs <= 64 * 64 ? 1 : (pairs <= 128 * 128 ? 2 : 4);
+    return gosma::Tile{w, 8192 / w};
+}
+
 template <class T>
 void dfree(T *&p)
 {
@@ -51,7 +59,6 @@ void free_problems(gosma_ctx *ctx)
     dfree(ctx->d_w1);
     dfree(ctx->d_pbar);
     dfree(ctx->d_vmf);
-    dfree(ctx->d_vmf64);
     dfree(ctx->d_cls);
     dfree(ctx->d_prob);
     ctx->n_problems = 0;
@@ -182,12 +189,24 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
     }
 
     HIP_TRY(ctx, hipSetDevice(ctx->device));
+    {
+        // every cell of a bound kernel stages its problem's components in LDS
+        int needM = 0, needN = 0, lds_max = 0;
+        for (int p = 0; p < n_problems; ++p) {
+            needM = std::max(needM, (int)(gmm_off[p + 1] - gmm_off[p]));
+            needN = std::max(needN, (int)(vmf_off[p + 1] - vmf_off[p]));
+        }
+        HIP_TRY(ctx, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+        const size_t need = std::max(gosma::s11_lds_bytes(needM), gosma::s12_lds_bytes(needM, needN)) + 1024;
+        if (need > (size_t)lds_max)
+            return fail(ctx, GOSMA_E_INVAL, "M = %d, N = %d need %zu bytes of LDS per block; the device has %d", needM,
+                        needN, need, lds_max);
+    }
     gosma_drop_graph(ctx);   // a captured iteration holds the old mixture pointers
     free_problems(ctx);
     std::vector<double> h_mu(3 * TM), h_isig2(TM);
     std::vector<float> h_w1(TM), h_pbar(TM);
     std::vector<float4> h_vmf(2 * TN);
-    std::vector<double> h_vmf64(4 * TN);
     std::vector<ClassRange> h_cls;
     std::vector<ProbDesc> h_prob(n_problems);
     ctx->gmm_order.assign(n_problems, {});
@@ -264,8 +283,6 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
             double coth = 1.0 + 2.0 / std::expm1(2.0 * k);
             h_vmf[2 * dst] = make_float4((float)dx[3 * j], (float)dx[3 * j + 1], (float)dx[3 * j + 2], (float)k);
             h_vmf[2 * dst + 1] = make_float4((float)w2[j], (float)G, (float)coth, 0.0f);
-            for (int a = 0; a < 3; ++a) h_vmf64[4 * dst + a] = dx[3 * j + a];
-            h_vmf64[4 * dst + 3] = k;
         }
         // S22 (FP64, host): sum over same-class vMF pairs of w w' Z(K)/(Z Z)
         double S22 = 0.0;
@@ -281,9 +298,10 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
         ctx->gmm_order[p] = og;
     }
     hipError_t e;
+    if ((e = gosma::prepare_bound_kernels(maxM, maxN)) != hipSuccess) return hip_fail(ctx, e, "bound kernel LDS limit");
     if ((e = upload(ctx->d_mu, h_mu)) != hipSuccess || (e = upload(ctx->d_isig2, h_isig2)) != hipSuccess ||
         (e = upload(ctx->d_w1, h_w1)) != hipSuccess || (e = upload(ctx->d_pbar, h_pbar)) != hipSuccess ||
-        (e = upload(ctx->d_vmf, h_vmf)) != hipSuccess || (e = upload(ctx->d_vmf64, h_vmf64)) != hipSuccess ||
+        (e = upload(ctx->d_vmf, h_vmf)) != hipSuccess ||
         (e = upload(ctx->d_cls, h_cls)) != hipSuccess ||
         (e = upload(ctx->d_prob, h_prob)) != hipSuccess) {
         free_problems(ctx);
@@ -294,6 +312,8 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
     ctx->maxM = maxM;
     ctx->maxN = maxN;
     ctx->has_domain = true;
+    ctx->tile11 = default_tile((int64_t)maxM * maxM / 2);
+    ctx->tile12 = default_tile((int64_t)maxM * maxN);
     return GOSMA_OK;
 }
 
@@ -377,12 +397,12 @@ int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tke
     gosma::DevMix mx = ctx->mix();
     int ti = ctx->time_begin(GOSMA_KERNEL_S11, s);
     HIP_TRY(ctx, gosma::launch_s11(mx, tkeys, problem, n, nullptr, gosma::S11Out{ctx->d_s11ub, ctx->d_s11lo},
-                                   ctx->maxM, 0, s));
+                                   ctx->maxM, ctx->tile11, s));
     ctx->time_end(ti, s);
     gosma::BoundOut out{ub, lb, nullptr, aux, flags, top8, nullptr, nullptr, 0};
     ti = ctx->time_begin(GOSMA_KERNEL_S12, s);
     HIP_TRY(ctx, gosma::launch_s12(mx, rkeys, tkeys, problem, nullptr, ctx->d_s11ub, ctx->d_s11lo, n, nullptr, 1, out,
-                                   0.0, ctx->maxM, top8 != nullptr, 0, s));
+                                   0.0, ctx->maxM, ctx->maxN, top8 != nullptr, ctx->tile12, s));
     ctx->time_end(ti, s);
     return GOSMA_OK;
 }

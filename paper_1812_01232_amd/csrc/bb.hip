@@ -41,7 +41,6 @@ namespace {
 constexpr int kHistBins = 2048;
 constexpr int kBlock = 256;
 constexpr int kGridX = 2048;            // blocks per grid-stride kernel (divided among problems)
-constexpr int kBoundGrid = 8192;        // blocks (one wavefront each) for the bound kernels
 constexpr int kMaxLevel = 19;
 // Rounding margin of the FP32 bounds, relative to the magnitude S11 + 2 S12 of
 // each bound: over 6x the largest relative error measured against the FP64
@@ -987,7 +986,7 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     const int64_t maxc = 8 * (int64_t)S.k * P;
     ti = T0(GOSMA_KERNEL_S11);
     hipError_t e = launch_s11(mx, b.tcells, b.tpid, maxc, &b.g->ntcell, S11Out{b.s11ub, b.s11lo}, ctx->maxM,
-                              kBoundGrid, st);
+                              ctx->tile11, st);
     T1(ti);
     if (e) return e;
     ti = T0(GOSMA_KERNEL_S12);
@@ -995,7 +994,7 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     BoundOut bo{b.cub, b.clb, b.clbs, nullptr, b.cflags, top8 ? b.ctop8 : nullptr, nullptr, &b.st->dstar,
                 (int)(sizeof(PState) / sizeof(unsigned long long))};
     e = launch_s12(mx, b.crk, b.ctk, b.cpid, b.ctidx, b.s11ub, b.s11lo, maxc, &b.g->nchild, 1, bo, kMarginGamma,
-                   ctx->maxM, top8, kBoundGrid, st);
+                   ctx->maxM, ctx->maxN, top8, ctx->tile12, st);
     T1(ti);
     if (e) return e;
     if (logging) hipLaunchKernelGGL(k_log_records, dim3(std::max(1, gx / 8), P), dim3(kBlock), 0, st, b, P);
@@ -1077,10 +1076,10 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         const DevMix mx = ctx->mix();
         BoundOut bo{b.cub, b.clb, b.clbs, nullptr, b.cflags, b.ctop8, nullptr, &b.st->dstar,
                     (int)(sizeof(PState) / sizeof(unsigned long long))};
-        e = launch_s11(mx, b.ctk, b.cpid, P, nullptr, S11Out{b.s11ub, b.s11lo}, ctx->maxM, 0, st);
+        e = launch_s11(mx, b.ctk, b.cpid, P, nullptr, S11Out{b.s11ub, b.s11lo}, ctx->maxM, ctx->tile11, st);
         if (!e)
             e = launch_s12(mx, b.crk, b.ctk, b.cpid, nullptr, b.s11ub, b.s11lo, P, nullptr, 1, bo, kMarginGamma,
-                           ctx->maxM, true, 0, st);
+                           ctx->maxM, ctx->maxN, true, ctx->tile12, st);
         if (!e) {
             hipLaunchKernelGGL(k_seed, dim3((P + 63) / 64), dim3(64), 0, st, b, P);
             e = hipGetLastError();

@@ -13,13 +13,18 @@
 // translation cell (k_s11) and shared by every rotation cell paired with it;
 // k_s12 evaluates the GMM-vMF sums and combines.
 //
-// Work mapping: one wavefront (64 lanes) per cell.  The per-component
-// quantities of the cell (kappa, its interval over the cell, uncertainty
-// half-angles, rotated directions, normaliser factors) are computed in FP64,
-// one component per lane, and staged in LDS as FP32 structure-of-arrays.  The
-// pair sums then run over the flattened (i, j) rectangle of each class, 64
-// consecutive pairs per step, with FP32 arithmetic in log space and FP64
-// accumulation per lane, and a wavefront shuffle reduction at the end.
+// Work mapping: one block of 64 x W threads per cell (W = 1, 2 or 4, the
+// launch shape chosen by the autotuner).  The per-component quantities of the
+// cell (kappa, its interval over the cell, uncertainty half-angles, rotated
+// directions, normaliser factors) are computed in FP64, one component per
+// thread, and staged in LDS as one 64-byte FP32 record per component, read
+// back with 16-byte loads.  The pair sums then run over the (i, j) rectangle
+// of each class: when the class's vMF count divides the block or is a
+// multiple of it, each thread keeps one vMF row in registers and walks the
+// GMM rows (the same row for the whole wave when the count is a multiple, so
+// the LDS reads are broadcasts); otherwise the rectangle is flattened with
+// 64 x W consecutive pairs per step.  Terms are FP32 in log space, summed in
+// FP32 over runs of 8 per thread and the runs in FP64; waves combine in LDS.
 //
 // Summand algebra.  With G(y) = y / (1 - e^{-2y}) and h(K) = (1 - e^{-2K})/K,
 //   Z(K) / (Z(a) Z(b)) = e^{K - a - b} h(K) G(a) G(b)            (eq. 2)
@@ -192,13 +197,27 @@ __device__ TransPrep trans_prep(const double *mu, double isig2, const double t0[
     return o;
 }
 
-__device__ __forceinline__ double G_of(double y) { return y / (-expm1(-2.0 * y)); }
-__device__ __forceinline__ double coth_of(double y) { return 1.0 + 2.0 / expm1(2.0 * y); }
-// nu(y) = 1 - L(y) = 1 + 1/y - coth(y), L the derivative of log Z (y >= 1 here).
-__device__ __forceinline__ double nu_of(double y) { return 1.0 / y - 2.0 / expm1(2.0 * y); }
+// Functions of one concentration y >= 1 from a single expm1; with
+// d = 1 - e^{-2y}:  G(y) = y / d,  coth y = (2 - d) / d,  and
+// nu(y) = 1 - L(y) = 1 + 1/y - coth y = 1/y - 2 (1 - d) / d, where L is the
+// derivative of log Z.
+struct YFun {
+    double G, coth, nu;
+};
+
+__device__ __forceinline__ YFun yfun(double y)
+{
+    const double d = -expm1(-2.0 * y);
+    YFun o;
+    o.G = y / d;
+    o.coth = (2.0 - d) / d;
+    o.nu = 1.0 / y - 2.0 * (1.0 - d) / d;
+    return o;
+}
 
 // Pair kernel pieces for concentrations a, b and squared chord q.
 struct PairK {
+    float ks;     // K^2
     float x;      // K - a - b
     float K, r;   // K and 1 / (K (K + a + b))
     float invK;   // 1 / K
@@ -211,8 +230,8 @@ __device__ __forceinline__ PairK pair_k(float a, float b, float q)
     PairK o;
     float s = a + b;
     float t = a * b * q;
-    float K2 = fmaxf(fmaf(s, s, -t), 0.0f);
-    float K = fmaxf(fsqrt(K2), 1e-20f);
+    o.ks = fmaxf(fmaf(s, s, -t), 0.0f);
+    float K = fmaxf(fsqrt(o.ks), 1e-20f);
     float den = K + s;
     float r = frcp(K * den);
     o.K = K;
@@ -238,458 +257,539 @@ __device__ __forceinline__ PairK pair_k(float a, float b, float q)
     return o;
 }
 
+// Block-level shared state of the bound kernels (up to kMaxWaves waves).
+struct BlockShared {
+    double s0[kMaxWaves], s1[kMaxWaves];
+    int drop[kMaxWaves], ubinf[kMaxWaves];
+    float psum[kMaxWaves];
+    float top[kMaxWaves][8];
+};
+
+// Pairs are summed in FP32 over runs of at most this many steps per lane and
+// the runs are accumulated in FP64.
+constexpr int kRun = 8;
+
 // ---------------------------------------------------------------------------
 // S11 over translation cells
 // ---------------------------------------------------------------------------
+//
+// Component record in LDS, four float4 (64 bytes):
+//   [0] u (unit vector mu - t0), weight      [1] kappa(t0), G(kappa), cos, sin of psi_t / 2
+//   [2] kappa interval centre ac, half-width ha, G(ac), nu(ac)
+//   [3] lambda = min(1/3, 1/klo^2), -, -, -
 
-enum S11Field { A_UX, A_UY, A_UZ, A_KAP, A_GK, A_AC, A_HA, A_GAC, A_NU, A_LAM, A_CPS, A_SPS, A_W, A_NF };
-
-__device__ void s11_cell(DevMix mx, const uint64_t *__restrict__ tkeys, const uint32_t *__restrict__ pids,
-                         int64_t cell, S11Out out, int stride, float *lds, int lane);
-
-__global__ __launch_bounds__(64) void k_s11(DevMix mx, const uint64_t *__restrict__ tkeys,
-                                            const uint32_t *__restrict__ pids, int64_t nt_host,
-                                            const uint32_t *__restrict__ nt_dev, S11Out out, int stride)
+__device__ __forceinline__ void s11_pair(const float4 *__restrict__ rec, int a_, int b_, float &sub, float &slo)
 {
-    extern __shared__ float lds[];
-    const int lane = threadIdx.x;
-    const int64_t nt = nt_dev ? (int64_t)nt_dev[0] : nt_host;
-    for (int64_t cell = blockIdx.x; cell < nt; cell += gridDim.x) {
-        __syncthreads();
-        s11_cell(mx, tkeys, pids, cell, out, stride, lds, lane);
+    const float4 A0 = rec[4 * a_], A1 = rec[4 * a_ + 1], A2 = rec[4 * a_ + 2], A3 = rec[4 * a_ + 3];
+    const float4 B0 = rec[4 * b_], B1 = rec[4 * b_ + 1], B2 = rec[4 * b_ + 2], B3 = rec[4 * b_ + 3];
+    const float dx = A0.x - B0.x, dy = A0.y - B0.y, dz = A0.z - B0.z;
+    const float q = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float px = A0.x + B0.x, py = A0.y + B0.y, pz = A0.z + B0.z;
+    const float pp = fmaf(px, px, fmaf(py, py, pz * pz));
+    const float w2 = 2.0f * A0.w * B0.w;
+    // upper bound summand at the centre
+    {
+        PairK k = pair_k(A1.x, B1.x, q);
+        sub += w2 * (fexp2(k.x * kLog2e) * k.hK * A1.y * B1.y);
+    }
+    // lower bound summand: angle A = min(pi, theta + psi_i + psi_i') (eq. 24)
+    // via half angles: A/2 = theta/2 + (psi_i + psi_i')/2, clamped at pi/2.
+    {
+        // half-angle sine and cosine from the two chords |u - v|, |u + v|
+        const float st = 0.5f * fsqrt(q), ct = 0.5f * fsqrt(pp);
+        const float ca = A1.z * B1.z - A1.w * B1.w, sa = A1.w * B1.z + A1.z * B1.w;
+        const float cA = ct * ca - st * sa;
+        float sA = st * ca + ct * sa;
+        sA = cA <= 0.0f ? 1.0f : sA;
+        const float qA = 4.0f * sA * sA;
+        const float a = A2.x, b = B2.x, ha = A2.y, hb = B2.y;
+        PairK k = pair_k(a, b, qA);
+        // gradient of g = log Z(K) - log Z(a) - log Z(b) at the box centre:
+        // g_a = (K_a - 1) + nu(a) - nu(K) K_a with
+        // K_a - 1 = b qA (a - b - K) / (2 K (K + a + b)).
+        const float ka1 = 0.5f * b * qA * (a - b - k.K) * k.r;
+        const float kb1 = 0.5f * a * qA * (b - a - k.K) * k.r;
+        const float ga = ka1 + A2.w - k.nuK * (1.0f + ka1);
+        const float gb = kb1 + B2.w - k.nuK * (1.0f + kb1);
+        const float lam = fmaxf(A3.x, B3.x);
+        const float corr = -fabsf(ga) * ha - fabsf(gb) * hb - 0.5f * lam * fmaf(ha, ha, hb * hb);
+        slo += w2 * (fexp2((k.x + corr) * kLog2e) * k.hK * A2.z * B2.z);
     }
 }
 
-__device__ void s11_cell(DevMix mx, const uint64_t *__restrict__ tkeys, const uint32_t *__restrict__ pids,
-                         int64_t cell, S11Out out, int stride, float *lds, int lane)
+__global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_t *__restrict__ tkeys,
+                                                         const uint32_t *__restrict__ pids, int64_t nt_host,
+                                                         const uint32_t *__restrict__ nt_dev, S11Out out)
 {
-    const uint32_t pid = pids ? pids[cell] : 0u;
-    if (pid >= (uint32_t)mx.n_prob) {     // invalid problem index: no bound
-        if (lane == 0) {
-            out.ub[cell] = NAN;
-            out.lo[cell] = NAN;
+    extern __shared__ float4 lds4[];
+    __shared__ BlockShared sh;
+    float4 *rec = lds4;
+    const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, wv = tid >> 6, lane = tid & 63;
+    const int64_t nt = nt_dev ? (int64_t)nt_dev[0] : nt_host;
+    for (int64_t cell = blockIdx.x; cell < nt; cell += gridDim.x) {
+        __syncthreads();
+        const uint32_t pid = pids ? pids[cell] : 0u;
+        if (pid >= (uint32_t)mx.n_prob) {     // invalid problem index: no bound
+            if (tid == 0) {
+                out.ub[cell] = NAN;
+                out.lo[cell] = NAN;
+            }
+            continue;
         }
-        return;
-    }
-    const ProbDesc P = mx.prob[pid];
-    double t0[3], tau[3];
-    decode_key(tkeys[cell], P.t_lo, P.t_w, t0, tau);
+        const ProbDesc P = mx.prob[pid];
+        double t0[3], tau[3];
+        decode_key(tkeys[cell], P.t_lo, P.t_w, t0, tau);
 
-    // per-component prep; the diagonal (i = i') summands are added here:
-    // Z(2k)/Z(k)^2 = k coth(k) / 2 at the centre, and at the low end of the
-    // kappa interval for the lower bound (the angle is exactly 0 and the
-    // summand increases with kappa).
-    double dub = 0.0, dlo = 0.0;
-    int drop = 0, ubinf = 0;
-    for (int i = lane; i < P.M; i += 64) {
-        int g = P.gmm_off + i;
-        TransPrep tp = trans_prep(mx.mu + 3 * g, mx.isig2[g], t0, tau, P.zeta);
-        drop |= tp.drop;
-        ubinf |= tp.ub_inf;
-        double w = mx.w1[g];
-        dub += w * w * 0.5 * tp.kap * coth_of(tp.kap);
-        dlo += w * w * 0.5 * tp.klo * coth_of(tp.klo);
-        lds[A_UX * stride + i] = (float)tp.u[0];
-        lds[A_UY * stride + i] = (float)tp.u[1];
-        lds[A_UZ * stride + i] = (float)tp.u[2];
-        lds[A_KAP * stride + i] = (float)tp.kap;
-        lds[A_GK * stride + i] = (float)G_of(tp.kap);
-        lds[A_AC * stride + i] = (float)tp.ac;
-        lds[A_HA * stride + i] = (float)tp.ha;
-        lds[A_GAC * stride + i] = (float)G_of(tp.ac);
-        lds[A_NU * stride + i] = (float)nu_of(tp.ac);
-        lds[A_LAM * stride + i] = (float)fmin(1.0 / 3.0, 1.0 / (tp.klo * tp.klo));
-        lds[A_CPS * stride + i] = (float)tp.cps;
-        lds[A_SPS * stride + i] = (float)tp.sps;
-        lds[A_W * stride + i] = (float)w;
-    }
-    drop = wave_or(drop);
-    ubinf = wave_or(ubinf);
-    __syncthreads();
-    if (drop) {
+        // per-component prep; the diagonal (i = i') summands are added here:
+        // Z(2k)/Z(k)^2 = k coth(k) / 2 at the centre, and at the low end of the
+        // kappa interval for the lower bound (the angle is exactly 0 and the
+        // summand increases with kappa).
+        double dub = 0.0, dlo = 0.0;
+        int drop = 0, ubinf = 0;
+        for (int i = tid; i < P.M; i += T) {
+            const int g = P.gmm_off + i;
+            const TransPrep tp = trans_prep(mx.mu + 3 * g, mx.isig2[g], t0, tau, P.zeta);
+            drop |= tp.drop;
+            ubinf |= tp.ub_inf;
+            const double w = mx.w1[g];
+            const YFun fk = yfun(tp.kap), fa = yfun(tp.ac), fl = yfun(tp.klo);
+            dub += w * w * 0.5 * tp.kap * fk.coth;
+            dlo += w * w * 0.5 * tp.klo * fl.coth;
+            rec[4 * i] = make_float4((float)tp.u[0], (float)tp.u[1], (float)tp.u[2], (float)w);
+            rec[4 * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)tp.cps, (float)tp.sps);
+            rec[4 * i + 2] = make_float4((float)tp.ac, (float)tp.ha, (float)fa.G, (float)fa.nu);
+            rec[4 * i + 3] = make_float4((float)fmin(1.0 / 3.0, 1.0 / (tp.klo * tp.klo)), 0.0f, 0.0f, 0.0f);
+        }
+        drop = wave_or(drop);
+        ubinf = wave_or(ubinf);
         if (lane == 0) {
-            out.ub[cell] = INFINITY;
-            out.lo[cell] = INFINITY;
+            sh.drop[wv] = drop;
+            sh.ubinf[wv] = ubinf;
         }
-        return;
-    }
+        __syncthreads();
+        drop = 0;
+        ubinf = 0;
+        for (int w = 0; w < W; ++w) {
+            drop |= sh.drop[w];
+            ubinf |= sh.ubinf[w];
+        }
+        if (drop) {
+            if (tid == 0) {
+                out.ub[cell] = INFINITY;
+                out.lo[cell] = INFINITY;
+            }
+            continue;
+        }
 
-    double acc_ub = dub, acc_lo = dlo;
-    for (int c = 0; c < P.n_cls; ++c) {
-        const ClassRange cr = mx.cls[P.cls_off + c];
-        const int n = cr.g1 - cr.g0;
-        if (n < 2) continue;
-        const int base = cr.g0 - P.gmm_off;
-        // The upper triangle (i <= i') of the class, folded into a rectangle of
-        // n2/2 rows and n2 + 1 columns (n2 = n rounded up to even): folded row
-        // r holds triangle rows r and n2 - 1 - r.
-        const int n2 = n + (n & 1);
-        const int R = n2 >> 1, C = n2 + 1;
-        int r = lane / C, col = lane % C;
-        const int dr = 64 / C, dc = 64 % C;
-        for (; r < R;) {
-            int i, i2;
-            if (col < n2 - r) {
-                i = r;
-                i2 = r + col;
-            } else {
-                i = n2 - 1 - r;
-                i2 = i + col - (n2 - r);
-            }
-            if (i2 < n && i != i2) {
-                const int a_ = base + i, b_ = base + i2;
-                float ux = lds[A_UX * stride + a_], uy = lds[A_UY * stride + a_], uz = lds[A_UZ * stride + a_];
-                float vx = lds[A_UX * stride + b_], vy = lds[A_UY * stride + b_], vz = lds[A_UZ * stride + b_];
-                float dx = ux - vx, dy = uy - vy, dz = uz - vz;
-                float q = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                float px = ux + vx, py = uy + vy, pz = uz + vz;
-                float pp = fmaf(px, px, fmaf(py, py, pz * pz));
-                float w2 = 2.0f * lds[A_W * stride + a_] * lds[A_W * stride + b_];
-                // upper bound summand at the centre
-                {
-                    PairK k = pair_k(lds[A_KAP * stride + a_], lds[A_KAP * stride + b_], q);
-                    float v = fexp2(k.x * kLog2e) * k.hK * lds[A_GK * stride + a_] * lds[A_GK * stride + b_];
-                    acc_ub += (double)(w2 * v);
+        double acc_ub = dub, acc_lo = dlo;
+        for (int c = 0; c < P.n_cls; ++c) {
+            const ClassRange cr = mx.cls[P.cls_off + c];
+            const int n = cr.g1 - cr.g0;
+            if (n < 2) continue;
+            const int base = cr.g0 - P.gmm_off;
+            // The upper triangle (i <= i') of the class, folded into a rectangle of
+            // n2/2 rows and n2 + 1 columns (n2 = n rounded up to even): folded row
+            // r holds triangle rows r and n2 - 1 - r.  T consecutive cells per step.
+            const int n2 = n + (n & 1);
+            const int R = n2 >> 1, C = n2 + 1;
+            int r = tid / C, col = tid % C;
+            const int dr = T / C, dc = T % C;
+            while (r < R) {
+                float sub = 0.0f, slo = 0.0f;
+                for (int u = 0; u < kRun && r < R; ++u) {
+                    int i, i2;
+                    if (col < n2 - r) {
+                        i = r;
+                        i2 = r + col;
+                    } else {
+                        i = n2 - 1 - r;
+                        i2 = i + col - (n2 - r);
+                    }
+                    if (i2 < n && i != i2) s11_pair(rec, base + i, base + i2, sub, slo);
+                    col += dc;
+                    r += dr;
+                    if (col >= C) {
+                        col -= C;
+                        r += 1;
+                    }
                 }
-                // lower bound summand: angle A = min(pi, theta + psi_i + psi_i') (eq. 24)
-                // via half angles: A/2 = theta/2 + (psi_i + psi_i')/2, clamped at pi/2.
-                {
-                    // half-angle sine and cosine from the two chords |u - v|, |u + v|
-                    float st = 0.5f * fsqrt(q), ct = 0.5f * fsqrt(pp);
-                    float ci = lds[A_CPS * stride + a_], si = lds[A_SPS * stride + a_];
-                    float cj = lds[A_CPS * stride + b_], sj = lds[A_SPS * stride + b_];
-                    float ca = ci * cj - si * sj, sa = si * cj + ci * sj;
-                    float cA = ct * ca - st * sa, sA = st * ca + ct * sa;
-                    sA = cA <= 0.0f ? 1.0f : sA;
-                    float qA = 4.0f * sA * sA;
-                    float a = lds[A_AC * stride + a_], b = lds[A_AC * stride + b_];
-                    float ha = lds[A_HA * stride + a_], hb = lds[A_HA * stride + b_];
-                    PairK k = pair_k(a, b, qA);
-                    // gradient of g = log Z(K) - log Z(a) - log Z(b) at the box centre:
-                    // g_a = (K_a - 1) + nu(a) - nu(K) K_a with
-                    // K_a - 1 = b qA (a - b - K) / (2 K (K + a + b)).
-                    float ka1 = 0.5f * b * qA * (a - b - k.K) * k.r;
-                    float kb1 = 0.5f * a * qA * (b - a - k.K) * k.r;
-                    float ga = ka1 + lds[A_NU * stride + a_] - k.nuK * (1.0f + ka1);
-                    float gb = kb1 + lds[A_NU * stride + b_] - k.nuK * (1.0f + kb1);
-                    float lam = fmaxf(lds[A_LAM * stride + a_], lds[A_LAM * stride + b_]);
-                    float corr = -fabsf(ga) * ha - fabsf(gb) * hb - 0.5f * lam * fmaf(ha, ha, hb * hb);
-                    float v = fexp2((k.x + corr) * kLog2e) * k.hK * lds[A_GAC * stride + a_] *
-                              lds[A_GAC * stride + b_];
-                    acc_lo += (double)(w2 * v);
-                }
-            }
-            col += dc;
-            r += dr;
-            if (col >= C) {
-                col -= C;
-                r += 1;
+                acc_ub += (double)sub;
+                acc_lo += (double)slo;
             }
         }
-    }
-    acc_ub = wave_sum(acc_ub);
-    acc_lo = wave_sum(acc_lo);
-    if (lane == 0) {
-        out.ub[cell] = ubinf ? INFINITY : acc_ub;
-        out.lo[cell] = acc_lo;
+        acc_ub = wave_sum(acc_ub);
+        acc_lo = wave_sum(acc_lo);
+        if (lane == 0) {
+            sh.s0[wv] = acc_ub;
+            sh.s1[wv] = acc_lo;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double su = 0.0, sl = 0.0;
+            for (int w = 0; w < W; ++w) {
+                su += sh.s0[w];
+                sl += sh.s1[w];
+            }
+            out.ub[cell] = ubinf ? INFINITY : su;
+            out.lo[cell] = sl;
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // S12 over rotation x translation cells, and the final bounds
 // ---------------------------------------------------------------------------
-
-enum S12Field { B_WX, B_WY, B_WZ, B_KAP, B_GK, B_AC, B_HA, B_GAC, B_NU, B_CPS, B_SPS, B_KHI, B_COTH, B_W, B_NF };
-// FP64 copies of the inputs of the lower-bound exponent (see s12_lower_exponent64)
-enum S12Field64 { D_WX, D_WY, D_WZ, D_CPS, D_SPS, D_AC, D_HA, D_NU, D_NF };
-
-// Exponent of the S12 upper summand in FP64.  The FP32 path loses about
-// u |x| to cancellation when x = K - a - b and the Taylor correction are both
-// large (wide kappa intervals of large translation cells), so those terms are
-// recomputed here from FP64 copies of their inputs.
-__device__ __noinline__ float s12_lower_exponent64(const double *L64, int stride, int a_, const double *v64)
-{
-    const double wx = L64[D_WX * stride + a_], wy = L64[D_WY * stride + a_], wz = L64[D_WZ * stride + a_];
-    const double mx = v64[0], my = v64[1], mz = v64[2], b = v64[3];
-    const double dx = wx - mx, dy = wy - my, dz = wz - mz;
-    const double px = wx + mx, py = wy + my, pz = wz + mz;
-    const double st = 0.5 * sqrt(dx * dx + dy * dy + dz * dz), ct = 0.5 * sqrt(px * px + py * py + pz * pz);
-    const double sB = fmax(st * L64[D_CPS * stride + a_] - ct * L64[D_SPS * stride + a_], 0.0);
-    const double qB = 4.0 * sB * sB;
-    const double a = L64[D_AC * stride + a_], ha = L64[D_HA * stride + a_];
-    const double s = a + b, t = a * b * qB;
-    const double K = fmax(sqrt(fmax(s * s - t, 0.0)), 1e-300);
-    const double r = 1.0 / (K * (K + s));
-    const double x = -t * K * r, invK = (K + s) * r;
-    const double nuK = invK - 2.0 / expm1(2.0 * K);
-    const double ka1 = 0.5 * b * qB * (a - b - K) * r;
-    const double ga = ka1 + L64[D_NU * stride + a_] - nuK * (1.0 + ka1);
-    const double b2s2 = b * b * qB * (1.0 - 0.25 * qB);
-    const double iK = fmin(invK, 1e6);
-    const double G2 = ha <= 0.5 * K ? fmin(1.0 / 3.0, 4.0 * iK * iK) + fmin(1.0 / 3.0, 8.0 * b2s2 * iK * iK * iK)
-                                    : 2.0 / 3.0;
-    return (float)(x + fabs(ga) * ha + 0.5 * G2 * ha * ha);
-}
+//
+// GMM component record in LDS, four float4 (64 bytes):
+//   [0] w = R_r0 u (rotated unit vector), weight
+//   [1] kappa(t0), G(kappa), cos, sin of Psi / 2 with Psi = psi_t + psi_r (eq. 25)
+//   [2] kappa interval [alo, ahi] over the cell, half-width ha, coth(alo)
+//   [3] G(alo), G(ahi), nu(alo), nu(ahi)
+// vMF record, two float4 (32 bytes): {dx, dy, dz, kappa}, {weight, G(kappa), coth(kappa), 0}.
+//
+// Upper bound of the summand over the cube (Theorem 1 with kappa_1i(t)
+// relaxed to [alo, ahi]): at the smallest angle B, and with
+//   g(a) = log Z(K) - log Z(a) - log Z(b) = x(a) + phi(a),  x = K - a - b,
+// x is convex in a (K is the norm of a u + b v), and phi'' <= min(1/3, 1/Kmin^2)
+// with Kmin the smallest K on the interval, so a second-order expansion of phi
+// at either end plus the exact x is a convex majorant whose maximum sits at an
+// end; the smaller of the two expansions is used, capped by the value for
+// aligned directions, min(ahi, b)(coth alo + coth b)/2.
 
 template <bool TOP8>
-__device__ void s12_cube(DevMix mx, const uint64_t *__restrict__ rkeys, const uint64_t *__restrict__ tkeys,
-                         const uint32_t *__restrict__ pids, const int64_t *__restrict__ tidx,
-                         const double *__restrict__ s11ub, const double *__restrict__ s11lo, int64_t cube,
-                         BoundOut out, double gamma, int stride, float *lds, int lane);
-
-template <bool TOP8>
-__global__ __launch_bounds__(64) void k_s12(DevMix mx, const uint64_t *__restrict__ rkeys,
-                                            const uint64_t *__restrict__ tkeys, const uint32_t *__restrict__ pids,
-                                            const int64_t *__restrict__ tidx, const double *__restrict__ s11ub,
-                                            const double *__restrict__ s11lo, int64_t n_host,
-                                            const uint32_t *__restrict__ n_dev, int n_dev_mul, BoundOut out,
-                                            double gamma, int stride)
+__device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, int a_, const float4 &v0, const float4 &v1,
+                                         float &sub, float &shi, float (&top)[8])
 {
-    extern __shared__ float lds[];
-    const int lane = threadIdx.x;
-    const int64_t n = n_dev ? (int64_t)n_dev[0] * n_dev_mul : n_host;
-    for (int64_t cube = blockIdx.x; cube < n; cube += gridDim.x) {
-        __syncthreads();
-        s12_cube<TOP8>(mx, rkeys, tkeys, pids, tidx, s11ub, s11lo, cube, out, gamma, stride, lds, lane);
-    }
-}
-
-template <bool TOP8>
-__device__ void s12_cube(DevMix mx, const uint64_t *__restrict__ rkeys, const uint64_t *__restrict__ tkeys,
-                         const uint32_t *__restrict__ pids, const int64_t *__restrict__ tidx,
-                         const double *__restrict__ s11ub, const double *__restrict__ s11lo, int64_t cube,
-                         BoundOut out, double gamma, int stride, float *lds, int lane)
-{
-    const uint32_t pid = pids ? pids[cube] : 0u;
-    if (pid >= (uint32_t)mx.n_prob) {     // invalid problem index: no bound, both drop flags
-        if (lane == 0) {
-            out.ub[cube] = NAN;
-            out.lb[cube] = NAN;
-            if (out.lb_safe) out.lb_safe[cube] = NAN;
-            out.flags[cube] = GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS;
-        }
-        return;
-    }
-    const ProbDesc P = mx.prob[pid];
-    double r0[3], hr[3], t0[3], tau[3];
-    decode_key(rkeys[cube], P.r_lo, P.r_w, r0, hr);
-    decode_key(tkeys[cube], P.t_lo, P.t_w, t0, tau);
-
-    // psi_r = min(|h_r|, pi) (Lemma 2 bounded with |angle(R_r p, R_s p)| <= |r - s|)
-    double psir = fmin(sqrt(hr[0] * hr[0] + hr[1] * hr[1] + hr[2] * hr[2]), kPi);
-    uint8_t flags = 0;
+    const float4 R0 = rec[4 * a_], R1 = rec[4 * a_ + 1], R2 = rec[4 * a_ + 2], R3 = rec[4 * a_ + 3];
+    const float b = v0.w;
+    const float dx = R0.x - v0.x, dy = R0.y - v0.y, dz = R0.z - v0.z;
+    const float q = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float px = R0.x + v0.x, py = R0.y + v0.y, pz = R0.z + v0.z;
+    const float pp = fmaf(px, px, fmaf(py, py, pz * pz));
+    const float ww = R0.w * v1.x;
+    // upper bound summand at the centre (eq. 12)
     {
-        double nr2 = 0.0;
-        for (int k = 0; k < 3; ++k) {
-            double lo = r0[k] - hr[k], hi = r0[k] + hr[k];
-            double nk = lo > 0.0 ? lo : (hi < 0.0 ? hi : 0.0);
-            nr2 += nk * nk;
-        }
-        if (nr2 > kPi * kPi) flags |= GOSMA_FLAG_DROP_ROT;
-    }
-    double R[9];
-    rotation_matrix(r0, R);
-    double crh, srh;
-    sincos(0.5 * psir, &srh, &crh);
-
-    int drop = 0, ubinf = 0;
-    float psum = 0.0f;
-    for (int i = lane; i < P.M; i += 64) {
-        int g = P.gmm_off + i;
-        TransPrep tp = trans_prep(mx.mu + 3 * g, mx.isig2[g], t0, tau, P.zeta);
-        drop |= tp.drop;
-        ubinf |= tp.ub_inf;
-        psum += mx.pbar[g] * tp.psi;
-        double w[3];
-        for (int a = 0; a < 3; ++a) w[a] = R[3 * a] * tp.u[0] + R[3 * a + 1] * tp.u[1] + R[3 * a + 2] * tp.u[2];
-        // half of Psi = psi_t + psi_r (eq. 25), as cos/sin
-        double cP = tp.cps * crh - tp.sps * srh, sP = tp.sps * crh + tp.cps * srh;
-        lds[B_WX * stride + i] = (float)w[0];
-        lds[B_WY * stride + i] = (float)w[1];
-        lds[B_WZ * stride + i] = (float)w[2];
-        lds[B_KAP * stride + i] = (float)tp.kap;
-        lds[B_GK * stride + i] = (float)G_of(tp.kap);
-        lds[B_AC * stride + i] = (float)tp.ac;
-        lds[B_HA * stride + i] = (float)tp.ha;
-        lds[B_GAC * stride + i] = (float)G_of(tp.ac);
-        lds[B_NU * stride + i] = (float)nu_of(tp.ac);
-        lds[B_CPS * stride + i] = (float)cP;
-        lds[B_SPS * stride + i] = (float)sP;
-        lds[B_KHI * stride + i] = (float)(tp.klo + 2.0 * tp.ha);
-        lds[B_COTH * stride + i] = (float)coth_of(tp.klo);
-        lds[B_W * stride + i] = mx.w1[g];
-        double *L64 = (double *)(lds + B_NF * stride);
-        L64[D_WX * stride + i] = w[0];
-        L64[D_WY * stride + i] = w[1];
-        L64[D_WZ * stride + i] = w[2];
-        L64[D_CPS * stride + i] = cP;
-        L64[D_SPS * stride + i] = sP;
-        L64[D_AC * stride + i] = tp.ac;
-        L64[D_HA * stride + i] = tp.ha;
-        L64[D_NU * stride + i] = nu_of(tp.ac);
-    }
-    drop = wave_or(drop);
-    ubinf = wave_or(ubinf);
-    psum = wave_sumf(psum);
-    if (drop) flags |= GOSMA_FLAG_DROP_TRANS;
-    if (ubinf) flags |= GOSMA_FLAG_UB_INF;
-    if ((double)psir >= (double)psum) flags |= GOSMA_FLAG_SPLIT_ROT;
-    __syncthreads();
-
-    const bool dropped = flags & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS);
-    double acc_ub = 0.0, acc_hi = 0.0;
-    float top[8];
+        PairK k = pair_k(R1.x, b, q);
+        const float v = ww * (fexp2(k.x * kLog2e) * k.hK * R1.y * v1.y);
+        sub += v;
+        if (TOP8 && v > top[7]) {
+            top[7] = v;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) top[k] = 0.0f;
-
-    if (!dropped) {
-        for (int c = 0; c < P.n_cls; ++c) {
-            const ClassRange cr = mx.cls[P.cls_off + c];
-            const int ni = cr.g1 - cr.g0, nj = cr.v1 - cr.v0;
-            if (ni <= 0 || nj <= 0) continue;
-            const int gbase = cr.g0 - P.gmm_off;
-            int i = lane / nj, j = lane % nj;
-            const int di = 64 / nj, dj = 64 % nj;
-            for (; i < ni;) {
-                const int a_ = gbase + i;
-                const float4 v0 = mx.vmf[2 * (cr.v0 + j)];
-                const float4 v1 = mx.vmf[2 * (cr.v0 + j) + 1];
-                const float b = v0.w;
-                const float wx = lds[B_WX * stride + a_], wy = lds[B_WY * stride + a_], wz = lds[B_WZ * stride + a_];
-                float dx = wx - v0.x, dy = wy - v0.y, dz = wz - v0.z;
-                float q = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                float px = wx + v0.x, py = wy + v0.y, pz = wz + v0.z;
-                float pp = fmaf(px, px, fmaf(py, py, pz * pz));
-                float ww = lds[B_W * stride + a_] * v1.x;
-                // upper bound summand at the centre (eq. 12)
-                {
-                    PairK k = pair_k(lds[B_KAP * stride + a_], b, q);
-                    float v = ww * fexp2(k.x * kLog2e) * k.hK * lds[B_GK * stride + a_] * v1.y;
-                    acc_ub += (double)v;
-                    if (TOP8 && v > top[7]) {
-                        top[7] = v;
-#pragma unroll
-                        for (int s = 7; s > 0; --s) {
-                            if (top[s] > top[s - 1]) {
-                                float tmp = top[s];
-                                top[s] = top[s - 1];
-                                top[s - 1] = tmp;
-                            }
-                        }
-                    }
-                }
-                // upper bound on the summand over the cube: B = max(0, theta - Psi) (eq. 25)
-                {
-                    float st = 0.5f * fsqrt(q), ct = 0.5f * fsqrt(pp);
-                    float sB = fmaxf(st * lds[B_CPS * stride + a_] - ct * lds[B_SPS * stride + a_], 0.0f);
-                    float qB = 4.0f * sB * sB;
-                    float a = lds[B_AC * stride + a_], ha = lds[B_HA * stride + a_];
-                    PairK k = pair_k(a, b, qB);
-                    float ka1 = 0.5f * b * qB * (a - b - k.K) * k.r;            // K_a - 1
-                    float ga = ka1 + lds[B_NU * stride + a_] - k.nuK * (1.0f + ka1);
-                    // curvature bound: g'' <= min(1/3, 1/m^2) + min(1/3, (b sin B)^2/m^3),
-                    // m <= K on the interval; with ha <= K/2, m >= K/2.
-                    float b2s2 = b * b * qB * (1.0f - 0.25f * qB);
-                    float iK = fminf(k.invK, 1e6f);
-                    float G2 = ha <= 0.5f * k.K
-                                   ? fminf(1.0f / 3.0f, 4.0f * iK * iK) + fminf(1.0f / 3.0f, 8.0f * b2s2 * iK * iK * iK)
-                                   : 2.0f / 3.0f;
-                    float corr = fabsf(ga) * ha + 0.5f * G2 * ha * ha;
-                    float expo = k.x + corr;
-                    if (__builtin_expect(k.x < -16.0f && expo > -60.0f, 0))
-                        expo = s12_lower_exponent64((const double *)(lds + B_NF * stride), stride, a_,
-                                                    mx.vmf64 + 4 * (cr.v0 + j));
-                    float vT = fexp2(expo * kLog2e) * k.hK * lds[B_GAC * stride + a_] * v1.y;
-                    float cap = 0.5f * fminf(lds[B_KHI * stride + a_], b) * (lds[B_COTH * stride + a_] + v1.z);
-                    acc_hi += (double)(ww * fminf(vT, cap));
-                }
-                j += dj;
-                i += di;
-                if (j >= nj) {
-                    j -= nj;
-                    i += 1;
+            for (int s = 7; s > 0; --s) {
+                if (top[s] > top[s - 1]) {
+                    const float tmp = top[s];
+                    top[s] = top[s - 1];
+                    top[s - 1] = tmp;
                 }
             }
         }
     }
-    acc_ub = wave_sum(acc_ub);
-    acc_hi = wave_sum(acc_hi);
-
-    if (TOP8 && out.top8) {
-        // merge the per-lane sorted lists: 8 rounds of a wave maximum
-        int head = 0;
-        for (int k = 0; k < 8; ++k) {
-            float mine = -1.0f;
-#pragma unroll
-            for (int s = 0; s < 8; ++s)
-                if (s == head) mine = top[s];
-            float m = mine;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-            // the lowest lane holding the maximum advances its list
-            unsigned long long ballot = __ballot(mine == m);
-            int winner = __ffsll((long long)ballot) - 1;
-            if (lane == winner) head++;
-            if (lane == 0) out.top8[8 * cube + k] = fmaxf(m, 0.0f);
-        }
+    // upper bound on the summand over the cube: B = max(0, theta - Psi) (eq. 25)
+    {
+        const float st = 0.5f * fsqrt(q), ct = 0.5f * fsqrt(pp);
+        const float sB = fmaxf(st * R1.z - ct * R1.w, 0.0f);
+        const float qB = 4.0f * sB * sB;
+        const float alo = R2.x, ahi = R2.y, ha = R2.z;
+        const PairK k1 = pair_k(alo, b, qB), k2 = pair_k(ahi, b, qB);
+        const float bc = b * fmaf(-0.5f, qB, 1.0f);             // b cos B
+        const float d1 = R3.z - k1.nuK * (alo + bc) * k1.invK;  // phi'(alo)
+        const float d2 = R3.w - k2.nuK * (ahi + bc) * k2.invK;  // phi'(ahi)
+        const float km2 = (-bc > alo && -bc < ahi) ? b * b * qB * fmaf(-0.25f, qB, 1.0f) : fminf(k1.ks, k2.ks);
+        const float G = fminf(1.0f / 3.0f, frcp(km2));
+        const float q2 = 2.0f * G * ha * ha;
+        const float eA = fmaxf(k1.x, fmaf(2.0f * d1, ha, k2.x + q2));
+        const float eB = fmaxf(k2.x, fmaf(-2.0f * d2, ha, k1.x + q2));
+        const float vA = fexp2(eA * kLog2e) * k1.hK * R3.x;
+        const float vB = fexp2(eB * kLog2e) * k2.hK * R3.y;
+        const float vT = fminf(vA, vB) * v1.y;
+        const float cap = 0.5f * fminf(ahi, b) * (R2.w + v1.z);
+        shi += ww * fminf(vT, cap);
     }
+}
 
-    if (lane == 0) {
-        double ub = INFINITY, lb = INFINITY, lbs = INFINITY;
-        const int64_t t = tidx ? tidx[cube] : cube;
-        double s11u = s11ub[t], s11l = s11lo[t];
+// Four waves per SIMD: the FP64 per-component prep then spills a few
+// registers once per cube, while the pair loops stay in registers.
+template <bool TOP8>
+__global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_s12(DevMix mx, const uint64_t *__restrict__ rkeys,
+                                                         const uint64_t *__restrict__ tkeys,
+                                                         const uint32_t *__restrict__ pids,
+                                                         const int64_t *__restrict__ tidx,
+                                                         const double *__restrict__ s11ub,
+                                                         const double *__restrict__ s11lo, int64_t n_host,
+                                                         const uint32_t *__restrict__ n_dev, int n_dev_mul,
+                                                         BoundOut out, double gamma, int maxM)
+{
+    extern __shared__ float4 lds4[];
+    __shared__ BlockShared sh;
+    float4 *rec = lds4;               // 4 per GMM component
+    float4 *vrec = lds4 + 4 * maxM;   // 2 per vMF component
+    const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, wv = tid >> 6, lane = tid & 63;
+    const int64_t n = n_dev ? (int64_t)n_dev[0] * n_dev_mul : n_host;
+    for (int64_t cube = blockIdx.x; cube < n; cube += gridDim.x) {
+        __syncthreads();
+        const uint32_t pid = pids ? pids[cube] : 0u;
+        if (pid >= (uint32_t)mx.n_prob) {     // invalid problem index: no bound, both drop flags
+            if (tid == 0) {
+                out.ub[cube] = NAN;
+                out.lb[cube] = NAN;
+                if (out.lb_safe) out.lb_safe[cube] = NAN;
+                out.flags[cube] = GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS;
+            }
+            continue;
+        }
+        const ProbDesc P = mx.prob[pid];
+        double r0[3], hr[3], t0[3], tau[3];
+        decode_key(rkeys[cube], P.r_lo, P.r_w, r0, hr);
+        decode_key(tkeys[cube], P.t_lo, P.t_w, t0, tau);
+
+        // psi_r = min(|h_r|, pi) (Lemma 2 bounded with |angle(R_r p, R_s p)| <= |r - s|)
+        const double psir = fmin(sqrt(hr[0] * hr[0] + hr[1] * hr[1] + hr[2] * hr[2]), kPi);
+        uint8_t flags = 0;
+        {
+            double nr2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double lo = r0[k] - hr[k], hi = r0[k] + hr[k];
+                const double nk = lo > 0.0 ? lo : (hi < 0.0 ? hi : 0.0);
+                nr2 += nk * nk;
+            }
+            if (nr2 > kPi * kPi) flags |= GOSMA_FLAG_DROP_ROT;
+        }
+        double R[9];
+        rotation_matrix(r0, R);
+        double crh, srh;
+        sincos(0.5 * psir, &srh, &crh);
+
+        int drop = 0, ubinf = 0;
+        float psum = 0.0f;
+        for (int i = tid; i < P.M; i += T) {
+            const int g = P.gmm_off + i;
+            const TransPrep tp = trans_prep(mx.mu + 3 * g, mx.isig2[g], t0, tau, P.zeta);
+            drop |= tp.drop;
+            ubinf |= tp.ub_inf;
+            psum += mx.pbar[g] * tp.psi;
+            double w[3];
+            for (int a = 0; a < 3; ++a) w[a] = R[3 * a] * tp.u[0] + R[3 * a + 1] * tp.u[1] + R[3 * a + 2] * tp.u[2];
+            // half of Psi = psi_t + psi_r (eq. 25), as cos/sin
+            const double cP = tp.cps * crh - tp.sps * srh, sP = tp.sps * crh + tp.cps * srh;
+            const double ahi = tp.klo + 2.0 * tp.ha;
+            const YFun fk = yfun(tp.kap), fl = yfun(tp.klo), fh = yfun(ahi);
+            rec[4 * i] = make_float4((float)w[0], (float)w[1], (float)w[2], mx.w1[g]);
+            rec[4 * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)cP, (float)sP);
+            rec[4 * i + 2] = make_float4((float)tp.klo, (float)ahi, (float)tp.ha, (float)fl.coth);
+            rec[4 * i + 3] = make_float4((float)fl.G, (float)fh.G, (float)fl.nu, (float)fh.nu);
+        }
+        for (int j = tid; j < P.N; j += T) {
+            vrec[2 * j] = mx.vmf[2 * (P.vmf_off + j)];
+            vrec[2 * j + 1] = mx.vmf[2 * (P.vmf_off + j) + 1];
+        }
+        drop = wave_or(drop);
+        ubinf = wave_or(ubinf);
+        psum = wave_sumf(psum);
+        if (lane == 0) {
+            sh.drop[wv] = drop;
+            sh.ubinf[wv] = ubinf;
+            sh.psum[wv] = psum;
+        }
+        __syncthreads();
+        drop = 0;
+        ubinf = 0;
+        psum = 0.0f;
+        for (int w = 0; w < W; ++w) {
+            drop |= sh.drop[w];
+            ubinf |= sh.ubinf[w];
+            psum += sh.psum[w];
+        }
+        if (drop) flags |= GOSMA_FLAG_DROP_TRANS;
+        if (ubinf) flags |= GOSMA_FLAG_UB_INF;
+        if (psir >= (double)psum) flags |= GOSMA_FLAG_SPLIT_ROT;
+
+        const bool dropped = flags & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS);
+        double acc_ub = 0.0, acc_hi = 0.0;
+        float top[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) top[k] = 0.0f;
+
         if (!dropped) {
-            ub = ubinf ? INFINITY : s11u - 2.0 * acc_ub;
-            lb = s11l - 2.0 * acc_hi;
-            lbs = lb - gamma * (s11l + 2.0 * acc_hi);
+            for (int c = 0; c < P.n_cls; ++c) {
+                const ClassRange cr = mx.cls[P.cls_off + c];
+                const int ni = cr.g1 - cr.g0, nj = cr.v1 - cr.v0;
+                if (ni <= 0 || nj <= 0) continue;
+                const int gb = cr.g0 - P.gmm_off, vb = cr.v0 - P.vmf_off;
+                if (nj % T == 0 || T % nj == 0) {
+                    // each lane keeps one vMF row per column block in registers
+                    // and walks the GMM rows; with T columns the row index is
+                    // the same for the whole block (broadcast LDS reads)
+                    const int cols = nj < T ? nj : T, g = T / cols;
+                    const int jl = tid % cols, i0 = tid / cols;
+                    for (int jb = 0; jb < nj; jb += cols) {
+                        const int j = vb + jb + jl;
+                        const float4 v0 = vrec[2 * j], v1 = vrec[2 * j + 1];
+                        if (g == 1) {
+                            for (int i = 0; i < ni; i += kRun) {
+                                float sub = 0.0f, shi = 0.0f;
+                                const int e = min(ni - i, kRun);
+                                for (int u = 0; u < e; ++u) s12_pair<TOP8>(rec, gb + i + u, v0, v1, sub, shi, top);
+                                acc_ub += (double)sub;
+                                acc_hi += (double)shi;
+                            }
+                        } else {
+                            for (int i = i0; i < ni; i += kRun * g) {
+                                float sub = 0.0f, shi = 0.0f;
+                                for (int u = 0, ii = i; u < kRun && ii < ni; ++u, ii += g)
+                                    s12_pair<TOP8>(rec, gb + ii, v0, v1, sub, shi, top);
+                                acc_ub += (double)sub;
+                                acc_hi += (double)shi;
+                            }
+                        }
+                    }
+                } else {
+                    // flattened (i, j) rectangle of the class, T consecutive pairs per step
+                    int i = tid / nj, j = tid % nj;
+                    const int di = T / nj, dj = T % nj;
+                    while (i < ni) {
+                        float sub = 0.0f, shi = 0.0f;
+                        for (int u = 0; u < kRun && i < ni; ++u) {
+                            const int jj = vb + j;
+                            s12_pair<TOP8>(rec, gb + i, vrec[2 * jj], vrec[2 * jj + 1], sub, shi, top);
+                            j += dj;
+                            i += di;
+                            if (j >= nj) {
+                                j -= nj;
+                                i += 1;
+                            }
+                        }
+                        acc_ub += (double)sub;
+                        acc_hi += (double)shi;
+                    }
+                }
+            }
         }
-        out.ub[cube] = ub;
-        out.lb[cube] = lb;
-        if (out.dstar_bits && ub < INFINITY) {
-            // read first: most cubes do not improve d*, and skipping their
-            // atomics avoids serialising every wave on one address
-            unsigned long long *d = out.dstar_bits + (size_t)pid * out.dstar_stride;
-            const unsigned long long u = ordered_bits(ub);
-            if (u < __atomic_load_n(d, __ATOMIC_RELAXED)) atomicMin(d, u);
+        acc_ub = wave_sum(acc_ub);
+        acc_hi = wave_sum(acc_hi);
+        if (TOP8 && out.top8) {
+            // merge the per-lane sorted lists: 8 rounds of a wave maximum
+            int head = 0;
+            for (int k = 0; k < 8; ++k) {
+                float mine = -1.0f;
+#pragma unroll
+                for (int s = 0; s < 8; ++s)
+                    if (s == head) mine = top[s];
+                float m = mine;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+                // the lowest lane holding the maximum advances its list
+                const unsigned long long ballot = __ballot(mine == m);
+                const int winner = __ffsll((long long)ballot) - 1;
+                if (lane == winner) head++;
+                if (lane == 0) sh.top[wv][k] = fmaxf(m, 0.0f);
+            }
         }
-        if (out.lb_safe) out.lb_safe[cube] = lbs;
-        out.flags[cube] = flags;
-        if (out.aux) {
-            out.aux[4 * cube + 0] = s11u;
-            out.aux[4 * cube + 1] = acc_ub;
-            out.aux[4 * cube + 2] = s11l;
-            out.aux[4 * cube + 3] = acc_hi;
+        if (lane == 0) {
+            sh.s0[wv] = acc_ub;
+            sh.s1[wv] = acc_hi;
         }
-        if (out.psi_gap) out.psi_gap[cube] = (float)(psir - (double)psum);
+        __syncthreads();
+
+        if (tid == 0) {
+            double sub = 0.0, shi = 0.0;
+            for (int w = 0; w < W; ++w) {
+                sub += sh.s0[w];
+                shi += sh.s1[w];
+            }
+            if (TOP8 && out.top8) {
+                // merge the per-wave sorted lists (4-bit heads packed in one word)
+                unsigned heads = 0;
+                for (int k = 0; k < 8; ++k) {
+                    int bw = 0;
+                    float bv = -1.0f;
+                    for (int w = 0; w < W; ++w) {
+                        const int h = (heads >> (4 * w)) & 15;
+                        if (h < 8 && sh.top[w][h] > bv) {
+                            bv = sh.top[w][h];
+                            bw = w;
+                        }
+                    }
+                    heads += 1u << (4 * bw);
+                    out.top8[8 * cube + k] = bv;
+                }
+            }
+            double ub = INFINITY, lb = INFINITY, lbs = INFINITY;
+            const int64_t t = tidx ? tidx[cube] : cube;
+            const double s11u = s11ub[t], s11l = s11lo[t];
+            if (!dropped) {
+                ub = ubinf ? INFINITY : s11u - 2.0 * sub;
+                lb = s11l - 2.0 * shi;
+                lbs = lb - gamma * (s11l + 2.0 * shi);
+            }
+            out.ub[cube] = ub;
+            out.lb[cube] = lb;
+            if (out.dstar_bits && ub < INFINITY) {
+                // read first: most cubes do not improve d*, and skipping their
+                // atomics avoids serialising every wave on one address
+                unsigned long long *d = out.dstar_bits + (size_t)pid * out.dstar_stride;
+                const unsigned long long u = ordered_bits(ub);
+                if (u < __atomic_load_n(d, __ATOMIC_RELAXED)) atomicMin(d, u);
+            }
+            if (out.lb_safe) out.lb_safe[cube] = lbs;
+            out.flags[cube] = flags;
+            if (out.aux) {
+                out.aux[4 * cube + 0] = s11u;
+                out.aux[4 * cube + 1] = sub;
+                out.aux[4 * cube + 2] = s11l;
+                out.aux[4 * cube + 3] = shi;
+            }
+            if (out.psi_gap) out.psi_gap[cube] = (float)(psir - (double)psum);
+        }
     }
 }
 
 }  // namespace
 
+size_t s11_lds_bytes(int maxM) { return sizeof(float4) * 4 * (size_t)maxM; }
+size_t s12_lds_bytes(int maxM, int maxN) { return sizeof(float4) * (4 * (size_t)maxM + 2 * (size_t)maxN); }
+
+hipError_t prepare_bound_kernels(int maxM, int maxN)
+{
+    // allow dynamic LDS beyond the default limit on devices that have it
+    hipError_t e = hipFuncSetAttribute((const void *)k_s11, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)s11_lds_bytes(maxM));
+    if (!e)
+        e = hipFuncSetAttribute((const void *)k_s12<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)s12_lds_bytes(maxM, maxN));
+    if (!e)
+        e = hipFuncSetAttribute((const void *)k_s12<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)s12_lds_bytes(maxM, maxN));
+    return e;
+}
+
+static bool tile_ok(const Tile &t) { return t.waves >= 1 && t.waves <= kMaxWaves && t.blocks >= 1; }
+
 hipError_t launch_s11(const DevMix &mx, const uint64_t *tkeys, const uint32_t *pids, int64_t nt, const uint32_t *nt_dev,
-                      S11Out out, int maxM, int grid, hipStream_t stream)
+                      S11Out out, int maxM, Tile tile, hipStream_t stream)
 {
     if (nt <= 0) return hipSuccess;
-    size_t lds = sizeof(float) * (size_t)A_NF * (size_t)maxM;
-    unsigned g = (unsigned)(grid > 0 ? std::min<int64_t>(grid, nt) : nt);
-    hipLaunchKernelGGL(k_s11, dim3(g), dim3(64), lds, stream, mx, tkeys, pids, nt, nt_dev, out, maxM);
+    if (!tile_ok(tile)) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)std::min<int64_t>(tile.blocks, nt);
+    hipLaunchKernelGGL(k_s11, dim3(g), dim3(64 * tile.waves), s11_lds_bytes(maxM), stream, mx, tkeys, pids, nt,
+                       nt_dev, out);
     return hipGetLastError();
 }
 
 hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                       const int64_t *tidx, const double *s11ub, const double *s11lo, int64_t n, const uint32_t *n_dev,
-                      int n_dev_mul, BoundOut out, double margin_gamma, int maxM, bool with_top8, int grid,
+                      int n_dev_mul, BoundOut out, double margin_gamma, int maxM, int maxN, bool with_top8, Tile tile,
                       hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
-    size_t lds = (sizeof(float) * (size_t)B_NF + sizeof(double) * (size_t)D_NF) * (size_t)maxM;
-    unsigned g = (unsigned)(grid > 0 ? std::min<int64_t>(grid, n) : n);
+    if (!tile_ok(tile)) return hipErrorInvalidValue;
+    const size_t lds = s12_lds_bytes(maxM, maxN);
+    const unsigned g = (unsigned)std::min<int64_t>(tile.blocks, n);
     if (with_top8)
-        hipLaunchKernelGGL(k_s12<true>, dim3(g), dim3(64), lds, stream, mx, rkeys, tkeys, pids, tidx, s11ub, s11lo, n,
-                           n_dev, n_dev_mul, out, margin_gamma, maxM);
+        hipLaunchKernelGGL(k_s12<true>, dim3(g), dim3(64 * tile.waves), lds, stream, mx, rkeys, tkeys, pids, tidx,
+                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM);
     else
-        hipLaunchKernelGGL(k_s12<false>, dim3(g), dim3(64), lds, stream, mx, rkeys, tkeys, pids, tidx, s11ub, s11lo,
-                           n, n_dev, n_dev_mul, out, margin_gamma, maxM);
+        hipLaunchKernelGGL(k_s12<false>, dim3(g), dim3(64 * tile.waves), lds, stream, mx, rkeys, tkeys, pids, tidx,
+                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM);
     return hipGetLastError();
 }
 

@@ -43,7 +43,6 @@ struct DevMix {
     const float *w1;
     const float *pbar;
     const float4 *vmf;
-    const double *vmf64;      // FP64 copy: {dx, dy, dz, kappa} per row
     const ClassRange *cls;
     const ProbDesc *prob;
     int n_prob;
@@ -62,16 +61,27 @@ struct S11Out {
     double *ub, *lo;   // S11 at the centre and its lower bound, per translation cube
 };
 
+// Launch shape of a bound kernel: waves per block (one cell per block; up to
+// kMaxWaves) and the number of blocks of the grid-stride loop over cells.
+constexpr int kMaxWaves = 4;
+struct Tile {
+    int waves, blocks;
+};
+
 // Launchers (bound.hip).  All asynchronous on `stream`.  With a device count
 // pointer (nt_dev / n_dev) the kernels read the number of cells from device
-// memory (times n_dev_mul) and loop over it with a grid of `grid` blocks;
-// the host count is then the maximum.  grid <= 0 launches one block per cell.
+// memory (times n_dev_mul); the host count is then the maximum.  Each launch
+// runs min(tile.blocks, count) blocks of 64 * tile.waves threads.
 hipError_t launch_s11(const DevMix &mx, const uint64_t *tkeys, const uint32_t *pids, int64_t nt, const uint32_t *nt_dev,
-                      S11Out out, int maxM, int grid, hipStream_t stream);
+                      S11Out out, int maxM, Tile tile, hipStream_t stream);
 hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                       const int64_t *tidx, const double *s11ub, const double *s11lo, int64_t n, const uint32_t *n_dev,
-                      int n_dev_mul, BoundOut out, double margin_gamma, int maxM, bool with_top8, int grid,
+                      int n_dev_mul, BoundOut out, double margin_gamma, int maxM, int maxN, bool with_top8, Tile tile,
                       hipStream_t stream);
+// Dynamic LDS of the two kernels, and the per-kernel limit setup for it.
+size_t s11_lds_bytes(int maxM);
+size_t s12_lds_bytes(int maxM, int maxN);
+hipError_t prepare_bound_kernels(int maxM, int maxN);
 
 struct Mlp;
 hipError_t mlp_predict(const Mlp &m, const float *X, int64_t n, const uint32_t *n_dev, float *y, int grid,
@@ -92,10 +102,12 @@ struct gosma_ctx {
     double *d_mu = nullptr, *d_isig2 = nullptr;
     float *d_w1 = nullptr, *d_pbar = nullptr;
     float4 *d_vmf = nullptr;
-    double *d_vmf64 = nullptr;
     gosma::ClassRange *d_cls = nullptr;
     gosma::ProbDesc *d_prob = nullptr;
     std::vector<std::vector<int32_t>> gmm_order;   // original row of each sorted row, per problem
+
+    // launch shapes of the two bound kernels (gosma_set_tiles / gosma_autotune)
+    gosma::Tile tile11{1, 8192}, tile12{1, 8192};
 
     // scratch for gosma_eval_bounds (grown on demand)
     int64_t s11_cap = 0;
@@ -117,6 +129,6 @@ struct gosma_ctx {
     void time_end(int idx, hipStream_t s);
 
     gosma::DevMix mix() const {
-        return gosma::DevMix{d_mu, d_isig2, d_w1, d_pbar, d_vmf, d_vmf64, d_cls, d_prob, n_problems};
+        return gosma::DevMix{d_mu, d_isig2, d_w1, d_pbar, d_vmf, d_cls, d_prob, n_problems};
     }
 };

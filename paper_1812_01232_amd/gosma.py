@@ -24,7 +24,7 @@ EXPORTS = ["gosma_create", "gosma_destroy", "gosma_last_error", "gosma_set_mixtu
            "gosma_set_problems", "gosma_get_S22", "gosma_eval_bounds", "gosma_solve", "gosma_solve_batch",
            "gosma_set_timing", "gosma_get_timing", "gosma_get_trace", "gosma_mlp_init", "gosma_mlp_set_params",
            "gosma_mlp_get_params", "gosma_mlp_predict", "gosma_mlp_loss_grad", "gosma_mlp_train",
-           "gosma_set_record_sink"]
+           "gosma_set_record_sink", "gosma_get_tiles", "gosma_set_tiles", "gosma_autotune"]
 MLP_FEATURES, MLP_RECORD, MLP_PARAMS = 20, 21, 35841
 KERNEL_KINDS = ["s11", "s12", "select", "branch", "push", "mlp"]
 
@@ -45,6 +45,14 @@ class Opts(C.Structure):
                 ("max_iters", C.c_int64), ("time_limit_s", C.c_double), ("order", C.c_int),
                 ("log_records", C.c_int), ("trace_every", C.c_int), ("no_graph", C.c_int),
                 ("learned_window", C.c_double)]
+
+
+class Tile(C.Structure):
+    _fields_ = [("waves", C.c_int32), ("blocks", C.c_int32)]
+
+
+class Tiles(C.Structure):
+    _fields_ = [("s11", Tile), ("s12", Tile)]
 
 
 class Result(C.Structure):
@@ -89,6 +97,10 @@ def lib():
         L.gosma_mlp_train.argtypes = [vp, vp, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_uint64, fp]
         L.gosma_set_record_sink.argtypes = [vp, vp, C.c_int64, vp]
         L.gosma_get_timing.argtypes = [vp, dp, C.POINTER(C.c_int64)]
+        L.gosma_get_tiles.argtypes = [vp, C.POINTER(Tiles)]
+        L.gosma_set_tiles.argtypes = [vp, C.POINTER(Tiles)]
+        L.gosma_autotune.argtypes = [vp, C.c_int64, C.c_uint64, dp, C.c_int64, C.POINTER(C.c_int64),
+                                     C.POINTER(Tiles)]
         _lib = L
     return _lib
 
@@ -272,6 +284,28 @@ class Context:
         """records: device float32 tensor [capacity, 21]; count: device int64 tensor [1] (zeroed)."""
         cap = 0 if records is None else int(records.shape[0])
         self._check(lib().gosma_set_record_sink(self._h, _ptr(records), cap, _ptr(count)), "gosma_set_record_sink")
+
+    # -- launch shapes of the bound kernels ---------------------------------
+    def get_tiles(self):
+        """{"s11": (waves, blocks), "s12": (waves, blocks)}"""
+        t = Tiles()
+        self._check(lib().gosma_get_tiles(self._h, C.byref(t)), "gosma_get_tiles")
+        return {"s11": (t.s11.waves, t.s11.blocks), "s12": (t.s12.waves, t.s12.blocks)}
+
+    def set_tiles(self, s11, s12):
+        t = Tiles(Tile(*s11), Tile(*s12))
+        self._check(lib().gosma_set_tiles(self._h, C.byref(t)), "gosma_set_tiles")
+
+    def autotune(self, n_cubes=32768, seed=0):
+        """Time the candidate launch shapes on random cubes and keep the fastest.
+        Returns {"chosen": get_tiles(), "table": [(kernel, waves, blocks, ms), ...]}."""
+        rows = np.zeros((64, 4))
+        n = C.c_int64()
+        t = Tiles()
+        self._check(lib().gosma_autotune(self._h, int(n_cubes), int(seed), _d(rows), rows.shape[0], C.byref(n),
+                                         C.byref(t)), "gosma_autotune")
+        table = [(KERNEL_KINDS[int(r[0])], int(r[1]), int(r[2]), float(r[3])) for r in rows[:min(n.value, 64)]]
+        return {"chosen": {"s11": (t.s11.waves, t.s11.blocks), "s12": (t.s12.waves, t.s12.blocks)}, "table": table}
 
     # -- kernel timing ----------------------------------------------------
     def set_timing(self, enable=True):

@@ -191,3 +191,70 @@ def test_deterministic(ctx):
     a = ctx.bounds(rk, tk)
     b = ctx.bounds(rk, tk)
     assert np.array_equal(a["ub"], b["ub"]) and np.array_equal(a["lb"], b["lb"])
+
+
+TILES = [(1, 8192), (2, 2048), (4, 1024), (4, 7), (1, 3)]
+
+
+@pytest.mark.parametrize("M,N", [(64, 64), (40, 32), (70, 128), (33, 45), (100, 256)])
+def test_launch_shapes_and_pair_mappings(ctx, M, N):
+    """Every launch shape (waves per block, grid size) on vMF counts that hit
+    each pair mapping: a multiple of the block (broadcast rows), a divisor of
+    it, and neither (flattened rectangle); all against the oracle, and the
+    shapes against each other to FP64 summation order."""
+    sc = scenes.small_scene(M, N, seed=M * 1000 + N, noise_deg=1.0, n_inliers=min(N, 3 * M // 4),
+                            sigma=(0.05, 0.3), t_half=1.0, room=((-5, -5, -1.5), (5, 5, 1.5)))
+    rk, tk = scenes.random_cubes(sc, 600, 5100 + M + N, r_levels=(1, 14), t_levels=(0, 12))
+    ctx.set_scene(sc)
+    o = oracle.OracleProblem(sc).bounds(rk, tk)
+    first = None
+    for t in TILES:
+        ctx.set_tiles(s11=t, s12=t)
+        assert ctx.get_tiles() == {"s11": t, "s12": t}
+        g = ctx.bounds(rk, tk, want_top8=True)
+        _compare(sc, g, o, top8=True, label=f"{M}x{N} tile {t}")
+        if first is None:
+            first = g
+        else:
+            fin = np.isfinite(first["ub"])
+            scale = np.abs(first["aux"][:, 0]) + 2 * np.abs(first["aux"][:, 1])
+            assert np.all(np.abs(g["ub"][fin] - first["ub"][fin]) <= 1e-6 * scale[fin])
+            assert np.array_equal(g["flags"], first["flags"])
+
+
+def test_autotune(ctx):
+    """The autotuner times 3 x 4 shapes per kernel, keeps one of them, and the
+    bounds under the chosen shapes still match the oracle."""
+    sc = scenes.cfg2_scene(0)
+    ctx.set_scene(sc)
+    res = ctx.autotune(n_cubes=8192, seed=1)
+    table = res["table"]
+    assert len(table) == 24
+    for kind in ("s11", "s12"):
+        rows = [r for r in table if r[0] == kind]
+        assert len(rows) == 12 and all(r[3] > 0 for r in rows)
+        best = min(rows, key=lambda r: r[3])
+        assert res["chosen"][kind] == (best[1], best[2])
+    assert ctx.get_tiles() == res["chosen"]
+    print("autotune chosen", res["chosen"])
+    rk, tk = scenes.random_cubes(sc, 1000, 2800, r_levels=(2, 12), t_levels=(1, 10))
+    g = ctx.bounds(rk, tk)
+    _compare(sc, g, oracle.OracleProblem(sc).bounds(rk, tk), label="after-autotune")
+    from paper_1812_01232_amd import GosmaError
+    with pytest.raises(GosmaError):
+        ctx.set_tiles(s11=(3, 10), s12=(1, 10))
+    with pytest.raises(GosmaError):
+        ctx.set_tiles(s11=(1, 0), s12=(1, 10))
+
+
+def test_max_components(ctx):
+    """The largest problem the library accepts: M = N = 1024 (LDS per block
+    64 M + 32 N bytes), a few cubes checked one by one."""
+    sc = scenes.small_scene(1024, 1024, seed=77, noise_deg=1.0, n_inliers=700, sigma=(0.05, 0.3), t_half=1.0,
+                            room=((-5, -5, -1.5), (5, 5, 1.5)))
+    rk, tk = scenes.random_cubes(sc, 12, 5300, r_levels=(2, 12), t_levels=(1, 10))
+    ctx.set_scene(sc)
+    for t in [(1, 64), (4, 64)]:
+        ctx.set_tiles(s11=t, s12=t)
+        g = ctx.bounds(rk, tk)
+        _compare(sc, g, oracle.OracleProblem(sc).bounds(rk, tk), label=f"1024x1024 tile {t}")
