@@ -34,15 +34,47 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Op model (VALU issue slots; a transcendental = 4 slots, everything else 1).
-S12_PLAIN, S12_TRANS = 90, 8
-TRANS_SLOTS = 4
+# Op model of one GMM-vMF pair in the bound kernel, counted from its source
+# (the design doc lists the count): 107 plain FP32 VALU operations and 12
+# transcendentals (sqrt, rcp, exp2).  A transcendental issues at half the
+# plain rate on gfx950 (measured 1.8-1.9 plain-op slots), so it counts 2.
+S12_PLAIN, S12_TRANS = 107, 12
+TRANS_SLOTS = 2
 S12_SLOTS = S12_PLAIN + TRANS_SLOTS * S12_TRANS
-S12_FLOPS = S12_PLAIN + S12_TRANS + 20      # FMAs counted twice (20 per pair)
+S12_FLOPS = S12_PLAIN + S12_TRANS + 13      # 13 of the plain operations are FMAs
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9            # CUs x SIMDs x lanes x clock
 PEAK_FP32_TFLOPS = 157.3
 BATCH_PARENTS = 4096
 BATCH = 8 * BATCH_PARENTS
+
+
+def measured_traffic():
+    """HBM bytes per launch of the bound kernel from the committed counter
+    summary, or None once the kernel source differs from the one measured."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "k_s12_64x64_pmc.md")
+    src = os.path.join(ROOT, "paper_1812_01232_amd", "csrc", "bound.hip")
+    try:
+        fields = dict(line.strip().split("=", 1) for line in open(prof) if "=" in line and " " not in line.strip())
+        with open(src, "rb") as f:
+            current = hashlib.sha256(f.read()).hexdigest()
+        if fields.get("bound_hip_sha256") == current:
+            return int(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        pass
+    return None
+
+
+def copy_calibration(mib):
+    """A plain device copy of `mib` MiB, three times (for scaling byte counters)."""
+    import torch
+    n = (mib << 20) // 4
+    a = torch.zeros(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_mib": mib, "launches": 3}), flush=True)
 
 
 def host_cores():
@@ -119,7 +151,9 @@ def learned_comparison(ctx, n_eval, eps, records_cap, epochs, time_cap):
     """Log records from searches, train the network on them, then time to eps
     with plain and learned order on fresh 64x64 scenes."""
     import torch
+    from paper_1812_01232_amd.gosma import GosmaError
     from synth import scenes
+    QUEUE_OVERFLOW = -4
     dev = torch.device("cuda", 0)
     recs = torch.zeros((records_cap, 21), dtype=torch.float32, device=dev)
     cnt = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -129,7 +163,11 @@ def learned_comparison(ctx, n_eval, eps, records_cap, epochs, time_cap):
     while int(cnt.item()) < records_cap and i < 12:
         for sc in (scenes.cfg1_scene(10 + i), scenes.cfg2_scene(10 + i)):
             ctx.set_scene(sc)
-            ctx.solve(eps, batch_parents=BATCH_PARENTS, max_queue=1 << 26, time_limit_s=6, log_records=1)
+            try:
+                ctx.solve(eps, batch_parents=BATCH_PARENTS, max_queue=1 << 27, time_limit_s=6, log_records=1)
+            except GosmaError as e:     # a full queue ends the search; its records stay valid
+                if e.code != QUEUE_OVERFLOW:
+                    raise
         i += 1
     ctx.set_record_sink(None, None)
     n = min(int(cnt.item()), records_cap)
@@ -148,19 +186,23 @@ def learned_comparison(ctx, n_eval, eps, records_cap, epochs, time_cap):
     out = {"records": n, "collect_s": collect_s, "train_s": train_s, "train_loss": [float(h) for h in hist],
            "heldout_mae": float(np.mean(np.abs(yp - yt))), "heldout_mae_mean_predictor": float(np.mean(np.abs(yt - yt.mean()))),
            "eps": eps, "scenes": []}
+    variants = (("plain", {}), ("learned", {"order": 1, "learned_window": eps}),
+                ("learned_unclamped", {"order": 1}))
     for k in range(n_eval):
         sc = scenes.cfg2_scene(seed=5000 + k)
         ctx.set_scene(sc)
         row = {"seed": 5000 + k}
-        for name, kw in (("plain", {}), ("learned", {"order": 1, "learned_window": eps})):
-            r = ctx.solve(eps, batch_parents=BATCH_PARENTS, max_queue=1 << 27, time_limit_s=time_cap, **kw)
+        for name, kw in variants:
+            r = ctx.solve(eps, batch_parents=BATCH_PARENTS, max_queue=1 << 29, time_limit_s=time_cap,
+                          allow_overflow=True, **kw)
             row[name] = {"status": r["status"], "seconds": r["seconds"], "cubes": r["cubes"],
                          "f_norm": r["f_norm_best"], "lb_norm": r["lb_norm"]}
         out["scenes"].append(row)
-    for name in ("plain", "learned"):
-        t = np.array([s[name]["seconds"] for s in out["scenes"]])
-        out[f"{name}_median_s"] = float(np.median(t))
-        out[f"{name}_iqr_s"] = [float(np.percentile(t, 25)), float(np.percentile(t, 75))]
+    # status 0 = eps-certified; 2 = time cap; 3 = queue capacity (both uncertified)
+    for name, _ in variants:
+        t = np.array([s[name]["seconds"] for s in out["scenes"] if s[name]["status"] == 0])
+        out[f"{name}_certified"] = int(t.size)
+        out[f"{name}_median_s_certified"] = float(np.median(t)) if t.size else None
     return out
 
 
@@ -171,8 +213,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-eps runs")
-    ap.add_argument("--learned-scenes", type=int, default=3)
+    ap.add_argument("--learned-scenes", type=int, default=4)
     ap.add_argument("--records", type=int, default=1_000_000)
+    ap.add_argument("--copy-mib", type=int, default=0, help="only run a plain copy of this size (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; how the search would shard over "
@@ -184,6 +227,9 @@ def main():
     from synth import scenes
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_mib > 0:
+        copy_calibration(args.copy_mib)
+        return
     scene = scenes.cfg2_scene(0)
     ctx = Context(0)
     ctx.set_scene(scene)
@@ -222,7 +268,7 @@ def main():
         "bound_kernels_only": {"cube_bounds_per_s": krate, "live_cubes": live,
                                "ms_per_launch": {"s12": s12_ms / s12_n, "s11": kt["s11"][0] / kt["s11"][1]}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
-                     "frac": achieved / peak, "traffic": None, "kernel": "k_s12 (GMM-vMF pair sums)",
+                     "frac": achieved / peak, "traffic": measured_traffic(), "traffic_unit": "bytes/launch", "kernel": "k_s12 (GMM-vMF pair sums)",
                      "fp32_tflops": live * M * N * S12_FLOPS / s12_avg_s / 1e12,
                      "fp32_peak_tflops": PEAK_FP32_TFLOPS},
     }
@@ -234,7 +280,7 @@ def main():
                                     "cubes": r1["cubes"], "f_norm": r1["f_norm_best"], "lb_norm": r1["lb_norm"]}
         if args.learned_scenes > 0:
             rec["time_to_eps_64x64_plain_vs_learned"] = learned_comparison(
-                ctx, args.learned_scenes, 1e-2, args.records, 4, 60)
+                ctx, args.learned_scenes, 1e-2, args.records, 4, 8.0)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(scene)
     ctx.close()

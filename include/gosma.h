@@ -154,12 +154,14 @@ typedef struct {
     int64_t iters, cubes;    /* iterations run, sub-cubes bounded */
     int64_t max_queue_used;
     double seconds;          /* wall time inside the call */
-    int status;              /* 0 eps-optimal, 1 queue exhausted, 2 iteration/time cap */
+    int status;              /* 0 eps-optimal, 1 queue exhausted, 2 iteration/time cap, 3 queue
+                                capacity reached (f_best and lb_global still bound the optimum) */
 } gosma_result;
 
 /* Solve problem 0 to eps-optimality (Algorithm 1 without local refinement).
  * Host structs in and out; synchronous.  GOSMA_E_QUEUE_OVERFLOW if the queue
- * capacity is exceeded (the result then holds the state reached). */
+ * capacity is exceeded: the result then holds the state reached, with status
+ * 3; its lb_global includes the lower bounds of the cubes that did not fit. */
 int gosma_solve(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *result);
 
 /* Search trace of the last gosma_solve with opts->trace_every > 0 (the
@@ -172,7 +174,9 @@ int gosma_get_trace(gosma_ctx *ctx, double *buf, int64_t cap, int64_t *n);
 /* Solve every problem of gosma_set_problems together: each iteration pops
  * up to opts->batch_parents cubes from every unfinished problem's queue and
  * bounds all their children in one launch.  result: host array of
- * n_problems structs.  Synchronous. */
+ * n_problems structs.  Synchronous.  A problem whose queue fills up stops with
+ * status 3 while the others go on; the call then returns
+ * GOSMA_E_QUEUE_OVERFLOW with every result filled. */
 int gosma_solve_batch(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *results);
 
 /* ------------------------------------------------------------------ */
@@ -248,7 +252,7 @@ int gosma_set_tiles(gosma_ctx *ctx, const gosma_tiles *tiles);
 /* Autotuner: draws n_cubes random cubes of the current problems (levels 2-10
  * in rotation, 1-8 in translation, inside the rotation ball; deterministic
  * per seed), times every candidate shape of both kernels on them with HIP
- * events (waves 1, 2, 4 x grids of 2048, 4096, 8192, 16384 waves; one
+ * events (waves 1, 2, 4 x grids of 2048 to 32768 waves in powers of 2; one
  * warm-up and three timed launches each), and keeps the fastest.  rows:
  * NULL or a host array of cap x 4 doubles receiving {kernel (GOSMA_KERNEL_S11
  * or GOSMA_KERNEL_S12), waves, blocks, ms per launch} per candidate; *n_rows

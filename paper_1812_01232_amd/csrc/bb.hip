@@ -1154,7 +1154,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         r.cubes = (int64_t)h.bounded;
         r.max_queue_used = (int64_t)h.nH[h.hcur] + h.nC[h.ccur];
         r.seconds = seconds;
-        r.status = h.done == EPS_OPTIMAL ? 0 : (h.done == EXHAUSTED ? 1 : 2);
+        r.status = h.done == EPS_OPTIMAL ? 0 : (h.done == EXHAUSTED ? 1 : (h.done == OVERFLOW ? 3 : 2));
         const ProbDesc &D = ctx->h_prob[p];
         auto centre = [](uint64_t key, const double *lo, const double *w, double *c) {
             const uint64_t m = (1ull << 19) - 1;

@@ -62,6 +62,27 @@ __device__ __forceinline__ void decode_key(uint64_t key, const double *lo, const
     }
 }
 
+// sin and cos in FP64 for the rotation angles of a cell: the argument is
+// reduced to [-pi, pi] with one multiple of 2 pi (exact enough for the
+// |x| < 1e6 of any finite domain) and both Maclaurin series are summed in
+// nested form through x^27 and x^26 (truncation below 3e-15 on [-pi, pi]).
+// A short fixed sequence keeps the register footprint of the per-cell set-up
+// small next to the library routine.
+__device__ __forceinline__ void sincos_reduced(double x, double *s, double *c)
+{
+    constexpr double kTwoPi = 6.283185307179586476925286766559;
+    x -= kTwoPi * rint(x * (1.0 / kTwoPi));
+    const double x2 = x * x;
+    double ts = 1.0, tc = 1.0;
+#pragma unroll
+    for (int k = 13; k >= 1; --k) {
+        ts = fma(-x2 * (1.0 / ((2.0 * k) * (2.0 * k + 1.0))), ts, 1.0);
+        tc = fma(-x2 * (1.0 / ((2.0 * k - 1.0) * (2.0 * k))), tc, 1.0);
+    }
+    *s = x * ts;
+    *c = tc;
+}
+
 // Rotation matrix of the angle-axis vector r (Section 5.1), as
 // I + A [r]x + B [r]x^2 with A = sin|r|/|r|, B = (1 - cos|r|)/|r|^2.
 __device__ void rotation_matrix(const double r[3], double R[9])
@@ -73,7 +94,7 @@ __device__ void rotation_matrix(const double r[3], double R[9])
         B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
     } else {
         double th = sqrt(th2), sh, ch;
-        sincos(0.5 * th, &sh, &ch);
+        sincos_reduced(0.5 * th, &sh, &ch);
         A = 2.0 * sh * ch / th;
         B = 2.0 * sh * sh / th2;
     }
@@ -167,6 +188,7 @@ __device__ TransPrep trans_prep(const double *mu, double isig2, const double t0[
     // with a = c - s tau, computed without cancellation.
     bool guard = inside;
     double best_s2 = -1.0, best_c2 = 1.0;
+#pragma unroll 1   // sequential: keeps the FP64 set-up's register footprint small
     for (int v = 0; v < 8; ++v) {
         double st[3] = {(v & 4) ? tau[0] : -tau[0], (v & 2) ? tau[1] : -tau[1], (v & 1) ? tau[2] : -tau[2]};
         double a[3] = {c[0] - st[0], c[1] - st[1], c[2] - st[2]};
@@ -557,7 +579,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         double R[9];
         rotation_matrix(r0, R);
         double crh, srh;
-        sincos(0.5 * psir, &srh, &crh);
+        sincos_reduced(0.5 * psir, &srh, &crh);
 
         int drop = 0, ubinf = 0;
         float psum = 0.0f;

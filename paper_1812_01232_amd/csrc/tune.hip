@@ -146,13 +146,13 @@ int gosma_autotune(gosma_ctx *ctx, int64_t n_cubes, uint64_t seed, double *rows,
     // S11 results feed the S12 launches; compute them once with the current shape
     e = run(GOSMA_KERNEL_S11, ctx->tile11);
     const int waves_c[3] = {1, 2, 4};
-    const int grid_c[4] = {2048, 4096, 8192, 16384};
+    const int grid_c[5] = {2048, 4096, 8192, 16384, 32768};
     Tile best[2] = {ctx->tile11, ctx->tile12};
     double best_ms[2] = {INFINITY, INFINITY};
     int64_t row = 0;
     for (int kernel = GOSMA_KERNEL_S11; kernel <= GOSMA_KERNEL_S12 && !e; ++kernel)
         for (int wi = 0; wi < 3 && !e; ++wi)
-            for (int gi = 0; gi < 4 && !e; ++gi) {
+            for (int gi = 0; gi < 5 && !e; ++gi) {
                 const Tile t{waves_c[wi], grid_c[gi] / waves_c[wi]};
                 if ((e = run(kernel, t))) break;    // warm-up
                 if ((e = hipEventRecord(ev0, nullptr))) break;

@@ -16,6 +16,7 @@ import numpy as np
 LIB_PATH = Path(__file__).resolve().parent / "libgosma.so"
 
 GOSMA_OK = 0
+QUEUE_OVERFLOW = -4
 ERRORS = {-1: "GOSMA_E_INVAL", -2: "GOSMA_E_NOMEM", -3: "GOSMA_E_HIP", -4: "GOSMA_E_QUEUE_OVERFLOW",
           -5: "GOSMA_E_STATE"}
 FLAG_SPLIT_ROT, FLAG_DROP_ROT, FLAG_DROP_TRANS, FLAG_UB_INF = 1, 2, 4, 8
@@ -320,11 +321,14 @@ class Context:
 
     # -- branch and bound -------------------------------------------------
     def solve(self, eps, batch_parents=4096, max_queue=1 << 24, max_iters=0, time_limit_s=0.0, order=0,
-              log_records=0, trace_every=0, no_graph=False, learned_window=0.0):
+              log_records=0, trace_every=0, no_graph=False, learned_window=0.0, allow_overflow=False):
+        """With allow_overflow a full queue returns the result (status 3) instead of raising."""
         o = Opts(eps, batch_parents, max_queue, max_iters, time_limit_s, order, log_records, trace_every,
                  int(bool(no_graph)), float(learned_window))
         r = Result()
-        self._check(lib().gosma_solve(self._h, C.byref(o), C.byref(r)), "gosma_solve")
+        rc = lib().gosma_solve(self._h, C.byref(o), C.byref(r))
+        if not (allow_overflow and rc == QUEUE_OVERFLOW):
+            self._check(rc, "gosma_solve")
         return _result_dict(r)
 
     def trace(self):
@@ -336,11 +340,14 @@ class Context:
         return buf[:n.value]
 
     def solve_batch(self, n_problems, eps, batch_parents=2048, max_queue=1 << 22, max_iters=0, time_limit_s=0.0,
-                    order=0, no_graph=False, learned_window=0.0):
+                    order=0, no_graph=False, learned_window=0.0, allow_overflow=False):
+        """With allow_overflow problems whose queue filled up come back with status 3 instead of raising."""
         o = Opts(eps, batch_parents, max_queue, max_iters, time_limit_s, order, 0, 0, int(bool(no_graph)),
                  float(learned_window))
         rs = (Result * n_problems)()
-        self._check(lib().gosma_solve_batch(self._h, C.byref(o), rs), "gosma_solve_batch")
+        rc = lib().gosma_solve_batch(self._h, C.byref(o), rs)
+        if not (allow_overflow and rc == QUEUE_OVERFLOW):
+            self._check(rc, "gosma_solve_batch")
         return [_result_dict(r) for r in rs]
 
 

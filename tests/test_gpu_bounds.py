@@ -223,16 +223,16 @@ def test_launch_shapes_and_pair_mappings(ctx, M, N):
 
 
 def test_autotune(ctx):
-    """The autotuner times 3 x 4 shapes per kernel, keeps one of them, and the
+    """The autotuner times 3 x 5 shapes per kernel, keeps one of them, and the
     bounds under the chosen shapes still match the oracle."""
     sc = scenes.cfg2_scene(0)
     ctx.set_scene(sc)
     res = ctx.autotune(n_cubes=8192, seed=1)
     table = res["table"]
-    assert len(table) == 24
+    assert len(table) == 30
     for kind in ("s11", "s12"):
         rows = [r for r in table if r[0] == kind]
-        assert len(rows) == 12 and all(r[3] > 0 for r in rows)
+        assert len(rows) == 15 and all(r[3] > 0 for r in rows)
         best = min(rows, key=lambda r: r[3])
         assert res["chosen"][kind] == (best[1], best[2])
     assert ctx.get_tiles() == res["chosen"]

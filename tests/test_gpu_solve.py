@@ -99,6 +99,8 @@ def test_solve_caps_and_errors(ctx):
     with pytest.raises(GosmaError) as ei:
         ctx.solve(1e-3, batch_parents=64, max_queue=64)
     assert ei.value.code == -4
+    full = ctx.solve(1e-3, batch_parents=64, max_queue=64, allow_overflow=True)
+    assert full["status"] == 3 and full["lb_norm"] <= full["f_norm_best"]
     with pytest.raises(GosmaError):
         ctx.solve(1e-3, batch_parents=0)
 
