@@ -107,6 +107,37 @@ def search_rate(ctx, steps, warmup):
     return cubes / dt, dt / steps * 1e3, kt, b, b["max_queue_used"]
 
 
+def other_workload_rates(ctx, warmup=20, steps=40):
+    """Search rate on the two other workload shapes, each after the autotuner:
+    the 256x256 labelled scene (16,384 parents = 131,072 cubes per step) and
+    128 problems with M, N uniform on [16, 256] (2,048 parents each, up to
+    2.1 M cubes per step), by the same two-search difference as the main rate."""
+    from synth import scenes
+    out = {}
+    ctx.set_scene(scenes.cfg3_scene(0))
+    tiles = ctx.autotune(32768, seed=3)["chosen"]
+    kw = dict(batch_parents=16384, max_queue=1 << 27)
+    ctx.solve(1e-9, max_iters=warmup, **kw)
+    a = ctx.solve(1e-9, max_iters=warmup, **kw)
+    b = ctx.solve(1e-9, max_iters=warmup + steps, **kw)
+    dt = b["seconds"] - a["seconds"]
+    out["labelled_256x256"] = {"cube_bounds_per_s": (b["cubes"] - a["cubes"]) / dt, "ms_per_step": dt / steps * 1e3,
+                               "cubes_per_step": (b["cubes"] - a["cubes"]) / steps, "tiles": tiles}
+    scs = scenes.batch_scenes(128, seed=4000)
+    ctx.set_scenes(scs)
+    tiles = ctx.autotune(32768, seed=4)["chosen"]
+    kw = dict(batch_parents=2048, max_queue=1 << 21, allow_overflow=True)
+    ctx.solve_batch(128, 1e-9, max_iters=warmup, **kw)
+    ra = ctx.solve_batch(128, 1e-9, max_iters=warmup, **kw)
+    rb = ctx.solve_batch(128, 1e-9, max_iters=warmup + steps, **kw)
+    dt = rb[0]["seconds"] - ra[0]["seconds"]
+    cubes = sum(r["cubes"] for r in rb) - sum(r["cubes"] for r in ra)
+    pairs = sum((r1["cubes"] - r0["cubes"]) * (s.M * s.N + s.M * (s.M - 1) // 2) for r0, r1, s in zip(ra, rb, scs))
+    out["batch_128"] = {"cube_bounds_per_s": cubes / dt, "ms_per_step": dt / steps * 1e3, "cubes_per_step": cubes / steps,
+                        "pair_terms_per_s": 2 * pairs / dt, "tiles": tiles}
+    return out
+
+
 def kernel_rate(ctx, scene, reps):
     """Bound kernels alone on one 32,768-cube batch (cells across levels 2-12 / 1-10)."""
     import torch
@@ -213,6 +244,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-eps runs")
+    ap.add_argument("--no-other", action="store_true", help="skip the 256x256 and 128-problem rates")
     ap.add_argument("--learned-scenes", type=int, default=4)
     ap.add_argument("--records", type=int, default=1_000_000)
     ap.add_argument("--copy-mib", type=int, default=0, help="only run a plain copy of this size (counter scaling)")
@@ -272,6 +304,8 @@ def main():
                      "fp32_tflops": live * M * N * S12_FLOPS / s12_avg_s / 1e12,
                      "fp32_peak_tflops": PEAK_FP32_TFLOPS},
     }
+    if not args.no_other:
+        rec["other_workloads"] = other_workload_rates(ctx)
     if not args.no_solve:
         sc1 = scenes.cfg1_scene(0)
         ctx.set_scene(sc1)
