@@ -17,8 +17,9 @@
 // launch shape chosen by the autotuner).  The per-component quantities of the
 // cell (kappa, its interval over the cell, uncertainty half-angles, rotated
 // directions, normaliser factors) are computed in FP64, one component per
-// thread, and staged in LDS as one 64-byte FP32 record per component, read
-// back with 16-byte loads.  The pair sums then run over the (i, j) rectangle
+// thread, and staged in LDS as one FP32 record per component (four float4,
+// padded to 80 bytes so that neighbouring records fall on distinct banks),
+// read back with 16-byte loads.  The pair sums then run over the (i, j) rectangle
 // of each class: when the class's vMF count divides the block or is a
 // multiple of it, each thread keeps one vMF row in registers and walks the
 // GMM rows (the same row for the whole wave when the count is a multiple, so
@@ -291,19 +292,24 @@ struct BlockShared {
 // the runs are accumulated in FP64.
 constexpr int kRun = 8;
 
+// LDS record strides in float4: a GMM record holds four float4 and a vMF
+// record two; the padding makes the strides 20 and 12 dwords, so 16-byte
+// reads of consecutive records by consecutive lanes hit distinct banks.
+constexpr int kG = 5, kV = 3;
+
 // ---------------------------------------------------------------------------
 // S11 over translation cells
 // ---------------------------------------------------------------------------
 //
-// Component record in LDS, four float4 (64 bytes):
+// Component record in LDS, four float4 (64 bytes, padded to 80):
 //   [0] u (unit vector mu - t0), weight      [1] kappa(t0), G(kappa), cos, sin of psi_t / 2
 //   [2] kappa interval centre ac, half-width ha, G(ac), nu(ac)
 //   [3] lambda = min(1/3, 1/klo^2), -, -, -
 
-__device__ __forceinline__ void s11_pair(const float4 *__restrict__ rec, int a_, int b_, float &sub, float &slo)
+__device__ __forceinline__ void s11_terms(const float4 &A0, const float4 &A1, const float4 &A2, const float4 &A3,
+                                          const float4 &B0, const float4 &B1, const float4 &B2, const float4 &B3,
+                                          float &sub, float &slo)
 {
-    const float4 A0 = rec[4 * a_], A1 = rec[4 * a_ + 1], A2 = rec[4 * a_ + 2], A3 = rec[4 * a_ + 3];
-    const float4 B0 = rec[4 * b_], B1 = rec[4 * b_ + 1], B2 = rec[4 * b_ + 2], B3 = rec[4 * b_ + 3];
     const float dx = A0.x - B0.x, dy = A0.y - B0.y, dz = A0.z - B0.z;
     const float q = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     const float px = A0.x + B0.x, py = A0.y + B0.y, pz = A0.z + B0.z;
@@ -337,6 +343,12 @@ __device__ __forceinline__ void s11_pair(const float4 *__restrict__ rec, int a_,
         const float corr = -fabsf(ga) * ha - fabsf(gb) * hb - 0.5f * lam * fmaf(ha, ha, hb * hb);
         slo += w2 * (fexp2((k.x + corr) * kLog2e) * k.hK * A2.z * B2.z);
     }
+}
+
+__device__ __forceinline__ void s11_pair(const float4 *__restrict__ rec, int a_, int b_, float &sub, float &slo)
+{
+    s11_terms(rec[kG * a_], rec[kG * a_ + 1], rec[kG * a_ + 2], rec[kG * a_ + 3], rec[kG * b_], rec[kG * b_ + 1],
+              rec[kG * b_ + 2], rec[kG * b_ + 3], sub, slo);
 }
 
 __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_t *__restrict__ tkeys,
@@ -377,10 +389,10 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             const YFun fk = yfun(tp.kap), fa = yfun(tp.ac), fl = yfun(tp.klo);
             dub += w * w * 0.5 * tp.kap * fk.coth;
             dlo += w * w * 0.5 * tp.klo * fl.coth;
-            rec[4 * i] = make_float4((float)tp.u[0], (float)tp.u[1], (float)tp.u[2], (float)w);
-            rec[4 * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)tp.cps, (float)tp.sps);
-            rec[4 * i + 2] = make_float4((float)tp.ac, (float)tp.ha, (float)fa.G, (float)fa.nu);
-            rec[4 * i + 3] = make_float4((float)fmin(1.0 / 3.0, 1.0 / (tp.klo * tp.klo)), 0.0f, 0.0f, 0.0f);
+            rec[kG * i] = make_float4((float)tp.u[0], (float)tp.u[1], (float)tp.u[2], (float)w);
+            rec[kG * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)tp.cps, (float)tp.sps);
+            rec[kG * i + 2] = make_float4((float)tp.ac, (float)tp.ha, (float)fa.G, (float)fa.nu);
+            rec[kG * i + 3] = make_float4((float)fmin(1.0 / 3.0, 1.0 / (tp.klo * tp.klo)), 0.0f, 0.0f, 0.0f);
         }
         drop = wave_or(drop);
         ubinf = wave_or(ubinf);
@@ -409,6 +421,38 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             const int n = cr.g1 - cr.g0;
             if (n < 2) continue;
             const int base = cr.g0 - P.gmm_off;
+            // Circulant walk: a thread keeps component f's record in registers and
+            // visits f + d (mod n) for d = 1 .. n/2, so each unordered pair is met
+            // once (d = n/2 only from f < n/2 when n is even); with n < T, g = T/n
+            // threads share f and take every g-th distance.  Used when it keeps at
+            // least 90% of the threads busy.
+            const int gq = n < T ? T / n : 1;
+            const int fstep = n < T ? n : T;
+            const int passes = (n + T - 1) / T;
+            if (n < T ? 10 * gq * n >= 9 * T : 10 * n >= 9 * T * passes) {
+                const int q = n < T ? tid / n : 0;
+                if (q < gq) {
+                    for (int f = n < T ? tid % n : tid; f < n; f += fstep) {
+                        const int a_ = base + f;
+                        const float4 A0 = rec[kG * a_], A1 = rec[kG * a_ + 1], A2 = rec[kG * a_ + 2],
+                                     A3 = rec[kG * a_ + 3];
+                        const int dmax = (n & 1) ? (n - 1) / 2 : (f < n / 2 ? n / 2 : n / 2 - 1);
+                        for (int d0 = 1 + q; d0 <= dmax; d0 += kRun * gq) {
+                            float sub = 0.0f, slo = 0.0f;
+                            for (int u = 0, d = d0; u < kRun && d <= dmax; ++u, d += gq) {
+                                int o = f + d;
+                                o -= o >= n ? n : 0;
+                                const int b_ = base + o;
+                                s11_terms(A0, A1, A2, A3, rec[kG * b_], rec[kG * b_ + 1], rec[kG * b_ + 2],
+                                          rec[kG * b_ + 3], sub, slo);
+                            }
+                            acc_ub += (double)sub;
+                            acc_lo += (double)slo;
+                        }
+                    }
+                }
+                continue;
+            }
             // The upper triangle (i <= i') of the class, folded into a rectangle of
             // n2/2 rows and n2 + 1 columns (n2 = n rounded up to even): folded row
             // r holds triangle rows r and n2 - 1 - r.  T consecutive cells per step.
@@ -462,12 +506,12 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
 // S12 over rotation x translation cells, and the final bounds
 // ---------------------------------------------------------------------------
 //
-// GMM component record in LDS, four float4 (64 bytes):
+// GMM component record in LDS, four float4 (64 bytes, padded to 80):
 //   [0] w = R_r0 u (rotated unit vector), weight
 //   [1] kappa(t0), G(kappa), cos, sin of Psi / 2 with Psi = psi_t + psi_r (eq. 25)
 //   [2] kappa interval [alo, ahi] over the cell, half-width ha, coth(alo)
 //   [3] G(alo), G(ahi), nu(alo), nu(ahi)
-// vMF record, two float4 (32 bytes): {dx, dy, dz, kappa}, {weight, G(kappa), coth(kappa), 0}.
+// vMF record, two float4 (32 bytes, padded to 48): {dx, dy, dz, kappa}, {weight, G(kappa), coth(kappa), 0}.
 //
 // Upper bound of the summand over the cube (Theorem 1 with kappa_1i(t)
 // relaxed to [alo, ahi]): at the smallest angle B, and with
@@ -482,7 +526,7 @@ template <bool TOP8>
 __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, int a_, const float4 &v0, const float4 &v1,
                                          float &sub, float &shi, float (&top)[8])
 {
-    const float4 R0 = rec[4 * a_], R1 = rec[4 * a_ + 1], R2 = rec[4 * a_ + 2], R3 = rec[4 * a_ + 3];
+    const float4 R0 = rec[kG * a_], R1 = rec[kG * a_ + 1], R2 = rec[kG * a_ + 2], R3 = rec[kG * a_ + 3];
     const float b = v0.w;
     const float dx = R0.x - v0.x, dy = R0.y - v0.y, dz = R0.z - v0.z;
     const float q = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
@@ -544,7 +588,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
     extern __shared__ float4 lds4[];
     __shared__ BlockShared sh;
     float4 *rec = lds4;               // 4 per GMM component
-    float4 *vrec = lds4 + 4 * maxM;   // 2 per vMF component
+    float4 *vrec = lds4 + kG * maxM;  // kV per vMF component
     const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, wv = tid >> 6, lane = tid & 63;
     const int64_t n = n_dev ? (int64_t)n_dev[0] * n_dev_mul : n_host;
     for (int64_t cube = blockIdx.x; cube < n; cube += gridDim.x) {
@@ -595,14 +639,14 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             const double cP = tp.cps * crh - tp.sps * srh, sP = tp.sps * crh + tp.cps * srh;
             const double ahi = tp.klo + 2.0 * tp.ha;
             const YFun fk = yfun(tp.kap), fl = yfun(tp.klo), fh = yfun(ahi);
-            rec[4 * i] = make_float4((float)w[0], (float)w[1], (float)w[2], mx.w1[g]);
-            rec[4 * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)cP, (float)sP);
-            rec[4 * i + 2] = make_float4((float)tp.klo, (float)ahi, (float)tp.ha, (float)fl.coth);
-            rec[4 * i + 3] = make_float4((float)fl.G, (float)fh.G, (float)fl.nu, (float)fh.nu);
+            rec[kG * i] = make_float4((float)w[0], (float)w[1], (float)w[2], mx.w1[g]);
+            rec[kG * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)cP, (float)sP);
+            rec[kG * i + 2] = make_float4((float)tp.klo, (float)ahi, (float)tp.ha, (float)fl.coth);
+            rec[kG * i + 3] = make_float4((float)fl.G, (float)fh.G, (float)fl.nu, (float)fh.nu);
         }
         for (int j = tid; j < P.N; j += T) {
-            vrec[2 * j] = mx.vmf[2 * (P.vmf_off + j)];
-            vrec[2 * j + 1] = mx.vmf[2 * (P.vmf_off + j) + 1];
+            vrec[kV * j] = mx.vmf[2 * (P.vmf_off + j)];
+            vrec[kV * j + 1] = mx.vmf[2 * (P.vmf_off + j) + 1];
         }
         drop = wave_or(drop);
         ubinf = wave_or(ubinf);
@@ -645,7 +689,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                     const int jl = tid % cols, i0 = tid / cols;
                     for (int jb = 0; jb < nj; jb += cols) {
                         const int j = vb + jb + jl;
-                        const float4 v0 = vrec[2 * j], v1 = vrec[2 * j + 1];
+                        const float4 v0 = vrec[kV * j], v1 = vrec[kV * j + 1];
                         if (g == 1) {
                             for (int i = 0; i < ni; i += kRun) {
                                 float sub = 0.0f, shi = 0.0f;
@@ -672,7 +716,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                         float sub = 0.0f, shi = 0.0f;
                         for (int u = 0; u < kRun && i < ni; ++u) {
                             const int jj = vb + j;
-                            s12_pair<TOP8>(rec, gb + i, vrec[2 * jj], vrec[2 * jj + 1], sub, shi, top);
+                            s12_pair<TOP8>(rec, gb + i, vrec[kV * jj], vrec[kV * jj + 1], sub, shi, top);
                             j += dj;
                             i += di;
                             if (j >= nj) {
@@ -767,8 +811,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
 
 }  // namespace
 
-size_t s11_lds_bytes(int maxM) { return sizeof(float4) * 4 * (size_t)maxM; }
-size_t s12_lds_bytes(int maxM, int maxN) { return sizeof(float4) * (4 * (size_t)maxM + 2 * (size_t)maxN); }
+size_t s11_lds_bytes(int maxM) { return sizeof(float4) * kG * (size_t)maxM; }
+size_t s12_lds_bytes(int maxM, int maxN) { return sizeof(float4) * (kG * (size_t)maxM + kV * (size_t)maxN); }
 
 hipError_t prepare_bound_kernels(int maxM, int maxN)
 {
