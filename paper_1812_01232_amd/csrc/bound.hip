@@ -220,21 +220,24 @@ __device__ TransPrep trans_prep(const double *mu, double isig2, const double t0[
     return o;
 }
 
-// Functions of one concentration y >= 1 from a single expm1; with
-// d = 1 - e^{-2y}:  G(y) = y / d,  coth y = (2 - d) / d,  and
-// nu(y) = 1 - L(y) = 1 + 1/y - coth y = 1/y - 2 (1 - d) / d, where L is the
+// Functions of one concentration y >= 1 (every kappa here is at least 1),
+// in FP32 because they are stored in FP32: with e = e^{-2y} and d = 1 - e
+// (d >= 0.86, so no cancellation), G(y) = y / d, coth y = (1 + e) / d and
+// nu(y) = 1 - L(y) = 1 + 1/y - coth y = 1/y - 2 e / d, where L is the
 // derivative of log Z.
 struct YFun {
-    double G, coth, nu;
+    float G, coth, nu;
 };
 
-__device__ __forceinline__ YFun yfun(double y)
+__device__ __forceinline__ YFun yfun(double y64)
 {
-    const double d = -expm1(-2.0 * y);
+    const float y = (float)y64;
+    const float e = fexp2(-2.0f * kLog2e * y);
+    const float id = frcp(1.0f - e);
     YFun o;
-    o.G = y / d;
-    o.coth = (2.0 - d) / d;
-    o.nu = 1.0 / y - 2.0 * (1.0 - d) / d;
+    o.G = y * id;
+    o.coth = (1.0f + e) * id;
+    o.nu = frcp(y) - 2.0f * e * id;
     return o;
 }
 
@@ -387,8 +390,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             ubinf |= tp.ub_inf;
             const double w = mx.w1[g];
             const YFun fk = yfun(tp.kap), fa = yfun(tp.ac), fl = yfun(tp.klo);
-            dub += w * w * 0.5 * tp.kap * fk.coth;
-            dlo += w * w * 0.5 * tp.klo * fl.coth;
+            dub += w * w * 0.5 * tp.kap * (double)fk.coth;
+            dlo += w * w * 0.5 * tp.klo * (double)fl.coth;
             rec[kG * i] = make_float4((float)tp.u[0], (float)tp.u[1], (float)tp.u[2], (float)w);
             rec[kG * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)tp.cps, (float)tp.sps);
             rec[kG * i + 2] = make_float4((float)tp.ac, (float)tp.ha, (float)fa.G, (float)fa.nu);
