@@ -88,6 +88,10 @@ def lib():
         L.oracle_psi_t.argtypes = [d3, d3, d3]
         L.oracle_psi_r.restype = C.c_double
         L.oracle_psi_r.argtypes = [d3]
+        L.oracle_psi_r_dir.restype = C.c_double
+        L.oracle_psi_r_dir.argtypes = [d3, d3, d3, C.c_double]
+        L.oracle_left_jacobian.restype = None
+        L.oracle_left_jacobian.argtypes = [d3, d3]
         L.oracle_s11_lower_log.restype = C.c_double
         L.oracle_s11_lower_log.argtypes = [C.c_double] * 5
         L.oracle_s12_upper_term.restype = C.c_double
@@ -188,6 +192,17 @@ def psi_t(p, t0, tau):
 def psi_r(half):
     h = np.ascontiguousarray(half, dtype=np.float64)
     return lib().oracle_psi_r(_dp(h))
+
+
+def psi_r_dir(r0, half, w, psit):
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (r0, half, w)]
+    return lib().oracle_psi_r_dir(_dp(a[0]), _dp(a[1]), _dp(a[2]), float(psit))
+
+
+def left_jacobian(r):
+    J = np.zeros(9)
+    lib().oracle_left_jacobian(_dp(np.ascontiguousarray(r, dtype=np.float64)), _dp(J))
+    return J.reshape(3, 3)
 
 
 def s11_lower_log(alo, ahi, blo, bhi, A):

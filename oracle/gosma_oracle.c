@@ -244,14 +244,73 @@ double oracle_psi_t(const double p[3], const double t0[3], const double tau[3])
 }
 
 /* Lemma 2 (rotation uncertainty angle).  The surface maximum of the lemma is
- * not given in computable form; this reading bounds it with the angle-axis
- * metric inequality angle(R_r p, R_s p) <= |r - s|, so for a cube with
- * half-widths h the angle is at most min(|h|, pi).  The bound is symmetric
- * under r -> -r and so also covers the inverse rotations used in eq. 25. */
+ * not given in computable form.  The angle-axis metric inequality
+ * angle(R_r p, R_s p) <= |r - s| bounds it for every direction by min(|h|, pi)
+ * for a cube of half-widths h; oracle_psi_r_dir below tightens it for one
+ * direction and is what the lower bound uses. */
 double oracle_psi_r(const double half[3])
 {
     double h = norm3(half);
     return h < M_PI ? h : M_PI;
+}
+
+/* Left Jacobian of the angle-axis parametrisation (Section 5.1):
+ * d/ds exp([r + s u]x) = [J(r) u]x exp([r]x) at s = 0, with
+ * J(r) = I + A [r]x + B [r]x^2, A = (1 - cos t)/t^2, B = (t - sin t)/t^3, t = |r|. */
+void oracle_left_jacobian(const double r[3], double J[9])
+{
+    double t2 = dot3(r, r), t = sqrt(t2), A, B;
+    if (t < 1e-4) {
+        A = 0.5 - t2 / 24.0 + t2 * t2 / 720.0;
+        B = 1.0 / 6.0 - t2 / 120.0 + t2 * t2 / 5040.0;
+    } else {
+        A = (1.0 - cos(t)) / t2;
+        B = (t - sin(t)) / (t2 * t);
+    }
+    const double K[9] = {0.0, -r[2], r[1], r[2], 0.0, -r[0], -r[1], r[0], 0.0};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double k2 = 0.0;
+            for (int k = 0; k < 3; ++k) k2 += K[3 * i + k] * K[3 * k + j];
+            J[3 * i + j] = (i == j ? 1.0 : 0.0) + A * K[3 * i + j] + B * k2;
+        }
+}
+
+/* Lemma 2 per direction.  For p in the cone of half-angle psi_t around a unit
+ * vector, w = R_{r0} times that vector, and r = r0 + d in the cube of
+ * half-widths h: the path s -> q(s) = R_{r0 + s d} p, s in [0, 1], has speed
+ * |omega(s) x q(s)| with omega(s) = J(r0 + s d) d, so the angle between its
+ * ends is at most the integral of
+ *   |omega(0) x q(0)| + |omega(0)| |q(s) - q(0)| + |omega(s) - omega(0)|
+ *   <= |(J(r0) d) x q(0)| + s |d|^2 + L s |d|^2
+ * (|J| <= 1; |q(s) - q(0)| <= s |d| by the angle-axis metric bound; L bounds
+ * the derivative of J along unit directions: with A' and B' the derivatives
+ * of A and B, |A'| t + A + |B'| t^2 + 2 B t <= 1.595 for t <= 5.5, so L = 1.6).
+ * The first term is the norm of a linear function of d, largest at a corner
+ * of the box; moving q(0) within the cone changes it by at most
+ * 2 sin(psi_t/2) |J(r0) d| <= 2 sin(psi_t/2) |h|.  So
+ *   angle <= max over corners c of |w x J(r0) c| + 2 sin(psi_t/2) |h| + 1.3 |h|^2,
+ * capped by the metric bound min(|h|, pi), which is also the value when the
+ * cube leaves |r| <= 5.5. */
+double oracle_psi_r_dir(const double r0[3], const double half[3], const double w[3], double psit)
+{
+    const double h = norm3(half);
+    double cap = h < M_PI ? h : M_PI;
+    if (norm3(r0) + h > 5.5) return cap;
+    double J[9];
+    oracle_left_jacobian(r0, J);
+    static const double corner[4][3] = {{1, 1, 1}, {1, 1, -1}, {1, -1, 1}, {1, -1, -1}};
+    double first = 0.0;
+    for (int q = 0; q < 4; ++q) {
+        double d[3], u[3], x[3];
+        for (int k = 0; k < 3; ++k) d[k] = corner[q][k] * half[k];
+        matvec(J, d, u);
+        cross3(w, u, x);
+        double n = norm3(x);
+        if (n > first) first = n;
+    }
+    double b = first + 2.0 * sin(0.5 * psit) * h + 1.3 * h * h;
+    return b < cap ? b : cap;
 }
 
 /* ------------------------------------------------------------------ */
@@ -427,21 +486,32 @@ int oracle_bounds_cube(const oracle_problem *p, const oracle_domain *d, uint64_t
         psit_mean += p->phi1[i] * psit[i];
     }
     psit_mean /= phisum;
-    out->psi_r = oracle_psi_r(hr);
+    /* Rotation uncertainty of each Gaussian's direction (Lemma 2, per
+     * direction, over the cone of its translation uncertainty). */
+    double R0[9];
+    oracle_rodrigues(r0, R0);
+    double *psir = malloc(sizeof(double) * M), psir_mean = 0;
+    for (int i = 0; i < M; ++i) {
+        double n = norm3(c + 3 * i), u[3], w[3];
+        for (int k = 0; k < 3; ++k) u[k] = c[3 * i + k] / n;
+        matvec(R0, u, w);
+        psir[i] = oracle_psi_r_dir(r0, hr, w, psit[i]);
+        psir_mean += p->phi1[i] * psir[i];
+    }
+    psir_mean /= phisum;
+    out->psi_r = psir_mean;
     out->psi_t_mean = psit_mean;
     /* Branching rule: split the group with the larger angular uncertainty
-     * (Section 5.1), ties to rotation. */
+     * (Section 5.1), the weighted means over the Gaussians; ties to rotation. */
     out->split_rot = out->psi_r >= psit_mean;
     if (infeasible) {
         out->status = 2;
-        free(w1); free(w2); free(c); free(klo); free(khi); free(psit);
+        free(w1); free(w2); free(c); free(klo); free(khi); free(psit); free(psir);
         return 0;
     }
 
     /* Upper bound, eq. 20: the objective at the centre (+inf if the centre
      * is not a feasible camera position). */
-    double R0[9];
-    oracle_rodrigues(r0, R0);
     if (!centre_infeasible) {
         double S11, S12;
         out->ub = oracle_objective(p, r0, t0, &S11, &S12);
@@ -491,7 +561,7 @@ int oracle_bounds_cube(const oracle_problem *p, const oracle_domain *d, uint64_t
             if (label_of(p->label1, i) != label_of(p->label2, j)) continue;
             double Rinv_mu[3];
             matTvec(R0, p->dir2 + 3 * j, Rinv_mu);                     /* R_{r0}^{-1} mu_2j */
-            double B = angle3(c + 3 * i, Rinv_mu) - psit[i] - out->psi_r;
+            double B = angle3(c + 3 * i, Rinv_mu) - psit[i] - psir[i];
             if (B < 0) B = 0;
             s12hi += w1[i] * w2[j] * s12_upper_term(klo[i], khi[i], p->kappa2[j], B);
         }
@@ -499,7 +569,7 @@ int oracle_bounds_cube(const oracle_problem *p, const oracle_domain *d, uint64_t
     out->s11_lo = phil * s11lo;
     out->s12_hi = phil * s12hi;
     out->lb = out->s11_lo - 2.0 * out->s12_hi;
-    free(w1); free(w2); free(c); free(klo); free(khi); free(psit);
+    free(w1); free(w2); free(c); free(klo); free(khi); free(psit); free(psir);
     return 0;
 }
 

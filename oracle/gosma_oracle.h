@@ -44,7 +44,7 @@ typedef struct {
     double ub, lb;                  /* Theorem 1 bounds (+inf when dropped) */
     double s11_ub, s12_ub;          /* upper-bound pair sums at the centre */
     double s11_lo, s12_hi;          /* lower-bound pair sums */
-    double psi_r, psi_t_mean;       /* branching statistics */
+    double psi_r, psi_t_mean;       /* branching statistics: weighted means of psi_r and psi_t */
     int32_t status;                 /* 0 ok, 1 rotation cube outside pi-ball, 2 translation infeasible */
     int32_t split_rot;              /* 1: next split is in rotation */
     double top8[8];                 /* largest S12 upper-bound pair terms, descending */
@@ -81,6 +81,8 @@ double oracle_S22(const oracle_problem *p);
 
 double oracle_psi_t(const double mu[3], const double t0[3], const double tau[3]);
 double oracle_psi_r(const double half[3]);
+void oracle_left_jacobian(const double r[3], double J[9]);
+double oracle_psi_r_dir(const double r0[3], const double half[3], const double w[3], double psit);
 
 double oracle_s11_lower_log(double alo, double ahi, double blo, double bhi, double A);
 double oracle_s12_upper_term(double alo, double ahi, double b, double B);

@@ -301,3 +301,80 @@ def test_decode_keys():
         assert np.allclose(c, lo + (2 * np.array(idx) + 1) * h)
         c2, h2 = scenes.cube_geometry(np.uint64(key), lo, hi)
         assert np.allclose(c2, c) and np.allclose(h2, h)
+
+
+def test_left_jacobian_is_the_derivative_of_the_rotation_map():
+    """[J(r) u]x = d/ds R(r + s u) R(r)^T at s = 0 (rotations from scipy)."""
+    rng = np.random.default_rng(31)
+    for _ in range(200):
+        r = rng.standard_normal(3) * rng.uniform(0, 3.0)
+        if rng.uniform() < 0.1:
+            r *= 1e-5
+        u = rng.standard_normal(3)
+        e = 1e-6
+        dR = (Rotation.from_rotvec(r + e * u).as_matrix() - Rotation.from_rotvec(r - e * u).as_matrix()) / (2 * e)
+        W = dR @ Rotation.from_rotvec(r).as_matrix().T
+        v = oracle.left_jacobian(r) @ u
+        assert np.allclose(W, [[0, -v[2], v[1]], [v[2], 0, -v[0]], [-v[1], v[0], 0]], atol=1e-8)
+
+
+def test_left_jacobian_derivative_constant():
+    """The constant 1.6 of the per-direction rotation bound: the derivative of
+    J along a unit direction has operator norm at most |A'| t + A + |B'| t^2 +
+    2 B t, whose supremum on (0, 5.5] is below 1.6 (fine grid, A and B and
+    their derivatives by central differences); sampled norms stay below it."""
+    t = np.linspace(1e-3, 5.5, 200001)
+    A = lambda x: (1 - np.cos(x)) / x ** 2
+    B = lambda x: (x - np.sin(x)) / x ** 3
+    h = 1e-5
+    dA = (A(t + h) - A(t - h)) / (2 * h)
+    dB = (B(t + h) - B(t - h)) / (2 * h)
+    g = np.abs(dA) * t + A(t) + np.abs(dB) * t ** 2 + 2 * B(t) * t
+    assert g.max() < 1.6 and g.max() > 1.5
+    rng = np.random.default_rng(32)
+    for _ in range(300):
+        r = rng.standard_normal(3)
+        r *= rng.uniform(0, 5.5) / np.linalg.norm(r)
+        u = rng.standard_normal(3)
+        u /= np.linalg.norm(u)
+        D = (oracle.left_jacobian(r + 1e-6 * u) - oracle.left_jacobian(r - 1e-6 * u)) / 2e-6
+        assert np.linalg.norm(D, 2) <= 1.6
+
+
+def test_psi_r_dir_bounds_sampled_angles():
+    """Per-direction rotation bound: for rotations sampled in the cube (3x3x3
+    grid and random points) and directions sampled in the cone of half-angle
+    psi_t, angle(R_r v, R_r0 p) <= psi_r_dir + psi_t; never above the metric
+    bound; clearly below it on deep cubes away from the identity."""
+    rng = np.random.default_rng(33)
+    grid = np.array(np.meshgrid([-1, 0, 1], [-1, 0, 1], [-1, 0, 1])).T.reshape(-1, 3)
+    ratios = []
+    for trial in range(600):
+        L = int(rng.integers(1, 13))
+        n = 2 ** L
+        w = 2 * math.pi / n
+        idx = rng.integers(0, n, size=3)
+        lo = -math.pi + idx * w
+        h = np.full(3, w / 2)
+        r0 = lo + h
+        if np.linalg.norm(np.clip(0.0, lo, lo + w)) > math.pi:
+            continue
+        p = rng.standard_normal(3)
+        p /= np.linalg.norm(p)
+        psit = rng.uniform(0, 0.3) * rng.uniform() ** 2 if rng.uniform() < 0.8 else 0.0
+        R0 = Rotation.from_rotvec(r0).as_matrix()
+        b = oracle.psi_r_dir(r0, h, R0 @ p, psit)
+        assert b <= oracle.psi_r(h) + 1e-15
+        rs = np.concatenate([r0 + h * grid, r0 + h * rng.uniform(-1, 1, size=(60, 3))])
+        Rs = Rotation.from_rotvec(rs).as_matrix()
+        vs = [p]
+        for _ in range(8):
+            q = np.cross(p, rng.standard_normal(3))
+            q /= np.linalg.norm(q)
+            a = psit * (1.0 if rng.uniform() < 0.5 else rng.uniform())
+            vs.append(math.cos(a) * p + math.sin(a) * q)
+        worst = max(_ang(Rs @ v, np.broadcast_to(R0 @ p, (len(rs), 3))).max() for v in vs)
+        assert worst <= b + psit + 1e-12
+        if L >= 8:
+            ratios.append(b / np.linalg.norm(h))
+    assert np.mean(ratios) < 0.95
