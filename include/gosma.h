@@ -142,7 +142,9 @@ typedef struct {
     int no_graph;            /* 1: launch each iteration's kernels directly instead of replaying
                                 a captured HIP graph of one iteration */
     double learned_window;   /* order = 1: the predicted rise added to a cube's normalised lower
-                                bound is clamped to [0, learned_window]; <= 0: not clamped */
+                                bound is clamped to [0, learned_window]; <= 0: to [0, 10].  Cubes
+                                whose lower bound is within eps of d* are ordered after all others
+                                (by lower bound) under either setting */
 } gosma_opts;
 
 typedef struct {

@@ -674,15 +674,25 @@ __global__ __launch_bounds__(kBlock) void k_child_features(Bufs b)
 }
 
 // Learned priority: the cube's normalised lower bound plus the predicted rise
-// of its children's; the plain order where the prediction is not finite.
+// of its children's (at most 10, the range of the features); the plain order
+// where the prediction is not finite.  A cube whose lower bound is already
+// within eps of d* never has to be split before the stop test holds (d* only
+// decreases), so it is ordered after every cube that has to be, by its lower
+// bound; the network only reorders the cubes that every order must split.
+constexpr float kMaxRise = 10.0f, kDeferred = 16.0f;
 __global__ __launch_bounds__(kBlock) void k_learned_prio(Bufs b, float window)
 {
     const uint32_t n = b.g->nchild;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t p = b.cpid[i];
+        const double S22 = b.prob[p].S22;
+        const double dstar_n = (unord64(b.st[p].dstar) + S22) / S22, eps_n = b.st[p].eps_f / S22;
         const float lbn = b.cfeat[(size_t)GOSMA_MLP_FEATURES * i + 11];
         const float y = b.cpred[i];
-        const float rise = window > 0.0f ? fminf(fmaxf(y, 0.0f), window) : fmaxf(y, 0.0f);
-        b.cprio[i] = isfinite(y) ? lbn + rise : lbn;
+        const float rise = fminf(fmaxf(y, 0.0f), window > 0.0f ? window : kMaxRise);
+        float pr = isfinite(y) ? lbn + rise : lbn;
+        if ((double)lbn >= dstar_n - eps_n) pr = lbn + kDeferred;
+        b.cprio[i] = pr;
     }
 }
 

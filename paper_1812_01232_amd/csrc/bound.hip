@@ -111,6 +111,23 @@ __device__ void rotation_matrix(const double r[3], double R[9])
     R[7] = A * r[0] + B * r[1] * r[2];
 }
 
+// Coefficients of the left Jacobian of the angle-axis map (Section 5.1),
+// J(r) = I + a [r]x + b [r]x^2 with a = (1 - cos|r|)/|r|^2 and
+// b = (|r| - sin|r|)/|r|^3: d/ds R(r + s d) = [J(r) d]x R(r) at s = 0.
+__device__ void left_jacobian_coef(const double r[3], double *a, double *b)
+{
+    const double t2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2], t = sqrt(t2);
+    if (t < 1e-4) {
+        *a = 0.5 - t2 / 24.0 + t2 * t2 / 720.0;
+        *b = 1.0 / 6.0 - t2 / 120.0 + t2 * t2 / 5040.0;
+    } else {
+        double sh, ch;
+        sincos_reduced(0.5 * t, &sh, &ch);
+        *a = 2.0 * sh * sh / t2;
+        *b = (t - 2.0 * sh * ch) / (t2 * t);
+    }
+}
+
 // Order-preserving map of a double onto unsigned 64-bit integers.
 __device__ __forceinline__ unsigned long long ordered_bits(double x)
 {
@@ -287,8 +304,9 @@ __device__ __forceinline__ PairK pair_k(float a, float b, float q)
 struct BlockShared {
     double s0[kMaxWaves], s1[kMaxWaves];
     int drop[kMaxWaves], ubinf[kMaxWaves];
-    float psum[kMaxWaves];
+    float psum[kMaxWaves], prsum[kMaxWaves];
     float top[kMaxWaves][8];
+    double jc[4][3];   // J(r0) applied to four corners of the rotation cell's half-width box
 };
 
 // Pairs are summed in FP32 over runs of at most this many steps per lane and
@@ -611,8 +629,32 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         decode_key(rkeys[cube], P.r_lo, P.r_w, r0, hr);
         decode_key(tkeys[cube], P.t_lo, P.t_w, t0, tau);
 
-        // psi_r = min(|h_r|, pi) (Lemma 2 bounded with |angle(R_r p, R_s p)| <= |r - s|)
-        const double psir = fmin(sqrt(hr[0] * hr[0] + hr[1] * hr[1] + hr[2] * hr[2]), kPi);
+        // Lemma 2, per direction.  The angle-axis metric bound
+        // angle(R_r p, R_s p) <= |r - s| caps every direction's rotation
+        // uncertainty at min(|h_r|, pi).  Along the segment r0 + s d (d in the
+        // half-width box) the image R_{r0 + s d} p moves with angular speed
+        // |(J(r0 + s d) d) x R p|; with |J| <= 1 and the derivative of J along
+        // a unit direction at most 1.6 while |r| <= 5.5, its length is at most
+        //   |(J(r0) d) x w'| + 1.3 |d|^2,   w' = R_r0 p.
+        // The first term is the norm of a linear function of d, largest at a
+        // corner of the box (corners come in opposite pairs, so four suffice),
+        // and moving w' inside the cone of half-angle psi_t around w = R_r0 u
+        // adds at most 2 sin(psi_t / 2) |h_r|.
+        const double hn = sqrt(hr[0] * hr[0] + hr[1] * hr[1] + hr[2] * hr[2]);
+        const double cap = fmin(hn, kPi);
+        const bool per_dir = sqrt(r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2]) + hn <= 5.5;
+        if (per_dir && tid < 4) {
+            double ja, jb;
+            left_jacobian_coef(r0, &ja, &jb);
+            const double d[3] = {hr[0], (tid & 2) ? -hr[1] : hr[1], (tid & 1) ? -hr[2] : hr[2]};
+            // J d = d + a (r x d) + b (r (r . d) - |r|^2 d)
+            const double x[3] = {r0[1] * d[2] - r0[2] * d[1], r0[2] * d[0] - r0[0] * d[2],
+                                 r0[0] * d[1] - r0[1] * d[0]};
+            const double rd = r0[0] * d[0] + r0[1] * d[1] + r0[2] * d[2];
+            const double rr = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
+            for (int k = 0; k < 3; ++k) sh.jc[tid][k] = d[k] + ja * x[k] + jb * (r0[k] * rd - rr * d[k]);
+        }
+        __syncthreads();
         uint8_t flags = 0;
         {
             double nr2 = 0.0;
@@ -625,11 +667,9 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         }
         double R[9];
         rotation_matrix(r0, R);
-        double crh, srh;
-        sincos_reduced(0.5 * psir, &srh, &crh);
 
         int drop = 0, ubinf = 0;
-        float psum = 0.0f;
+        float psum = 0.0f, prsum = 0.0f;
         for (int i = tid; i < P.M; i += T) {
             const int g = P.gmm_off + i;
             const TransPrep tp = trans_prep(mx.mu + 3 * g, mx.isig2[g], t0, tau, P.zeta);
@@ -638,6 +678,21 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             psum += mx.pbar[g] * tp.psi;
             double w[3];
             for (int a = 0; a < 3; ++a) w[a] = R[3 * a] * tp.u[0] + R[3 * a + 1] * tp.u[1] + R[3 * a + 2] * tp.u[2];
+            double psir = cap;
+            if (per_dir) {
+                double m2 = 0.0;
+#pragma unroll 1
+                for (int q = 0; q < 4; ++q) {
+                    const double *v = sh.jc[q];
+                    const double x = w[1] * v[2] - w[2] * v[1], y = w[2] * v[0] - w[0] * v[2],
+                                 z = w[0] * v[1] - w[1] * v[0];
+                    m2 = fmax(m2, x * x + y * y + z * z);
+                }
+                psir = fmin(sqrt(m2) + 2.0 * tp.sps * hn + 1.3 * hn * hn, cap);
+            }
+            prsum += mx.pbar[g] * (float)psir;
+            double crh, srh;
+            sincos_reduced(0.5 * psir, &srh, &crh);
             // half of Psi = psi_t + psi_r (eq. 25), as cos/sin
             const double cP = tp.cps * crh - tp.sps * srh, sP = tp.sps * crh + tp.cps * srh;
             const double ahi = tp.klo + 2.0 * tp.ha;
@@ -654,23 +709,28 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         drop = wave_or(drop);
         ubinf = wave_or(ubinf);
         psum = wave_sumf(psum);
+        prsum = wave_sumf(prsum);
         if (lane == 0) {
             sh.drop[wv] = drop;
             sh.ubinf[wv] = ubinf;
             sh.psum[wv] = psum;
+            sh.prsum[wv] = prsum;
         }
         __syncthreads();
         drop = 0;
         ubinf = 0;
         psum = 0.0f;
+        prsum = 0.0f;
         for (int w = 0; w < W; ++w) {
             drop |= sh.drop[w];
             ubinf |= sh.ubinf[w];
             psum += sh.psum[w];
+            prsum += sh.prsum[w];
         }
         if (drop) flags |= GOSMA_FLAG_DROP_TRANS;
         if (ubinf) flags |= GOSMA_FLAG_UB_INF;
-        if (psir >= (double)psum) flags |= GOSMA_FLAG_SPLIT_ROT;
+        // branching rule (Section 5.1): the weighted means of the two uncertainties
+        if (prsum >= psum) flags |= GOSMA_FLAG_SPLIT_ROT;
 
         const bool dropped = flags & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS);
         double acc_ub = 0.0, acc_hi = 0.0;
@@ -807,7 +867,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                 out.aux[4 * cube + 2] = s11l;
                 out.aux[4 * cube + 3] = shi;
             }
-            if (out.psi_gap) out.psi_gap[cube] = (float)(psir - (double)psum);
+            if (out.psi_gap) out.psi_gap[cube] = prsum - psum;
         }
     }
 }

@@ -52,7 +52,7 @@ struct BoundOut {
     double *ub, *lb, *lb_safe, *aux;
     uint8_t *flags;
     float *top8;
-    float *psi_gap;    // optional: psi_r - weighted mean psi_t (branching statistic)
+    float *psi_gap;    // optional: weighted mean psi_r - weighted mean psi_t (branching statistic)
     unsigned long long *dstar_bits;   // optional: atomic minimum of finite upper bounds (ordered bits),
     int dstar_stride;                 // at dstar_bits[problem * dstar_stride]
 };
