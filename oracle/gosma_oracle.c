@@ -393,7 +393,13 @@ static double s11_lower_log(double alo, double ahi, double blo, double bhi, doub
  * is the smaller of the two expansions and of the value for perfectly aligned
  * directions,
  *   Z(a + b)/(Z(a) Z(b)) = a b (coth a + coth b) / (2 (a + b)) <= min(ahi, b)(coth alo + coth b)/2,
- * which bounds every angle since Z increases and K <= a + b. */
+ * which bounds every angle since Z increases and K <= a + b.  A third bound
+ * serves directions far apart: with G(y) = y / (1 - e^{-2y}) increasing and
+ * h(K) = (1 - e^{-2K})/K <= 2,
+ *   Z(K)/(Z(a) Z(b)) = e^{K - a - b} h(K) G(a) G(b)
+ *                    <= 2 G(ahi) G(b) exp(-q alo b / (2 (alo + b))),
+ * q = 4 sin^2(B/2), because K - a - b = -a b q / (K + a + b) with K <= a + b,
+ * and a b / (a + b) increases with a.  The term is the smallest of the three. */
 static double ell(double y) { return oracle_log_Z(y) - y; }
 
 static double s12_upper_term(double alo, double ahi, double b, double B)
@@ -416,7 +422,9 @@ static double s12_upper_term(double alo, double ahi, double b, double B)
     const double from_hi = phi2 + fmax(x2, x1 - 2.0 * d2 * h + q);
     const double expansion = exp(fmin(from_lo, from_hi));
     const double aligned = 0.5 * fmin(ahi, b) * (1.0 / tanh(alo) + 1.0 / tanh(b));
-    return fmin(expansion, aligned);
+    /* log G(y) = y - log Z(y) = -ell(y) */
+    const double far = exp(log(2.0) - ell(ahi) - ell(b) - chord2 * alo * b / (2.0 * (alo + b)));
+    return fmin(fmin(expansion, aligned), far);
 }
 
 /* Test hooks for the two summand bounds above. */

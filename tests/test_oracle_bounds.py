@@ -45,6 +45,36 @@ def test_s12_upper_term_bounds_interval_maximum():
             assert bound <= exact * (1 + 1e-2)   # tight for small intervals
 
 
+def test_s12_far_apart_bound():
+    """For directions far apart the S12 summand bound is at most
+    2 G(ahi) G(b) exp(-q alo b / (2 (alo + b))) (G(y) = y / (1 - e^{-2y}),
+    q = 4 sin^2(B/2)), and that expression bounds the ratio Z(K)/(Z(a) Z(b))
+    over a dense grid of concentrations in [alo, ahi] and angles >= B."""
+    rng = np.random.default_rng(5)
+    G = lambda y: y / -np.expm1(-2 * y)
+    active = 0
+    for _ in range(2000):
+        a = math.exp(rng.uniform(0, math.log(3e4)))
+        b = math.exp(rng.uniform(0, math.log(3e4)))
+        w = 10 ** rng.uniform(-5, 1.5)
+        B = rng.uniform(0, math.pi)
+        ahi = a * (1 + w)
+        q = 4 * math.sin(0.5 * B) ** 2
+        lfar = math.log(2 * G(ahi) * G(b)) - q * a * b / (2 * (a + b))
+        far = math.exp(lfar)
+        bound = oracle.s12_upper_term(a, ahi, b, B)
+        # FP64 rounding of an exponent of size |log far|, and of log Z(y) - y
+        # (the oracle's log G) for y up to ahi
+        tol = 1e-13 * (1 + abs(lfar)) + 4e-16 * (ahi + b)
+        assert bound <= far * (1 + tol)
+        active += bound > 0 and bound >= far * (1 - tol)
+        ag = np.linspace(a, ahi, 81)[:, None]
+        tg = np.linspace(B, math.pi, 81)[None, :]
+        g = _g(ag, b, tg)
+        assert g.max() <= lfar + 1e-12 * (1 + np.abs(g).max())
+    assert active > 20
+
+
 def test_s11_lower_log_bounds_box_minimum():
     rng = np.random.default_rng(1)
     for _ in range(1500):
