@@ -34,11 +34,14 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Op model of one GMM-vMF pair in the bound kernel, counted from its source
-# (the design doc lists the count): 107 plain FP32 VALU operations and 12
-# transcendentals (sqrt, rcp, exp2).  A transcendental issues at half the
-# plain rate on gfx950 (measured 1.8-1.9 plain-op slots), so it counts 2.
-S12_PLAIN, S12_TRANS = 107, 12
+# Op model of the GMM-vMF pair sums, counted from the kernel source: every
+# same-class pair of a live cube is screened (12 plain FP32 operations: the
+# cosine, the lower bound of the squared chord at angle B and the threshold
+# test), and each pair that passes is evaluated in full (117 plain operations
+# and 14 transcendentals: sqrt, rcp, exp2).  A transcendental issues at half
+# the plain rate on gfx950 (measured 1.8-1.9 plain-op slots), so it counts 2.
+SCREEN_SLOTS, SCREEN_FLOPS = 12, 12 + 5     # 5 of the screen's operations are FMAs
+S12_PLAIN, S12_TRANS = 117, 14
 TRANS_SLOTS = 2
 S12_SLOTS = S12_PLAIN + TRANS_SLOTS * S12_TRANS
 S12_FLOPS = S12_PLAIN + S12_TRANS + 13      # 13 of the plain operations are FMAs
@@ -99,12 +102,15 @@ def search_rate(ctx, steps, warmup):
     dt = b["seconds"] - a["seconds"]
     cubes = b["cubes"] - a["cubes"]
     # per-kernel split of the same iterations (direct launches with HIP events)
+    # and the pair counts of the GMM-vMF sums
     ctx.get_timing()
+    ctx.get_pair_counts()
     ctx.set_timing(True)
     ctx.solve(1e-9, max_iters=total, **kw)
     ctx.set_timing(False)
     kt = ctx.get_timing()
-    return cubes / dt, dt / steps * 1e3, kt, b, b["max_queue_used"]
+    pairs = ctx.get_pair_counts()
+    return cubes / dt, dt / steps * 1e3, kt, b, b["max_queue_used"], pairs
 
 
 def other_workload_rates(ctx, warmup=20, steps=40):
@@ -153,6 +159,7 @@ def kernel_rate(ctx, scene, reps):
         ctx.eval_bounds(rk, tk, ub, lb, fl)
     torch.cuda.synchronize()
     ctx.get_timing()
+    ctx.get_pair_counts()
     ctx.set_timing(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -163,8 +170,9 @@ def kernel_rate(ctx, scene, reps):
     torch.cuda.synchronize()
     ctx.set_timing(False)
     kt = ctx.get_timing()
+    pairs = ctx.get_pair_counts()
     live = int(((fl.cpu().numpy() & 6) == 0).sum())
-    return BATCH * reps / (e0.elapsed_time(e1) / 1e3), kt, live, rk_np, tk_np
+    return BATCH * reps / (e0.elapsed_time(e1) / 1e3), kt, live, pairs
 
 
 def cpu_baseline(scene, budget_s=15.0):
@@ -269,15 +277,20 @@ def main():
 
     # whole hot path: the search itself
     torch.cuda.synchronize()
-    value, ms_step, kt_search, r_search, queue = search_rate(ctx, args.steps, args.warmup)
+    value, ms_step, kt_search, r_search, queue, pairs_search = search_rate(ctx, args.steps, args.warmup)
     torch.cuda.synchronize()
 
-    # bound kernels alone + roofline of the GMM-vMF pair kernel
-    krate, kt, live, rk_np, tk_np = kernel_rate(ctx, scene, 10)
-    s12_ms, s12_n = kt["s12"]
-    s12_avg_s = s12_ms / s12_n / 1e3
-    achieved = live * M * N * S12_SLOTS / s12_avg_s / 1e12
+    # roofline of the GMM-vMF pair kernel over its launches in the search
+    # (HIP events on its stream), with the algorithmic work from the pair counts
+    s12_ms, s12_n = kt_search["s12"]
+    s12_s = s12_ms / 1e3
+    screened, evaluated = pairs_search
+    achieved = (screened * SCREEN_SLOTS + evaluated * S12_SLOTS) / s12_s / 1e12
+    tflops = (screened * SCREEN_FLOPS + evaluated * S12_FLOPS) / s12_s / 1e12
     peak = PEAK_SLOTS / 1e12
+
+    # bound kernels alone on a fixed batch of cubes across levels
+    krate, kt, live, pairs_k = kernel_rate(ctx, scene, 10)
 
     rec = {
         "metric": "sub-cube bounds/s at 64x64 comps; time-to-eps-optimum plain vs learned order",
@@ -298,11 +311,14 @@ def main():
         "pair_terms_per_s": value * (M * N + M * (M - 1) // 2) * 2,
         "search_kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt_search.items() if v[1]},
         "bound_kernels_only": {"cube_bounds_per_s": krate, "live_cubes": live,
-                               "ms_per_launch": {"s12": s12_ms / s12_n, "s11": kt["s11"][0] / kt["s11"][1]}},
+                               "pairs_evaluated_frac": pairs_k[1] / max(pairs_k[0], 1),
+                               "ms_per_launch": {"s12": kt["s12"][0] / kt["s12"][1], "s11": kt["s11"][0] / kt["s11"][1]}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
-                     "frac": achieved / peak, "traffic": measured_traffic(), "traffic_unit": "bytes/launch", "kernel": "k_s12 (GMM-vMF pair sums)",
-                     "fp32_tflops": live * M * N * S12_FLOPS / s12_avg_s / 1e12,
-                     "fp32_peak_tflops": PEAK_FP32_TFLOPS},
+                     "frac": achieved / peak, "traffic": measured_traffic(), "traffic_unit": "bytes/launch",
+                     "kernel": "k_s12 (GMM-vMF pair sums), its launches in the search",
+                     "launches": s12_n, "ms_per_launch": s12_ms / s12_n,
+                     "pairs_screened": screened, "pairs_evaluated": evaluated,
+                     "fp32_tflops": tflops, "fp32_peak_tflops": PEAK_FP32_TFLOPS},
     }
     if not args.no_other:
         rec["other_workloads"] = other_workload_rates(ctx)

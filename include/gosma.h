@@ -279,6 +279,15 @@ int gosma_autotune(gosma_ctx *ctx, int64_t n_cubes, uint64_t seed, double *rows,
 int gosma_set_timing(gosma_ctx *ctx, int enable);
 int gosma_get_timing(gosma_ctx *ctx, double *ms, int64_t *launches);
 
+/* Pair counts of the GMM-vMF sums (Theorem 1, eq. 20-21, second sums) in the
+ * gosma_eval_bounds calls and search iterations run while timing was enabled
+ * (searches launch their kernels directly then): *screened receives
+ * the number of same-class GMM-vMF pairs of the live cubes, *evaluated the
+ * number that passed the screen of negligible pairs and were evaluated in
+ * full.  Both host int64; the counts are cleared.  Synchronises the device.
+ * Both are 0 if timing was never enabled. */
+int gosma_get_pair_counts(gosma_ctx *ctx, int64_t *screened, int64_t *evaluated);
+
 #ifdef __cplusplus
 }
 #endif

@@ -133,6 +133,7 @@ void gosma_destroy(gosma_ctx *ctx)
     free_problems(ctx);
     dfree(ctx->d_s11ub);
     dfree(ctx->d_s11lo);
+    dfree(ctx->d_pairs);
     gosma_release_solver(ctx);
     gosma_release_mlp(ctx);
     delete ctx;
@@ -197,7 +198,7 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
             needN = std::max(needN, (int)(vmf_off[p + 1] - vmf_off[p]));
         }
         HIP_TRY(ctx, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
-        const size_t need = std::max(gosma::s11_lds_bytes(needM), gosma::s12_lds_bytes(needM, needN)) + 1024;
+        const size_t need = std::max(gosma::s11_lds_bytes(needM), gosma::s12_lds_bytes(needM, needN, gosma::kMaxWaves)) + 1024;
         if (need > (size_t)lds_max)
             return fail(ctx, GOSMA_E_INVAL, "M = %d, N = %d need %zu bytes of LDS per block; the device has %d", needM,
                         needN, need, lds_max);
@@ -282,7 +283,16 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
             double G = k / (-std::expm1(-2.0 * k));
             double coth = 1.0 + 2.0 / std::expm1(2.0 * k);
             h_vmf[2 * dst] = make_float4((float)dx[3 * j], (float)dx[3 * j + 1], (float)dx[3 * j + 2], (float)k);
-            h_vmf[2 * dst + 1] = make_float4((float)w2[j], (float)G, (float)coth, 0.0f);
+            const double ell = w2[j] > 0 ? std::log(w2[j] * G) : -1e30;
+            h_vmf[2 * dst + 1] = make_float4((float)w2[j], (float)G, (float)coth, (float)std::max(ell, -1e30));
+        }
+        // Threshold of the pair screen: 1e-9 of D = sum_i w_i^2 / 2 (a lower
+        // bound of S11, hence of the scale of every bound) over the M N pairs.
+        {
+            double D = 0.0;
+            for (int i = 0; i < M; ++i) D += 0.5 * (double)h_w1[g0 + i] * (double)h_w1[g0 + i];
+            P.cull_thr = 1e-9 * D / ((double)M * (double)N);
+            P.cull_lthr = P.cull_thr > 0 ? std::log(P.cull_thr) : -INFINITY;
         }
         // S22 (FP64, host): sum over same-class vMF pairs of w w' Z(K)/(Z Z)
         double S22 = 0.0;
@@ -399,7 +409,8 @@ int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tke
     HIP_TRY(ctx, gosma::launch_s11(mx, tkeys, problem, n, nullptr, gosma::S11Out{ctx->d_s11ub, ctx->d_s11lo},
                                    ctx->maxM, ctx->tile11, s));
     ctx->time_end(ti, s);
-    gosma::BoundOut out{ub, lb, nullptr, aux, flags, top8, nullptr, nullptr, 0};
+    gosma::BoundOut out{ub, lb, nullptr, aux, flags, top8, nullptr, nullptr, 0, nullptr};
+    if (ctx->timing) out.pair_counts = ctx->d_pairs;
     ti = ctx->time_begin(GOSMA_KERNEL_S12, s);
     HIP_TRY(ctx, gosma::launch_s12(mx, rkeys, tkeys, problem, nullptr, ctx->d_s11ub, ctx->d_s11lo, n, nullptr, 1, out,
                                    0.0, ctx->maxM, ctx->maxN, top8 != nullptr, ctx->tile12, s));
@@ -425,7 +436,31 @@ int gosma_set_record_sink(gosma_ctx *ctx, float *records, int64_t capacity, unsi
 int gosma_set_timing(gosma_ctx *ctx, int enable)
 {
     if (!ctx) return GOSMA_E_INVAL;
+    ctx->err.clear();
+    if (enable && !ctx->d_pairs) {
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        HIP_TRY(ctx, hipMalloc((void **)&ctx->d_pairs, 2 * gosma::kCountSlots * sizeof(unsigned long long)));
+        HIP_TRY(ctx, hipMemset(ctx->d_pairs, 0, 2 * gosma::kCountSlots * sizeof(unsigned long long)));
+    }
     ctx->timing = enable != 0;
+    return GOSMA_OK;
+}
+
+int gosma_get_pair_counts(gosma_ctx *ctx, int64_t *screened, int64_t *evaluated)
+{
+    if (!ctx || !screened || !evaluated) return GOSMA_E_INVAL;
+    ctx->err.clear();
+    *screened = *evaluated = 0;
+    if (!ctx->d_pairs) return GOSMA_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    unsigned long long h[2 * gosma::kCountSlots];
+    HIP_TRY(ctx, hipMemcpy(h, ctx->d_pairs, sizeof h, hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemset(ctx->d_pairs, 0, sizeof h));
+    for (int k = 0; k < gosma::kCountSlots; ++k) {
+        *screened += (int64_t)h[2 * k];
+        *evaluated += (int64_t)h[2 * k + 1];
+    }
     return GOSMA_OK;
 }
 

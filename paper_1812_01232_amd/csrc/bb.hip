@@ -1002,7 +1002,7 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     ti = T0(GOSMA_KERNEL_S12);
     const bool top8 = learned || logging;
     BoundOut bo{b.cub, b.clb, b.clbs, nullptr, b.cflags, top8 ? b.ctop8 : nullptr, nullptr, &b.st->dstar,
-                (int)(sizeof(PState) / sizeof(unsigned long long))};
+                (int)(sizeof(PState) / sizeof(unsigned long long)), timed ? ctx->d_pairs : nullptr};
     e = launch_s12(mx, b.crk, b.ctk, b.cpid, b.ctidx, b.s11ub, b.s11lo, maxc, &b.g->nchild, 1, bo, kMarginGamma,
                    ctx->maxM, ctx->maxN, top8, ctx->tile12, st);
     T1(ti);

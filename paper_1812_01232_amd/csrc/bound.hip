@@ -42,6 +42,7 @@ namespace gosma {
 namespace {
 
 constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
 constexpr double kPi = 3.14159265358979323846;
 
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -147,6 +148,15 @@ __device__ __forceinline__ float wave_sumf(float v)
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
+// Orders this wave's LDS accesses before and after the call (LDS operations
+// of one wave complete in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ int wave_or(int v)
 {
 #pragma unroll
@@ -308,6 +318,11 @@ struct BlockShared {
     float top[kMaxWaves][8];
     double jc[4][3];   // J(r0) applied to four corners of the rotation cell's half-width box
 };
+
+// Pairs that pass the screen are evaluated kBatch per lane at a time (several
+// independent pairs in flight per lane); each wave collects them in a list of
+// kList entries (a full batch plus one step of 64 offers).
+constexpr int kBatch = 4, kList = 64 * kBatch + 64;
 
 // Pairs are summed in FP32 over runs of at most this many steps per lane and
 // the runs are accumulated in FP64.
@@ -527,12 +542,14 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
 // S12 over rotation x translation cells, and the final bounds
 // ---------------------------------------------------------------------------
 //
-// GMM component record in LDS, four float4 (64 bytes, padded to 80):
+// GMM component record in LDS, five float4 (80 bytes):
 //   [0] w = R_r0 u (rotated unit vector), weight
 //   [1] kappa(t0), G(kappa), cos, sin of Psi / 2 with Psi = psi_t + psi_r (eq. 25)
 //   [2] kappa interval [alo, ahi] over the cell, half-width ha, coth(alo)
 //   [3] G(alo), G(ahi), nu(alo), nu(ahi)
-// vMF record, two float4 (32 bytes, padded to 48): {dx, dy, dz, kappa}, {weight, G(kappa), coth(kappa), 0}.
+//   [4] cos Psi, sin Psi, alo, Lam (pair screen, below)
+// vMF record, two float4 (32 bytes, padded to 48):
+//   {dx, dy, dz, kappa}, {weight, G(kappa), coth(kappa), ell = ln(weight G(kappa))}.
 //
 // Upper bound of the summand over the cube (Theorem 1 with kappa_1i(t)
 // relaxed to [alo, ahi]): at the smallest angle B, and with
@@ -541,7 +558,24 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
 // with Kmin the smallest K on the interval, so a second-order expansion of phi
 // at either end plus the exact x is a convex majorant whose maximum sits at an
 // end; the smaller of the two expansions is used, capped by the value for
-// aligned directions, min(ahi, b)(coth alo + coth b)/2.
+// aligned directions, min(ahi, b)(coth alo + coth b)/2, and by the bound for
+// directions far apart,
+//   2 G(ahi) G(b) exp(-qB alo b / (2 (alo + b)))                       (*)
+// (h(K) <= 2, G increasing, K <= a + b, and a b / (a + b) increasing in a).
+//
+// Pair screen.  (*) also bounds the summand at the centre, so a pair whose
+// weighted (*) is below a per-problem threshold thr contributes less than thr
+// to either sum.  With the lower bound cos B <= d cos Psi + sin Psi of the
+// angle B = max(0, theta - Psi) (d = cos theta; valid for Psi <= pi/2), the
+// test takes five multiply-adds per pair:
+//   qlo alo b >= 2 (Lam_i + ell_j)(alo + b),   qlo = 2 - 2 (d cos Psi + sin Psi),
+// Lam_i = ln(2 w_i G(ahi)) - ln thr, ell_j = ln(w_j G(b_j)).  A pair that passes
+// is dropped: it adds nothing to S12 at the centre (the upper bound rises by
+// at most 2 thr) and thr to the upper bound S12hi (which stays an upper
+// bound).  thr = 1e-9 D / (M N) with D = sum_i w_i^2 / 2, a lower bound of S11
+// (each diagonal summand is w_i^2 k coth(k) / 2 >= w_i^2 / 2), so all dropped
+// pairs together move a bound by at most 1e-9 of its scale.  The pairs that
+// remain are collected per wave in LDS and evaluated 64 at a time.
 
 template <bool TOP8>
 __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, int a_, const float4 &v0, const float4 &v1,
@@ -590,7 +624,8 @@ __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, int a_,
         const float vB = fexp2(eB * kLog2e) * k2.hK * R3.y;
         const float vT = fminf(vA, vB) * v1.y;
         const float cap = 0.5f * fminf(ahi, b) * (R2.w + v1.z);
-        shi += ww * fminf(vT, cap);
+        const float far = 2.0f * R3.y * v1.y * fexp2(-qB * alo * b * frcp(2.0f * (alo + b)) * kLog2e);
+        shi += ww * fminf(fminf(vT, cap), far);
     }
 }
 
@@ -604,14 +639,17 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                                                          const double *__restrict__ s11ub,
                                                          const double *__restrict__ s11lo, int64_t n_host,
                                                          const uint32_t *__restrict__ n_dev, int n_dev_mul,
-                                                         BoundOut out, double gamma, int maxM)
+                                                         BoundOut out, double gamma, int maxM, int maxN)
 {
     extern __shared__ float4 lds4[];
     __shared__ BlockShared sh;
-    float4 *rec = lds4;               // 4 per GMM component
+    float4 *rec = lds4;               // kG per GMM component
     float4 *vrec = lds4 + kG * maxM;  // kV per vMF component
+    // per wave: pairs that passed the screen
+    uint32_t *plist = reinterpret_cast<uint32_t *>(lds4 + kG * maxM + kV * maxN);
     const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, wv = tid >> 6, lane = tid & 63;
     const int64_t n = n_dev ? (int64_t)n_dev[0] * n_dev_mul : n_host;
+    unsigned nscr = 0, ncull_all = 0;   // per lane: pairs screened and dropped, over all cubes of the block
     for (int64_t cube = blockIdx.x; cube < n; cube += gridDim.x) {
         __syncthreads();
         const uint32_t pid = pids ? pids[cube] : 0u;
@@ -697,10 +735,16 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             const double cP = tp.cps * crh - tp.sps * srh, sP = tp.sps * crh + tp.cps * srh;
             const double ahi = tp.klo + 2.0 * tp.ha;
             const YFun fk = yfun(tp.kap), fl = yfun(tp.klo), fh = yfun(ahi);
-            rec[kG * i] = make_float4((float)w[0], (float)w[1], (float)w[2], mx.w1[g]);
+            const float wi = mx.w1[g];
+            // pair screen: never for Psi > pi/2 (where the bound on cos B fails)
+            const float lam = cP >= sP ? fminf(fmaxf(__builtin_amdgcn_logf(2.0f * wi * fh.G) * kLn2 -
+                                                         (float)P.cull_lthr, -1e30f), 1e30f)
+                                       : 1e30f;
+            rec[kG * i] = make_float4((float)w[0], (float)w[1], (float)w[2], wi);
             rec[kG * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)cP, (float)sP);
             rec[kG * i + 2] = make_float4((float)tp.klo, (float)ahi, (float)tp.ha, (float)fl.coth);
             rec[kG * i + 3] = make_float4((float)fl.G, (float)fh.G, (float)fl.nu, (float)fh.nu);
+            rec[kG * i + 4] = make_float4((float)(cP * cP - sP * sP), (float)(2.0 * cP * sP), (float)tp.klo, lam);
         }
         for (int j = tid; j < P.N; j += T) {
             vrec[kV * j] = mx.vmf[2 * (P.vmf_off + j)];
@@ -739,6 +783,60 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         for (int k = 0; k < 8; ++k) top[k] = 0.0f;
 
         if (!dropped) {
+            // Candidate pairs are offered by every lane of a wave in lockstep
+            // (a lane without one offers nothing); the pairs that are not
+            // screened out are appended to the wave's list and evaluated 64 at
+            // a time, with FP32 runs of kRun evaluations per lane.
+            uint32_t *pl = plist + kList * wv;
+            int pc = 0, run = 0, ncull = 0;
+            float sub = 0.0f, shi = 0.0f;
+            // evaluate the cnt (<= 64 kBatch) listed pairs from pl[base]
+            auto evaluate = [&](int base, int cnt) {
+                uint32_t e[kBatch];
+#pragma unroll
+                for (int k = 0; k < kBatch; ++k) {
+                    const int x = 64 * k + lane;
+                    e[k] = x < cnt ? pl[base + x] : 0xffffffffu;
+                }
+                wave_lds_sync();
+#pragma unroll
+                for (int k = 0; k < kBatch; ++k) {
+                    if (e[k] != 0xffffffffu) {
+                        const int jj = (int)(e[k] & 0xffffu);
+                        s12_pair<TOP8>(rec, (int)(e[k] >> 16), vrec[kV * jj], vrec[kV * jj + 1], sub, shi, top);
+                    }
+                }
+                run += kBatch;
+                if (run >= kRun) {
+                    acc_ub += (double)sub;
+                    acc_hi += (double)shi;
+                    sub = shi = 0.0f;
+                    run = 0;
+                }
+            };
+            auto offer = [&](int a_, int jj, const float4 &v0, const float4 &v1, bool valid) {
+                bool keep = false;
+                if (valid) {
+                    const float4 W0 = rec[kG * a_], S = rec[kG * a_ + 4];
+                    const float d = fmaf(W0.x, v0.x, fmaf(W0.y, v0.y, W0.z * v0.z));
+                    const float qlo = fmaf(-2.0f, fmaf(d, S.x, S.y), 2.0f);
+                    keep = qlo * S.z * v0.w < 2.0f * (S.w + v1.w) * (S.z + v0.w);
+                    ncull += keep ? 0 : 1;
+                    nscr += 1u;
+                }
+                const unsigned long long m = __ballot(keep);
+                if (keep) {
+                    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    pl[pc + rank] = ((uint32_t)a_ << 16) | (uint32_t)jj;
+                }
+                pc += __popcll(m);
+                if (pc >= 64 * kBatch) {
+                    pc -= 64 * kBatch;
+                    wave_lds_sync();
+                    evaluate(pc, 64 * kBatch);
+                }
+            };
             for (int c = 0; c < P.n_cls; ++c) {
                 const ClassRange cr = mx.cls[P.cls_off + c];
                 const int ni = cr.g1 - cr.g0, nj = cr.v1 - cr.v0;
@@ -753,45 +851,35 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                     for (int jb = 0; jb < nj; jb += cols) {
                         const int j = vb + jb + jl;
                         const float4 v0 = vrec[kV * j], v1 = vrec[kV * j + 1];
-                        if (g == 1) {
-                            for (int i = 0; i < ni; i += kRun) {
-                                float sub = 0.0f, shi = 0.0f;
-                                const int e = min(ni - i, kRun);
-                                for (int u = 0; u < e; ++u) s12_pair<TOP8>(rec, gb + i + u, v0, v1, sub, shi, top);
-                                acc_ub += (double)sub;
-                                acc_hi += (double)shi;
-                            }
-                        } else {
-                            for (int i = i0; i < ni; i += kRun * g) {
-                                float sub = 0.0f, shi = 0.0f;
-                                for (int u = 0, ii = i; u < kRun && ii < ni; ++u, ii += g)
-                                    s12_pair<TOP8>(rec, gb + ii, v0, v1, sub, shi, top);
-                                acc_ub += (double)sub;
-                                acc_hi += (double)shi;
-                            }
+                        for (int ib = 0; ib < ni; ib += g) {
+                            const int i = ib + i0;
+                            offer(gb + min(i, ni - 1), j, v0, v1, i < ni);
                         }
                     }
                 } else {
                     // flattened (i, j) rectangle of the class, T consecutive pairs per step
                     int i = tid / nj, j = tid % nj;
                     const int di = T / nj, dj = T % nj;
-                    while (i < ni) {
-                        float sub = 0.0f, shi = 0.0f;
-                        for (int u = 0; u < kRun && i < ni; ++u) {
-                            const int jj = vb + j;
-                            s12_pair<TOP8>(rec, gb + i, vrec[kV * jj], vrec[kV * jj + 1], sub, shi, top);
-                            j += dj;
-                            i += di;
-                            if (j >= nj) {
-                                j -= nj;
-                                i += 1;
-                            }
+                    const int steps = (ni * nj + T - 1) / T;
+                    for (int st = 0; st < steps; ++st) {
+                        const bool valid = i < ni;
+                        const int jj = vb + j;
+                        offer(gb + min(i, ni - 1), jj, vrec[kV * jj], vrec[kV * jj + 1], valid);
+                        j += dj;
+                        i += di;
+                        if (j >= nj) {
+                            j -= nj;
+                            i += 1;
                         }
-                        acc_ub += (double)sub;
-                        acc_hi += (double)shi;
                     }
                 }
             }
+            // the rest of the list
+            wave_lds_sync();
+            if (pc > 0) evaluate(0, pc);
+            acc_ub += (double)sub;
+            acc_hi += (double)shi + (double)ncull * P.cull_thr;
+            ncull_all += (unsigned)ncull;
         }
         acc_ub = wave_sum(acc_ub);
         acc_hi = wave_sum(acc_hi);
@@ -870,12 +958,24 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             if (out.psi_gap) out.psi_gap[cube] = prsum - psum;
         }
     }
+    if (out.pair_counts) {
+        // one pair of atomics per wave, spread over kCountSlots addresses
+        const double s_ = wave_sum((double)nscr), c_ = wave_sum((double)ncull_all);
+        if (lane == 0) {
+            unsigned long long *pc2 = out.pair_counts + 2 * (blockIdx.x % kCountSlots);
+            atomicAdd(pc2, (unsigned long long)s_);
+            atomicAdd(pc2 + 1, (unsigned long long)(s_ - c_));
+        }
+    }
 }
 
 }  // namespace
 
 size_t s11_lds_bytes(int maxM) { return sizeof(float4) * kG * (size_t)maxM; }
-size_t s12_lds_bytes(int maxM, int maxN) { return sizeof(float4) * (kG * (size_t)maxM + kV * (size_t)maxN); }
+size_t s12_lds_bytes(int maxM, int maxN, int waves)
+{
+    return sizeof(float4) * (kG * (size_t)maxM + kV * (size_t)maxN) + sizeof(uint32_t) * kList * (size_t)waves;
+}
 
 hipError_t prepare_bound_kernels(int maxM, int maxN)
 {
@@ -884,10 +984,10 @@ hipError_t prepare_bound_kernels(int maxM, int maxN)
                                        (int)s11_lds_bytes(maxM));
     if (!e)
         e = hipFuncSetAttribute((const void *)k_s12<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)s12_lds_bytes(maxM, maxN));
+                                (int)s12_lds_bytes(maxM, maxN, kMaxWaves));
     if (!e)
         e = hipFuncSetAttribute((const void *)k_s12<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)s12_lds_bytes(maxM, maxN));
+                                (int)s12_lds_bytes(maxM, maxN, kMaxWaves));
     return e;
 }
 
@@ -911,14 +1011,14 @@ hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *t
 {
     if (n <= 0) return hipSuccess;
     if (!tile_ok(tile)) return hipErrorInvalidValue;
-    const size_t lds = s12_lds_bytes(maxM, maxN);
+    const size_t lds = s12_lds_bytes(maxM, maxN, tile.waves);
     const unsigned g = (unsigned)std::min<int64_t>(tile.blocks, n);
     if (with_top8)
         hipLaunchKernelGGL(k_s12<true>, dim3(g), dim3(64 * tile.waves), lds, stream, mx, rkeys, tkeys, pids, tidx,
-                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM);
+                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, maxN);
     else
         hipLaunchKernelGGL(k_s12<false>, dim3(g), dim3(64 * tile.waves), lds, stream, mx, rkeys, tkeys, pids, tidx,
-                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM);
+                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, maxN);
     return hipGetLastError();
 }
 

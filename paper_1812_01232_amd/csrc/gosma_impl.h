@@ -23,6 +23,9 @@ struct ProbDesc {
     double r_lo[3], r_w[3];     // rotation root box: lo and width
     double t_lo[3], t_w[3];     // translation root box
     double zeta, S22;
+    // pair screen of the GMM-vMF sums: a pair whose summand is provably below
+    // cull_thr (weights included) is dropped and counted as cull_thr
+    double cull_thr, cull_lthr;   // cull_lthr = ln cull_thr (-inf: no screen)
 };
 
 struct ClassRange {
@@ -55,7 +58,10 @@ struct BoundOut {
     float *psi_gap;    // optional: weighted mean psi_r - weighted mean psi_t (branching statistic)
     unsigned long long *dstar_bits;   // optional: atomic minimum of finite upper bounds (ordered bits),
     int dstar_stride;                 // at dstar_bits[problem * dstar_stride]
+    unsigned long long *pair_counts;  // optional: kCountSlots pairs of counters {GMM-vMF pairs screened,
+                                      // evaluated}, added to; the totals are the sums over the slots
 };
+constexpr int kCountSlots = 64;
 
 struct S11Out {
     double *ub, *lo;   // S11 at the centre and its lower bound, per translation cube
@@ -78,9 +84,10 @@ hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *t
                       const int64_t *tidx, const double *s11ub, const double *s11lo, int64_t n, const uint32_t *n_dev,
                       int n_dev_mul, BoundOut out, double margin_gamma, int maxM, int maxN, bool with_top8, Tile tile,
                       hipStream_t stream);
-// Dynamic LDS of the two kernels, and the per-kernel limit setup for it.
+// Dynamic LDS of the two kernels (the pair kernel's grows with the waves per
+// block), and the per-kernel limit setup for it.
 size_t s11_lds_bytes(int maxM);
-size_t s12_lds_bytes(int maxM, int maxN);
+size_t s12_lds_bytes(int maxM, int maxN, int waves);
 hipError_t prepare_bound_kernels(int maxM, int maxN);
 
 struct Mlp;
@@ -112,6 +119,7 @@ struct gosma_ctx {
     // scratch for gosma_eval_bounds (grown on demand)
     int64_t s11_cap = 0;
     double *d_s11ub = nullptr, *d_s11lo = nullptr;
+    unsigned long long *d_pairs = nullptr;   // pair counts of timed gosma_eval_bounds calls
 
     gosma::Solver *solver = nullptr;
     gosma::Mlp *mlp = nullptr;

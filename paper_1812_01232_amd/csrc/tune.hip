@@ -130,7 +130,7 @@ int gosma_autotune(gosma_ctx *ctx, int64_t n_cubes, uint64_t seed, double *rows,
 
     const DevMix mx = ctx->mix();
     const S11Out s11{(double *)d_s11u.p, (double *)d_s11l.p};
-    BoundOut bo{(double *)d_ub.p, (double *)d_lb.p, nullptr, nullptr, (uint8_t *)d_fl.p, nullptr, nullptr, nullptr, 0};
+    BoundOut bo{(double *)d_ub.p, (double *)d_lb.p, nullptr, nullptr, (uint8_t *)d_fl.p, nullptr, nullptr, nullptr, 0, nullptr};
     auto run = [&](int kernel, Tile t) -> hipError_t {
         if (kernel == GOSMA_KERNEL_S11)
             return launch_s11(mx, (const uint64_t *)d_tk.p, (const uint32_t *)d_pid.p, n, nullptr, s11, ctx->maxM, t,

@@ -25,7 +25,7 @@ EXPORTS = ["gosma_create", "gosma_destroy", "gosma_last_error", "gosma_set_mixtu
            "gosma_set_problems", "gosma_get_S22", "gosma_eval_bounds", "gosma_solve", "gosma_solve_batch",
            "gosma_set_timing", "gosma_get_timing", "gosma_get_trace", "gosma_mlp_init", "gosma_mlp_set_params",
            "gosma_mlp_get_params", "gosma_mlp_predict", "gosma_mlp_loss_grad", "gosma_mlp_train",
-           "gosma_set_record_sink", "gosma_get_tiles", "gosma_set_tiles", "gosma_autotune"]
+           "gosma_set_record_sink", "gosma_get_tiles", "gosma_set_tiles", "gosma_autotune", "gosma_get_pair_counts"]
 MLP_FEATURES, MLP_RECORD, MLP_PARAMS = 20, 21, 35841
 KERNEL_KINDS = ["s11", "s12", "select", "branch", "push", "mlp"]
 
@@ -98,6 +98,7 @@ def lib():
         L.gosma_mlp_train.argtypes = [vp, vp, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_uint64, fp]
         L.gosma_set_record_sink.argtypes = [vp, vp, C.c_int64, vp]
         L.gosma_get_timing.argtypes = [vp, dp, C.POINTER(C.c_int64)]
+        L.gosma_get_pair_counts.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.gosma_get_tiles.argtypes = [vp, C.POINTER(Tiles)]
         L.gosma_set_tiles.argtypes = [vp, C.POINTER(Tiles)]
         L.gosma_autotune.argtypes = [vp, C.c_int64, C.c_uint64, dp, C.c_int64, C.POINTER(C.c_int64),
@@ -318,6 +319,13 @@ class Context:
         n = (C.c_int64 * 8)()
         self._check(lib().gosma_get_timing(self._h, ms, n), "gosma_get_timing")
         return {KERNEL_KINDS[k]: (ms[k], n[k]) for k in range(len(KERNEL_KINDS))}
+
+    def get_pair_counts(self):
+        """(screened, evaluated) GMM-vMF pairs of the timed eval_bounds calls
+        since the last call; synchronises."""
+        a, b = C.c_int64(), C.c_int64()
+        self._check(lib().gosma_get_pair_counts(self._h, C.byref(a), C.byref(b)), "gosma_get_pair_counts")
+        return a.value, b.value
 
     # -- branch and bound -------------------------------------------------
     def solve(self, eps, batch_parents=4096, max_queue=1 << 24, max_iters=0, time_limit_s=0.0, order=0,

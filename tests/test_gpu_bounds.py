@@ -258,3 +258,29 @@ def test_max_components(ctx):
         ctx.set_tiles(s11=t, s12=t)
         g = ctx.bounds(rk, tk)
         _compare(sc, g, oracle.OracleProblem(sc).bounds(rk, tk), label=f"1024x1024 tile {t}")
+
+
+def test_pair_screen_counts_and_parity(ctx):
+    """The screen of negligible GMM-vMF pairs: every same-class pair of a live
+    cube is screened, most of them are dropped on deep cubes (where the
+    uncertainty angles are small), none on the root cube, and the bounds of
+    the same cubes still match the oracle (dropped pairs are counted at the
+    threshold, 1e-9 of the bound scale in all)."""
+    sc = scenes.cfg2_scene(0)
+    ctx.set_scene(sc)
+    for levels, lo_frac, hi_frac in [((10, 12), 0.0, 0.6), ((0, 0), 1.0, 1.0)]:
+        rk, tk = scenes.random_cubes(sc, 2000, 5900, r_levels=levels, t_levels=(levels[0] - 1 if levels[0] else 0,
+                                                                              levels[1] - 1 if levels[1] else 0))
+        ctx.get_pair_counts()
+        ctx.set_timing(True)
+        g = ctx.bounds(rk, tk)
+        ctx.set_timing(False)
+        ctx.get_timing()
+        screened, evaluated = ctx.get_pair_counts()
+        live = int(((g["flags"] & 6) == 0).sum())
+        assert screened == live * sc.M * sc.N
+        frac = evaluated / screened
+        print(f"levels {levels}: {live} live cubes, {frac:.3f} of the pairs evaluated")
+        assert lo_frac <= frac <= hi_frac
+        o = oracle.OracleProblem(sc).bounds(rk, tk)
+        _compare(sc, g, o, label=f"screen {levels}")
