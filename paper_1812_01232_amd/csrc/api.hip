@@ -198,7 +198,7 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
             needN = std::max(needN, (int)(vmf_off[p + 1] - vmf_off[p]));
         }
         HIP_TRY(ctx, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
-        const size_t need = std::max(gosma::s11_lds_bytes(needM), gosma::s12_lds_bytes(needM, needN, gosma::kMaxWaves)) + 1024;
+        const size_t need = std::max(gosma::s11_lds_bytes(needM, gosma::kMaxWaves), gosma::s12_lds_bytes(needM, needN, gosma::kMaxWaves)) + 1024;
         if (need > (size_t)lds_max)
             return fail(ctx, GOSMA_E_INVAL, "M = %d, N = %d need %zu bytes of LDS per block; the device has %d", needM,
                         needN, need, lds_max);
@@ -293,6 +293,8 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
             for (int i = 0; i < M; ++i) D += 0.5 * (double)h_w1[g0 + i] * (double)h_w1[g0 + i];
             P.cull_thr = 1e-9 * D / ((double)M * (double)N);
             P.cull_lthr = P.cull_thr > 0 ? std::log(P.cull_thr) : -INFINITY;
+            P.cull11_thr = M > 1 ? 1e-9 * D / (0.5 * (double)M * (double)(M - 1)) : 0.0;
+            P.cull11_lthr = P.cull11_thr > 0 ? std::log(P.cull11_thr) : -INFINITY;
         }
         // S22 (FP64, host): sum over same-class vMF pairs of w w' Z(K)/(Z Z)
         double S22 = 0.0;

@@ -181,7 +181,8 @@ __device__ TransPrep trans_prep(const double *mu, double isig2, const double t0[
     double c[3] = {mu[0] - t0[0], mu[1] - t0[1], mu[2] - t0[2]};
     double rho2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
     double rho = sqrt(rho2);
-    for (int k = 0; k < 3; ++k) o.u[k] = c[k] / rho;
+    const double irho = 1.0 / rho;
+    for (int k = 0; k < 3; ++k) o.u[k] = c[k] * irho;
     o.kap = rho2 * isig2 + 1.0;
     // distance interval from mu to the cell: [max(zeta, dist to box), farthest vertex]
     double dmin2 = 0.0, dmax2 = 0.0, width = 0.0;
@@ -213,22 +214,28 @@ __device__ TransPrep trans_prep(const double *mu, double isig2, const double t0[
     // psi_t: largest vertex angle between mu - v and mu - t0 (Lemma 3); pi if
     // mu is in the cell or any vertex angle exceeds pi/2.  For angles below
     // pi/2 the largest angle has the largest sine, |c x (s tau)|^2 / (|a|^2 |c|^2)
-    // with a = c - s tau, computed without cancellation.
+    // with a = c - s tau, computed without cancellation.  FP32 (the angle
+    // enters the bound through FP32 records): the sines are compared as
+    // fractions by cross-multiplication, and only the largest is divided out.
     bool guard = inside;
-    double best_s2 = -1.0, best_c2 = 1.0;
-#pragma unroll 1   // sequential: keeps the FP64 set-up's register footprint small
+    const float cf[3] = {(float)c[0], (float)c[1], (float)c[2]};
+    const float tf[3] = {(float)tau[0], (float)tau[1], (float)tau[2]};
+    const float rho2f = (float)rho2;
+    float bn = -1.0f, bd = 1.0f, bdot = 1.0f;   // largest sine^2 = bn / bd, its cosine's numerator
+#pragma unroll 1   // sequential: keeps the set-up's register footprint small
     for (int v = 0; v < 8; ++v) {
-        double st[3] = {(v & 4) ? tau[0] : -tau[0], (v & 2) ? tau[1] : -tau[1], (v & 1) ? tau[2] : -tau[2]};
-        double a[3] = {c[0] - st[0], c[1] - st[1], c[2] - st[2]};
-        double a2 = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
-        double dot = rho2 - (st[0] * c[0] + st[1] * c[1] + st[2] * c[2]);
-        double cr[3] = {c[1] * st[2] - c[2] * st[1], c[2] * st[0] - c[0] * st[2], c[0] * st[1] - c[1] * st[0]};
-        double den = a2 * rho2;
-        double s2 = (cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]) / den;
-        if (dot < 0.0) guard = true;
-        if (s2 > best_s2) {
-            best_s2 = s2;
-            best_c2 = dot * dot / den;
+        const float st[3] = {(v & 4) ? tf[0] : -tf[0], (v & 2) ? tf[1] : -tf[1], (v & 1) ? tf[2] : -tf[2]};
+        const float a[3] = {cf[0] - st[0], cf[1] - st[1], cf[2] - st[2]};
+        const float a2 = fmaf(a[0], a[0], fmaf(a[1], a[1], a[2] * a[2]));
+        const float dot = rho2f - fmaf(st[0], cf[0], fmaf(st[1], cf[1], st[2] * cf[2]));
+        const float cr[3] = {cf[1] * st[2] - cf[2] * st[1], cf[2] * st[0] - cf[0] * st[2], cf[0] * st[1] - cf[1] * st[0]};
+        const float num = fmaf(cr[0], cr[0], fmaf(cr[1], cr[1], cr[2] * cr[2]));
+        const float den = a2 * rho2f;
+        if (dot < 0.0f) guard = true;
+        if (num * bd > bn * den) {
+            bn = num;
+            bd = den;
+            bdot = dot;
         }
     }
     if (guard) {
@@ -236,13 +243,13 @@ __device__ TransPrep trans_prep(const double *mu, double isig2, const double t0[
         o.sps = 1.0;
         o.psi = (float)kPi;
     } else {
-        double sp = sqrt(best_s2), cp = sqrt(best_c2);
-        double nrm = sqrt(best_s2 + best_c2);     // 1 up to rounding
-        sp /= nrm;
-        cp /= nrm;
-        o.cps = sqrt(0.5 * (1.0 + cp));
-        o.sps = sp / (2.0 * o.cps);
-        o.psi = atan2f((float)sp, (float)cp);
+        // sine and cosine of the angle from |c x s tau|^2 and (a . c)^2 over the same denominator
+        const float nrm = frcp(fsqrt(bn + bdot * bdot));
+        const float sp = fsqrt(bn) * nrm, cp = fabsf(bdot) * nrm;
+        const float cps = fsqrt(0.5f * (1.0f + cp));
+        o.cps = cps;
+        o.sps = sp * frcp(2.0f * cps);
+        o.psi = atan2f(sp, cp);
     }
     return o;
 }
@@ -340,7 +347,16 @@ constexpr int kG = 5, kV = 3;
 // Component record in LDS, four float4 (64 bytes, padded to 80):
 //   [0] u (unit vector mu - t0), weight      [1] kappa(t0), G(kappa), cos, sin of psi_t / 2
 //   [2] kappa interval centre ac, half-width ha, G(ac), nu(ac)
-//   [3] lambda = min(1/3, 1/klo^2), -, -, -
+//   [3] lambda = min(1/3, 1/klo^2), Lam (pair screen), kappa(t0), -
+//
+// Pair screen.  The summand of a pair at the centre is at most
+// 2 G(k) G(k') exp(-q k k' / (2 (k + k'))) (h <= 2, K <= k + k'), and the lower
+// term over the cell is at most the centre value (the centre lies in the box
+// of concentrations and A >= theta).  A pair whose weighted bound is below
+// thr11 is dropped: the lower sum loses at most thr11 (and stays a lower
+// bound) and the centre sum is charged thr11 (and stays an upper bound).  The
+// test is  q k k' >= 2 (Lam_i + Lam_i')(k + k'),  Lam_i = ln(2 w_i G(k_i)) -
+// ln(thr11) / 2, with thr11 = 1e-9 D / (M (M - 1) / 2), D = sum_i w_i^2 / 2.
 
 __device__ __forceinline__ void s11_terms(const float4 &A0, const float4 &A1, const float4 &A2, const float4 &A3,
                                           const float4 &B0, const float4 &B1, const float4 &B2, const float4 &B3,
@@ -389,11 +405,13 @@ __device__ __forceinline__ void s11_pair(const float4 *__restrict__ rec, int a_,
 
 __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_t *__restrict__ tkeys,
                                                          const uint32_t *__restrict__ pids, int64_t nt_host,
-                                                         const uint32_t *__restrict__ nt_dev, S11Out out)
+                                                         const uint32_t *__restrict__ nt_dev, S11Out out, int maxM)
 {
     extern __shared__ float4 lds4[];
     __shared__ BlockShared sh;
     float4 *rec = lds4;
+    // per wave: pairs that passed the screen
+    uint32_t *plist = reinterpret_cast<uint32_t *>(lds4 + kG * maxM);
     const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, wv = tid >> 6, lane = tid & 63;
     const int64_t nt = nt_dev ? (int64_t)nt_dev[0] : nt_host;
     for (int64_t cell = blockIdx.x; cell < nt; cell += gridDim.x) {
@@ -428,7 +446,9 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             rec[kG * i] = make_float4((float)tp.u[0], (float)tp.u[1], (float)tp.u[2], (float)w);
             rec[kG * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)tp.cps, (float)tp.sps);
             rec[kG * i + 2] = make_float4((float)tp.ac, (float)tp.ha, (float)fa.G, (float)fa.nu);
-            rec[kG * i + 3] = make_float4((float)fmin(1.0 / 3.0, 1.0 / (tp.klo * tp.klo)), 0.0f, 0.0f, 0.0f);
+            const float lam = fminf(fmaxf(__builtin_amdgcn_logf(2.0f * (float)w * fk.G) * kLn2 -
+                                              (float)(0.5 * P.cull11_lthr), -1e30f), 1e30f);
+            rec[kG * i + 3] = make_float4((float)fmin(1.0 / 3.0, 1.0 / (tp.klo * tp.klo)), lam, (float)tp.kap, 0.0f);
         }
         drop = wave_or(drop);
         ubinf = wave_or(ubinf);
@@ -452,6 +472,52 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
         }
 
         double acc_ub = dub, acc_lo = dlo;
+        // Candidate pairs are offered by every lane of a wave in lockstep; the
+        // pairs not screened out are listed per wave and evaluated kBatch per lane.
+        uint32_t *pl = plist + kList * wv;
+        int pc = 0, run = 0, ncull = 0;
+        float sub = 0.0f, slo = 0.0f;
+        auto evaluate = [&](int base_, int cnt) {
+            uint32_t e[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int x = 64 * k + lane;
+                e[k] = x < cnt ? pl[base_ + x] : 0xffffffffu;
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k)
+                if (e[k] != 0xffffffffu) s11_pair(rec, (int)(e[k] >> 16), (int)(e[k] & 0xffffu), sub, slo);
+            run += kBatch;
+            if (run >= kRun) {
+                acc_ub += (double)sub;
+                acc_lo += (double)slo;
+                sub = slo = 0.0f;
+                run = 0;
+            }
+        };
+        auto offer = [&](const float4 &A0, const float4 &A3, int a_, int b_, bool valid) {
+            bool keep = false;
+            if (valid) {
+                const float4 B0 = rec[kG * b_], B3 = rec[kG * b_ + 3];
+                const float dx = A0.x - B0.x, dy = A0.y - B0.y, dz = A0.z - B0.z;
+                const float q = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                keep = q * A3.z * B3.z < 2.0f * (A3.y + B3.y) * (A3.z + B3.z);
+                ncull += keep ? 0 : 1;
+            }
+            const unsigned long long m = __ballot(keep);
+            if (keep) {
+                const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                pl[pc + rank] = ((uint32_t)a_ << 16) | (uint32_t)b_;
+            }
+            pc += __popcll(m);
+            if (pc >= 64 * kBatch) {
+                pc -= 64 * kBatch;
+                wave_lds_sync();
+                evaluate(pc, 64 * kBatch);
+            }
+        };
         for (int c = 0; c < P.n_cls; ++c) {
             const ClassRange cr = mx.cls[P.cls_off + c];
             const int n = cr.g1 - cr.g0;
@@ -467,24 +533,21 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             const int passes = (n + T - 1) / T;
             if (n < T ? 10 * gq * n >= 9 * T : 10 * n >= 9 * T * passes) {
                 const int q = n < T ? tid / n : 0;
-                if (q < gq) {
-                    for (int f = n < T ? tid % n : tid; f < n; f += fstep) {
-                        const int a_ = base + f;
-                        const float4 A0 = rec[kG * a_], A1 = rec[kG * a_ + 1], A2 = rec[kG * a_ + 2],
-                                     A3 = rec[kG * a_ + 3];
-                        const int dmax = (n & 1) ? (n - 1) / 2 : (f < n / 2 ? n / 2 : n / 2 - 1);
-                        for (int d0 = 1 + q; d0 <= dmax; d0 += kRun * gq) {
-                            float sub = 0.0f, slo = 0.0f;
-                            for (int u = 0, d = d0; u < kRun && d <= dmax; ++u, d += gq) {
-                                int o = f + d;
-                                o -= o >= n ? n : 0;
-                                const int b_ = base + o;
-                                s11_terms(A0, A1, A2, A3, rec[kG * b_], rec[kG * b_ + 1], rec[kG * b_ + 2],
-                                          rec[kG * b_ + 3], sub, slo);
-                            }
-                            acc_ub += (double)sub;
-                            acc_lo += (double)slo;
-                        }
+                const int f0 = n < T ? tid % n : tid;
+                const int smax = (n / 2 + gq - 1) / gq;   // steps of the longest walk
+                for (int pass = 0; pass < passes; ++pass) {
+                    const int f = f0 + pass * fstep;
+                    const bool on = q < gq && f < n;
+                    const int fa = on ? f : 0;
+                    const int a_ = base + fa;
+                    const float4 A0 = rec[kG * a_], A3 = rec[kG * a_ + 3];
+                    const int dmax = (n & 1) ? (n - 1) / 2 : (fa < n / 2 ? n / 2 : n / 2 - 1);
+                    for (int st = 0; st < smax; ++st) {
+                        const int d = 1 + q + st * gq;
+                        const bool valid = on && d <= dmax;
+                        int o = fa + (valid ? d : 0);
+                        o -= o >= n ? n : 0;
+                        offer(A0, A3, a_, base + o, valid);
                     }
                 }
                 continue;
@@ -496,10 +559,10 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             const int R = n2 >> 1, C = n2 + 1;
             int r = tid / C, col = tid % C;
             const int dr = T / C, dc = T % C;
-            while (r < R) {
-                float sub = 0.0f, slo = 0.0f;
-                for (int u = 0; u < kRun && r < R; ++u) {
-                    int i, i2;
+            const int steps = (R * C + T - 1) / T;
+            for (int st = 0; st < steps; ++st) {
+                int i = 0, i2 = 0;
+                if (r < R) {
                     if (col < n2 - r) {
                         i = r;
                         i2 = r + col;
@@ -507,18 +570,24 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
                         i = n2 - 1 - r;
                         i2 = i + col - (n2 - r);
                     }
-                    if (i2 < n && i != i2) s11_pair(rec, base + i, base + i2, sub, slo);
-                    col += dc;
-                    r += dr;
-                    if (col >= C) {
-                        col -= C;
-                        r += 1;
-                    }
                 }
-                acc_ub += (double)sub;
-                acc_lo += (double)slo;
+                const bool valid = r < R && i2 < n && i != i2;
+                const int a_ = base + (valid ? i : 0), b_ = base + (valid ? i2 : 0);
+                const float4 A0 = rec[kG * a_], A3 = rec[kG * a_ + 3];
+                offer(A0, A3, a_, b_, valid);
+                col += dc;
+                r += dr;
+                if (col >= C) {
+                    col -= C;
+                    r += 1;
+                }
             }
         }
+        // the rest of the list; dropped pairs are charged to the centre sum
+        wave_lds_sync();
+        if (pc > 0) evaluate(0, pc);
+        acc_ub += (double)sub + (double)ncull * P.cull11_thr;
+        acc_lo += (double)slo;
         acc_ub = wave_sum(acc_ub);
         acc_lo = wave_sum(acc_lo);
         if (lane == 0) {
@@ -971,7 +1040,10 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
 
 }  // namespace
 
-size_t s11_lds_bytes(int maxM) { return sizeof(float4) * kG * (size_t)maxM; }
+size_t s11_lds_bytes(int maxM, int waves)
+{
+    return sizeof(float4) * kG * (size_t)maxM + sizeof(uint32_t) * kList * (size_t)waves;
+}
 size_t s12_lds_bytes(int maxM, int maxN, int waves)
 {
     return sizeof(float4) * (kG * (size_t)maxM + kV * (size_t)maxN) + sizeof(uint32_t) * kList * (size_t)waves;
@@ -981,7 +1053,7 @@ hipError_t prepare_bound_kernels(int maxM, int maxN)
 {
     // allow dynamic LDS beyond the default limit on devices that have it
     hipError_t e = hipFuncSetAttribute((const void *)k_s11, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)s11_lds_bytes(maxM));
+                                       (int)s11_lds_bytes(maxM, kMaxWaves));
     if (!e)
         e = hipFuncSetAttribute((const void *)k_s12<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)s12_lds_bytes(maxM, maxN, kMaxWaves));
@@ -999,8 +1071,8 @@ hipError_t launch_s11(const DevMix &mx, const uint64_t *tkeys, const uint32_t *p
     if (nt <= 0) return hipSuccess;
     if (!tile_ok(tile)) return hipErrorInvalidValue;
     const unsigned g = (unsigned)std::min<int64_t>(tile.blocks, nt);
-    hipLaunchKernelGGL(k_s11, dim3(g), dim3(64 * tile.waves), s11_lds_bytes(maxM), stream, mx, tkeys, pids, nt,
-                       nt_dev, out);
+    hipLaunchKernelGGL(k_s11, dim3(g), dim3(64 * tile.waves), s11_lds_bytes(maxM, tile.waves), stream, mx, tkeys,
+                       pids, nt, nt_dev, out, maxM);
     return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ struct ProbDesc {
     // pair screen of the GMM-vMF sums: a pair whose summand is provably below
     // cull_thr (weights included) is dropped and counted as cull_thr
     double cull_thr, cull_lthr;   // cull_lthr = ln cull_thr (-inf: no screen)
+    double cull11_thr, cull11_lthr;   // the same for the GMM-GMM sums (per unordered pair)
 };
 
 struct ClassRange {
@@ -86,7 +87,7 @@ hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *t
                       hipStream_t stream);
 // Dynamic LDS of the two kernels (the pair kernel's grows with the waves per
 // block), and the per-kernel limit setup for it.
-size_t s11_lds_bytes(int maxM);
+size_t s11_lds_bytes(int maxM, int waves);
 size_t s12_lds_bytes(int maxM, int maxN, int waves);
 hipError_t prepare_bound_kernels(int maxM, int maxN);
 
