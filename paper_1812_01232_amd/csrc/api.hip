@@ -286,16 +286,7 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
             const double ell = w2[j] > 0 ? std::log(w2[j] * G) : -1e30;
             h_vmf[2 * dst + 1] = make_float4((float)w2[j], (float)G, (float)coth, (float)std::max(ell, -1e30));
         }
-        // Threshold of the pair screen: 1e-9 of D = sum_i w_i^2 / 2 (a lower
-        // bound of S11, hence of the scale of every bound) over the M N pairs.
-        {
-            double D = 0.0;
-            for (int i = 0; i < M; ++i) D += 0.5 * (double)h_w1[g0 + i] * (double)h_w1[g0 + i];
-            P.cull_thr = 1e-9 * D / ((double)M * (double)N);
-            P.cull_lthr = P.cull_thr > 0 ? std::log(P.cull_thr) : -INFINITY;
-            P.cull11_thr = M > 1 ? 1e-9 * D / (0.5 * (double)M * (double)(M - 1)) : 0.0;
-            P.cull11_lthr = P.cull11_thr > 0 ? std::log(P.cull11_thr) : -INFINITY;
-        }
+
         // S22 (FP64, host): sum over same-class vMF pairs of w w' Z(K)/(Z Z)
         double S22 = 0.0;
         for (int j = 0; j < N; ++j)

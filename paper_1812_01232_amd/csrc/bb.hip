@@ -6,10 +6,11 @@
 // Queue of each problem: a small "hot" part holding every queued cube whose
 // priority key is below a threshold theta, and a large append-only "cold"
 // part holding the rest.  Each iteration only the hot part is scanned:
-//   select   3 radix passes (11 + 11 + 10 bits) over the ordered 32-bit key of
-//            the priority find the k-th lowest key; compaction moves the k
-//            lowest into the parent list and keeps the rest (cubes whose lower
-//            bound is no longer below d* are dropped)
+//   select   2 radix passes (11 + 11 bits) over the ordered 32-bit key of
+//            the priority find the bucket (top 22 bits) of the k-th lowest
+//            key; compaction moves the k lowest (ties within the bucket in
+//            arbitrary order) into the parent list and keeps the rest (cubes
+//            whose lower bound is no longer below d* are dropped)
 //   branch   8 children per parent, split in rotation or translation by the
 //            flag the bound kernel computed for the parent (Section 5.1); a
 //            rotation split shares one translation cell among its 8 children
@@ -97,24 +98,33 @@ __device__ __forceinline__ uint32_t key32(float x)
 // A NaN bound is never pruned: it orders like -inf.
 __device__ __forceinline__ double sane_lb(double x) { return x != x ? -INFINITY : x; }
 
-// Block-aggregated reservation of cnt consecutive slots per thread.
+// Block-aggregated reservation of cnt consecutive slots per thread: an
+// inclusive scan within each wave (shuffles), wave totals combined in LDS, one
+// atomic per block.
 __device__ __forceinline__ uint32_t block_reserve(uint32_t *counter, uint32_t cnt)
 {
-    __shared__ uint32_t part[kBlock];
+    __shared__ uint32_t wtot[kBlock / 64];
     __shared__ uint32_t base;
-    part[threadIdx.x] = cnt;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    if (lane == 63) wtot[wave] = incl;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t s = 0;
-        for (int t = 0; t < kBlock; ++t) {
-            uint32_t c = part[t];
-            part[t] = s;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            const uint32_t c = wtot[w];
+            wtot[w] = s;
             s += c;
         }
         base = s ? atomicAdd(counter, s) : 0u;
     }
     __syncthreads();
-    const uint32_t r = base + part[threadIdx.x];
+    const uint32_t r = base + wtot[wave] + incl - cnt;
     __syncthreads();
     return r;
 }
@@ -190,7 +200,7 @@ __device__ __forceinline__ void copy_payload(const Queue &dst, uint32_t d, const
 // store the element.  Each block handles tiles of kBlock * kPer elements with
 // one atomic per output per tile; element e of a tile is i = base + e * kBlock
 // + thread, so reads and writes stay coalesced.  All threads must call it.
-constexpr int kPer = 16;
+constexpr int kPer = 4;
 
 template <class Classify, class WriteA, class WriteB>
 __device__ __forceinline__ void partition_tiles(uint32_t n, uint32_t *cntA, uint32_t *cntB, Classify classify,
@@ -258,7 +268,9 @@ __device__ __forceinline__ void partition_tiles(uint32_t n, uint32_t *cntA, uint
 
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_iter_begin(Bufs b, int P)
+// rb_slot: this iteration runs the re-partition kernels (the problems that
+// asked for one re-partition now).
+__global__ __launch_bounds__(kBlock) void k_iter_begin(Bufs b, int P, int rb_slot)
 {
     const int p = blockIdx.x;
     PState &s = b.st[p];
@@ -282,40 +294,52 @@ __global__ __launch_bounds__(kBlock) void k_iter_begin(Bufs b, int P)
         s.eq_taken = 0;
         s.nH[s.hcur ^ 1] = 0;
         s.minH = ord64(INFINITY);
-        if (s.rebuild) {
+        if (rb_slot && s.rebuild) {
             s.nC[s.ccur ^ 1] = 0;
             s.minC = ord64(INFINITY);
         }
     }
 }
 
-// Radix pass over a problem's hot part (selection) or hot + cold parts
-// (re-partition): histogram of the digit below the prefix fixed so far.
+// Radix select over the ordered 32-bit key of the priority, in two passes of
+// 11 bits: the k-th lowest key's top 22 bits (the bucket) are found exactly;
+// within that bucket (keys equal to 1.2e-4 relative) cubes are taken in
+// arbitrary order up to the quota.
+constexpr int kLowBits = 10;
+constexpr uint32_t kHistPer = 16;   // keys per thread of a histogram pass (at least)
+__device__ __forceinline__ uint32_t kbucket(uint32_t key) { return key >> kLowBits; }
+
+// One radix pass over a problem's hot part (selection) or hot + cold parts
+// (re-partition): histogram of the next 11-bit digit below the prefix fixed
+// so far.
 __global__ __launch_bounds__(kBlock) void k_hist(Bufs b, int rebuild_pass, int pass)
 {
     __shared__ uint32_t h[kHistBins];
     const int p = blockIdx.y;
     const PState &s = b.st[p];
     if (s.done || s.take_all || (rebuild_pass && !s.rebuild)) return;
+    const int nparts = rebuild_pass ? 2 : 1;
+    // only as many blocks as give each thread about kHistPer keys take part:
+    // every block pays for clearing and flushing its histogram
+    const uint32_t total = s.nH[s.hcur] + (rebuild_pass ? s.nC[s.ccur] : 0u);
+    const uint32_t nb = min(gridDim.x, max(1u, (total + kBlock * kHistPer - 1) / (kBlock * kHistPer)));
+    if (blockIdx.x >= nb) return;
     for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) h[i] = 0;
     __syncthreads();
-    const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
-    const uint32_t mask = pass == 2 ? 0x3ffu : 0x7ffu;
-    const int pshift = pass == 1 ? 21 : 10;
+    const int shift = pass == 0 ? 21 : 10;
     const uint32_t prefix = s.prefix;
-    const int nparts = rebuild_pass ? 2 : 1;
+    const int lane = threadIdx.x & 63;
     for (int part = 0; part < nparts; ++part) {
         const Queue q = part == 0 ? qoff(b.H[s.hcur], (size_t)p * b.hcap) : qoff(b.C[s.ccur], (size_t)p * b.ccap);
         const uint32_t n = part == 0 ? s.nH[s.hcur] : s.nC[s.ccur];
-        const int lane = threadIdx.x & 63;
-        for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += nb * blockDim.x) {
             const uint32_t i = base + threadIdx.x;
             uint32_t bin = 0;
             bool m = false;
             if (i < n) {
                 const uint32_t key = key32(q.prio[i]);
-                m = pass == 0 || (key >> pshift) == prefix;
-                bin = (key >> shift) & mask;
+                m = pass == 0 || (key >> 21) == prefix;
+                bin = (key >> shift) & 0x7ffu;
             }
             // keys cluster: when every counted lane of the wave hits one bin,
             // add the count once instead of serialising 64 LDS atomics
@@ -383,9 +407,9 @@ __global__ __launch_bounds__(kBlock) void k_scan(Bufs b, int rebuild_pass, int p
     __syncthreads();
     for (int j = 0; j < per; ++j) gh[t * per + j] = 0;
     if (t == 0) {
-        s.prefix = (s.prefix << (pass == 2 ? 10 : 11)) | found;
+        s.prefix = (pass == 0 ? 0u : s.prefix << 11) | found;
         s.need = left;
-        if (pass == 2) s.eq_quota = left;
+        if (pass == 1) s.eq_quota = left;
     }
 }
 
@@ -396,6 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_rebuild_compact(Bufs b)
     const int p = blockIdx.y;
     PState &s = b.st[p];
     if (s.done || !s.rebuild) return;
+    if ((uint32_t)blockIdx.x * kBlock * kPer >= max(s.nH[s.hcur], s.nC[s.ccur])) return;   // no tile for this block
     const double dstar = unord64(s.dstar);
     const uint32_t T = s.prefix;
     const bool all = s.take_all;
@@ -409,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_rebuild_compact(Bufs b)
         auto classify = [&](uint32_t i) -> int {
             const double lb = sane_lb(q.lb[i]);
             if (!(lb < dstar)) return 0;
-            const uint32_t key = key32(q.prio[i]);
+            const uint32_t key = kbucket(key32(q.prio[i]));
             return (all || key < T || (key == T && atomicAdd(&s.eq_taken, 1u) < s.eq_quota)) ? 1 : 2;
         };
         auto move = [&](const Queue &o, uint32_t cap, uint32_t i, uint32_t slot, double &mn) {
@@ -450,7 +475,7 @@ __global__ void k_rebuild_finish(Bufs b, int P)
         s.done = OVERFLOW;
         return;
     }
-    s.theta = s.take_all ? 0xffffffffu : s.prefix;
+    s.theta = s.take_all ? 0xffffffffu : s.prefix << kLowBits;   // hot iff the key's bucket is below the prefix
     s.minH = ord64(INFINITY);  // recomputed by the selection and the pushes
     s.hcur ^= 1;
     s.ccur ^= 1;
@@ -473,6 +498,7 @@ __global__ __launch_bounds__(kBlock) void k_select_compact(Bufs b)
     const double dstar = unord64(s.dstar);
     const uint32_t T = s.prefix;
     const bool all = s.take_all;
+    if ((uint32_t)blockIdx.x * kBlock * kPer >= s.nH[s.hcur]) return;   // no tile for this block
     const Queue q = qoff(b.H[s.hcur], (size_t)p * b.hcap);
     const Queue Hout = qoff(b.H[s.hcur ^ 1], (size_t)p * b.hcap);
     const Queue par = qoff(b.par, (size_t)p * b.k);
@@ -480,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void k_select_compact(Bufs b)
     auto classify = [&](uint32_t i) -> int {
         const double lb = sane_lb(q.lb[i]);
         if (!(lb < dstar)) return 0;
-        const uint32_t key = key32(q.prio[i]);
+        const uint32_t key = kbucket(key32(q.prio[i]));
         return (all || key < T || (key == T && atomicAdd(&s.eq_taken, 1u) < s.eq_quota)) ? 1 : 2;
     };
     partition_tiles(
@@ -724,8 +750,10 @@ __global__ __launch_bounds__(kBlock) void k_log_records(Bufs b, int P)
     }
 }
 
-// Per-problem control at the end of an iteration.
-__global__ void k_iter_end(Bufs b, int P)
+// Per-problem control at the end of an iteration.  Re-partitions run once
+// every rb_every iterations, so one is asked for when the hot part would run
+// low or fill up within that many iterations.
+__global__ void k_iter_end(Bufs b, int P, int rb_every)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
@@ -748,7 +776,8 @@ __global__ void k_iter_end(Bufs b, int P)
     if (s.done) return;
     atomicAdd(&b.g->running, 1u);
     // re-partition when the hot part runs low (and cold cubes exist) or fills up
-    if ((nh < b.k && nc > 0) || nh + 8u * b.k > b.hcap) {
+    const uint32_t span = b.k * (uint32_t)rb_every;
+    if ((nh < span && nc > 0) || nh + 8u * span > b.hcap) {
         s.rebuild = 1;
         const uint32_t total = nh + nc;
         s.rb_target = min(max(total / 16u, 16u * b.k), b.hcap / 2u);
@@ -807,6 +836,7 @@ struct Solver {
     bool payload = false;     // logging payload buffers present
     int graph_mode = -1;      // captured mode: learned | logging
     float graph_window = 0.0f;
+    int graph_iters = 0;      // iterations per captured graph
 };
 
 }  // namespace gosma
@@ -963,7 +993,7 @@ unsigned long long ordh(double x)
 // Launch one iteration (all problems).  Every launch has a fixed shape and
 // reads its work counts from device memory, so the sequence can be captured.
 hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool timed, bool learned, bool logging,
-                            float window)
+                            float window, bool rb_slot, int rb_every)
 {
     using namespace gosma;
     Bufs &b = S.b;
@@ -975,16 +1005,18 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
         if (timed) ctx->time_end(idx, st);
     };
     int ti = T0(GOSMA_KERNEL_SELECT);
-    hipLaunchKernelGGL(k_iter_begin, dim3(P), dim3(kBlock), 0, st, b, P);
+    hipLaunchKernelGGL(k_iter_begin, dim3(P), dim3(kBlock), 0, st, b, P, (int)rb_slot);
     // re-partition of the problems that asked for it
-    for (int pass = 0; pass < 3; ++pass) {
-        hipLaunchKernelGGL(k_hist, dim3(gx, P), dim3(kBlock), 0, st, b, 1, pass);
-        hipLaunchKernelGGL(k_scan, dim3(P), dim3(kBlock), 0, st, b, 1, pass);
+    if (rb_slot) {
+        for (int pass = 0; pass < 2; ++pass) {
+            hipLaunchKernelGGL(k_hist, dim3(gx, P), dim3(kBlock), 0, st, b, 1, pass);
+            hipLaunchKernelGGL(k_scan, dim3(P), dim3(kBlock), 0, st, b, 1, pass);
+        }
+        hipLaunchKernelGGL(k_rebuild_compact, dim3(gx, P), dim3(kBlock), 0, st, b);
+        hipLaunchKernelGGL(k_rebuild_finish, dim3((P + 63) / 64), dim3(64), 0, st, b, P);
     }
-    hipLaunchKernelGGL(k_rebuild_compact, dim3(gx, P), dim3(kBlock), 0, st, b);
-    hipLaunchKernelGGL(k_rebuild_finish, dim3((P + 63) / 64), dim3(64), 0, st, b, P);
     // selection of the k lowest hot cubes
-    for (int pass = 0; pass < 3; ++pass) {
+    for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(k_hist, dim3(gx, P), dim3(kBlock), 0, st, b, 0, pass);
         hipLaunchKernelGGL(k_scan, dim3(P), dim3(kBlock), 0, st, b, 0, pass);
     }
@@ -1018,7 +1050,7 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     }
     ti = T0(GOSMA_KERNEL_PUSH);
     hipLaunchKernelGGL(k_push, dim3(kGridX), dim3(kBlock), 0, st, b, learned ? (const float *)b.cprio : nullptr);
-    hipLaunchKernelGGL(k_iter_end, dim3((P + 63) / 64), dim3(64), 0, st, b, P);
+    hipLaunchKernelGGL(k_iter_end, dim3((P + 63) / 64), dim3(64), 0, st, b, P, rb_every);
     T1(ti);
     return hipGetLastError();
 }
@@ -1048,11 +1080,16 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
     Solver &S = *ctx->solver;
     const size_t k = (size_t)opts->batch_parents;
     const size_t ccap = (size_t)opts->max_queue;
+    // hot part: room for a re-partition's target (at most half of it) plus the
+    // children of the iterations until the next re-partition (7 k net each)
     const size_t hcap = std::max<size_t>(std::min<size_t>(std::max<size_t>(256 * k, (size_t)1 << 20), ccap),
-                                         24 * k + 16);
+                                         64 * k + 16);
     const float window = (float)opts->learned_window;
     const int mode = (learned ? 1 : 0) | (logging ? 2 : 0);
-    if (S.graph_maxM != ctx->maxM || S.graph_mode != mode || S.graph_window != window)
+    const bool timed = ctx->timing;
+    const bool tracing = opts->trace_every > 0 && P == 1;
+    const int check = (timed || tracing) ? 1 : 4;   // iterations between status reads
+    if (S.graph_maxM != ctx->maxM || S.graph_mode != mode || S.graph_window != window || S.graph_iters != check)
         drop_graph(&S);   // the captured launches depend on these
     if ((e = ensure_solver(&S, P, k, hcap, ccap, logging)))
         return fail(GOSMA_E_NOMEM, "allocating solver buffers", e);
@@ -1099,14 +1136,14 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
 
     // iterations: replay a captured graph of one iteration, reading the
     // status every `check` iterations (every iteration when tracing or timing)
-    const bool timed = ctx->timing;
-    const bool tracing = opts->trace_every > 0 && P == 1;
-    const int check = (timed || tracing) ? 1 : 4;
     bool use_graph = !timed && !opts->no_graph;
+    // The graph holds `check` iterations; re-partitions run in the first.
     if (use_graph && !S.exec) {
         e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (!e) {
-            hipError_t le = launch_iteration(ctx, S, st, false, learned, logging, window);
+            hipError_t le = hipSuccess;
+            for (int r = 0; r < check && !le; ++r)
+                le = launch_iteration(ctx, S, st, false, learned, logging, window, r == 0, check);
             e = hipStreamEndCapture(st, &S.graph);
             if (!e) e = le;
         }
@@ -1119,6 +1156,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
             S.graph_maxM = ctx->maxM;
             S.graph_mode = mode;
             S.graph_window = window;
+            S.graph_iters = check;
         }
     }
     int rc = GOSMA_OK;
@@ -1141,9 +1179,11 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         }
         if (running == 0) break;
         if (opts->time_limit_s > 0 && el > opts->time_limit_s) break;
-        for (int r = 0; r < check && !e; ++r)
-            e = use_graph ? hipGraphLaunch(S.exec, st)
-                          : launch_iteration(ctx, S, st, timed, learned, logging, window);
+        if (use_graph)
+            e = hipGraphLaunch(S.exec, st);
+        else
+            for (int r = 0; r < check && !e; ++r)
+                e = launch_iteration(ctx, S, st, timed, learned, logging, window, r == 0, check);
         if (e) {
             rc = fail(GOSMA_E_HIP, "branch-and-bound iteration", e);
             break;

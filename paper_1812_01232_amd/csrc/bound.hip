@@ -324,7 +324,15 @@ struct BlockShared {
     float psum[kMaxWaves], prsum[kMaxWaves];
     float top[kMaxWaves][8];
     double jc[4][3];   // J(r0) applied to four corners of the rotation cell's half-width box
+    double dk[kMaxWaves];   // per wave: sum of w_i^2 klo_i / 2 (the pair screen's scale)
 };
+
+// The pair screens drop a pair when its summand is provably below
+// kCullRel D / (number of pairs), D = sum_i w_i^2 klo_i / 2 over the cell's
+// components: D is at most each diagonal summand sum w_i^2 k coth(k) / 2 of
+// S11 (k >= klo), hence a lower bound of the scale S11 + 2 S12 of both bounds,
+// and all dropped pairs together move a bound by at most kCullRel of it.
+constexpr double kCullRel = 1e-8;
 
 // Pairs that pass the screen are evaluated kBatch per lane at a time (several
 // independent pairs in flight per lane); each wave collects them in a list of
@@ -355,8 +363,8 @@ constexpr int kG = 5, kV = 3;
 // of concentrations and A >= theta).  A pair whose weighted bound is below
 // thr11 is dropped: the lower sum loses at most thr11 (and stays a lower
 // bound) and the centre sum is charged thr11 (and stays an upper bound).  The
-// test is  q k k' >= 2 (Lam_i + Lam_i')(k + k'),  Lam_i = ln(2 w_i G(k_i)) -
-// ln(thr11) / 2, with thr11 = 1e-9 D / (M (M - 1) / 2), D = sum_i w_i^2 / 2.
+// test is  q k k' >= 2 (Lam_i + Lam_i' - ln thr11)(k + k'),  Lam_i =
+// ln(2 w_i G(k_i)), with thr11 = kCullRel D / (M (M - 1) / 2).
 
 __device__ __forceinline__ void s11_terms(const float4 &A0, const float4 &A1, const float4 &A2, const float4 &A3,
                                           const float4 &B0, const float4 &B1, const float4 &B2, const float4 &B3,
@@ -432,7 +440,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
         // Z(2k)/Z(k)^2 = k coth(k) / 2 at the centre, and at the low end of the
         // kappa interval for the lower bound (the angle is exactly 0 and the
         // summand increases with kappa).
-        double dub = 0.0, dlo = 0.0;
+        double dub = 0.0, dlo = 0.0, dk = 0.0;
         int drop = 0, ubinf = 0;
         for (int i = tid; i < P.M; i += T) {
             const int g = P.gmm_off + i;
@@ -446,22 +454,26 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             rec[kG * i] = make_float4((float)tp.u[0], (float)tp.u[1], (float)tp.u[2], (float)w);
             rec[kG * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)tp.cps, (float)tp.sps);
             rec[kG * i + 2] = make_float4((float)tp.ac, (float)tp.ha, (float)fa.G, (float)fa.nu);
-            const float lam = fminf(fmaxf(__builtin_amdgcn_logf(2.0f * (float)w * fk.G) * kLn2 -
-                                              (float)(0.5 * P.cull11_lthr), -1e30f), 1e30f);
+            const float lam = fminf(fmaxf(__builtin_amdgcn_logf(2.0f * (float)w * fk.G) * kLn2, -1e30f), 1e30f);
+            dk += 0.5 * w * w * tp.klo;
             rec[kG * i + 3] = make_float4((float)fmin(1.0 / 3.0, 1.0 / (tp.klo * tp.klo)), lam, (float)tp.kap, 0.0f);
         }
         drop = wave_or(drop);
         ubinf = wave_or(ubinf);
+        dk = wave_sum(dk);
         if (lane == 0) {
             sh.drop[wv] = drop;
             sh.ubinf[wv] = ubinf;
+            sh.dk[wv] = dk;
         }
         __syncthreads();
         drop = 0;
         ubinf = 0;
+        dk = 0.0;
         for (int w = 0; w < W; ++w) {
             drop |= sh.drop[w];
             ubinf |= sh.ubinf[w];
+            dk += sh.dk[w];
         }
         if (drop) {
             if (tid == 0) {
@@ -470,6 +482,9 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             }
             continue;
         }
+        // threshold of the pair screen, per unordered GMM pair
+        const double thr11 = P.M > 1 ? kCullRel * dk / (0.5 * (double)P.M * (double)(P.M - 1)) : 0.0;
+        const float lthr11 = thr11 > 0.0 ? (float)log(thr11) : -INFINITY;
 
         double acc_ub = dub, acc_lo = dlo;
         // Candidate pairs are offered by every lane of a wave in lockstep; the
@@ -477,7 +492,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
         uint32_t *pl = plist + kList * wv;
         int pc = 0, run = 0, ncull = 0;
         float sub = 0.0f, slo = 0.0f;
-        auto evaluate = [&](int base_, int cnt) {
+        auto evaluate = [&](int base_, int cnt) __attribute__((always_inline)) {
             uint32_t e[kBatch];
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
@@ -496,13 +511,13 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
                 run = 0;
             }
         };
-        auto offer = [&](const float4 &A0, const float4 &A3, int a_, int b_, bool valid) {
+        auto offer = [&](const float4 &A0, const float4 &A3, int a_, int b_, bool valid) __attribute__((always_inline)) {
             bool keep = false;
             if (valid) {
                 const float4 B0 = rec[kG * b_], B3 = rec[kG * b_ + 3];
                 const float dx = A0.x - B0.x, dy = A0.y - B0.y, dz = A0.z - B0.z;
                 const float q = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                keep = q * A3.z * B3.z < 2.0f * (A3.y + B3.y) * (A3.z + B3.z);
+                keep = q * A3.z * B3.z < 2.0f * (A3.y + B3.y - lthr11) * (A3.z + B3.z);
                 ncull += keep ? 0 : 1;
             }
             const unsigned long long m = __ballot(keep);
@@ -586,7 +601,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
         // the rest of the list; dropped pairs are charged to the centre sum
         wave_lds_sync();
         if (pc > 0) evaluate(0, pc);
-        acc_ub += (double)sub + (double)ncull * P.cull11_thr;
+        acc_ub += (double)sub + (double)ncull * thr11;
         acc_lo += (double)slo;
         acc_ub = wave_sum(acc_ub);
         acc_lo = wave_sum(acc_lo);
@@ -616,7 +631,9 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
 //   [1] kappa(t0), G(kappa), cos, sin of Psi / 2 with Psi = psi_t + psi_r (eq. 25)
 //   [2] kappa interval [alo, ahi] over the cell, half-width ha, coth(alo)
 //   [3] G(alo), G(ahi), nu(alo), nu(ahi)
-//   [4] cos Psi, sin Psi, alo, Lam (pair screen, below)
+//   [4] Lam, 1 / alo, -, - (pair screen)
+// Screen row of the component (a separate LDS array, one float4):
+//   {w cos Psi, 1 - sin Psi - Lam / alo}
 // vMF record, two float4 (32 bytes, padded to 48):
 //   {dx, dy, dz, kappa}, {weight, G(kappa), coth(kappa), ell = ln(weight G(kappa))}.
 //
@@ -634,17 +651,17 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
 //
 // Pair screen.  (*) also bounds the summand at the centre, so a pair whose
 // weighted (*) is below a per-problem threshold thr contributes less than thr
-// to either sum.  With the lower bound cos B <= d cos Psi + sin Psi of the
-// angle B = max(0, theta - Psi) (d = cos theta; valid for Psi <= pi/2), the
-// test takes five multiply-adds per pair:
-//   qlo alo b >= 2 (Lam_i + ell_j)(alo + b),   qlo = 2 - 2 (d cos Psi + sin Psi),
-// Lam_i = ln(2 w_i G(ahi)) - ln thr, ell_j = ln(w_j G(b_j)).  A pair that passes
-// is dropped: it adds nothing to S12 at the centre (the upper bound rises by
-// at most 2 thr) and thr to the upper bound S12hi (which stays an upper
-// bound).  thr = 1e-9 D / (M N) with D = sum_i w_i^2 / 2, a lower bound of S11
-// (each diagonal summand is w_i^2 k coth(k) / 2 >= w_i^2 / 2), so all dropped
-// pairs together move a bound by at most 1e-9 of its scale.  The pairs that
-// remain are collected per wave in LDS and evaluated 64 at a time.
+// to either sum.  With q = 4 sin^2(B/2) >= 2 - 2 (d cos Psi + sin Psi), a
+// lower bound for the angle B = max(0, theta - Psi) (d = cos theta; valid for
+// Psi <= pi/2), and a = 1/alo, c = 1/b, the pair is below thr when
+//   (w_i cos Psi_i) . mu_j <= (1 - sin Psi_i - Lam_i a) - l_j c - Lam_i c - l_j a,
+// Lam_i = ln(2 w_i G(ahi)) and l_j = ln(w_j G(b_j)) - ln thr, thr = kCullRel D / (M N):
+// a dot product and four multiply-adds per pair, from the component's screen
+// row and record slot (broadcast LDS reads) and per-lane vMF constants.  A pair that
+// passes is dropped: it adds nothing to S12 at the centre (the upper bound
+// rises by at most 2 thr) and thr to the upper bound S12hi (which stays an
+// upper bound).  The pairs that remain are collected per wave in LDS and
+// evaluated kBatch per lane at a time.
 
 template <bool TOP8>
 __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, int a_, const float4 &v0, const float4 &v1,
@@ -714,11 +731,12 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
     __shared__ BlockShared sh;
     float4 *rec = lds4;               // kG per GMM component
     float4 *vrec = lds4 + kG * maxM;  // kV per vMF component
+    float4 *scr = vrec + kV * maxN;   // screen row per GMM component
     // per wave: pairs that passed the screen
-    uint32_t *plist = reinterpret_cast<uint32_t *>(lds4 + kG * maxM + kV * maxN);
+    uint32_t *plist = reinterpret_cast<uint32_t *>(scr + maxM);
     const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, wv = tid >> 6, lane = tid & 63;
     const int64_t n = n_dev ? (int64_t)n_dev[0] * n_dev_mul : n_host;
-    unsigned nscr = 0, ncull_all = 0;   // per lane: pairs screened and dropped, over all cubes of the block
+    unsigned nscr = 0, ncull_all = 0;   // per wave: pairs screened and dropped, over all cubes of the block
     for (int64_t cube = blockIdx.x; cube < n; cube += gridDim.x) {
         __syncthreads();
         const uint32_t pid = pids ? pids[cube] : 0u;
@@ -777,6 +795,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
 
         int drop = 0, ubinf = 0;
         float psum = 0.0f, prsum = 0.0f;
+        double dk = 0.0;
         for (int i = tid; i < P.M; i += T) {
             const int g = P.gmm_off + i;
             const TransPrep tp = trans_prep(mx.mu + 3 * g, mx.isig2[g], t0, tau, P.zeta);
@@ -805,15 +824,23 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             const double ahi = tp.klo + 2.0 * tp.ha;
             const YFun fk = yfun(tp.kap), fl = yfun(tp.klo), fh = yfun(ahi);
             const float wi = mx.w1[g];
-            // pair screen: never for Psi > pi/2 (where the bound on cos B fails)
-            const float lam = cP >= sP ? fminf(fmaxf(__builtin_amdgcn_logf(2.0f * wi * fh.G) * kLn2 -
-                                                         (float)P.cull_lthr, -1e30f), 1e30f)
-                                       : 1e30f;
+            dk += 0.5 * (double)wi * (double)wi * tp.klo;
+            // pair screen rows: none dropped for Psi > pi/2 (where the bound on
+            // cos B fails); Lam clamped below at -100 (a smaller threshold term
+            // only screens out fewer pairs)
+            {
+                const float cf = (float)cP, sf = (float)sP;
+                const float cPsi = cf * cf - sf * sf, sPsi = 2.0f * cf * sf;
+                const float lam = fmaxf(__builtin_amdgcn_logf(2.0f * wi * fh.G) * kLn2, -100.0f);
+                const float ia = frcp((float)tp.klo);
+                const float r0 = cf >= sf ? 1.0f - sPsi - lam * ia : -1e30f;
+                scr[i] = make_float4((float)w[0] * cPsi, (float)w[1] * cPsi, (float)w[2] * cPsi, r0);
+                rec[kG * i + 4] = make_float4(lam, ia, 0.0f, 0.0f);
+            }
             rec[kG * i] = make_float4((float)w[0], (float)w[1], (float)w[2], wi);
             rec[kG * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)cP, (float)sP);
             rec[kG * i + 2] = make_float4((float)tp.klo, (float)ahi, (float)tp.ha, (float)fl.coth);
             rec[kG * i + 3] = make_float4((float)fl.G, (float)fh.G, (float)fl.nu, (float)fh.nu);
-            rec[kG * i + 4] = make_float4((float)(cP * cP - sP * sP), (float)(2.0 * cP * sP), (float)tp.klo, lam);
         }
         for (int j = tid; j < P.N; j += T) {
             vrec[kV * j] = mx.vmf[2 * (P.vmf_off + j)];
@@ -823,23 +850,30 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         ubinf = wave_or(ubinf);
         psum = wave_sumf(psum);
         prsum = wave_sumf(prsum);
+        dk = wave_sum(dk);
         if (lane == 0) {
             sh.drop[wv] = drop;
             sh.ubinf[wv] = ubinf;
             sh.psum[wv] = psum;
             sh.prsum[wv] = prsum;
+            sh.dk[wv] = dk;
         }
         __syncthreads();
         drop = 0;
         ubinf = 0;
         psum = 0.0f;
         prsum = 0.0f;
+        dk = 0.0;
         for (int w = 0; w < W; ++w) {
             drop |= sh.drop[w];
             ubinf |= sh.ubinf[w];
             psum += sh.psum[w];
             prsum += sh.prsum[w];
+            dk += sh.dk[w];
         }
+        // threshold of the pair screen, per GMM-vMF pair
+        const double thr = kCullRel * dk / ((double)P.M * (double)P.N);
+        const float lthr = thr > 0.0 ? (float)log(thr) : -INFINITY;
         if (drop) flags |= GOSMA_FLAG_DROP_TRANS;
         if (ubinf) flags |= GOSMA_FLAG_UB_INF;
         // branching rule (Section 5.1): the weighted means of the two uncertainties
@@ -857,10 +891,11 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             // screened out are appended to the wave's list and evaluated 64 at
             // a time, with FP32 runs of kRun evaluations per lane.
             uint32_t *pl = plist + kList * wv;
-            int pc = 0, run = 0, ncull = 0;
+            int pc = 0, run = 0;
+            unsigned noff = 0, nkeep = 0;   // this wave's pairs offered and kept (wave-uniform)
             float sub = 0.0f, shi = 0.0f;
             // evaluate the cnt (<= 64 kBatch) listed pairs from pl[base]
-            auto evaluate = [&](int base, int cnt) {
+            auto evaluate = [&](int base, int cnt) __attribute__((always_inline)) {
                 uint32_t e[kBatch];
 #pragma unroll
                 for (int k = 0; k < kBatch; ++k) {
@@ -883,21 +918,21 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                     run = 0;
                 }
             };
-            auto offer = [&](int a_, int jj, const float4 &v0, const float4 &v1, bool valid) {
-                bool keep = false;
-                if (valid) {
-                    const float4 W0 = rec[kG * a_], S = rec[kG * a_ + 4];
-                    const float d = fmaf(W0.x, v0.x, fmaf(W0.y, v0.y, W0.z * v0.z));
-                    const float qlo = fmaf(-2.0f, fmaf(d, S.x, S.y), 2.0f);
-                    keep = qlo * S.z * v0.w < 2.0f * (S.w + v1.w) * (S.z + v0.w);
-                    ncull += keep ? 0 : 1;
-                    nscr += 1u;
-                }
-                const unsigned long long m = __ballot(keep);
+            // the screen test; vm = {mu_j, l_j c_j}, vc = {c_j = 1 / b_j, l_j}: the
+            // lane's vMF screen constants
+            auto screened_in = [&](int a_, const float4 &vm, const float2 &vc) __attribute__((always_inline)) {
+                const float4 S0 = scr[a_], S1 = rec[kG * a_ + 4];
+                const float d = fmaf(S0.x, vm.x, fmaf(S0.y, vm.y, S0.z * vm.z));
+                const float rhs = fmaf(-S1.y, vc.y, fmaf(-S1.x, vc.x, S0.w - vm.w));
+                return !(d <= rhs);
+            };
+            // append the kept pairs (mask m) to the wave's list; evaluate a full batch
+            auto append = [&](bool keep, unsigned long long m, uint32_t packed) __attribute__((always_inline)) {
+                nkeep += (unsigned)__popcll(m);
                 if (keep) {
                     const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    pl[pc + rank] = ((uint32_t)a_ << 16) | (uint32_t)jj;
+                    pl[pc + rank] = packed;
                 }
                 pc += __popcll(m);
                 if (pc >= 64 * kBatch) {
@@ -905,6 +940,11 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                     wave_lds_sync();
                     evaluate(pc, 64 * kBatch);
                 }
+            };
+            auto offer = [&](int a_, int jj, const float4 &vm, const float2 &vc, bool valid) __attribute__((always_inline)) {
+                const bool keep = valid && screened_in(a_, vm, vc);
+                noff += (unsigned)__popcll(__ballot(valid));
+                append(keep, __ballot(keep), ((uint32_t)a_ << 16) | (uint32_t)jj);
             };
             for (int c = 0; c < P.n_cls; ++c) {
                 const ClassRange cr = mx.cls[P.cls_off + c];
@@ -920,9 +960,22 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                     for (int jb = 0; jb < nj; jb += cols) {
                         const int j = vb + jb + jl;
                         const float4 v0 = vrec[kV * j], v1 = vrec[kV * j + 1];
-                        for (int ib = 0; ib < ni; ib += g) {
-                            const int i = ib + i0;
-                            offer(gb + min(i, ni - 1), j, v0, v1, i < ni);
+                        const float c = frcp(v0.w), l = fmaxf(v1.w, -100.0f) - lthr;
+                        const float4 vm = make_float4(v0.x, v0.y, v0.z, l * c);
+                        const float2 vc = make_float2(c, l);
+                        if (cols % 64 == 0) {
+                            // the row index is the same across the wave: uniform
+                            // addresses, every lane offers a pair
+                            for (int i = __builtin_amdgcn_readfirstlane(i0); i < ni; i += g) {
+                                const bool keep = screened_in(gb + i, vm, vc);
+                                noff += 64u;
+                                append(keep, __ballot(keep), ((uint32_t)(gb + i) << 16) | (uint32_t)j);
+                            }
+                        } else {
+                            for (int ib = 0; ib < ni; ib += g) {
+                                const int i = ib + i0;
+                                offer(gb + min(i, ni - 1), j, vm, vc, i < ni);
+                            }
                         }
                     }
                 } else {
@@ -933,7 +986,9 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                     for (int st = 0; st < steps; ++st) {
                         const bool valid = i < ni;
                         const int jj = vb + j;
-                        offer(gb + min(i, ni - 1), jj, vrec[kV * jj], vrec[kV * jj + 1], valid);
+                        const float4 v0 = vrec[kV * jj], v1 = vrec[kV * jj + 1];
+                        const float c = frcp(v0.w), l = fmaxf(v1.w, -100.0f) - lthr;
+                        offer(gb + min(i, ni - 1), jj, make_float4(v0.x, v0.y, v0.z, l * c), make_float2(c, l), valid);
                         j += dj;
                         i += di;
                         if (j >= nj) {
@@ -947,8 +1002,10 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             wave_lds_sync();
             if (pc > 0) evaluate(0, pc);
             acc_ub += (double)sub;
-            acc_hi += (double)shi + (double)ncull * P.cull_thr;
-            ncull_all += (unsigned)ncull;
+            acc_hi += (double)shi;
+            if (lane == 0) acc_hi += (double)(noff - nkeep) * thr;   // dropped pairs, once per wave
+            nscr += noff;
+            ncull_all += noff - nkeep;
         }
         acc_ub = wave_sum(acc_ub);
         acc_hi = wave_sum(acc_hi);
@@ -1027,14 +1084,11 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             if (out.psi_gap) out.psi_gap[cube] = prsum - psum;
         }
     }
-    if (out.pair_counts) {
+    if (out.pair_counts && lane == 0) {
         // one pair of atomics per wave, spread over kCountSlots addresses
-        const double s_ = wave_sum((double)nscr), c_ = wave_sum((double)ncull_all);
-        if (lane == 0) {
-            unsigned long long *pc2 = out.pair_counts + 2 * (blockIdx.x % kCountSlots);
-            atomicAdd(pc2, (unsigned long long)s_);
-            atomicAdd(pc2 + 1, (unsigned long long)(s_ - c_));
-        }
+        unsigned long long *pc2 = out.pair_counts + 2 * (blockIdx.x % kCountSlots);
+        atomicAdd(pc2, (unsigned long long)nscr);
+        atomicAdd(pc2 + 1, (unsigned long long)(nscr - ncull_all));
     }
 }
 
@@ -1046,7 +1100,7 @@ size_t s11_lds_bytes(int maxM, int waves)
 }
 size_t s12_lds_bytes(int maxM, int maxN, int waves)
 {
-    return sizeof(float4) * (kG * (size_t)maxM + kV * (size_t)maxN) + sizeof(uint32_t) * kList * (size_t)waves;
+    return sizeof(float4) * ((kG + 1) * (size_t)maxM + kV * (size_t)maxN) + sizeof(uint32_t) * kList * (size_t)waves;
 }
 
 hipError_t prepare_bound_kernels(int maxM, int maxN)

@@ -23,10 +23,6 @@ struct ProbDesc {
     double r_lo[3], r_w[3];     // rotation root box: lo and width
     double t_lo[3], t_w[3];     // translation root box
     double zeta, S22;
-    // pair screen of the GMM-vMF sums: a pair whose summand is provably below
-    // cull_thr (weights included) is dropped and counted as cull_thr
-    double cull_thr, cull_lthr;   // cull_lthr = ln cull_thr (-inf: no screen)
-    double cull11_thr, cull11_lthr;   // the same for the GMM-GMM sums (per unordered pair)
 };
 
 struct ClassRange {
