@@ -35,12 +35,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Op model of the GMM-vMF pair sums, counted from the kernel source: every
-# same-class pair of a live cube is screened (12 plain FP32 operations: the
-# cosine, the lower bound of the squared chord at angle B and the threshold
-# test), and each pair that passes is evaluated in full (117 plain operations
-# and 14 transcendentals: sqrt, rcp, exp2).  A transcendental issues at half
-# the plain rate on gfx950 (measured 1.8-1.9 plain-op slots), so it counts 2.
-SCREEN_SLOTS, SCREEN_FLOPS = 12, 12 + 5     # 5 of the screen's operations are FMAs
+# same-class pair of a live cube is screened (7 plain FP32 operations: a dot
+# product, the threshold's three terms and the comparison), and each pair that
+# passes is evaluated in full (117 plain operations and 14 transcendentals:
+# sqrt, rcp, exp2).  A transcendental issues at half the plain rate on gfx950
+# (measured 1.8-1.9 plain-op slots), so it counts 2.
+SCREEN_SLOTS, SCREEN_FLOPS = 7, 7 + 4      # 4 of the screen's operations are FMAs
 S12_PLAIN, S12_TRANS = 117, 14
 TRANS_SLOTS = 2
 S12_SLOTS = S12_PLAIN + TRANS_SLOTS * S12_TRANS
