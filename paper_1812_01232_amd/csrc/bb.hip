@@ -6,11 +6,10 @@
 // Queue of each problem: a small "hot" part holding every queued cube whose
 // priority key is below a threshold theta, and a large append-only "cold"
 // part holding the rest.  Each iteration only the hot part is scanned:
-//   select   2 radix passes (11 + 11 bits) over the ordered 32-bit key of
-//            the priority find the bucket (top 22 bits) of the k-th lowest
-//            key; compaction moves the k lowest (ties within the bucket in
-//            arbitrary order) into the parent list and keeps the rest (cubes
-//            whose lower bound is no longer below d* are dropped)
+//   select   3 radix passes (11 + 11 + 10 bits) over the ordered 32-bit key of
+//            the priority find the k-th lowest key; compaction moves the k
+//            lowest into the parent list and keeps the rest (cubes whose lower
+//            bound is no longer below d* are dropped)
 //   branch   8 children per parent, split in rotation or translation by the
 //            flag the bound kernel computed for the parent (Section 5.1); a
 //            rotation split shares one translation cell among its 8 children
@@ -301,13 +300,14 @@ __global__ __launch_bounds__(kBlock) void k_iter_begin(Bufs b, int P, int rb_slo
     }
 }
 
-// Radix select over the ordered 32-bit key of the priority, in two passes of
-// 11 bits: the k-th lowest key's top 22 bits (the bucket) are found exactly;
-// within that bucket (keys equal to 1.2e-4 relative) cubes are taken in
-// arbitrary order up to the quota.
-constexpr int kLowBits = 10;
+// Radix select over the ordered 32-bit key of the priority, in passes of 11,
+// 11 and 10 bits: the k-th lowest key is found exactly, and cubes whose key
+// equals it are taken in arbitrary order up to the quota.  (Stopping at a
+// coarser bucket is not enough: children inherit their parent's lower bound,
+// so a bucket that straddles d* - eps keeps refilling itself with cubes that
+// best-first order would never split.)
+constexpr int kRadixPasses = 3;
 constexpr uint32_t kHistPer = 16;   // keys per thread of a histogram pass (at least)
-__device__ __forceinline__ uint32_t kbucket(uint32_t key) { return key >> kLowBits; }
 
 // One radix pass over a problem's hot part (selection) or hot + cold parts
 // (re-partition): histogram of the next 11-bit digit below the prefix fixed
@@ -326,7 +326,9 @@ __global__ __launch_bounds__(kBlock) void k_hist(Bufs b, int rebuild_pass, int p
     if (blockIdx.x >= nb) return;
     for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) h[i] = 0;
     __syncthreads();
-    const int shift = pass == 0 ? 21 : 10;
+    const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
+    const uint32_t mask = pass == 2 ? 0x3ffu : 0x7ffu;
+    const int pshift = pass == 1 ? 21 : 10;
     const uint32_t prefix = s.prefix;
     const int lane = threadIdx.x & 63;
     for (int part = 0; part < nparts; ++part) {
@@ -338,8 +340,8 @@ __global__ __launch_bounds__(kBlock) void k_hist(Bufs b, int rebuild_pass, int p
             bool m = false;
             if (i < n) {
                 const uint32_t key = key32(q.prio[i]);
-                m = pass == 0 || (key >> 21) == prefix;
-                bin = (key >> shift) & 0x7ffu;
+                m = pass == 0 || (key >> pshift) == prefix;
+                bin = (key >> shift) & mask;
             }
             // keys cluster: when every counted lane of the wave hits one bin,
             // add the count once instead of serialising 64 LDS atomics
@@ -407,9 +409,9 @@ __global__ __launch_bounds__(kBlock) void k_scan(Bufs b, int rebuild_pass, int p
     __syncthreads();
     for (int j = 0; j < per; ++j) gh[t * per + j] = 0;
     if (t == 0) {
-        s.prefix = (pass == 0 ? 0u : s.prefix << 11) | found;
+        s.prefix = (pass == 0 ? 0u : s.prefix << (pass == 2 ? 10 : 11)) | found;
         s.need = left;
-        if (pass == 1) s.eq_quota = left;
+        if (pass == kRadixPasses - 1) s.eq_quota = left;
     }
 }
 
@@ -434,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_rebuild_compact(Bufs b)
         auto classify = [&](uint32_t i) -> int {
             const double lb = sane_lb(q.lb[i]);
             if (!(lb < dstar)) return 0;
-            const uint32_t key = kbucket(key32(q.prio[i]));
+            const uint32_t key = key32(q.prio[i]);
             return (all || key < T || (key == T && atomicAdd(&s.eq_taken, 1u) < s.eq_quota)) ? 1 : 2;
         };
         auto move = [&](const Queue &o, uint32_t cap, uint32_t i, uint32_t slot, double &mn) {
@@ -475,7 +477,7 @@ __global__ void k_rebuild_finish(Bufs b, int P)
         s.done = OVERFLOW;
         return;
     }
-    s.theta = s.take_all ? 0xffffffffu : s.prefix << kLowBits;   // hot iff the key's bucket is below the prefix
+    s.theta = s.take_all ? 0xffffffffu : s.prefix;   // hot iff the key is below the threshold
     s.minH = ord64(INFINITY);  // recomputed by the selection and the pushes
     s.hcur ^= 1;
     s.ccur ^= 1;
@@ -506,7 +508,7 @@ __global__ __launch_bounds__(kBlock) void k_select_compact(Bufs b)
     auto classify = [&](uint32_t i) -> int {
         const double lb = sane_lb(q.lb[i]);
         if (!(lb < dstar)) return 0;
-        const uint32_t key = kbucket(key32(q.prio[i]));
+        const uint32_t key = key32(q.prio[i]);
         return (all || key < T || (key == T && atomicAdd(&s.eq_taken, 1u) < s.eq_quota)) ? 1 : 2;
     };
     partition_tiles(
@@ -1008,7 +1010,7 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     hipLaunchKernelGGL(k_iter_begin, dim3(P), dim3(kBlock), 0, st, b, P, (int)rb_slot);
     // re-partition of the problems that asked for it
     if (rb_slot) {
-        for (int pass = 0; pass < 2; ++pass) {
+        for (int pass = 0; pass < kRadixPasses; ++pass) {
             hipLaunchKernelGGL(k_hist, dim3(gx, P), dim3(kBlock), 0, st, b, 1, pass);
             hipLaunchKernelGGL(k_scan, dim3(P), dim3(kBlock), 0, st, b, 1, pass);
         }
@@ -1016,7 +1018,7 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
         hipLaunchKernelGGL(k_rebuild_finish, dim3((P + 63) / 64), dim3(64), 0, st, b, P);
     }
     // selection of the k lowest hot cubes
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = 0; pass < kRadixPasses; ++pass) {
         hipLaunchKernelGGL(k_hist, dim3(gx, P), dim3(kBlock), 0, st, b, 0, pass);
         hipLaunchKernelGGL(k_scan, dim3(P), dim3(kBlock), 0, st, b, 0, pass);
     }
