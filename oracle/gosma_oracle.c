@@ -394,12 +394,17 @@ static double s11_lower_log(double alo, double ahi, double blo, double bhi, doub
  * directions,
  *   Z(a + b)/(Z(a) Z(b)) = a b (coth a + coth b) / (2 (a + b)) <= min(ahi, b)(coth alo + coth b)/2,
  * which bounds every angle since Z increases and K <= a + b.  A third bound
- * serves directions far apart: with G(y) = y / (1 - e^{-2y}) increasing and
- * h(K) = (1 - e^{-2K})/K <= 2,
- *   Z(K)/(Z(a) Z(b)) = e^{K - a - b} h(K) G(a) G(b)
- *                    <= 2 G(ahi) G(b) exp(-q alo b / (2 (alo + b))),
- * q = 4 sin^2(B/2), because K - a - b = -a b q / (K + a + b) with K <= a + b,
- * and a b / (a + b) increases with a.  The term is the smallest of the three. */
+ * serves directions far apart.  The ratio decreases with the angle (K does),
+ * so its largest value over angles >= B is at B, where
+ *   Z(K)/(Z(a) Z(b)) = e^{K - a - b} h(K) G(a) G(b),
+ * G(y) = y / (1 - e^{-2y}) increasing, h(K) = (1 - e^{-2K})/K <= min(2, 1/K),
+ * and K - a - b = -a b q / (K + a + b) <= -a b q / (2 (a + b)) with
+ * q = 4 sin^2(B/2) (K <= a + b; a b / (a + b) increases with a).  For
+ * B <= pi/2, K^2 = a^2 + b^2 + 2 a b cos B >= 2 a b >= 2 alo b, so
+ *   ratio <= G(ahi) G(b) exp(-q alo b / (2 (alo + b))) / sqrt(2 alo b);
+ * for B > pi/2 the same holds with q = 2 (the value at pi/2 bounds every
+ * larger angle), and also ratio <= 2 G(ahi) G(b) exp(-q alo b / (2 (alo + b))).
+ * The term is the smallest of these bounds. */
 static double ell(double y) { return oracle_log_Z(y) - y; }
 
 static double s12_upper_term(double alo, double ahi, double b, double B)
@@ -423,8 +428,10 @@ static double s12_upper_term(double alo, double ahi, double b, double B)
     const double expansion = exp(fmin(from_lo, from_hi));
     const double aligned = 0.5 * fmin(ahi, b) * (1.0 / tanh(alo) + 1.0 / tanh(b));
     /* log G(y) = y - log Z(y) = -ell(y) */
-    const double far = exp(log(2.0) - ell(ahi) - ell(b) - chord2 * alo * b / (2.0 * (alo + b)));
-    return fmin(fmin(expansion, aligned), far);
+    const double cf = alo * b / (2.0 * (alo + b));
+    const double far2 = exp(log(2.0) - ell(ahi) - ell(b) - chord2 * cf);
+    const double farK = exp(-ell(ahi) - ell(b) - fmin(chord2, 2.0) * cf - 0.5 * log(2.0 * alo * b));
+    return fmin(fmin(expansion, aligned), fmin(far2, farK));
 }
 
 /* Test hooks for the two summand bounds above. */

@@ -46,10 +46,11 @@ def test_s12_upper_term_bounds_interval_maximum():
 
 
 def test_s12_far_apart_bound():
-    """For directions far apart the S12 summand bound is at most
-    2 G(ahi) G(b) exp(-q alo b / (2 (alo + b))) (G(y) = y / (1 - e^{-2y}),
-    q = 4 sin^2(B/2)), and that expression bounds the ratio Z(K)/(Z(a) Z(b))
-    over a dense grid of concentrations in [alo, ahi] and angles >= B."""
+    """For directions far apart the S12 summand bound is at most the smaller of
+    2 G(ahi) G(b) exp(-q c) and G(ahi) G(b) exp(-min(q, 2) c) / sqrt(2 alo b)
+    (G(y) = y / (1 - e^{-2y}), q = 4 sin^2(B/2), c = alo b / (2 (alo + b))),
+    and both expressions bound the ratio Z(K)/(Z(a) Z(b)) over a dense grid
+    of concentrations in [alo, ahi] and angles >= B."""
     rng = np.random.default_rng(5)
     G = lambda y: y / -np.expm1(-2 * y)
     active = 0
@@ -60,7 +61,10 @@ def test_s12_far_apart_bound():
         B = rng.uniform(0, math.pi)
         ahi = a * (1 + w)
         q = 4 * math.sin(0.5 * B) ** 2
-        lfar = math.log(2 * G(ahi) * G(b)) - q * a * b / (2 * (a + b))
+        c = a * b / (2 * (a + b))
+        l2 = math.log(2 * G(ahi) * G(b)) - q * c
+        lK = math.log(G(ahi) * G(b)) - min(q, 2.0) * c - 0.5 * math.log(2 * a * b)
+        lfar = min(l2, lK)
         far = math.exp(lfar)
         bound = oracle.s12_upper_term(a, ahi, b, B)
         # FP64 rounding of an exponent of size |log far|, and of log Z(y) - y
@@ -71,7 +75,9 @@ def test_s12_far_apart_bound():
         ag = np.linspace(a, ahi, 81)[:, None]
         tg = np.linspace(B, math.pi, 81)[None, :]
         g = _g(ag, b, tg)
-        assert g.max() <= lfar + 1e-12 * (1 + np.abs(g).max())
+        slack = 1e-12 * (1 + np.abs(g).max())
+        assert g.max() <= l2 + slack
+        assert g.max() <= lK + slack
     assert active > 20
 
 
