@@ -283,6 +283,7 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
             double G = k / (-std::expm1(-2.0 * k));
             double coth = 1.0 + 2.0 / std::expm1(2.0 * k);
             h_vmf[2 * dst] = make_float4((float)dx[3 * j], (float)dx[3 * j + 1], (float)dx[3 * j + 2], (float)k);
+            // the pair screen's column term ln(weight G(kappa)) (the kernel subtracts ln(2 kappa) / 2)
             const double ell = w2[j] > 0 ? std::log(w2[j] * G) : -1e30;
             h_vmf[2 * dst + 1] = make_float4((float)w2[j], (float)G, (float)coth, (float)std::max(ell, -1e30));
         }

@@ -86,20 +86,26 @@ __device__ __forceinline__ void sincos_reduced(double x, double *s, double *c)
 }
 
 // Rotation matrix of the angle-axis vector r (Section 5.1), as
-// I + A [r]x + B [r]x^2 with A = sin|r|/|r|, B = (1 - cos|r|)/|r|^2.
-__device__ void rotation_matrix(const double r[3], double R[9])
+// I + A [r]x + B [r]x^2 with A = sin|r|/|r|, B = (1 - cos|r|)/|r|^2; also the
+// left Jacobian coefficients of the same map, J(r) = I + a [r]x + b [r]x^2 with
+// a = (1 - cos|r|)/|r|^2 = B and b = (|r| - sin|r|)/|r|^3, so that
+// d/ds R(r + s d) = [J(r) d]x R(r) at s = 0.
+__device__ void rotation_matrix(const double r[3], double R[9], double *ja, double *jb)
 {
     double th2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
     double A, B;
     if (th2 < 1e-8) {
         A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
         B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+        *jb = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
     } else {
         double th = sqrt(th2), sh, ch;
         sincos_reduced(0.5 * th, &sh, &ch);
         A = 2.0 * sh * ch / th;
         B = 2.0 * sh * sh / th2;
+        *jb = th < 1e-4 ? 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0 : (th - 2.0 * sh * ch) / (th2 * th);
     }
+    *ja = B;
     // [r]x^2 = r r^T - |r|^2 I
     R[0] = 1.0 + B * (r[0] * r[0] - th2);
     R[4] = 1.0 + B * (r[1] * r[1] - th2);
@@ -112,21 +118,19 @@ __device__ void rotation_matrix(const double r[3], double R[9])
     R[7] = A * r[0] + B * r[1] * r[2];
 }
 
-// Coefficients of the left Jacobian of the angle-axis map (Section 5.1),
-// J(r) = I + a [r]x + b [r]x^2 with a = (1 - cos|r|)/|r|^2 and
-// b = (|r| - sin|r|)/|r|^3: d/ds R(r + s d) = [J(r) d]x R(r) at s = 0.
-__device__ void left_jacobian_coef(const double r[3], double *a, double *b)
+// sin and cos of x in [0, pi/2] in FP32: Maclaurin series through x^13 and
+// x^14 in nested form (truncation below 1e-9).
+__device__ __forceinline__ void sincos_half(float x, float *s, float *c)
 {
-    const double t2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2], t = sqrt(t2);
-    if (t < 1e-4) {
-        *a = 0.5 - t2 / 24.0 + t2 * t2 / 720.0;
-        *b = 1.0 / 6.0 - t2 / 120.0 + t2 * t2 / 5040.0;
-    } else {
-        double sh, ch;
-        sincos_reduced(0.5 * t, &sh, &ch);
-        *a = 2.0 * sh * sh / t2;
-        *b = (t - 2.0 * sh * ch) / (t2 * t);
+    const float x2 = x * x;
+    float ts = 1.0f, tc = 1.0f;
+#pragma unroll
+    for (int k = 7; k >= 1; --k) {
+        ts = fmaf(-x2 * (1.0f / ((2.0f * k) * (2.0f * k + 1.0f))), ts, 1.0f);
+        tc = fmaf(-x2 * (1.0f / ((2.0f * k - 1.0f) * (2.0f * k))), tc, 1.0f);
     }
+    *s = x * ts;
+    *c = tc;
 }
 
 // Order-preserving map of a double onto unsigned 64-bit integers.
@@ -323,7 +327,7 @@ struct BlockShared {
     int drop[kMaxWaves], ubinf[kMaxWaves];
     float psum[kMaxWaves], prsum[kMaxWaves];
     float top[kMaxWaves][8];
-    double jc[4][3];   // J(r0) applied to four corners of the rotation cell's half-width box
+    float jc[4][3];    // J(r0) applied to four corners of the rotation cell's half-width box
     double dk[kMaxWaves];   // per wave: sum of w_i^2 klo_i / 2 (the pair screen's scale)
 };
 
@@ -358,13 +362,15 @@ constexpr int kG = 5, kV = 3;
 //   [3] lambda = min(1/3, 1/klo^2), Lam (pair screen), kappa(t0), -
 //
 // Pair screen.  The summand of a pair at the centre is at most
-// 2 G(k) G(k') exp(-q k k' / (2 (k + k'))) (h <= 2, K <= k + k'), and the lower
-// term over the cell is at most the centre value (the centre lies in the box
-// of concentrations and A >= theta).  A pair whose weighted bound is below
-// thr11 is dropped: the lower sum loses at most thr11 (and stays a lower
-// bound) and the centre sum is charged thr11 (and stays an upper bound).  The
+// G(k) G(k') exp(-min(q, 2) k k' / (2 (k + k'))) / sqrt(2 k k') (h(K) <= 1/K,
+// K <= k + k', K^2 >= 2 k k' up to a right angle, and the summand decreases
+// with the angle), and the lower term over the cell is at most the centre
+// value (the centre lies in the box of concentrations and A >= theta).  A
+// pair whose weighted bound is below thr11 is dropped: the lower sum loses at
+// most thr11 (and stays a lower bound) and the centre sum is charged thr11
+// (and stays an upper bound).  With min(q, 2) in place of q, the
 // test is  q k k' >= 2 (Lam_i + Lam_i' - ln thr11)(k + k'),  Lam_i =
-// ln(2 w_i G(k_i)), with thr11 = kCullRel D / (M (M - 1) / 2).
+// ln(w_i G(k_i) / sqrt(k_i)) + ln(2) / 4, with thr11 = kCullRel D / (M (M - 1) / 2).
 
 __device__ __forceinline__ void s11_terms(const float4 &A0, const float4 &A1, const float4 &A2, const float4 &A3,
                                           const float4 &B0, const float4 &B1, const float4 &B2, const float4 &B3,
@@ -454,7 +460,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             rec[kG * i] = make_float4((float)tp.u[0], (float)tp.u[1], (float)tp.u[2], (float)w);
             rec[kG * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)tp.cps, (float)tp.sps);
             rec[kG * i + 2] = make_float4((float)tp.ac, (float)tp.ha, (float)fa.G, (float)fa.nu);
-            const float lam = fminf(fmaxf(__builtin_amdgcn_logf(2.0f * (float)w * fk.G) * kLn2, -1e30f), 1e30f);
+            const float lam = fminf(fmaxf(__builtin_amdgcn_logf((float)w * fk.G * __builtin_amdgcn_rsqf((float)tp.kap)) *
+                                                  kLn2 + 0.25f * kLn2, -1e30f), 1e30f);
             dk += 0.5 * w * w * tp.klo;
             rec[kG * i + 3] = make_float4((float)fmin(1.0 / 3.0, 1.0 / (tp.klo * tp.klo)), lam, (float)tp.kap, 0.0f);
         }
@@ -516,7 +523,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             if (valid) {
                 const float4 B0 = rec[kG * b_], B3 = rec[kG * b_ + 3];
                 const float dx = A0.x - B0.x, dy = A0.y - B0.y, dz = A0.z - B0.z;
-                const float q = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const float q = fminf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), 2.0f);
                 keep = q * A3.z * B3.z < 2.0f * (A3.y + B3.y - lthr11) * (A3.z + B3.z);
                 ncull += keep ? 0 : 1;
             }
@@ -631,11 +638,12 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
 //   [1] kappa(t0), G(kappa), cos, sin of Psi / 2 with Psi = psi_t + psi_r (eq. 25)
 //   [2] kappa interval [alo, ahi] over the cell, half-width ha, coth(alo)
 //   [3] G(alo), G(ahi), nu(alo), nu(ahi)
-//   [4] Lam, 1 / alo, -, - (pair screen)
+//   [4] Lam, 1 / alo, -sin Psi, ln(alo) / 2 (pair screen, far-apart cap)
 // Screen row of the component (a separate LDS array, one float4):
 //   {w cos Psi, 1 - sin Psi - Lam / alo}
-// vMF record, two float4 (32 bytes, padded to 48):
-//   {dx, dy, dz, kappa}, {weight, G(kappa), coth(kappa), ell = ln(weight G(kappa))}.
+// vMF record, three float4 (48 bytes):
+//   {dx, dy, dz, kappa}, {weight, G(kappa), coth(kappa), ln(2 kappa) / 2}, {l, -, -, -}
+// with l = ln(weight G(kappa)) - ln(2 kappa) / 2 (the screen's column term).
 //
 // Upper bound of the summand over the cube (Theorem 1 with kappa_1i(t)
 // relaxed to [alo, ahi]): at the smallest angle B, and with
@@ -651,13 +659,15 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
 //
 // Pair screen.  (*) also bounds the summand at the centre, so a pair whose
 // weighted (*) is below a per-problem threshold thr contributes less than thr
-// to either sum.  With q = 4 sin^2(B/2) >= 2 - 2 (d cos Psi + sin Psi), a
-// lower bound for the angle B = max(0, theta - Psi) (d = cos theta; valid for
-// Psi <= pi/2), and a = 1/alo, c = 1/b, the pair is below thr when
-//   (w_i cos Psi_i) . mu_j <= (1 - sin Psi_i - Lam_i a) - l_j c - Lam_i c - l_j a,
-// Lam_i = ln(2 w_i G(ahi)) and l_j = ln(w_j G(b_j)) - ln thr, thr = kCullRel D / (M N):
-// a dot product and four multiply-adds per pair, from the component's screen
-// row and record slot (broadcast LDS reads) and per-lane vMF constants.  A pair that
+// to either sum.  With the smaller far-apart cap, weighted, the pair is below
+// thr when min(q, 2) / 2 >= (Lam_i + l_j)(1/alo + 1/b), Lam_i = ln(w_i G(ahi) /
+// sqrt(alo)), l_j = ln(w_j G(b_j) / sqrt(2 b_j)) - ln thr, thr = kCullRel D / (M N).
+// With q = 4 sin^2(B/2) >= 2 - 2 (d cos Psi + sin Psi), a lower bound for the
+// angle B = max(0, theta - Psi) (d = cos theta; valid for Psi <= pi/2), and
+// a = 1/alo, c = 1/b, that holds when
+//   max((w_i cos Psi_i) . mu_j, -sin Psi_i) <= (1 - sin Psi_i - Lam_i a) - l_j c - Lam_i c - l_j a:
+// a dot product, four multiply-adds and a max per pair, from the component's
+// screen row and record slot (broadcast LDS reads) and per-lane vMF constants.  A pair that
 // passes is dropped: it adds nothing to S12 at the centre (the upper bound
 // rises by at most 2 thr) and thr to the upper bound S12hi (which stays an
 // upper bound).  The pairs that remain are collected per wave in LDS and
@@ -667,7 +677,8 @@ template <bool TOP8>
 __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, int a_, const float4 &v0, const float4 &v1,
                                          float &sub, float &shi, float (&top)[8])
 {
-    const float4 R0 = rec[kG * a_], R1 = rec[kG * a_ + 1], R2 = rec[kG * a_ + 2], R3 = rec[kG * a_ + 3];
+    const float4 R0 = rec[kG * a_], R1 = rec[kG * a_ + 1], R2 = rec[kG * a_ + 2], R3 = rec[kG * a_ + 3],
+                 R4 = rec[kG * a_ + 4];
     const float b = v0.w;
     const float dx = R0.x - v0.x, dy = R0.y - v0.y, dz = R0.z - v0.z;
     const float q = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
@@ -710,7 +721,11 @@ __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, int a_,
         const float vB = fexp2(eB * kLog2e) * k2.hK * R3.y;
         const float vT = fminf(vA, vB) * v1.y;
         const float cap = 0.5f * fminf(ahi, b) * (R2.w + v1.z);
-        const float far = 2.0f * R3.y * v1.y * fexp2(-qB * alo * b * frcp(2.0f * (alo + b)) * kLog2e);
+        // far-apart caps: 2 G G e^{-qB cf} and G G e^{-min(qB, 2) cf} / sqrt(2 alo b)
+        const float cf = alo * b * frcp(2.0f * (alo + b));
+        const float e2 = fmaf(-qB, cf, kLn2);
+        const float eK = fmaf(-fminf(qB, 2.0f), cf, -(R4.w + v1.w));
+        const float far = R3.y * v1.y * fexp2(fminf(e2, eK) * kLog2e);
         shi += ww * fminf(fminf(vT, cap), far);
     }
 }
@@ -766,18 +781,18 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         // and moving w' inside the cone of half-angle psi_t around w = R_r0 u
         // adds at most 2 sin(psi_t / 2) |h_r|.
         const double hn = sqrt(hr[0] * hr[0] + hr[1] * hr[1] + hr[2] * hr[2]);
-        const double cap = fmin(hn, kPi);
+        const float hnf = (float)hn, cap = fminf(hnf, (float)kPi);
         const bool per_dir = sqrt(r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2]) + hn <= 5.5;
+        double R[9], ja, jb;
+        rotation_matrix(r0, R, &ja, &jb);
         if (per_dir && tid < 4) {
-            double ja, jb;
-            left_jacobian_coef(r0, &ja, &jb);
             const double d[3] = {hr[0], (tid & 2) ? -hr[1] : hr[1], (tid & 1) ? -hr[2] : hr[2]};
             // J d = d + a (r x d) + b (r (r . d) - |r|^2 d)
             const double x[3] = {r0[1] * d[2] - r0[2] * d[1], r0[2] * d[0] - r0[0] * d[2],
                                  r0[0] * d[1] - r0[1] * d[0]};
             const double rd = r0[0] * d[0] + r0[1] * d[1] + r0[2] * d[2];
             const double rr = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
-            for (int k = 0; k < 3; ++k) sh.jc[tid][k] = d[k] + ja * x[k] + jb * (r0[k] * rd - rr * d[k]);
+            for (int k = 0; k < 3; ++k) sh.jc[tid][k] = (float)(d[k] + ja * x[k] + jb * (r0[k] * rd - rr * d[k]));
         }
         __syncthreads();
         uint8_t flags = 0;
@@ -790,9 +805,6 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             }
             if (nr2 > kPi * kPi) flags |= GOSMA_FLAG_DROP_ROT;
         }
-        double R[9];
-        rotation_matrix(r0, R);
-
         int drop = 0, ubinf = 0;
         float psum = 0.0f, prsum = 0.0f;
         double dk = 0.0;
@@ -804,21 +816,25 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             psum += mx.pbar[g] * tp.psi;
             double w[3];
             for (int a = 0; a < 3; ++a) w[a] = R[3 * a] * tp.u[0] + R[3 * a + 1] * tp.u[1] + R[3 * a + 2] * tp.u[2];
-            double psir = cap;
+            // the rotation uncertainty of this direction (FP32: it enters the
+            // bound through FP32 records)
+            float psir = cap;
             if (per_dir) {
-                double m2 = 0.0;
-#pragma unroll 1
+                const float wf[3] = {(float)w[0], (float)w[1], (float)w[2]};
+                float m2 = 0.0f;
+#pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const double *v = sh.jc[q];
-                    const double x = w[1] * v[2] - w[2] * v[1], y = w[2] * v[0] - w[0] * v[2],
-                                 z = w[0] * v[1] - w[1] * v[0];
-                    m2 = fmax(m2, x * x + y * y + z * z);
+                    const float *v = sh.jc[q];
+                    const float x = wf[1] * v[2] - wf[2] * v[1], y = wf[2] * v[0] - wf[0] * v[2],
+                                z = wf[0] * v[1] - wf[1] * v[0];
+                    m2 = fmaxf(m2, fmaf(x, x, fmaf(y, y, z * z)));
                 }
-                psir = fmin(sqrt(m2) + 2.0 * tp.sps * hn + 1.3 * hn * hn, cap);
+                psir = fminf(fsqrt(m2) + 2.0f * (float)tp.sps * hnf + 1.3f * hnf * hnf, cap);
             }
-            prsum += mx.pbar[g] * (float)psir;
-            double crh, srh;
-            sincos_reduced(0.5 * psir, &srh, &crh);
+            prsum += mx.pbar[g] * psir;
+            float crf, srf;
+            sincos_half(0.5f * psir, &srf, &crf);
+            const double crh = crf, srh = srf;
             // half of Psi = psi_t + psi_r (eq. 25), as cos/sin
             const double cP = tp.cps * crh - tp.sps * srh, sP = tp.sps * crh + tp.cps * srh;
             const double ahi = tp.klo + 2.0 * tp.ha;
@@ -831,11 +847,12 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             {
                 const float cf = (float)cP, sf = (float)sP;
                 const float cPsi = cf * cf - sf * sf, sPsi = 2.0f * cf * sf;
-                const float lam = fmaxf(__builtin_amdgcn_logf(2.0f * wi * fh.G) * kLn2, -100.0f);
+                const float hla = 0.5f * kLn2 * __builtin_amdgcn_logf((float)tp.klo);   // ln(alo) / 2
+                const float lam = fmaxf(__builtin_amdgcn_logf(wi * fh.G) * kLn2 - hla, -100.0f);
                 const float ia = frcp((float)tp.klo);
                 const float r0 = cf >= sf ? 1.0f - sPsi - lam * ia : -1e30f;
                 scr[i] = make_float4((float)w[0] * cPsi, (float)w[1] * cPsi, (float)w[2] * cPsi, r0);
-                rec[kG * i + 4] = make_float4(lam, ia, 0.0f, 0.0f);
+                rec[kG * i + 4] = make_float4(lam, ia, -sPsi, hla);
             }
             rec[kG * i] = make_float4((float)w[0], (float)w[1], (float)w[2], wi);
             rec[kG * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)cP, (float)sP);
@@ -843,8 +860,11 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             rec[kG * i + 3] = make_float4((float)fl.G, (float)fh.G, (float)fl.nu, (float)fh.nu);
         }
         for (int j = tid; j < P.N; j += T) {
-            vrec[kV * j] = mx.vmf[2 * (P.vmf_off + j)];
-            vrec[kV * j + 1] = mx.vmf[2 * (P.vmf_off + j) + 1];
+            const float4 v0 = mx.vmf[2 * (P.vmf_off + j)], v1 = mx.vmf[2 * (P.vmf_off + j) + 1];
+            const float hlb = 0.5f * kLn2 * __builtin_amdgcn_logf(2.0f * v0.w);   // ln(2 kappa) / 2
+            vrec[kV * j] = v0;
+            vrec[kV * j + 1] = make_float4(v1.x, v1.y, v1.z, hlb);
+            vrec[kV * j + 2] = make_float4(v1.w - hlb, 0.0f, 0.0f, 0.0f);
         }
         drop = wave_or(drop);
         ubinf = wave_or(ubinf);
@@ -922,7 +942,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             // lane's vMF screen constants
             auto screened_in = [&](int a_, const float4 &vm, const float2 &vc) __attribute__((always_inline)) {
                 const float4 S0 = scr[a_], S1 = rec[kG * a_ + 4];
-                const float d = fmaf(S0.x, vm.x, fmaf(S0.y, vm.y, S0.z * vm.z));
+                const float d = fmaxf(fmaf(S0.x, vm.x, fmaf(S0.y, vm.y, S0.z * vm.z)), S1.z);
                 const float rhs = fmaf(-S1.y, vc.y, fmaf(-S1.x, vc.x, S0.w - vm.w));
                 return !(d <= rhs);
             };
@@ -959,8 +979,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                     const int jl = tid % cols, i0 = tid / cols;
                     for (int jb = 0; jb < nj; jb += cols) {
                         const int j = vb + jb + jl;
-                        const float4 v0 = vrec[kV * j], v1 = vrec[kV * j + 1];
-                        const float c = frcp(v0.w), l = fmaxf(v1.w, -100.0f) - lthr;
+                        const float4 v0 = vrec[kV * j];
+                        const float c = frcp(v0.w), l = fmaxf(vrec[kV * j + 2].x, -100.0f) - lthr;
                         const float4 vm = make_float4(v0.x, v0.y, v0.z, l * c);
                         const float2 vc = make_float2(c, l);
                         if (cols % 64 == 0) {
@@ -986,8 +1006,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                     for (int st = 0; st < steps; ++st) {
                         const bool valid = i < ni;
                         const int jj = vb + j;
-                        const float4 v0 = vrec[kV * jj], v1 = vrec[kV * jj + 1];
-                        const float c = frcp(v0.w), l = fmaxf(v1.w, -100.0f) - lthr;
+                        const float4 v0 = vrec[kV * jj];
+                        const float c = frcp(v0.w), l = fmaxf(vrec[kV * jj + 2].x, -100.0f) - lthr;
                         offer(gb + min(i, ni - 1), jj, make_float4(v0.x, v0.y, v0.z, l * c), make_float2(c, l), valid);
                         j += dj;
                         i += di;
