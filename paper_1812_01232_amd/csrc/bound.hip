@@ -70,6 +70,14 @@ __device__ __forceinline__ void decode_key(uint64_t key, const double *lo, const
 // nested form through x^27 and x^26 (truncation below 3e-15 on [-pi, pi]).
 // A short fixed sequence keeps the register footprint of the per-cell set-up
 // small next to the library routine.
+// Series factors 1/((2k)(2k+1)) and 1/((2k-1)(2k)), k = 1..13, in constant
+// memory: read with scalar loads, so the unrolled series needs no vector
+// registers for its coefficients.
+__constant__ double kSinF[13] = {1.0 / 6, 1.0 / 20, 1.0 / 42, 1.0 / 72, 1.0 / 110, 1.0 / 156, 1.0 / 210,
+                                 1.0 / 272, 1.0 / 342, 1.0 / 420, 1.0 / 506, 1.0 / 600, 1.0 / 702};
+__constant__ double kCosF[13] = {1.0 / 2, 1.0 / 12, 1.0 / 30, 1.0 / 56, 1.0 / 90, 1.0 / 132, 1.0 / 182,
+                                 1.0 / 240, 1.0 / 306, 1.0 / 380, 1.0 / 462, 1.0 / 552, 1.0 / 650};
+
 __device__ __forceinline__ void sincos_reduced(double x, double *s, double *c)
 {
     constexpr double kTwoPi = 6.283185307179586476925286766559;
@@ -77,9 +85,9 @@ __device__ __forceinline__ void sincos_reduced(double x, double *s, double *c)
     const double x2 = x * x;
     double ts = 1.0, tc = 1.0;
 #pragma unroll
-    for (int k = 13; k >= 1; --k) {
-        ts = fma(-x2 * (1.0 / ((2.0 * k) * (2.0 * k + 1.0))), ts, 1.0);
-        tc = fma(-x2 * (1.0 / ((2.0 * k - 1.0) * (2.0 * k))), tc, 1.0);
+    for (int k = 12; k >= 0; --k) {
+        ts = fma(-x2 * kSinF[k], ts, 1.0);
+        tc = fma(-x2 * kCosF[k], tc, 1.0);
     }
     *s = x * ts;
     *c = tc;
@@ -491,7 +499,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
         }
         // threshold of the pair screen, per unordered GMM pair
         const double thr11 = P.M > 1 ? kCullRel * dk / (0.5 * (double)P.M * (double)(P.M - 1)) : 0.0;
-        const float lthr11 = thr11 > 0.0 ? (float)log(thr11) : -INFINITY;
+        const float lthr11 = thr11 > 0.0 ? __builtin_amdgcn_logf((float)thr11) * kLn2 : -INFINITY;
 
         double acc_ub = dub, acc_lo = dlo;
         // Candidate pairs are offered by every lane of a wave in lockstep; the
@@ -893,7 +901,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         }
         // threshold of the pair screen, per GMM-vMF pair
         const double thr = kCullRel * dk / ((double)P.M * (double)P.N);
-        const float lthr = thr > 0.0 ? (float)log(thr) : -INFINITY;
+        const float lthr = thr > 0.0 ? __builtin_amdgcn_logf((float)thr) * kLn2 : -INFINITY;
         if (drop) flags |= GOSMA_FLAG_DROP_TRANS;
         if (ubinf) flags |= GOSMA_FLAG_UB_INF;
         // branching rule (Section 5.1): the weighted means of the two uncertainties
