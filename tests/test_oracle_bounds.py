@@ -198,3 +198,67 @@ def test_top8_are_the_largest_pair_terms():
         assert np.all(np.diff(top) <= 0)
         assert top.sum() <= b["s12_ub"][q] * (1 + 1e-12)
         assert top[0] >= b["s12_ub"][q] / (sc.M * sc.N)
+
+
+def test_pair_screen_inequality_implies_negligible_summand():
+    """The GMM-vMF pair screen of the bound kernel, written out on the CPU: a
+    pair is dropped when max(d cos Psi, -sin Psi) <= (1 - sin Psi - Lam/alo)
+    - l/b - Lam/b - l/alo with d = cos(theta), Lam = ln(w1 G(ahi)/sqrt(alo)),
+    l = ln(w2 G(b)/sqrt(2 b)) - ln(thr).  Whenever it drops a pair, the
+    oracle's S12 summand bound at B = max(0, theta - Psi), weighted, and the
+    centre summand at any concentration in [alo, ahi] are below thr."""
+    rng = np.random.default_rng(7)
+    G = lambda y: y / -np.expm1(-2 * y)
+    dropped = 0
+    for _ in range(4000):
+        alo = math.exp(rng.uniform(math.log(2), math.log(2e4)))
+        ahi = alo * (1 + 10 ** rng.uniform(-4, 0.5))
+        b = math.exp(rng.uniform(math.log(2), math.log(2e4)))
+        psi = rng.uniform(0, math.pi / 2) * rng.uniform() ** 2
+        theta = rng.uniform(0, math.pi)
+        w1, w2 = 10 ** rng.uniform(-3, 0, size=2)
+        thr = 10 ** rng.uniform(-14, -6)
+        lam = math.log(w1 * G(ahi) / math.sqrt(alo))
+        l = math.log(w2 * G(b) / math.sqrt(2 * b)) - math.log(thr)
+        d = math.cos(theta)
+        rhs = (1 - math.sin(psi) - lam / alo) - l / b - lam / b - l / alo
+        if not max(d * math.cos(psi), -math.sin(psi)) <= rhs:
+            continue
+        dropped += 1
+        B = max(0.0, theta - psi)
+        assert w1 * w2 * oracle.s12_upper_term(alo, ahi, b, B) <= thr * (1 + 1e-9)
+        for a in (alo, 0.5 * (alo + ahi), ahi):
+            centre = math.exp(_g(np.array([a]), b, np.array([theta]))[0])
+            assert w1 * w2 * centre <= thr * (1 + 1e-9)
+    assert dropped > 500
+
+
+def test_gmm_pair_screen_inequality_implies_negligible_summand():
+    """The GMM-GMM pair screen, written out on the CPU: a pair of centre
+    concentrations k, k' at angle theta is dropped when
+    min(q, 2) k k' >= 2 (Lam + Lam' - ln thr)(k + k'), q = 2 - 2 cos(theta),
+    Lam = ln(w G(k)/sqrt(k)) + ln(2)/4.  Whenever it drops a pair, the weighted
+    centre summand 2 w w' Z(K)/(Z(k) Z(k')) and the oracle's lower term over
+    any box of concentrations around the centre, at any angle >= theta, are
+    below thr."""
+    rng = np.random.default_rng(8)
+    G = lambda y: y / -np.expm1(-2 * y)
+    dropped = 0
+    for _ in range(4000):
+        k1, k2 = np.exp(rng.uniform(math.log(2), math.log(2e4), size=2))
+        theta = rng.uniform(0, math.pi)
+        w1, w2 = 10 ** rng.uniform(-3, 0, size=2)
+        thr = 10 ** rng.uniform(-14, -6)
+        lam1 = math.log(w1 * G(k1) / math.sqrt(k1)) + 0.25 * math.log(2)
+        lam2 = math.log(w2 * G(k2) / math.sqrt(k2)) + 0.25 * math.log(2)
+        q = 2 - 2 * math.cos(theta)
+        if not min(q, 2.0) * k1 * k2 >= 2 * (lam1 + lam2 - math.log(thr)) * (k1 + k2):
+            continue
+        dropped += 1
+        centre = math.exp(_g(np.array([k1]), k2, np.array([theta]))[0])
+        assert 2 * w1 * w2 * centre <= thr * (1 + 1e-9)
+        h1, h2 = k1 * rng.uniform(0, 0.5), k2 * rng.uniform(0, 0.5)
+        A = min(math.pi, theta + rng.uniform(0, 0.3))
+        lo = oracle.s11_lower_log(k1 - h1, k1 + h1, k2 - h2, k2 + h2, A)
+        assert 2 * w1 * w2 * math.exp(lo) <= thr * (1 + 1e-9)
+    assert dropped > 500
