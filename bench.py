@@ -34,15 +34,21 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Op model of the GMM-vMF pair sums, counted from the kernel source: every
-# same-class pair of a live cube is screened (7 plain FP32 operations: a dot
-# product, the threshold's three terms and the comparison), and each pair that
-# passes is evaluated in full (117 plain operations and 14 transcendentals:
-# sqrt, rcp, exp2).  A transcendental issues at half the plain rate on gfx950
-# (measured 1.8-1.9 plain-op slots), so it counts 2.
+# Op model of the GMM-vMF pair kernel, counted from its source (the design doc lists
+# the counts).  A plain FP32 operation takes one issue slot per lane; a
+# transcendental (sqrt, rcp, exp2, log2) issues at half that rate on gfx950
+# (measured 1.8-1.9 plain-op slots), and so does an FP64 operation (the FP64
+# vector peak is half the FP32 one), so both count 2.
+#   per component and cube (the set-up of Lemmas 2-3 and of the kappa
+#   interval): 54 FP64 + 409 plain FP32 + 17 transcendentals;
+#   per same-class pair screened: 7 plain (a dot product, three threshold
+#   terms, a compare);
+#   per pair evaluated in full: 125 plain + 14 transcendentals.
+TRANS_SLOTS = FP64_SLOTS = 2
+PREP_SLOTS = 54 * FP64_SLOTS + 409 + 17 * TRANS_SLOTS
+PREP_FLOPS = 54 + 409 + 17
 SCREEN_SLOTS, SCREEN_FLOPS = 7, 7 + 4      # 4 of the screen's operations are FMAs
-S12_PLAIN, S12_TRANS = 117, 14
-TRANS_SLOTS = 2
+S12_PLAIN, S12_TRANS = 125, 14
 S12_SLOTS = S12_PLAIN + TRANS_SLOTS * S12_TRANS
 S12_FLOPS = S12_PLAIN + S12_TRANS + 13      # 13 of the plain operations are FMAs
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9            # CUs x SIMDs x lanes x clock
@@ -285,8 +291,9 @@ def main():
     s12_ms, s12_n = kt_search["s12"]
     s12_s = s12_ms / 1e3
     screened, evaluated = pairs_search
-    achieved = (screened * SCREEN_SLOTS + evaluated * S12_SLOTS) / s12_s / 1e12
-    tflops = (screened * SCREEN_FLOPS + evaluated * S12_FLOPS) / s12_s / 1e12
+    comps = screened // N        # live cubes x M (one problem, no classes: M N pairs per live cube)
+    achieved = (comps * PREP_SLOTS + screened * SCREEN_SLOTS + evaluated * S12_SLOTS) / s12_s / 1e12
+    tflops = (comps * PREP_FLOPS + screened * SCREEN_FLOPS + evaluated * S12_FLOPS) / s12_s / 1e12
     peak = PEAK_SLOTS / 1e12
 
     # bound kernels alone on a fixed batch of cubes across levels
