@@ -35,16 +35,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Op model of the GMM-vMF pair kernel, counted from its source (the design doc lists
-# the counts).  A plain FP32 operation takes one issue slot per lane; a
-# transcendental (sqrt, rcp, exp2, log2) issues at half that rate on gfx950
-# (measured 1.8-1.9 plain-op slots), and so does an FP64 operation (the FP64
-# vector peak is half the FP32 one), so both count 2.
+# the counts).  A plain FP32 or FP64 operation takes one issue slot per lane
+# (the FP64 vector peak, 78.6 TFLOP/s, is one FMA per lane per clock, like
+# unpacked FP32); a transcendental (sqrt, rcp, exp2, log2) issues at half that
+# rate on gfx950 (measured 1.8-1.9 plain-op slots), so it counts 2.
 #   per component and cube (the set-up of Lemmas 2-3 and of the kappa
 #   interval): 54 FP64 + 409 plain FP32 + 17 transcendentals;
 #   per same-class pair screened: 7 plain (a dot product, three threshold
 #   terms, a compare);
 #   per pair evaluated in full: 125 plain + 14 transcendentals.
-TRANS_SLOTS = FP64_SLOTS = 2
+TRANS_SLOTS, FP64_SLOTS = 2, 1
 PREP_SLOTS = 54 * FP64_SLOTS + 409 + 17 * TRANS_SLOTS
 PREP_FLOPS = 54 + 409 + 17
 SCREEN_SLOTS, SCREEN_FLOPS = 7, 7 + 4      # 4 of the screen's operations are FMAs

@@ -133,6 +133,7 @@ void gosma_destroy(gosma_ctx *ctx)
     free_problems(ctx);
     dfree(ctx->d_s11ub);
     dfree(ctx->d_s11lo);
+    dfree(ctx->d_setup);
     dfree(ctx->d_pairs);
     gosma_release_solver(ctx);
     gosma_release_mlp(ctx);
@@ -393,9 +394,11 @@ int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tke
     if (ctx->s11_cap < n) {
         dfree(ctx->d_s11ub);
         dfree(ctx->d_s11lo);
+        dfree(ctx->d_setup);
         ctx->s11_cap = 0;
         HIP_TRY(ctx, hipMalloc((void **)&ctx->d_s11ub, sizeof(double) * n));
         HIP_TRY(ctx, hipMalloc((void **)&ctx->d_s11lo, sizeof(double) * n));
+        HIP_TRY(ctx, hipMalloc((void **)&ctx->d_setup, sizeof(gosma::CubeSetup) * n));
         ctx->s11_cap = n;
     }
     gosma::DevMix mx = ctx->mix();
@@ -407,7 +410,7 @@ int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tke
     if (ctx->timing) out.pair_counts = ctx->d_pairs;
     ti = ctx->time_begin(GOSMA_KERNEL_S12, s);
     HIP_TRY(ctx, gosma::launch_s12(mx, rkeys, tkeys, problem, nullptr, ctx->d_s11ub, ctx->d_s11lo, n, nullptr, 1, out,
-                                   0.0, ctx->maxM, ctx->maxN, top8 != nullptr, ctx->tile12, s));
+                                   0.0, ctx->maxM, ctx->maxN, top8 != nullptr, ctx->tile12, ctx->d_setup, s));
     ctx->time_end(ti, s);
     return GOSMA_OK;
 }

@@ -168,6 +168,7 @@ struct Bufs {
     double *cub, *clb, *clbs;
     uint8_t *cflags;
     double *s11ub, *s11lo;
+    CubeSetup *csetup;            // per-child set-up of the pair kernel
     uint32_t *hist;               // kHistBins per problem
     PState *st;
     GState *g;
@@ -913,6 +914,7 @@ void free_solver(Solver *s)
     dfree(b.cflags);
     dfree(b.s11ub);
     dfree(b.s11lo);
+    dfree(b.csetup);
     dfree(b.hist);
     dfree(b.st);
     dfree(b.g);
@@ -964,6 +966,7 @@ hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap, b
     if (!e) e = dalloc(b.cflags, nc);
     if (!e) e = dalloc(b.s11ub, nc);
     if (!e) e = dalloc(b.s11lo, nc);
+    if (!e) e = dalloc(b.csetup, nc);
     if (!e) e = dalloc(b.hist, (size_t)gosma::kHistBins * P);
     if (!e) e = dalloc(b.st, (size_t)P);
     if (!e) e = dalloc(b.g, 1);
@@ -1038,7 +1041,7 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     BoundOut bo{b.cub, b.clb, b.clbs, nullptr, b.cflags, top8 ? b.ctop8 : nullptr, nullptr, &b.st->dstar,
                 (int)(sizeof(PState) / sizeof(unsigned long long)), timed ? ctx->d_pairs : nullptr};
     e = launch_s12(mx, b.crk, b.ctk, b.cpid, b.ctidx, b.s11ub, b.s11lo, maxc, &b.g->nchild, 1, bo, kMarginGamma,
-                   ctx->maxM, ctx->maxN, top8, ctx->tile12, st);
+                   ctx->maxM, ctx->maxN, top8, ctx->tile12, b.csetup, st);
     T1(ti);
     if (e) return e;
     if (logging) hipLaunchKernelGGL(k_log_records, dim3(std::max(1, gx / 8), P), dim3(kBlock), 0, st, b, P);
@@ -1128,7 +1131,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         e = launch_s11(mx, b.ctk, b.cpid, P, nullptr, S11Out{b.s11ub, b.s11lo}, ctx->maxM, ctx->tile11, st);
         if (!e)
             e = launch_s12(mx, b.crk, b.ctk, b.cpid, nullptr, b.s11ub, b.s11lo, P, nullptr, 1, bo, kMarginGamma,
-                           ctx->maxM, ctx->maxN, true, ctx->tile12, st);
+                           ctx->maxM, ctx->maxN, true, ctx->tile12, b.csetup, st);
         if (!e) {
             hipLaunchKernelGGL(k_seed, dim3((P + 63) / 64), dim3(64), 0, st, b, P);
             e = hipGetLastError();

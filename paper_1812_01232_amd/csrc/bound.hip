@@ -335,7 +335,6 @@ struct BlockShared {
     int drop[kMaxWaves], ubinf[kMaxWaves];
     float psum[kMaxWaves], prsum[kMaxWaves];
     float top[kMaxWaves][8];
-    float jc[4][3];    // J(r0) applied to four corners of the rotation cell's half-width box
     double dk[kMaxWaves];   // per wave: sum of w_i^2 klo_i / 2 (the pair screen's scale)
 };
 
@@ -355,10 +354,10 @@ constexpr int kBatch = 4, kList = 64 * kBatch + 64;
 // the runs are accumulated in FP64.
 constexpr int kRun = 8;
 
-// LDS record strides in float4: a GMM record holds four float4 and a vMF
-// record two; the padding makes the strides 20 and 12 dwords, so 16-byte
-// reads of consecutive records by consecutive lanes hit distinct banks.
-constexpr int kG = 5, kV = 3;
+// LDS record strides in float4: a GMM record holds five float4 (a stride of
+// 20 dwords, so 16-byte reads of consecutive records by consecutive lanes hit
+// distinct banks) and a vMF record two.
+constexpr int kG = 5, kV = 2;
 
 // ---------------------------------------------------------------------------
 // S11 over translation cells
@@ -649,9 +648,10 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
 //   [4] Lam, 1 / alo, -sin Psi, ln(alo) / 2 (pair screen, far-apart cap)
 // Screen row of the component (a separate LDS array, one float4):
 //   {w cos Psi, 1 - sin Psi - Lam / alo}
-// vMF record, three float4 (48 bytes):
-//   {dx, dy, dz, kappa}, {weight, G(kappa), coth(kappa), ln(2 kappa) / 2}, {l, -, -, -}
-// with l = ln(weight G(kappa)) - ln(2 kappa) / 2 (the screen's column term).
+// vMF record, two float4 (32 bytes):
+//   {dx, dy, dz, kappa}, {weight, G(kappa), coth(kappa), ln(2 kappa) / 2};
+// the screen's column term l = ln(weight G(kappa)) - ln(2 kappa) / 2 - ln thr is
+// formed per lane from the problem's vMF row (which holds ln(weight G(kappa))).
 //
 // Upper bound of the summand over the cube (Theorem 1 with kappa_1i(t)
 // relaxed to [alo, ahi]): at the smallest angle B, and with
@@ -738,17 +738,72 @@ __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, int a_,
     }
 }
 
-// Four waves per SIMD: the FP64 per-component prep then spills a few
-// registers once per cube, while the pair loops stay in registers.
+// Per-cube set-up of k_s12 (one thread per cube): the two cells, the rotation
+// matrix and, for Lemma 2 per direction (reading in k_s12 below), the left
+// Jacobian applied to four corners of the rotation cell's half-width box.
+__global__ __launch_bounds__(256) void k_cube_setup(DevMix mx, const uint64_t *__restrict__ rkeys,
+                                                    const uint64_t *__restrict__ tkeys,
+                                                    const uint32_t *__restrict__ pids, int64_t n_host,
+                                                    const uint32_t *__restrict__ n_dev, int n_dev_mul,
+                                                    CubeSetup *__restrict__ out)
+{
+    const int64_t n = n_dev ? (int64_t)n_dev[0] * n_dev_mul : n_host;
+    for (int64_t cube = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cube < n;
+         cube += (int64_t)gridDim.x * blockDim.x) {
+        CubeSetup cs;
+        const uint32_t pid = pids ? pids[cube] : 0u;
+        if (pid >= (uint32_t)mx.n_prob) {
+            cs = CubeSetup{};
+            cs.flags = kSetupInvalid;
+            out[cube] = cs;
+            continue;
+        }
+        const ProbDesc &P = mx.prob[pid];
+        double r0[3], hr[3];
+        decode_key(rkeys[cube], P.r_lo, P.r_w, r0, hr);
+        decode_key(tkeys[cube], P.t_lo, P.t_w, cs.t0, cs.tau);
+        const double hn = sqrt(hr[0] * hr[0] + hr[1] * hr[1] + hr[2] * hr[2]);
+        cs.hn = (float)hn;
+        cs.cap = fminf(cs.hn, (float)kPi);
+        const double rr = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
+        uint32_t flags = sqrt(rr) + hn <= 5.5 ? kSetupPerDir : 0u;
+        double ja, jb;
+        rotation_matrix(r0, cs.R, &ja, &jb);
+        for (int q = 0; q < 4; ++q) {
+            const double d[3] = {hr[0], (q & 2) ? -hr[1] : hr[1], (q & 1) ? -hr[2] : hr[2]};
+            // J d = d + a (r x d) + b (r (r . d) - |r|^2 d)
+            const double x[3] = {r0[1] * d[2] - r0[2] * d[1], r0[2] * d[0] - r0[0] * d[2],
+                                 r0[0] * d[1] - r0[1] * d[0]};
+            const double rd = r0[0] * d[0] + r0[1] * d[1] + r0[2] * d[2];
+            for (int k = 0; k < 3; ++k) cs.jc[q][k] = (float)(d[k] + ja * x[k] + jb * (r0[k] * rd - rr * d[k]));
+        }
+        // rotation cells with no point in the radius-pi ball hold no rotation
+        double nr2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double lo = r0[k] - hr[k], hi = r0[k] + hr[k];
+            const double nk = lo > 0.0 ? lo : (hi < 0.0 ? hi : 0.0);
+            nr2 += nk * nk;
+        }
+        if (nr2 > kPi * kPi) flags |= GOSMA_FLAG_DROP_ROT;
+        cs.flags = flags;
+        cs.pad = 0;
+        out[cube] = cs;
+    }
+}
+
+// Five waves per SIMD fit the plain kernel's registers without spills; the
+// variant that also keeps the top-8 terms (learned order, record logging) is
+// held to four.
 template <bool TOP8>
-__global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_s12(DevMix mx, const uint64_t *__restrict__ rkeys,
+__global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(TOP8 ? 4 : 5))) void k_s12(DevMix mx, const uint64_t *__restrict__ rkeys,
                                                          const uint64_t *__restrict__ tkeys,
                                                          const uint32_t *__restrict__ pids,
                                                          const int64_t *__restrict__ tidx,
                                                          const double *__restrict__ s11ub,
                                                          const double *__restrict__ s11lo, int64_t n_host,
                                                          const uint32_t *__restrict__ n_dev, int n_dev_mul,
-                                                         BoundOut out, double gamma, int maxM, int maxN)
+                                                         BoundOut out, double gamma, int maxM, int maxN,
+                                                         const CubeSetup *__restrict__ setup)
 {
     extern __shared__ float4 lds4[];
     __shared__ BlockShared sh;
@@ -762,8 +817,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
     unsigned nscr = 0, ncull_all = 0;   // per wave: pairs screened and dropped, over all cubes of the block
     for (int64_t cube = blockIdx.x; cube < n; cube += gridDim.x) {
         __syncthreads();
-        const uint32_t pid = pids ? pids[cube] : 0u;
-        if (pid >= (uint32_t)mx.n_prob) {     // invalid problem index: no bound, both drop flags
+        const CubeSetup &cs = setup[cube];
+        if (cs.flags & kSetupInvalid) {     // invalid problem index: no bound, both drop flags
             if (tid == 0) {
                 out.ub[cube] = NAN;
                 out.lb[cube] = NAN;
@@ -772,10 +827,9 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             }
             continue;
         }
+        const uint32_t pid = pids ? pids[cube] : 0u;
         const ProbDesc P = mx.prob[pid];
-        double r0[3], hr[3], t0[3], tau[3];
-        decode_key(rkeys[cube], P.r_lo, P.r_w, r0, hr);
-        decode_key(tkeys[cube], P.t_lo, P.t_w, t0, tau);
+        const double *R = cs.R, *t0 = cs.t0, *tau = cs.tau;
 
         // Lemma 2, per direction.  The angle-axis metric bound
         // angle(R_r p, R_s p) <= |r - s| caps every direction's rotation
@@ -785,34 +839,12 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         // a unit direction at most 1.6 while |r| <= 5.5, its length is at most
         //   |(J(r0) d) x w'| + 1.3 |d|^2,   w' = R_r0 p.
         // The first term is the norm of a linear function of d, largest at a
-        // corner of the box (corners come in opposite pairs, so four suffice),
-        // and moving w' inside the cone of half-angle psi_t around w = R_r0 u
-        // adds at most 2 sin(psi_t / 2) |h_r|.
-        const double hn = sqrt(hr[0] * hr[0] + hr[1] * hr[1] + hr[2] * hr[2]);
-        const float hnf = (float)hn, cap = fminf(hnf, (float)kPi);
-        const bool per_dir = sqrt(r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2]) + hn <= 5.5;
-        double R[9], ja, jb;
-        rotation_matrix(r0, R, &ja, &jb);
-        if (per_dir && tid < 4) {
-            const double d[3] = {hr[0], (tid & 2) ? -hr[1] : hr[1], (tid & 1) ? -hr[2] : hr[2]};
-            // J d = d + a (r x d) + b (r (r . d) - |r|^2 d)
-            const double x[3] = {r0[1] * d[2] - r0[2] * d[1], r0[2] * d[0] - r0[0] * d[2],
-                                 r0[0] * d[1] - r0[1] * d[0]};
-            const double rd = r0[0] * d[0] + r0[1] * d[1] + r0[2] * d[2];
-            const double rr = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
-            for (int k = 0; k < 3; ++k) sh.jc[tid][k] = (float)(d[k] + ja * x[k] + jb * (r0[k] * rd - rr * d[k]));
-        }
-        __syncthreads();
-        uint8_t flags = 0;
-        {
-            double nr2 = 0.0;
-            for (int k = 0; k < 3; ++k) {
-                const double lo = r0[k] - hr[k], hi = r0[k] + hr[k];
-                const double nk = lo > 0.0 ? lo : (hi < 0.0 ? hi : 0.0);
-                nr2 += nk * nk;
-            }
-            if (nr2 > kPi * kPi) flags |= GOSMA_FLAG_DROP_ROT;
-        }
+        // corner of the box (corners come in opposite pairs, so four suffice:
+        // cs.jc), and moving w' inside the cone of half-angle psi_t around
+        // w = R_r0 u adds at most 2 sin(psi_t / 2) |h_r|.
+        const float hnf = cs.hn, cap = cs.cap;
+        const bool per_dir = (cs.flags & kSetupPerDir) != 0;
+        uint8_t flags = (uint8_t)(cs.flags & GOSMA_FLAG_DROP_ROT);
         int drop = 0, ubinf = 0;
         float psum = 0.0f, prsum = 0.0f;
         double dk = 0.0;
@@ -832,7 +864,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                 float m2 = 0.0f;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const float *v = sh.jc[q];
+                    const float *v = cs.jc[q];
                     const float x = wf[1] * v[2] - wf[2] * v[1], y = wf[2] * v[0] - wf[0] * v[2],
                                 z = wf[0] * v[1] - wf[1] * v[0];
                     m2 = fmaxf(m2, fmaf(x, x, fmaf(y, y, z * z)));
@@ -872,7 +904,6 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             const float hlb = 0.5f * kLn2 * __builtin_amdgcn_logf(2.0f * v0.w);   // ln(2 kappa) / 2
             vrec[kV * j] = v0;
             vrec[kV * j + 1] = make_float4(v1.x, v1.y, v1.z, hlb);
-            vrec[kV * j + 2] = make_float4(v1.w - hlb, 0.0f, 0.0f, 0.0f);
         }
         drop = wave_or(drop);
         ubinf = wave_or(ubinf);
@@ -988,7 +1019,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                     for (int jb = 0; jb < nj; jb += cols) {
                         const int j = vb + jb + jl;
                         const float4 v0 = vrec[kV * j];
-                        const float c = frcp(v0.w), l = fmaxf(vrec[kV * j + 2].x, -100.0f) - lthr;
+                        const float lw = mx.vmf[2 * (P.vmf_off + j) + 1].w - vrec[kV * j + 1].w;
+                        const float c = frcp(v0.w), l = fmaxf(lw, -100.0f) - lthr;
                         const float4 vm = make_float4(v0.x, v0.y, v0.z, l * c);
                         const float2 vc = make_float2(c, l);
                         if (cols % 64 == 0) {
@@ -1015,7 +1047,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                         const bool valid = i < ni;
                         const int jj = vb + j;
                         const float4 v0 = vrec[kV * jj];
-                        const float c = frcp(v0.w), l = fmaxf(vrec[kV * jj + 2].x, -100.0f) - lthr;
+                        const float lw = mx.vmf[2 * (P.vmf_off + jj) + 1].w - vrec[kV * jj + 1].w;
+                        const float c = frcp(v0.w), l = fmaxf(lw, -100.0f) - lthr;
                         offer(gb + min(i, ni - 1), jj, make_float4(v0.x, v0.y, v0.z, l * c), make_float2(c, l), valid);
                         j += dj;
                         i += di;
@@ -1161,18 +1194,23 @@ hipError_t launch_s11(const DevMix &mx, const uint64_t *tkeys, const uint32_t *p
 hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                       const int64_t *tidx, const double *s11ub, const double *s11lo, int64_t n, const uint32_t *n_dev,
                       int n_dev_mul, BoundOut out, double margin_gamma, int maxM, int maxN, bool with_top8, Tile tile,
-                      hipStream_t stream)
+                      CubeSetup *setup, hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
-    if (!tile_ok(tile)) return hipErrorInvalidValue;
+    if (!tile_ok(tile) || !setup) return hipErrorInvalidValue;
+    {
+        const unsigned gs = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+        hipLaunchKernelGGL(k_cube_setup, dim3(gs), dim3(256), 0, stream, mx, rkeys, tkeys, pids, n, n_dev, n_dev_mul,
+                           setup);
+    }
     const size_t lds = s12_lds_bytes(maxM, maxN, tile.waves);
     const unsigned g = (unsigned)std::min<int64_t>(tile.blocks, n);
     if (with_top8)
         hipLaunchKernelGGL(k_s12<true>, dim3(g), dim3(64 * tile.waves), lds, stream, mx, rkeys, tkeys, pids, tidx,
-                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, maxN);
+                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, maxN, setup);
     else
         hipLaunchKernelGGL(k_s12<false>, dim3(g), dim3(64 * tile.waves), lds, stream, mx, rkeys, tkeys, pids, tidx,
-                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, maxN);
+                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, maxN, setup);
     return hipGetLastError();
 }
 

@@ -64,6 +64,23 @@ struct S11Out {
     double *ub, *lo;   // S11 at the centre and its lower bound, per translation cube
 };
 
+// Per-cube set-up of the GMM-vMF pair kernel: both cells decoded, the rotation
+// matrix at the rotation cell's centre and the left Jacobian applied to four
+// corners of its half-width box.  Uniform across the cube's block, so a small
+// kernel computes it once per cube ahead of the pair kernel (one thread per
+// cube) instead of every lane of the block; callers of launch_s12 provide
+// scratch for one per cube.
+struct alignas(16) CubeSetup {
+    double R[9];
+    double t0[3], tau[3];
+    float jc[4][3];
+    float hn, cap;       // |h_r| and min(|h_r|, pi)
+    uint32_t flags;      // GOSMA_FLAG_DROP_ROT, kSetupPerDir, kSetupInvalid
+    uint32_t pad;
+};
+constexpr uint32_t kSetupPerDir = 0x100u;    // the per-direction Lemma 2 bound applies
+constexpr uint32_t kSetupInvalid = 0x200u;   // problem index out of range
+
 // Launch shape of a bound kernel: waves per block (one cell per block; up to
 // kMaxWaves) and the number of blocks of the grid-stride loop over cells.
 constexpr int kMaxWaves = 4;
@@ -80,7 +97,7 @@ hipError_t launch_s11(const DevMix &mx, const uint64_t *tkeys, const uint32_t *p
 hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                       const int64_t *tidx, const double *s11ub, const double *s11lo, int64_t n, const uint32_t *n_dev,
                       int n_dev_mul, BoundOut out, double margin_gamma, int maxM, int maxN, bool with_top8, Tile tile,
-                      hipStream_t stream);
+                      CubeSetup *setup, hipStream_t stream);
 // Dynamic LDS of the two kernels (the pair kernel's grows with the waves per
 // block), and the per-kernel limit setup for it.
 size_t s11_lds_bytes(int maxM, int waves);
@@ -116,6 +133,7 @@ struct gosma_ctx {
     // scratch for gosma_eval_bounds (grown on demand)
     int64_t s11_cap = 0;
     double *d_s11ub = nullptr, *d_s11lo = nullptr;
+    gosma::CubeSetup *d_setup = nullptr;
     unsigned long long *d_pairs = nullptr;   // pair counts of timed gosma_eval_bounds calls
 
     gosma::Solver *solver = nullptr;

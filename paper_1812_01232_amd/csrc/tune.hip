@@ -118,10 +118,11 @@ int gosma_autotune(gosma_ctx *ctx, int64_t n_cubes, uint64_t seed, double *rows,
         tk[c] = random_key(s, 1, 8, idx, &L);
         pid[c] = p;
     }
-    DevBuf d_rk, d_tk, d_pid, d_s11u, d_s11l, d_ub, d_lb, d_fl;
+    DevBuf d_rk, d_tk, d_pid, d_s11u, d_s11l, d_ub, d_lb, d_fl, d_setup;
     if ((e = hipMalloc(&d_rk.p, 8 * n)) || (e = hipMalloc(&d_tk.p, 8 * n)) || (e = hipMalloc(&d_pid.p, 4 * n)) ||
         (e = hipMalloc(&d_s11u.p, 8 * n)) || (e = hipMalloc(&d_s11l.p, 8 * n)) || (e = hipMalloc(&d_ub.p, 8 * n)) ||
-        (e = hipMalloc(&d_lb.p, 8 * n)) || (e = hipMalloc(&d_fl.p, n)))
+        (e = hipMalloc(&d_lb.p, 8 * n)) || (e = hipMalloc(&d_fl.p, n)) ||
+        (e = hipMalloc(&d_setup.p, sizeof(CubeSetup) * n)))
         return fail(ctx, GOSMA_E_NOMEM, "autotune buffers", e);
     if ((e = hipMemcpy(d_rk.p, rk.data(), 8 * n, hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(d_tk.p, tk.data(), 8 * n, hipMemcpyHostToDevice)) ||
@@ -136,7 +137,8 @@ int gosma_autotune(gosma_ctx *ctx, int64_t n_cubes, uint64_t seed, double *rows,
             return launch_s11(mx, (const uint64_t *)d_tk.p, (const uint32_t *)d_pid.p, n, nullptr, s11, ctx->maxM, t,
                               nullptr);
         return launch_s12(mx, (const uint64_t *)d_rk.p, (const uint64_t *)d_tk.p, (const uint32_t *)d_pid.p, nullptr,
-                          s11.ub, s11.lo, n, nullptr, 1, bo, 0.0, ctx->maxM, ctx->maxN, false, t, nullptr);
+                          s11.ub, s11.lo, n, nullptr, 1, bo, 0.0, ctx->maxM, ctx->maxN, false, t,
+                          (CubeSetup *)d_setup.p, nullptr);
     };
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if ((e = hipEventCreate(&ev0)) || (e = hipEventCreate(&ev1))) {
