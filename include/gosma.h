@@ -80,9 +80,11 @@ const char *gosma_last_error(const gosma_ctx *ctx);
  * both to use one class.  With labels only same-class pairs contribute and
  * the objective is sum_l f_l / n_labels, the weights being renormalised
  * within each class; without labels the weights are renormalised to sum 1.
- * All arrays are host FP64/int32 and are copied.  1 <= M, N <= 1024, and
- * 64 M + 32 N + 1024 bytes must fit in one block's LDS (GOSMA_E_INVAL
- * otherwise; 160 KB on gfx950). */
+ * All arrays are host FP64/int32 and are copied.  1 <= M, N <= 1024
+ * (GOSMA_E_INVAL otherwise); a bound-kernel block stages 96 bytes per GMM
+ * component in LDS plus 1,280 bytes per wave, which fits gfx950's 160 KB at
+ * M = 1024, and a device with less LDS per block rejects larger M with
+ * GOSMA_E_INVAL. */
 int gosma_set_mixtures(gosma_ctx *ctx, int M, const double *mu, const double *sigma, const double *phi1,
                        const int32_t *label1, int N, const double *dir2, const double *kappa2,
                        const double *phi2, const int32_t *label2, int n_labels);

@@ -199,7 +199,7 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
             needN = std::max(needN, (int)(vmf_off[p + 1] - vmf_off[p]));
         }
         HIP_TRY(ctx, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
-        const size_t need = std::max(gosma::s11_lds_bytes(needM, gosma::kMaxWaves), gosma::s12_lds_bytes(needM, needN, gosma::kMaxWaves)) + 1024;
+        const size_t need = std::max(gosma::s11_lds_bytes(needM, gosma::kMaxWaves), gosma::s12_lds_bytes(needM, gosma::kMaxWaves)) + 1024;
         if (need > (size_t)lds_max)
             return fail(ctx, GOSMA_E_INVAL, "M = %d, N = %d need %zu bytes of LDS per block; the device has %d", needM,
                         needN, need, lds_max);
@@ -284,9 +284,8 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
             double G = k / (-std::expm1(-2.0 * k));
             double coth = 1.0 + 2.0 / std::expm1(2.0 * k);
             h_vmf[2 * dst] = make_float4((float)dx[3 * j], (float)dx[3 * j + 1], (float)dx[3 * j + 2], (float)k);
-            // the pair screen's column term ln(weight G(kappa)) (the kernel subtracts ln(2 kappa) / 2)
-            const double ell = w2[j] > 0 ? std::log(w2[j] * G) : -1e30;
-            h_vmf[2 * dst + 1] = make_float4((float)w2[j], (float)G, (float)coth, (float)std::max(ell, -1e30));
+            // ln(2 kappa) / 2 enters the far-apart cap of the upper term
+            h_vmf[2 * dst + 1] = make_float4((float)w2[j], (float)G, (float)coth, (float)(0.5 * std::log(2.0 * k)));
         }
 
         // S22 (FP64, host): sum over same-class vMF pairs of w w' Z(K)/(Z Z)

@@ -354,10 +354,11 @@ constexpr int kBatch = 4, kList = 64 * kBatch + 64;
 // the runs are accumulated in FP64.
 constexpr int kRun = 8;
 
-// LDS record strides in float4: a GMM record holds five float4 (a stride of
+// LDS record stride in float4: a GMM record holds five float4 (a stride of
 // 20 dwords, so 16-byte reads of consecutive records by consecutive lanes hit
-// distinct banks) and a vMF record two.
-constexpr int kG = 5, kV = 2;
+// distinct banks).  The vMF rows are read from the global table (two float4
+// per component, a few KB per problem, resident in L1/L2).
+constexpr int kG = 5;
 
 // ---------------------------------------------------------------------------
 // S11 over translation cells
@@ -682,7 +683,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
 // evaluated kBatch per lane at a time.
 
 template <bool TOP8>
-__device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, int a_, const float4 &v0, const float4 &v1,
+__device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, int a_, const float4 v0, const float4 v1,
                                          float &sub, float &shi, float (&top)[8])
 {
     const float4 R0 = rec[kG * a_], R1 = rec[kG * a_ + 1], R2 = rec[kG * a_ + 2], R3 = rec[kG * a_ + 3],
@@ -802,14 +803,13 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                                                          const double *__restrict__ s11ub,
                                                          const double *__restrict__ s11lo, int64_t n_host,
                                                          const uint32_t *__restrict__ n_dev, int n_dev_mul,
-                                                         BoundOut out, double gamma, int maxM, int maxN,
+                                                         BoundOut out, double gamma, int maxM,
                                                          const CubeSetup *__restrict__ setup)
 {
     extern __shared__ float4 lds4[];
     __shared__ BlockShared sh;
     float4 *rec = lds4;               // kG per GMM component
-    float4 *vrec = lds4 + kG * maxM;  // kV per vMF component
-    float4 *scr = vrec + kV * maxN;   // screen row per GMM component
+    float4 *scr = lds4 + kG * maxM;   // screen row per GMM component
     // per wave: pairs that passed the screen
     uint32_t *plist = reinterpret_cast<uint32_t *>(scr + maxM);
     const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, wv = tid >> 6, lane = tid & 63;
@@ -899,12 +899,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             rec[kG * i + 2] = make_float4((float)tp.klo, (float)ahi, (float)tp.ha, (float)fl.coth);
             rec[kG * i + 3] = make_float4((float)fl.G, (float)fh.G, (float)fl.nu, (float)fh.nu);
         }
-        for (int j = tid; j < P.N; j += T) {
-            const float4 v0 = mx.vmf[2 * (P.vmf_off + j)], v1 = mx.vmf[2 * (P.vmf_off + j) + 1];
-            const float hlb = 0.5f * kLn2 * __builtin_amdgcn_logf(2.0f * v0.w);   // ln(2 kappa) / 2
-            vrec[kV * j] = v0;
-            vrec[kV * j + 1] = make_float4(v1.x, v1.y, v1.z, hlb);
-        }
+        // the problem's vMF rows {mu, kappa}, {weight, G(kappa), coth kappa, ln(2 kappa) / 2}
+        const float4 *__restrict__ vt = mx.vmf + 2 * (int64_t)P.vmf_off;
         drop = wave_or(drop);
         ubinf = wave_or(ubinf);
         psum = wave_sumf(psum);
@@ -966,7 +962,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                 for (int k = 0; k < kBatch; ++k) {
                     if (e[k] != 0xffffffffu) {
                         const int jj = (int)(e[k] & 0xffffu);
-                        s12_pair<TOP8>(rec, (int)(e[k] >> 16), vrec[kV * jj], vrec[kV * jj + 1], sub, shi, top);
+                        s12_pair<TOP8>(rec, (int)(e[k] >> 16), vt[2 * jj], vt[2 * jj + 1], sub, shi, top);
                     }
                 }
                 run += kBatch;
@@ -1018,8 +1014,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                     const int jl = tid % cols, i0 = tid / cols;
                     for (int jb = 0; jb < nj; jb += cols) {
                         const int j = vb + jb + jl;
-                        const float4 v0 = vrec[kV * j];
-                        const float lw = mx.vmf[2 * (P.vmf_off + j) + 1].w - vrec[kV * j + 1].w;
+                        const float4 v0 = vt[2 * j], v1 = vt[2 * j + 1];
+                        const float lw = __builtin_amdgcn_logf(v1.x * v1.y) * kLn2 - v1.w;
                         const float c = frcp(v0.w), l = fmaxf(lw, -100.0f) - lthr;
                         const float4 vm = make_float4(v0.x, v0.y, v0.z, l * c);
                         const float2 vc = make_float2(c, l);
@@ -1046,8 +1042,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                     for (int st = 0; st < steps; ++st) {
                         const bool valid = i < ni;
                         const int jj = vb + j;
-                        const float4 v0 = vrec[kV * jj];
-                        const float lw = mx.vmf[2 * (P.vmf_off + jj) + 1].w - vrec[kV * jj + 1].w;
+                        const float4 v0 = vt[2 * jj], v1 = vt[2 * jj + 1];
+                        const float lw = __builtin_amdgcn_logf(v1.x * v1.y) * kLn2 - v1.w;
                         const float c = frcp(v0.w), l = fmaxf(lw, -100.0f) - lthr;
                         offer(gb + min(i, ni - 1), jj, make_float4(v0.x, v0.y, v0.z, l * c), make_float2(c, l), valid);
                         j += dj;
@@ -1159,9 +1155,9 @@ size_t s11_lds_bytes(int maxM, int waves)
 {
     return sizeof(float4) * kG * (size_t)maxM + sizeof(uint32_t) * kList * (size_t)waves;
 }
-size_t s12_lds_bytes(int maxM, int maxN, int waves)
+size_t s12_lds_bytes(int maxM, int waves)
 {
-    return sizeof(float4) * ((kG + 1) * (size_t)maxM + kV * (size_t)maxN) + sizeof(uint32_t) * kList * (size_t)waves;
+    return sizeof(float4) * (kG + 1) * (size_t)maxM + sizeof(uint32_t) * kList * (size_t)waves;
 }
 
 hipError_t prepare_bound_kernels(int maxM, int maxN)
@@ -1171,10 +1167,10 @@ hipError_t prepare_bound_kernels(int maxM, int maxN)
                                        (int)s11_lds_bytes(maxM, kMaxWaves));
     if (!e)
         e = hipFuncSetAttribute((const void *)k_s12<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)s12_lds_bytes(maxM, maxN, kMaxWaves));
+                                (int)s12_lds_bytes(maxM, kMaxWaves));
     if (!e)
         e = hipFuncSetAttribute((const void *)k_s12<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)s12_lds_bytes(maxM, maxN, kMaxWaves));
+                                (int)s12_lds_bytes(maxM, kMaxWaves));
     return e;
 }
 
@@ -1203,14 +1199,14 @@ hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *t
         hipLaunchKernelGGL(k_cube_setup, dim3(gs), dim3(256), 0, stream, mx, rkeys, tkeys, pids, n, n_dev, n_dev_mul,
                            setup);
     }
-    const size_t lds = s12_lds_bytes(maxM, maxN, tile.waves);
+    const size_t lds = s12_lds_bytes(maxM, tile.waves);
     const unsigned g = (unsigned)std::min<int64_t>(tile.blocks, n);
     if (with_top8)
         hipLaunchKernelGGL(k_s12<true>, dim3(g), dim3(64 * tile.waves), lds, stream, mx, rkeys, tkeys, pids, tidx,
-                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, maxN, setup);
+                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, setup);
     else
         hipLaunchKernelGGL(k_s12<false>, dim3(g), dim3(64 * tile.waves), lds, stream, mx, rkeys, tkeys, pids, tidx,
-                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, maxN, setup);
+                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, setup);
     return hipGetLastError();
 }
 
