@@ -183,6 +183,32 @@ int gosma_get_trace(gosma_ctx *ctx, double *buf, int64_t cap, int64_t *n);
  * GOSMA_E_QUEUE_OVERFLOW with every result filled. */
 int gosma_solve_batch(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *results);
 
+/* Checkpoint of the search (Algorithm 1's state between two iterations: the
+ * queued sub-cubes with their lower bounds, d* and its pose, the counters).
+ * gosma_snapshot writes the state left by the last gosma_solve or
+ * gosma_solve_batch of the current problems into the caller's host buffer:
+ * with buf NULL, *bytes receives the size needed; otherwise *bytes holds the
+ * buffer's capacity on entry and the size written on return (25 bytes per
+ * queued cube plus a few hundred per problem).  Errors: GOSMA_E_STATE if no
+ * search of the current problems has finished (or the problems or domain
+ * changed since), or if a problem overflowed its queue (its queue is then
+ * incomplete); GOSMA_E_INVAL if the buffer is too small (*bytes receives the
+ * size needed).  Synchronous.
+ *
+ * gosma_resume checks a snapshot against the current problems (sizes, S22
+ * and domain must match: GOSMA_E_INVAL otherwise, also for a malformed or
+ * truncated buffer) and copies it; the next gosma_solve / gosma_solve_batch
+ * then starts from that state instead of the root cubes, under its own
+ * options: a new eps (a search certified at eps can be resumed to a smaller
+ * one), queue capacity (GOSMA_E_INVAL if a problem's snapshot holds more than
+ * max_queue cubes), order and caps (max_iters counts the iterations of that
+ * call).  The resumed search runs at least one iteration; its result counts
+ * iterations and cubes from the original root.  Queue priorities restart
+ * from the lower bounds.  Record logging cannot start from a snapshot
+ * (GOSMA_E_STATE).  buf NULL with bytes 0 discards a pending snapshot. */
+int gosma_snapshot(gosma_ctx *ctx, void *buf, size_t *bytes);
+int gosma_resume(gosma_ctx *ctx, const void *buf, size_t bytes);
+
 /* ------------------------------------------------------------------ */
 /* Learned queue order (not part of the paper's method).               */
 /* ------------------------------------------------------------------ */

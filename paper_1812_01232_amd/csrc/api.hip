@@ -65,6 +65,8 @@ void free_problems(gosma_ctx *ctx)
     ctx->h_prob.clear();
     ctx->gmm_order.clear();
     ctx->has_domain = false;
+    ctx->snap_ready = false;
+    ctx->resume.clear();
 }
 
 double log_Z(double x) { return x <= 0 ? std::log(2.0) : x + std::log(-std::expm1(-2.0 * x)) - std::log(x); }
@@ -361,6 +363,7 @@ int gosma_set_domain(gosma_ctx *ctx, const gosma_domain *domain)
     int rc = check_domain(ctx, domain);
     if (rc) return rc;
     set_domain_desc(ctx->h_prob[0], *domain);
+    ctx->snap_ready = false;   // the solver's queue belongs to the old domain
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipMemcpy(ctx->d_prob, ctx->h_prob.data(), sizeof(ProbDesc), hipMemcpyHostToDevice));
     ctx->has_domain = true;

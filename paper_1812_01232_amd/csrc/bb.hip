@@ -1060,6 +1060,75 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     return hipGetLastError();
 }
 
+// Search-state snapshot (gosma_snapshot / gosma_resume), host bytes: a
+// SnapHead, one SnapProb per problem, then per problem its n queued cubes as
+// n rkeys (u64), n tkeys (u64), n margined lower bounds (f64) and n flag
+// bytes, padded to a multiple of 8 bytes.  The problem's sizes, S22 and
+// domain are stored to reject a snapshot of another problem.
+struct SnapHead {
+    char magic[8];
+    uint32_t version, n_problems;
+    uint64_t bytes;
+};
+struct SnapProb {
+    int32_t M, N;
+    double S22, zeta, r_lo[3], r_w[3], t_lo[3], t_w[3];
+    double dstar, floor_lb;
+    uint64_t best_rkey, best_tkey, bounded, n;
+    uint32_t iters, pad;
+};
+constexpr char kSnapMagic[8] = {'G', 'O', 'S', 'M', 'A', 'Q', 'S', '1'};
+constexpr uint32_t kSnapVersion = 1;
+
+size_t snap_cube_bytes(uint64_t n) { return 24 * (size_t)n + (size_t)((n + 7) & ~7ull); }
+
+void snap_fingerprint(const gosma::ProbDesc &D, SnapProb &q)
+{
+    q.M = D.M;
+    q.N = D.N;
+    q.S22 = D.S22;
+    q.zeta = D.zeta;
+    for (int a = 0; a < 3; ++a) {
+        q.r_lo[a] = D.r_lo[a];
+        q.r_w[a] = D.r_w[a];
+        q.t_lo[a] = D.t_lo[a];
+        q.t_w[a] = D.t_w[a];
+    }
+}
+
+// Check a snapshot against the context's problems; fills the per-problem
+// records and the offset of each problem's cube arrays.
+int snap_parse(gosma_ctx *ctx, const uint8_t *buf, size_t bytes, std::vector<SnapProb> &pr, std::vector<size_t> &off)
+{
+    auto bad = [&](const char *what) {
+        ctx->err = std::string("snapshot: ") + what;
+        return GOSMA_E_INVAL;
+    };
+    SnapHead h;
+    if (bytes < sizeof h) return bad("shorter than its header");
+    std::memcpy(&h, buf, sizeof h);
+    if (std::memcmp(h.magic, kSnapMagic, 8) != 0 || h.version != kSnapVersion) return bad("not a snapshot of this format");
+    if (h.bytes != bytes) return bad("size differs from the size it records");
+    if ((int)h.n_problems != ctx->n_problems) return bad("problem count differs from the current problems");
+    size_t at = sizeof h + sizeof(SnapProb) * (size_t)h.n_problems;
+    if (at > bytes) return bad("truncated");
+    pr.resize(h.n_problems);
+    off.resize(h.n_problems);
+    for (uint32_t p = 0; p < h.n_problems; ++p) {
+        std::memcpy(&pr[p], buf + sizeof h + sizeof(SnapProb) * p, sizeof(SnapProb));
+        SnapProb want{};
+        snap_fingerprint(ctx->h_prob[p], want);
+        const SnapProb &q = pr[p];
+        if (q.M != want.M || q.N != want.N || std::memcmp(&q.S22, &want.S22, sizeof(double) * 14) != 0)
+            return bad("recorded for different mixtures or a different domain");
+        if (q.n > ((uint64_t)1 << 34) || snap_cube_bytes(q.n) > bytes - at) return bad("truncated");
+        off[p] = at;
+        at += snap_cube_bytes(q.n);
+    }
+    if (at != bytes) return bad("size does not match its contents");
+    return GOSMA_OK;
+}
+
 int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, int P)
 {
     using namespace gosma;
@@ -1077,8 +1146,21 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
     if (opts->order != 0 && opts->order != 1) return fail(GOSMA_E_INVAL, "order must be 0 (best-first) or 1 (learned)");
     if (learned && !ctx->mlp_ready()) return fail(GOSMA_E_STATE, "learned order needs a network (gosma_mlp_init/set_params)");
     if (logging && !ctx->rec_sink) return fail(GOSMA_E_STATE, "record logging needs gosma_set_record_sink");
+    // a pending gosma_resume: the problems may have changed since, so check again
+    const bool resuming = !ctx->resume.empty();
+    std::vector<SnapProb> sp;
+    std::vector<size_t> soff;
+    if (resuming) {
+        if (logging) return fail(GOSMA_E_STATE, "record logging cannot start from a snapshot (its cubes carry no records)");
+        const int rc = snap_parse(ctx, ctx->resume.data(), ctx->resume.size(), sp, soff);
+        if (rc) return rc;
+        for (int p = 0; p < P; ++p)
+            if (sp[p].n > (uint64_t)opts->max_queue)
+                return fail(GOSMA_E_INVAL, "the snapshot holds more cubes of a problem than max_queue");
+    }
     hipError_t e = hipSetDevice(ctx->device);
     if (e) return fail(GOSMA_E_HIP, "hipSetDevice", e);
+    ctx->snap_ready = false;   // the solver's buffers are about to change
     ctx->trace.clear();
     for (int p = 0; p < P; ++p) std::memset(res + p, 0, sizeof *res);
     if (!ctx->solver) ctx->solver = new Solver;
@@ -1115,16 +1197,60 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         s.theta = 0xffffffffu;
         s.max_iters = (uint32_t)std::min<int64_t>(opts->max_iters, 0xffffffffll);
     }
-    std::vector<uint64_t> zeros(P, 0);
-    std::vector<uint32_t> pids(P);
-    for (int p = 0; p < P; ++p) pids[p] = (uint32_t)p;
-    if ((e = hipMemcpyAsync(b.st, init.data(), sizeof(PState) * P, hipMemcpyHostToDevice, st)) ||
-        (e = hipMemcpyAsync(b.crk, zeros.data(), 8 * P, hipMemcpyHostToDevice, st)) ||
-        (e = hipMemcpyAsync(b.ctk, zeros.data(), 8 * P, hipMemcpyHostToDevice, st)) ||
-        (e = hipMemcpyAsync(b.cpid, pids.data(), 4 * P, hipMemcpyHostToDevice, st)) ||
-        (e = hipStreamSynchronize(st)))
-        return fail(GOSMA_E_HIP, "solver initialisation", e);
-    {
+    if (resuming) {
+        // the snapshot's cubes go to the cold part; the first iteration
+        // re-partitions them (hot part: the lowest keys) before it selects
+        for (int p = 0; p < P; ++p) {
+            PState &s = init[p];
+            const SnapProb &q = sp[p];
+            const uint8_t *base = ctx->resume.data() + soff[p];
+            const size_t n = (size_t)q.n;
+            std::vector<double> lbv(n);
+            std::vector<float> prio(n);
+            std::memcpy(lbv.data(), base + 16 * n, 8 * n);
+            double mn = INFINITY;
+            for (size_t i = 0; i < n; ++i) {
+                prio[i] = (float)lbv[i];
+                mn = std::min(mn, lbv[i]);
+            }
+            s.dstar = ordh(q.dstar);
+            s.floor_lb = ordh(q.floor_lb);
+            s.minC = ordh(mn);
+            s.best_rkey = q.best_rkey;
+            s.best_tkey = q.best_tkey;
+            s.bounded = q.bounded;
+            s.iters = q.iters;
+            if (opts->max_iters > 0)
+                s.max_iters = (uint32_t)std::min<int64_t>((int64_t)q.iters + opts->max_iters, 0xffffffffll);
+            s.nC[0] = (uint32_t)n;
+            s.rebuild = n > 0;
+            s.rb_target = (uint32_t)std::min<size_t>(std::max<size_t>(n / 16, 16 * k), hcap / 2);
+            s.done = n > 0 ? RUNNING : EXHAUSTED;
+            const Queue C = b.C[0];
+            const size_t at = (size_t)p * ccap;
+            if ((e = hipMemcpyAsync(C.rkey + at, base, 8 * n, hipMemcpyHostToDevice, st)) ||
+                (e = hipMemcpyAsync(C.tkey + at, base + 8 * n, 8 * n, hipMemcpyHostToDevice, st)) ||
+                (e = hipMemcpyAsync(C.lb + at, base + 16 * n, 8 * n, hipMemcpyHostToDevice, st)) ||
+                (e = hipMemcpyAsync(C.flags + at, base + 24 * n, n, hipMemcpyHostToDevice, st)) ||
+                (e = hipMemcpyAsync(C.prio + at, prio.data(), 4 * n, hipMemcpyHostToDevice, st)) ||
+                (e = hipStreamSynchronize(st)))
+                return fail(GOSMA_E_HIP, "restoring the snapshot", e);
+        }
+        if ((e = hipMemcpyAsync(b.st, init.data(), sizeof(PState) * P, hipMemcpyHostToDevice, st)) ||
+            (e = hipStreamSynchronize(st)))
+            return fail(GOSMA_E_HIP, "solver initialisation", e);
+        ctx->resume.clear();   // one solve starts from it
+    }
+    if (!resuming) {
+        std::vector<uint64_t> zeros(P, 0);
+        std::vector<uint32_t> pids(P);
+        for (int p = 0; p < P; ++p) pids[p] = (uint32_t)p;
+        if ((e = hipMemcpyAsync(b.st, init.data(), sizeof(PState) * P, hipMemcpyHostToDevice, st)) ||
+            (e = hipMemcpyAsync(b.crk, zeros.data(), 8 * P, hipMemcpyHostToDevice, st)) ||
+            (e = hipMemcpyAsync(b.ctk, zeros.data(), 8 * P, hipMemcpyHostToDevice, st)) ||
+            (e = hipMemcpyAsync(b.cpid, pids.data(), 4 * P, hipMemcpyHostToDevice, st)) ||
+            (e = hipStreamSynchronize(st)))
+            return fail(GOSMA_E_HIP, "solver initialisation", e);
         const DevMix mx = ctx->mix();
         BoundOut bo{b.cub, b.clb, b.clbs, nullptr, b.cflags, b.ctop8, nullptr, &b.st->dstar,
                     (int)(sizeof(PState) / sizeof(unsigned long long))};
@@ -1222,6 +1348,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         if (h.done == OVERFLOW && rc == GOSMA_OK)
             rc = fail(GOSMA_E_QUEUE_OVERFLOW, "branch-and-bound queue capacity exceeded");
     }
+    ctx->snap_ready = rc == GOSMA_OK || rc == GOSMA_E_QUEUE_OVERFLOW;
     return rc;
 }
 
@@ -1237,6 +1364,7 @@ void gosma_drop_graph(gosma_ctx *ctx)
 void gosma_release_solver(gosma_ctx *ctx)
 {
     if (!ctx || !ctx->solver) return;
+    ctx->snap_ready = false;
     free_solver(ctx->solver);
     delete ctx->solver;
     ctx->solver = nullptr;
@@ -1258,6 +1386,119 @@ int gosma_solve_batch(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res)
     if (!ctx) return GOSMA_E_INVAL;
     ctx->err.clear();
     return solve_problems(ctx, opts, res, ctx->n_problems);
+}
+
+int gosma_snapshot(gosma_ctx *ctx, void *buf, size_t *bytes)
+{
+    using namespace gosma;
+    if (!ctx || !bytes) return GOSMA_E_INVAL;
+    ctx->err.clear();
+    Solver *S = ctx->solver;
+    if (!ctx->snap_ready || !S || S->P != ctx->n_problems) {
+        ctx->err = "no finished search of the current problems to snapshot";
+        return GOSMA_E_STATE;
+    }
+    const int P = S->P;
+    hipError_t e = hipSetDevice(ctx->device);
+    std::vector<PState> st(P);
+    if (!e) e = hipMemcpyAsync(st.data(), S->b.st, sizeof(PState) * P, hipMemcpyDeviceToHost, S->stream);
+    if (!e) e = hipStreamSynchronize(S->stream);
+    if (e) {
+        ctx->err = std::string("snapshot: ") + hipGetErrorString(e);
+        return GOSMA_E_HIP;
+    }
+    size_t total = sizeof(SnapHead) + sizeof(SnapProb) * (size_t)P;
+    std::vector<SnapProb> pr(P);
+    for (int p = 0; p < P; ++p) {
+        const PState &h = st[p];
+        if (h.done == OVERFLOW) {
+            ctx->err = "snapshot: a problem overflowed its queue, so its queued cubes are incomplete";
+            return GOSMA_E_STATE;
+        }
+        if (h.nH[h.hcur] > S->hcap || h.nC[h.ccur] > S->ccap) {
+            ctx->err = "snapshot: queue counts exceed the queue's capacity";
+            return GOSMA_E_STATE;
+        }
+        SnapProb &q = pr[p];
+        std::memset(&q, 0, sizeof q);
+        snap_fingerprint(ctx->h_prob[p], q);
+        q.dstar = unord64(h.dstar);
+        q.floor_lb = unord64(h.floor_lb);
+        q.best_rkey = h.best_rkey;
+        q.best_tkey = h.best_tkey;
+        q.bounded = h.bounded;
+        q.iters = h.iters;
+        q.n = (uint64_t)h.nH[h.hcur] + h.nC[h.ccur];
+        total += snap_cube_bytes(q.n);
+    }
+    if (!buf) {
+        *bytes = total;
+        return GOSMA_OK;
+    }
+    if (*bytes < total) {
+        ctx->err = "snapshot: buffer of " + std::to_string(*bytes) + " bytes, " + std::to_string(total) + " needed";
+        *bytes = total;
+        return GOSMA_E_INVAL;
+    }
+    uint8_t *out = static_cast<uint8_t *>(buf);
+    SnapHead hd;
+    std::memcpy(hd.magic, kSnapMagic, 8);
+    hd.version = kSnapVersion;
+    hd.n_problems = (uint32_t)P;
+    hd.bytes = total;
+    std::memcpy(out, &hd, sizeof hd);
+    std::memcpy(out + sizeof hd, pr.data(), sizeof(SnapProb) * (size_t)P);
+    size_t at = sizeof hd + sizeof(SnapProb) * (size_t)P;
+    for (int p = 0; p < P && !e; ++p) {
+        const PState &h = st[p];
+        const size_t n = (size_t)pr[p].n, nh = h.nH[h.hcur], nc = h.nC[h.ccur];
+        uint8_t *rk = out + at, *tk = rk + 8 * n, *lb = tk + 8 * n, *fl = lb + 8 * n;
+        // the hot part's cubes, then the cold part's
+        auto copy_part = [&](const Queue &q, size_t o, size_t cnt, size_t dst) {
+            if (!cnt || e) return;
+            if ((e = hipMemcpyAsync(rk + 8 * dst, q.rkey + o, 8 * cnt, hipMemcpyDeviceToHost, S->stream)) ||
+                (e = hipMemcpyAsync(tk + 8 * dst, q.tkey + o, 8 * cnt, hipMemcpyDeviceToHost, S->stream)) ||
+                (e = hipMemcpyAsync(lb + 8 * dst, q.lb + o, 8 * cnt, hipMemcpyDeviceToHost, S->stream)))
+                return;
+            e = hipMemcpyAsync(fl + dst, q.flags + o, cnt, hipMemcpyDeviceToHost, S->stream);
+        };
+        copy_part(S->b.H[h.hcur], (size_t)p * S->hcap, nh, 0);
+        copy_part(S->b.C[h.ccur], (size_t)p * S->ccap, nc, nh);
+        std::memset(fl + n, 0, snap_cube_bytes(n) - 25 * n);   // padding
+        at += snap_cube_bytes(n);
+    }
+    if (!e) e = hipStreamSynchronize(S->stream);
+    if (e) {
+        ctx->err = std::string("snapshot: ") + hipGetErrorString(e);
+        return GOSMA_E_HIP;
+    }
+    *bytes = total;
+    return GOSMA_OK;
+}
+
+int gosma_resume(gosma_ctx *ctx, const void *buf, size_t bytes)
+{
+    if (!ctx) return GOSMA_E_INVAL;
+    ctx->err.clear();
+    if (!buf) {
+        if (bytes) {
+            ctx->err = "resume: NULL buffer with a non-zero size";
+            return GOSMA_E_INVAL;
+        }
+        ctx->resume.clear();
+        return GOSMA_OK;
+    }
+    if (ctx->n_problems < 1 || !ctx->has_domain) {
+        ctx->err = "resume: no problem set";
+        return GOSMA_E_STATE;
+    }
+    std::vector<SnapProb> pr;
+    std::vector<size_t> off;
+    const uint8_t *b = static_cast<const uint8_t *>(buf);
+    const int rc = snap_parse(ctx, b, bytes, pr, off);
+    if (rc) return rc;
+    ctx->resume.assign(b, b + bytes);
+    return GOSMA_OK;
 }
 
 int gosma_get_trace(gosma_ctx *ctx, double *buf, int64_t cap, int64_t *n)

@@ -33,7 +33,7 @@ struct ClassRange {
 //   GMM rows: mu (FP64 xyz), 1/sigma^2 (FP64), weight (FP32, see below), and
 //   the plain normalised weight used by the branching rule.
 //   vMF rows: two float4 per row, {dx, dy, dz, kappa}, {weight, G(kappa),
-//   coth(kappa), 0}, with G(y) = y / (1 - e^{-2y}).
+//   coth(kappa), ln(2 kappa) / 2}, with G(y) = y / (1 - e^{-2y}).
 // Weights carry the semantic class weight: with phi_l = 1/|Lambda| and w the
 // weights renormalised within the class, the stored weight is sqrt(phi_l) w,
 // so the product of two stored weights is phi_l w w' (eq. 17).
@@ -137,6 +137,8 @@ struct gosma_ctx {
     unsigned long long *d_pairs = nullptr;   // pair counts of timed gosma_eval_bounds calls
 
     gosma::Solver *solver = nullptr;
+    bool snap_ready = false;      // the solver holds the finished search of the current problems
+    std::vector<uint8_t> resume;  // gosma_resume: the search state the next solve starts from
     gosma::Mlp *mlp = nullptr;
     float *rec_sink = nullptr;               // gosma_set_record_sink
     int64_t rec_cap = 0;

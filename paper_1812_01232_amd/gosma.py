@@ -25,7 +25,8 @@ EXPORTS = ["gosma_create", "gosma_destroy", "gosma_last_error", "gosma_set_mixtu
            "gosma_set_problems", "gosma_get_S22", "gosma_eval_bounds", "gosma_solve", "gosma_solve_batch",
            "gosma_set_timing", "gosma_get_timing", "gosma_get_trace", "gosma_mlp_init", "gosma_mlp_set_params",
            "gosma_mlp_get_params", "gosma_mlp_predict", "gosma_mlp_loss_grad", "gosma_mlp_train",
-           "gosma_set_record_sink", "gosma_get_tiles", "gosma_set_tiles", "gosma_autotune", "gosma_get_pair_counts"]
+           "gosma_set_record_sink", "gosma_get_tiles", "gosma_set_tiles", "gosma_autotune", "gosma_get_pair_counts",
+           "gosma_snapshot", "gosma_resume"]
 MLP_FEATURES, MLP_RECORD, MLP_PARAMS = 20, 21, 35841
 KERNEL_KINDS = ["s11", "s12", "select", "branch", "push", "mlp"]
 
@@ -99,6 +100,8 @@ def lib():
         L.gosma_set_record_sink.argtypes = [vp, vp, C.c_int64, vp]
         L.gosma_get_timing.argtypes = [vp, dp, C.POINTER(C.c_int64)]
         L.gosma_get_pair_counts.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.gosma_snapshot.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+        L.gosma_resume.argtypes = [vp, vp, C.c_size_t]
         L.gosma_get_tiles.argtypes = [vp, C.POINTER(Tiles)]
         L.gosma_set_tiles.argtypes = [vp, C.POINTER(Tiles)]
         L.gosma_autotune.argtypes = [vp, C.c_int64, C.c_uint64, dp, C.c_int64, C.POINTER(C.c_int64),
@@ -357,6 +360,23 @@ class Context:
         if not (allow_overflow and rc == QUEUE_OVERFLOW):
             self._check(rc, "gosma_solve_batch")
         return [_result_dict(r) for r in rs]
+
+    # -- checkpoint of the search -------------------------------------------
+    def snapshot(self):
+        """The search state left by the last solve, as bytes."""
+        n = C.c_size_t(0)
+        self._check(lib().gosma_snapshot(self._h, None, C.byref(n)), "gosma_snapshot")
+        buf = (C.c_uint8 * n.value)()
+        self._check(lib().gosma_snapshot(self._h, buf, C.byref(n)), "gosma_snapshot")
+        return bytes(buf[:n.value])
+
+    def resume(self, data):
+        """The next solve starts from this snapshot (None discards a pending one)."""
+        if data is None:
+            self._check(lib().gosma_resume(self._h, None, 0), "gosma_resume")
+            return
+        b = bytes(data)
+        self._check(lib().gosma_resume(self._h, C.c_char_p(b), len(b)), "gosma_resume")
 
 
 def _result_dict(r):

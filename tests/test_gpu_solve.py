@@ -202,3 +202,98 @@ def test_autotune_on_a_batch_then_solve(ctx):
         assert a["status"] == b["status"] == 0
         assert abs(a["f_norm_best"] - b["f_norm_best"]) <= 1e-2
         assert a["lb_norm"] <= b["f_norm_best"] and b["lb_norm"] <= a["f_norm_best"]
+
+
+def test_snapshot_resume_continues_the_search(ctx):
+    """A search stopped by its iteration cap, written out and resumed, reaches
+    the certificate of the uninterrupted search (same queue order: best-first)."""
+    sc = scenes.small_scene(6, 6, seed=88)
+    ctx.set_scene(sc)
+    full = ctx.solve(1e-2, batch_parents=256)
+    part = ctx.solve(1e-2, batch_parents=256, max_iters=5)
+    assert part["status"] == 2 and part["iters"] == 5
+    snap = ctx.snapshot()
+    assert len(snap) >= 25 * part["max_queue_used"]
+    ctx.resume(snap)
+    rest = ctx.solve(1e-2, batch_parents=256)
+    assert rest["status"] == 0 and rest["iters"] > 5
+    assert rest["f_norm_best"] - rest["lb_norm"] <= 1e-2
+    assert abs(rest["cubes"] - full["cubes"]) <= 0.02 * full["cubes"]
+    assert abs(rest["f_norm_best"] - full["f_norm_best"]) <= 1e-2
+    assert rest["lb_norm"] <= full["f_norm_best"] and full["lb_norm"] <= rest["f_norm_best"]
+    o = oracle.OracleProblem(sc).solve(1e-2, 256)
+    assert abs(rest["f_norm_best"] - o["f_norm_best"]) <= 1e-2
+    # the pending snapshot was used once: the next solve starts from the root
+    again = ctx.solve(1e-2, batch_parents=256)
+    assert abs(again["cubes"] - full["cubes"]) <= 0.02 * full["cubes"]
+
+
+def test_resume_to_a_smaller_eps(ctx):
+    """A search certified at eps = 0.1 continues to eps = 0.01 from its queue."""
+    sc = scenes.small_scene(5, 6, seed=90, noise_deg=2.0, n_inliers=4)
+    ctx.set_scene(sc)
+    coarse = ctx.solve(1e-1, batch_parents=256)
+    assert coarse["status"] == 0
+    ctx.resume(ctx.snapshot())
+    fine = ctx.solve(1e-2, batch_parents=256)
+    direct = ctx.solve(1e-2, batch_parents=256)
+    assert fine["status"] == 0 and fine["f_norm_best"] - fine["lb_norm"] <= 1e-2
+    assert fine["cubes"] > coarse["cubes"] and fine["iters"] > coarse["iters"]
+    assert abs(fine["f_norm_best"] - direct["f_norm_best"]) <= 1e-2
+    assert fine["lb_norm"] <= direct["f_norm_best"] and direct["lb_norm"] <= fine["f_norm_best"]
+    assert fine["cubes"] <= 1.25 * direct["cubes"] + 4096
+    o = oracle.OracleProblem(sc).solve(1e-2, 256)
+    assert fine["lb_norm"] - 1e-9 <= o["f_norm_best"] and o["lb_norm"] - 1e-9 <= fine["f_norm_best"]
+
+
+def test_snapshot_resume_batch(ctx):
+    """Snapshot and resume of a batched search, problem by problem."""
+    scs = [scenes.small_scene(4, 4, seed=81), scenes.small_scene(5, 5, seed=86),
+           scenes.small_scene(6, 5, seed=91, noise_deg=1.0, n_inliers=4)]
+    ctx.set_scenes(scs)
+    full = ctx.solve_batch(3, 1e-2, batch_parents=256)
+    ctx.solve_batch(3, 1e-2, batch_parents=256, max_iters=3)
+    ctx.resume(ctx.snapshot())
+    rest = ctx.solve_batch(3, 1e-2, batch_parents=256)
+    for a, b in zip(full, rest):
+        assert b["status"] == a["status"] == 0
+        assert abs(b["cubes"] - a["cubes"]) <= 0.02 * a["cubes"]
+        assert abs(b["f_norm_best"] - a["f_norm_best"]) <= 1e-2
+        assert b["lb_norm"] <= a["f_norm_best"] and a["lb_norm"] <= b["f_norm_best"]
+
+
+def test_snapshot_resume_errors(ctx):
+    from paper_1812_01232_amd import GosmaError
+    sc = scenes.small_scene(6, 6, seed=88)
+    ctx.set_scene(sc)
+    with pytest.raises(GosmaError) as ei:
+        ctx.snapshot()                      # no search of these problems yet
+    assert ei.value.code == -5
+    ctx.solve(1e-2, batch_parents=256, max_iters=4)
+    snap = ctx.snapshot()
+    for bad in (b"", snap[:-8], b"x" * len(snap), snap[:8] + bytes([snap[8] ^ 1]) + snap[9:]):
+        with pytest.raises(GosmaError) as ei:
+            ctx.resume(bad)
+        assert ei.value.code == -1
+    # a queue capacity below the snapshot's cube count
+    ctx.resume(snap)
+    with pytest.raises(GosmaError) as ei:
+        ctx.solve(1e-2, batch_parents=256, max_queue=16)
+    assert ei.value.code == -1
+    # record logging cannot start from a snapshot
+    recs = torch.zeros((1024, 21), dtype=torch.float32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ctx.set_record_sink(recs, cnt)
+    with pytest.raises(GosmaError) as ei:
+        ctx.solve(1e-2, batch_parents=256, log_records=1)
+    assert ei.value.code == -5
+    ctx.set_record_sink(None, None)
+    # discarding the pending snapshot: the solve starts from the root
+    ctx.resume(None)
+    r = ctx.solve(1e-2, batch_parents=256, max_iters=4)
+    assert r["iters"] == 4
+    # another scene's snapshot is rejected; changing the domain drops the state
+    ctx.set_scene(scenes.small_scene(5, 5, seed=86))
+    with pytest.raises(GosmaError) as ei:
+        ctx.resume(snap)
+    assert ei.value.code == -1
