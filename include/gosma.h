@@ -110,7 +110,11 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
 int gosma_get_S22(gosma_ctx *ctx, int problem, double *S22);
 
 /* Theorem 1 bounds (Section 5.2) for n sub-cubes C_r x C_t.
- * Device pointers (all n-element arrays):
+ * All n-element arrays; each may be memory of the context's device (used in
+ * place: the call is asynchronous) or host memory of any kind (copied
+ * through device buffers of the context, which grow to the largest call;
+ * the call then returns after the results are in place).  Device memory of
+ * another device is rejected (GOSMA_E_INVAL).
  *   rkeys, tkeys  in:  octree keys of the rotation and translation cells
  *   problem       in:  uint32 problem index per cube, or NULL (all problem 0);
  *                      an index >= the number of problems gives NaN bounds
@@ -124,7 +128,7 @@ int gosma_get_S22(gosma_ctx *ctx, int problem, double *S22);
  *                      S11 lower sum, S12 upper sum} (class-weighted)
  *   top8          out: NULL or n x 8 floats, the largest S12 pair terms at the
  *                      centre in descending order (zeros past the pair count)
- * Runs asynchronously on `stream` (a hipStream_t, NULL = null stream).
+ * Runs on `stream` (a hipStream_t, NULL = null stream).
  * n = 0 is a no-op.  Errors: GOSMA_E_STATE before mixtures and a domain are
  * set, GOSMA_E_INVAL for n < 0 or a NULL required pointer. */
 int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *problem,

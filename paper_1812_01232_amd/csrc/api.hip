@@ -137,6 +137,7 @@ void gosma_destroy(gosma_ctx *ctx)
     dfree(ctx->d_s11lo);
     dfree(ctx->d_setup);
     dfree(ctx->d_pairs);
+    dfree(ctx->d_stage);
     gosma_release_solver(ctx);
     gosma_release_mlp(ctx);
     delete ctx;
@@ -378,6 +379,22 @@ int gosma_get_S22(gosma_ctx *ctx, int problem, double *S22)
     return GOSMA_OK;
 }
 
+// Where an argument of gosma_eval_bounds lives: memory of the context's
+// device (used in place), host memory of any kind (staged), or memory of
+// another device (rejected).
+enum class Where { device, host, other };
+static Where where_is(const gosma_ctx *ctx, const void *p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();   // not known to HIP: plain host memory
+        return Where::host;
+    }
+    if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged)
+        return a.device == ctx->device ? Where::device : Where::other;
+    return Where::host;
+}
+
 int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *problem,
                       int64_t n, double *ub, double *lb, uint8_t *flags, double *aux, float *top8, void *stream)
 {
@@ -393,6 +410,54 @@ int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tke
         return fail(ctx, GOSMA_E_INVAL, "problem indices are required when several problems are set");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
+
+    // host arrays go through device copies: inputs before the launches,
+    // outputs after them, then the call waits for the copies
+    struct Arg {
+        void *user;
+        size_t bytes;
+        bool in;
+        void *dev;
+    } args[8] = {{(void *)rkeys, 8, true, nullptr},  {(void *)tkeys, 8, true, nullptr},
+                 {(void *)problem, 4, true, nullptr}, {(void *)ub, 8, false, nullptr},
+                 {(void *)lb, 8, false, nullptr},     {(void *)flags, 1, false, nullptr},
+                 {(void *)aux, 32, false, nullptr},   {(void *)top8, 32, false, nullptr}};
+    size_t stage = 0;
+    for (Arg &a : args) {
+        a.bytes *= (size_t)n;
+        if (!a.user) continue;
+        const Where w = where_is(ctx, a.user);
+        if (w == Where::other) return fail(ctx, GOSMA_E_INVAL, "an array is device memory of another device");
+        if (w == Where::host) stage += (a.bytes + 255) & ~(size_t)255;
+    }
+    if (stage > ctx->stage_cap) {
+        dfree(ctx->d_stage);
+        ctx->stage_cap = 0;
+        HIP_TRY(ctx, hipMalloc((void **)&ctx->d_stage, stage));
+        ctx->stage_cap = stage;
+    }
+    {
+        size_t at = 0;
+        for (Arg &a : args) {
+            if (!a.user) continue;
+            if (where_is(ctx, a.user) != Where::host) {
+                a.dev = a.user;
+                continue;
+            }
+            a.dev = ctx->d_stage + at;
+            at += (a.bytes + 255) & ~(size_t)255;
+            if (a.in) HIP_TRY(ctx, hipMemcpyAsync(a.dev, a.user, a.bytes, hipMemcpyHostToDevice, s));
+        }
+    }
+    rkeys = (const uint64_t *)args[0].dev;
+    tkeys = (const uint64_t *)args[1].dev;
+    problem = (const uint32_t *)args[2].dev;
+    ub = (double *)args[3].dev;
+    lb = (double *)args[4].dev;
+    flags = (uint8_t *)args[5].dev;
+    aux = (double *)args[6].dev;
+    top8 = (float *)args[7].dev;
+
     if (ctx->s11_cap < n) {
         dfree(ctx->d_s11ub);
         dfree(ctx->d_s11lo);
@@ -414,6 +479,12 @@ int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tke
     HIP_TRY(ctx, gosma::launch_s12(mx, rkeys, tkeys, problem, nullptr, ctx->d_s11ub, ctx->d_s11lo, n, nullptr, 1, out,
                                    0.0, ctx->maxM, ctx->maxN, top8 != nullptr, ctx->tile12, ctx->d_setup, s));
     ctx->time_end(ti, s);
+    if (stage) {
+        for (const Arg &a : args)
+            if (a.user && !a.in && a.dev != a.user)
+                HIP_TRY(ctx, hipMemcpyAsync(a.user, a.dev, a.bytes, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+    }
     return GOSMA_OK;
 }
 

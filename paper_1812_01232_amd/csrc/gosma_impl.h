@@ -135,6 +135,8 @@ struct gosma_ctx {
     double *d_s11ub = nullptr, *d_s11lo = nullptr;
     gosma::CubeSetup *d_setup = nullptr;
     unsigned long long *d_pairs = nullptr;   // pair counts of timed gosma_eval_bounds calls
+    uint8_t *d_stage = nullptr;              // device copies of host arrays given to gosma_eval_bounds
+    size_t stage_cap = 0;
 
     gosma::Solver *solver = nullptr;
     bool snap_ready = false;      // the solver holds the finished search of the current problems

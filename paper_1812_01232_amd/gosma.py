@@ -206,7 +206,8 @@ class Context:
 
     # -- bounds -----------------------------------------------------------
     def eval_bounds(self, rkeys, tkeys, ub, lb, flags, aux=None, top8=None, problem=None, stream=None):
-        """Device tensors in/out (see gosma_eval_bounds); runs on the current stream."""
+        """Tensors in/out (see gosma_eval_bounds: device memory is used in place, host
+        memory is staged by the library); runs on the current stream."""
         n = int(rkeys.numel())
         s = _current_stream() if stream is None else C.c_void_p(stream)
         self._check(lib().gosma_eval_bounds(self._h, _ptr(rkeys), _ptr(tkeys), _ptr(problem), n, _ptr(ub), _ptr(lb),
@@ -234,6 +235,24 @@ class Context:
             out["aux"] = aux.cpu().numpy()
         if want_top8:
             out["top8"] = t8.cpu().numpy()
+        return out
+
+    def bounds_host(self, rkeys_np, tkeys_np, problem_np=None, want_aux=True, want_top8=False):
+        """Host (numpy) arrays straight through the C-ABI: the library copies
+        them to and from the device itself; synchronous."""
+        n = len(rkeys_np)
+        rk = np.ascontiguousarray(rkeys_np, dtype=np.uint64)
+        tk = np.ascontiguousarray(tkeys_np, dtype=np.uint64)
+        pr = None if problem_np is None else np.ascontiguousarray(problem_np, dtype=np.uint32)
+        out = {"ub": np.empty(n), "lb": np.empty(n), "flags": np.empty(n, np.uint8)}
+        if want_aux:
+            out["aux"] = np.empty((n, 4))
+        if want_top8:
+            out["top8"] = np.empty((n, 8), np.float32)
+        p = lambda a: None if a is None else C.c_void_p(a.ctypes.data)
+        self._check(lib().gosma_eval_bounds(self._h, p(rk), p(tk), p(pr), n, p(out["ub"]), p(out["lb"]),
+                                            p(out["flags"]), p(out.get("aux")), p(out.get("top8")), None),
+                    "gosma_eval_bounds")
         return out
 
     # -- queue-ordering network -------------------------------------------

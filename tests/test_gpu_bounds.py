@@ -284,3 +284,31 @@ def test_pair_screen_counts_and_parity(ctx):
         assert lo_frac <= frac <= hi_frac
         o = oracle.OracleProblem(sc).bounds(rk, tk)
         _compare(sc, g, o, label=f"screen {levels}")
+
+
+def test_host_arrays_through_the_abi(ctx):
+    """Host arrays handed to gosma_eval_bounds are staged by the library and
+    give the device path's results bit for bit; pinned host memory and mixed
+    host/device arguments too; a larger call after a smaller one grows the
+    staging buffers."""
+    sc = scenes.cfg1_scene(0)
+    ctx.set_scene(sc)
+    for n, seed in [(1000, 1601), (5000, 1602)]:
+        rk, tk = scenes.random_cubes(sc, n, seed)
+        dev = ctx.bounds(rk, tk, want_top8=True)
+        host = ctx.bounds_host(rk, tk, want_top8=True)
+        for key in ("ub", "lb", "flags", "aux", "top8"):
+            assert np.array_equal(dev[key], host[key], equal_nan=True), (n, key)
+    # pinned host inputs, device outputs
+    n = 777
+    rk, tk = scenes.random_cubes(sc, n, 1603)
+    ref = ctx.bounds(rk, tk)
+    prk = torch.from_numpy(rk.view(np.int64)).pin_memory()
+    ptk = torch.from_numpy(tk.view(np.int64)).pin_memory()
+    ub = torch.empty(n, dtype=torch.float64, device="cuda")
+    lb = torch.empty(n, dtype=torch.float64, device="cuda")
+    fl = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ctx.eval_bounds(prk, ptk, ub, lb, fl)
+    torch.cuda.synchronize()
+    assert np.array_equal(ub.cpu().numpy(), ref["ub"]) and np.array_equal(lb.cpu().numpy(), ref["lb"])
+    assert np.array_equal(fl.cpu().numpy(), ref["flags"])
