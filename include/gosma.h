@@ -82,8 +82,9 @@ const char *gosma_last_error(const gosma_ctx *ctx);
  * within each class; without labels the weights are renormalised to sum 1.
  * All arrays are host FP64/int32 and are copied.  1 <= M, N <= 1024
  * (GOSMA_E_INVAL otherwise); a bound-kernel block stages 96 bytes per GMM
- * component in LDS plus 1,280 bytes per wave, which fits gfx950's 160 KB at
- * M = 1024, and a device with less LDS per block rejects larger M with
+ * component in LDS plus 512 bytes per wave (and 32 bytes per vMF component
+ * when several problems are set), which fits gfx950's 160 KB at M = N =
+ * 1024; a device with less LDS per block rejects larger sizes with
  * GOSMA_E_INVAL. */
 int gosma_set_mixtures(gosma_ctx *ctx, int M, const double *mu, const double *sigma, const double *phi1,
                        const int32_t *label1, int N, const double *dir2, const double *kappa2,

@@ -202,7 +202,7 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
             needN = std::max(needN, (int)(vmf_off[p + 1] - vmf_off[p]));
         }
         HIP_TRY(ctx, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
-        const size_t need = std::max(gosma::s11_lds_bytes(needM, gosma::kMaxWaves), gosma::s12_lds_bytes(needM, gosma::kMaxWaves)) + 1024;
+        const size_t need = std::max(gosma::s11_lds_bytes(needM, gosma::kMaxWaves), gosma::s12_lds_bytes(needM, needN, gosma::kMaxWaves, n_problems > 1)) + 1024;
         if (need > (size_t)lds_max)
             return fail(ctx, GOSMA_E_INVAL, "M = %d, N = %d need %zu bytes of LDS per block; the device has %d", needM,
                         needN, need, lds_max);

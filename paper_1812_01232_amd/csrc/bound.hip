@@ -300,18 +300,19 @@ struct PairK {
 __device__ __forceinline__ PairK pair_k(float a, float b, float q)
 {
     PairK o;
-    float s = a + b;
-    float t = a * b * q;
-    o.ks = fmaxf(fmaf(s, s, -t), 0.0f);
-    float K = fmaxf(fsqrt(o.ks), 1e-20f);
-    float den = K + s;
-    float r = frcp(K * den);
+    const float s = a + b;
+    const float t = a * b * q;
+    // K^2 = (a + b)^2 - a b q, kept off zero for the reciprocal square root
+    o.ks = fmaxf(fmaf(s, s, -t), 1e-36f);
+    const float iK = __builtin_amdgcn_rsqf(o.ks);   // 1 / K
+    const float K = o.ks * iK;
+    const float rd = frcp(K + s);                   // 1 / (K + a + b)
     o.K = K;
-    o.r = r;
-    o.x = -t * K * r;
-    o.invK = den * r;
-    o.hK = o.invK;
-    o.nuK = o.invK;
+    o.r = iK * rd;
+    o.x = -t * rd;                                  // K - a - b without cancellation
+    o.invK = iK;
+    o.hK = iK;
+    o.nuK = iK;
     if (__builtin_expect(K < 9.0f, 0)) {
         // e^{-2K} is not negligible next to 1 in FP32 below K = 9.
         float e = fexp2(-2.0f * kLog2e * K);
@@ -345,10 +346,12 @@ struct BlockShared {
 // and all dropped pairs together move a bound by at most kCullRel of it.
 constexpr double kCullRel = 1e-8;
 
-// Pairs that pass the screen are evaluated kBatch per lane at a time (several
-// independent pairs in flight per lane); each wave collects them in a list of
-// kList entries (a full batch plus one step of 64 offers).
-constexpr int kBatch = 4, kList = 64 * kBatch + 64;
+// Pairs that pass the screen are evaluated kBatch per lane at a time; each
+// wave collects them in a list of kList entries (a full batch plus one step
+// of 64 offers).  One pair per lane measured fastest: five waves per SIMD
+// already keep enough independent work in flight, and a short list flushes
+// with fewer idle lanes.
+constexpr int kBatch = 1, kList = 64 * kBatch + 64;
 
 // Pairs are summed in FP32 over runs of at most this many steps per lane and
 // the runs are accumulated in FP64.
@@ -356,8 +359,10 @@ constexpr int kRun = 8;
 
 // LDS record stride in float4: a GMM record holds five float4 (a stride of
 // 20 dwords, so 16-byte reads of consecutive records by consecutive lanes hit
-// distinct banks).  The vMF rows are read from the global table (two float4
-// per component, a few KB per problem, resident in L1/L2).
+// distinct banks).  The vMF rows (two float4 per component) are read from the
+// global table when one problem is set (every block reads the same few KB,
+// which stay in L1/L2); with several problems a block's successive cubes
+// belong to different problems, so their rows are staged in LDS per cube.
 constexpr int kG = 5;
 
 // ---------------------------------------------------------------------------
@@ -795,7 +800,7 @@ __global__ __launch_bounds__(256) void k_cube_setup(DevMix mx, const uint64_t *_
 // Five waves per SIMD fit the plain kernel's registers without spills; the
 // variant that also keeps the top-8 terms (learned order, record logging) is
 // held to four.
-template <bool TOP8>
+template <bool TOP8, bool VLDS>
 __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(TOP8 ? 4 : 5))) void k_s12(DevMix mx, const uint64_t *__restrict__ rkeys,
                                                          const uint64_t *__restrict__ tkeys,
                                                          const uint32_t *__restrict__ pids,
@@ -803,15 +808,16 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                                                          const double *__restrict__ s11ub,
                                                          const double *__restrict__ s11lo, int64_t n_host,
                                                          const uint32_t *__restrict__ n_dev, int n_dev_mul,
-                                                         BoundOut out, double gamma, int maxM,
+                                                         BoundOut out, double gamma, int maxM, int maxN,
                                                          const CubeSetup *__restrict__ setup)
 {
     extern __shared__ float4 lds4[];
     __shared__ BlockShared sh;
     float4 *rec = lds4;               // kG per GMM component
     float4 *scr = lds4 + kG * maxM;   // screen row per GMM component
+    float4 *vrec = scr + maxM;        // vMF rows (VLDS only)
     // per wave: pairs that passed the screen
-    uint32_t *plist = reinterpret_cast<uint32_t *>(scr + maxM);
+    uint32_t *plist = reinterpret_cast<uint32_t *>(vrec + (VLDS ? 2 * maxN : 0));
     const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, wv = tid >> 6, lane = tid & 63;
     const int64_t n = n_dev ? (int64_t)n_dev[0] * n_dev_mul : n_host;
     unsigned nscr = 0, ncull_all = 0;   // per wave: pairs screened and dropped, over all cubes of the block
@@ -901,6 +907,14 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         }
         // the problem's vMF rows {mu, kappa}, {weight, G(kappa), coth kappa, ln(2 kappa) / 2}
         const float4 *__restrict__ vt = mx.vmf + 2 * (int64_t)P.vmf_off;
+        if (VLDS)
+            for (int j = tid; j < 2 * P.N; j += T) vrec[j] = vt[j];
+        auto vrow = [&](int j, int h) __attribute__((always_inline)) -> float4 {
+            if constexpr (VLDS)
+                return vrec[2 * j + h];
+            else
+                return vt[2 * j + h];
+        };
         drop = wave_or(drop);
         ubinf = wave_or(ubinf);
         psum = wave_sumf(psum);
@@ -962,7 +976,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                 for (int k = 0; k < kBatch; ++k) {
                     if (e[k] != 0xffffffffu) {
                         const int jj = (int)(e[k] & 0xffffu);
-                        s12_pair<TOP8>(rec, (int)(e[k] >> 16), vt[2 * jj], vt[2 * jj + 1], sub, shi, top);
+                        s12_pair<TOP8>(rec, (int)(e[k] >> 16), vrow(jj, 0), vrow(jj, 1), sub, shi, top);
                     }
                 }
                 run += kBatch;
@@ -1014,7 +1028,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                     const int jl = tid % cols, i0 = tid / cols;
                     for (int jb = 0; jb < nj; jb += cols) {
                         const int j = vb + jb + jl;
-                        const float4 v0 = vt[2 * j], v1 = vt[2 * j + 1];
+                        const float4 v0 = vrow(j, 0), v1 = vrow(j, 1);
                         const float lw = __builtin_amdgcn_logf(v1.x * v1.y) * kLn2 - v1.w;
                         const float c = frcp(v0.w), l = fmaxf(lw, -100.0f) - lthr;
                         const float4 vm = make_float4(v0.x, v0.y, v0.z, l * c);
@@ -1042,7 +1056,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                     for (int st = 0; st < steps; ++st) {
                         const bool valid = i < ni;
                         const int jj = vb + j;
-                        const float4 v0 = vt[2 * jj], v1 = vt[2 * jj + 1];
+                        const float4 v0 = vrow(jj, 0), v1 = vrow(jj, 1);
                         const float lw = __builtin_amdgcn_logf(v1.x * v1.y) * kLn2 - v1.w;
                         const float c = frcp(v0.w), l = fmaxf(lw, -100.0f) - lthr;
                         offer(gb + min(i, ni - 1), jj, make_float4(v0.x, v0.y, v0.z, l * c), make_float2(c, l), valid);
@@ -1155,9 +1169,10 @@ size_t s11_lds_bytes(int maxM, int waves)
 {
     return sizeof(float4) * kG * (size_t)maxM + sizeof(uint32_t) * kList * (size_t)waves;
 }
-size_t s12_lds_bytes(int maxM, int waves)
+size_t s12_lds_bytes(int maxM, int maxN, int waves, bool vlds)
 {
-    return sizeof(float4) * (kG + 1) * (size_t)maxM + sizeof(uint32_t) * kList * (size_t)waves;
+    return sizeof(float4) * ((kG + 1) * (size_t)maxM + (vlds ? 2 * (size_t)maxN : 0)) +
+           sizeof(uint32_t) * kList * (size_t)waves;
 }
 
 hipError_t prepare_bound_kernels(int maxM, int maxN)
@@ -1165,12 +1180,11 @@ hipError_t prepare_bound_kernels(int maxM, int maxN)
     // allow dynamic LDS beyond the default limit on devices that have it
     hipError_t e = hipFuncSetAttribute((const void *)k_s11, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)s11_lds_bytes(maxM, kMaxWaves));
-    if (!e)
-        e = hipFuncSetAttribute((const void *)k_s12<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)s12_lds_bytes(maxM, kMaxWaves));
-    if (!e)
-        e = hipFuncSetAttribute((const void *)k_s12<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)s12_lds_bytes(maxM, kMaxWaves));
+    const int l0 = (int)s12_lds_bytes(maxM, maxN, kMaxWaves, false), l1 = (int)s12_lds_bytes(maxM, maxN, kMaxWaves, true);
+    if (!e) e = hipFuncSetAttribute((const void *)k_s12<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, l0);
+    if (!e) e = hipFuncSetAttribute((const void *)k_s12<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, l0);
+    if (!e) e = hipFuncSetAttribute((const void *)k_s12<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, l1);
+    if (!e) e = hipFuncSetAttribute((const void *)k_s12<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, l1);
     return e;
 }
 
@@ -1199,14 +1213,17 @@ hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *t
         hipLaunchKernelGGL(k_cube_setup, dim3(gs), dim3(256), 0, stream, mx, rkeys, tkeys, pids, n, n_dev, n_dev_mul,
                            setup);
     }
-    const size_t lds = s12_lds_bytes(maxM, tile.waves);
+    const bool vlds = mx.n_prob > 1;   // see kG
+    const size_t lds = s12_lds_bytes(maxM, maxN, tile.waves, vlds);
     const unsigned g = (unsigned)std::min<int64_t>(tile.blocks, n);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(g), dim3(64 * tile.waves), lds, stream, mx, rkeys, tkeys, pids, tidx, s11ub,
+                           s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, maxN, setup);
+    };
     if (with_top8)
-        hipLaunchKernelGGL(k_s12<true>, dim3(g), dim3(64 * tile.waves), lds, stream, mx, rkeys, tkeys, pids, tidx,
-                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, setup);
+        vlds ? go(k_s12<true, true>) : go(k_s12<true, false>);
     else
-        hipLaunchKernelGGL(k_s12<false>, dim3(g), dim3(64 * tile.waves), lds, stream, mx, rkeys, tkeys, pids, tidx,
-                           s11ub, s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, setup);
+        vlds ? go(k_s12<false, true>) : go(k_s12<false, false>);
     return hipGetLastError();
 }
 

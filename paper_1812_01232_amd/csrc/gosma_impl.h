@@ -101,7 +101,7 @@ hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *t
 // Dynamic LDS of the two kernels (the pair kernel's grows with the waves per
 // block), and the per-kernel limit setup for it.
 size_t s11_lds_bytes(int maxM, int waves);
-size_t s12_lds_bytes(int maxM, int waves);
+size_t s12_lds_bytes(int maxM, int maxN, int waves, bool vlds);
 hipError_t prepare_bound_kernels(int maxM, int maxN);
 
 struct Mlp;

@@ -249,7 +249,7 @@ def test_autotune(ctx):
 
 def test_max_components(ctx):
     """The largest problem the library accepts: M = N = 1024 (LDS per block
-    96 M bytes plus 1,280 per wave), a few cubes checked one by one."""
+    96 M bytes plus 512 per wave), a few cubes checked one by one."""
     sc = scenes.small_scene(1024, 1024, seed=77, noise_deg=1.0, n_inliers=700, sigma=(0.05, 0.3), t_half=1.0,
                             room=((-5, -5, -1.5), (5, 5, 1.5)))
     rk, tk = scenes.random_cubes(sc, 12, 5300, r_levels=(2, 12), t_levels=(1, 10))
