@@ -366,12 +366,12 @@ __global__ __launch_bounds__(kBlock) void k_hist(Bufs b, int rebuild_pass, int p
 // Radix pass: the digit holding the need-th lowest key.  One block per problem.
 __global__ __launch_bounds__(kBlock) void k_scan(Bufs b, int rebuild_pass, int pass)
 {
-    __shared__ uint32_t part[kBlock];
+    __shared__ uint32_t wtot[kBlock / 64];
     __shared__ uint32_t found, left;
     const int p = blockIdx.x;
     PState &s = b.st[p];
     if (s.done || s.take_all || (rebuild_pass && !s.rebuild)) return;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const uint32_t want = rebuild_pass ? s.rb_target : b.k;
     if (pass == 0) {
         const uint32_t total = rebuild_pass ? s.nH[s.hcur] + s.nC[s.ccur] : s.nH[s.hcur];
@@ -392,14 +392,21 @@ __global__ __launch_bounds__(kBlock) void k_scan(Bufs b, int rebuild_pass, int p
         loc[j] = gh[t * per + j];
         sum += loc[j];
     }
-    part[t] = sum;
+    // exclusive prefix of the per-thread sums: wave scan, then wave totals
+    uint32_t incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    if (lane == 63) wtot[wave] = incl;
     if (t == 0) {
         found = 0;
         left = need;
     }
     __syncthreads();
-    uint32_t cum = 0;
-    for (int u = 0; u < t; ++u) cum += part[u];
+    uint32_t cum = incl - sum;
+    for (int w = 0; w < wave; ++w) cum += wtot[w];
     for (int j = 0; j < per; ++j) {
         if (cum < need && need <= cum + loc[j]) {   // exactly one bin qualifies
             found = (uint32_t)(t * per + j);
@@ -1021,8 +1028,10 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
         hipLaunchKernelGGL(k_rebuild_finish, dim3((P + 63) / 64), dim3(64), 0, st, b, P);
     }
     // selection of the k lowest hot cubes
+    // the hot part holds at most hcap keys: blocks for kHistPer keys per thread
+    const int gh = std::max(1, std::min<int>(gx, (int)((b.hcap + kBlock * kHistPer - 1) / (kBlock * kHistPer))));
     for (int pass = 0; pass < kRadixPasses; ++pass) {
-        hipLaunchKernelGGL(k_hist, dim3(gx, P), dim3(kBlock), 0, st, b, 0, pass);
+        hipLaunchKernelGGL(k_hist, dim3(gh, P), dim3(kBlock), 0, st, b, 0, pass);
         hipLaunchKernelGGL(k_scan, dim3(P), dim3(kBlock), 0, st, b, 0, pass);
     }
     hipLaunchKernelGGL(k_select_compact, dim3(gx, P), dim3(kBlock), 0, st, b);
