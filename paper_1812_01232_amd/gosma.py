@@ -188,6 +188,9 @@ class Context:
         vo = np.cumsum([0] + [s.N for s in scenes_list]).astype(np.int64)
         cat = lambda f: _f64(np.concatenate([getattr(s, f) for s in scenes_list]))
         labelled = scenes_list[0].label1 is not None
+        if any((s.label1 is not None) != labelled or s.n_labels != scenes_list[0].n_labels for s in scenes_list):
+            raise ValueError("the problems of one batch must all be labelled with the same number of classes, "
+                             "or all unlabelled")
         l1 = _i32(np.concatenate([s.label1 for s in scenes_list])) if labelled else None
         l2 = _i32(np.concatenate([s.label2 for s in scenes_list])) if labelled else None
         doms = (Domain * len(scenes_list))(*[domain_of(s) for s in scenes_list])

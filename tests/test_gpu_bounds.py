@@ -162,10 +162,23 @@ def test_empty_batch_and_errors(ctx):
         ctx.set_scene(bad)
 
 
-def test_batched_problems(ctx):
-    """Several problems of different sizes in one launch (problem index per cube)."""
-    scs = scenes.batch_scenes(6, seed=4100, lo=16, hi=96)
+@pytest.mark.parametrize("tile,labelled", [(None, False), (None, True), ((1, 3), False), ((2, 2048), True),
+                                           ((4, 1024), False)])
+def test_batched_problems(ctx, tile, labelled):
+    """Several problems of different sizes in one launch, problem index per
+    cube; with several problems the pair kernel stages each cube's vMF rows in
+    LDS, on every launch shape.  Labelled batches: three classes each."""
+    if labelled:
+        scs = [scenes.small_scene(m, n, seed=4107 + m, noise_deg=1.0, n_inliers=3 * min(m, n) // 4,
+                                  sigma=(0.05, 0.3), t_half=1.0, room=((-5, -5, -1.5), (5, 5, 1.5)), n_labels=3)
+               for m, n in [(40, 50), (24, 17), (64, 64), (33, 70), (16, 16), (90, 45)]]
+        with pytest.raises(ValueError):   # one class count for the whole batch
+            ctx.set_scenes(scenes.batch_scenes(2, seed=4100, lo=16, hi=32) + scs[:1])
+    else:
+        scs = scenes.batch_scenes(6, seed=4100, lo=16, hi=96)
     ctx.set_scenes(scs)
+    if tile is not None:
+        ctx.set_tiles(s11=tile, s12=tile)
     rks, tks, pids = [], [], []
     for p, s in enumerate(scs):
         rk, tk = scenes.random_cubes(s, 300, 4700 + p, r_levels=(1, 10), t_levels=(0, 9))
@@ -180,7 +193,7 @@ def test_batched_problems(ctx):
     for p, s in enumerate(scs):
         m = pid == p
         o = oracle.OracleProblem(s).bounds(rk[m], tk[m])
-        _compare(s, {k: v[m] for k, v in g.items()}, o, label=f"batch-{p}")
+        _compare(s, {k: v[m] for k, v in g.items()}, o, label=f"batch-{p} tile {tile}")
         assert ctx.S22(p) == pytest.approx(oracle.OracleProblem(s).S22(), rel=1e-12)
 
 
