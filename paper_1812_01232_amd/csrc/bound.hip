@@ -372,7 +372,7 @@ constexpr int kG = 5;
 // Component record in LDS, four float4 (64 bytes, padded to 80):
 //   [0] u (unit vector mu - t0), weight      [1] kappa(t0), G(kappa), cos, sin of psi_t / 2
 //   [2] kappa interval centre ac, half-width ha, G(ac), nu(ac)
-//   [3] lambda = min(1/3, 1/klo^2), Lam (pair screen), kappa(t0), -
+//   [3] lambda = min(1/3, 1/klo^2), Lam (pair screen), 2 / kappa(t0), -
 //
 // Pair screen.  The summand of a pair at the centre is at most
 // G(k) G(k') exp(-min(q, 2) k k' / (2 (k + k'))) / sqrt(2 k k') (h(K) <= 1/K,
@@ -383,7 +383,9 @@ constexpr int kG = 5;
 // most thr11 (and stays a lower bound) and the centre sum is charged thr11
 // (and stays an upper bound).  With min(q, 2) in place of q, the
 // test is  q k k' >= 2 (Lam_i + Lam_i' - ln thr11)(k + k'),  Lam_i =
-// ln(w_i G(k_i) / sqrt(k_i)) + ln(2) / 4, with thr11 = kCullRel D / (M (M - 1) / 2).
+// ln(w_i G(k_i) / sqrt(k_i)) + ln(2) / 4, with thr11 = kCullRel D / (M (M - 1) / 2);
+// the kernel divides it by k k' and takes q from the dot product of the
+// two unit vectors.
 
 __device__ __forceinline__ void s11_terms(const float4 &A0, const float4 &A1, const float4 &A2, const float4 &A3,
                                           const float4 &B0, const float4 &B1, const float4 &B2, const float4 &B3,
@@ -476,7 +478,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             const float lam = fminf(fmaxf(__builtin_amdgcn_logf((float)w * fk.G * __builtin_amdgcn_rsqf((float)tp.kap)) *
                                                   kLn2 + 0.25f * kLn2, -1e30f), 1e30f);
             dk += 0.5 * w * w * tp.klo;
-            rec[kG * i + 3] = make_float4((float)fmin(1.0 / 3.0, 1.0 / (tp.klo * tp.klo)), lam, (float)tp.kap, 0.0f);
+            rec[kG * i + 3] = make_float4((float)fmin(1.0 / 3.0, 1.0 / (tp.klo * tp.klo)), lam, (float)(2.0 / tp.kap), 0.0f);
         }
         drop = wave_or(drop);
         ubinf = wave_or(ubinf);
@@ -535,16 +537,18 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             bool keep = false;
             if (valid) {
                 const float4 B0 = rec[kG * b_], B3 = rec[kG * b_ + 3];
-                const float dx = A0.x - B0.x, dy = A0.y - B0.y, dz = A0.z - B0.z;
-                const float q = fminf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), 2.0f);
-                keep = q * A3.z * B3.z < 2.0f * (A3.y + B3.y - lthr11) * (A3.z + B3.z);
+                // q = |u - u'|^2 = 2 - 2 u.u', the test divided by k k' (slot 3 holds 2 / k)
+                const float dot = fmaf(A0.x, B0.x, fmaf(A0.y, B0.y, A0.z * B0.z));
+                const float q = fminf(fmaf(-2.0f, dot, 2.0f), 2.0f);
+                keep = q < (A3.y + B3.y - lthr11) * (A3.z + B3.z);
                 ncull += keep ? 0 : 1;
             }
             const unsigned long long m = __ballot(keep);
             if (keep) {
-                const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                pl[pc + rank] = ((uint32_t)a_ << 16) | (uint32_t)b_;
+                // slot = pc + kept lanes below this one (mbcnt adds to pc)
+                const uint32_t slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)pc));
+                pl[slot] = ((uint32_t)a_ << 16) | (uint32_t)b_;
             }
             pc += __popcll(m);
             if (pc >= 64 * kBatch) {
@@ -999,9 +1003,10 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             auto append = [&](bool keep, unsigned long long m, uint32_t packed) __attribute__((always_inline)) {
                 nkeep += (unsigned)__popcll(m);
                 if (keep) {
-                    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    pl[pc + rank] = packed;
+                    // slot = pc + kept lanes below this one (mbcnt adds to pc)
+                    const uint32_t slot = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)pc));
+                    pl[slot] = packed;
                 }
                 pc += __popcll(m);
                 if (pc >= 64 * kBatch) {
