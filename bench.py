@@ -57,17 +57,26 @@ BATCH_PARENTS = 4096
 BATCH = 8 * BATCH_PARENTS
 
 
+def kernel_code_hash(path):
+    """SHA-256 of a source file's code: comments removed, whitespace collapsed."""
+    import hashlib
+    import re
+    with open(path) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = re.sub(r"\s+", " ", src).strip()
+    return hashlib.sha256(src.encode()).hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per launch of the bound kernel from the committed counter
-    summary, or None once the kernel source differs from the one measured."""
-    import hashlib
+    summary, or None once the kernel code differs from the one measured."""
     prof = os.path.join(ROOT, "profiles", "k_s12_64x64_pmc.md")
     src = os.path.join(ROOT, "paper_1812_01232_amd", "csrc", "bound.hip")
     try:
         fields = dict(line.strip().split("=", 1) for line in open(prof) if "=" in line and " " not in line.strip())
-        with open(src, "rb") as f:
-            current = hashlib.sha256(f.read()).hexdigest()
-        if fields.get("bound_hip_sha256") == current:
+        if fields.get("bound_hip_code_sha256") == kernel_code_hash(src):
             return int(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         pass

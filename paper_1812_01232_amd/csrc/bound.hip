@@ -658,10 +658,10 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
 //   [4] Lam, 1 / alo, -sin Psi, ln(alo) / 2 (pair screen, far-apart cap)
 // Screen row of the component (a separate LDS array, one float4):
 //   {w cos Psi, 1 - sin Psi - Lam / alo}
-// vMF record, two float4 (32 bytes):
+// vMF row, two float4 (32 bytes, global table or LDS):
 //   {dx, dy, dz, kappa}, {weight, G(kappa), coth(kappa), ln(2 kappa) / 2};
 // the screen's column term l = ln(weight G(kappa)) - ln(2 kappa) / 2 - ln thr is
-// formed per lane from the problem's vMF row (which holds ln(weight G(kappa))).
+// formed once per lane and column block from that row.
 //
 // Upper bound of the summand over the cube (Theorem 1 with kappa_1i(t)
 // relaxed to [alo, ahi]): at the smallest angle B, and with
