@@ -708,15 +708,15 @@ __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, int a_,
         PairK k = pair_k(R1.x, b, q);
         const float v = ww * (fexp2(k.x * kLog2e) * k.hK * R1.y * v1.y);
         sub += v;
-        if (TOP8 && v > top[7]) {
-            top[7] = v;
+        if (TOP8) {
+            // insert v into the descending list and drop the smallest: each
+            // position keeps the larger value and passes the smaller one on
+            float c = v;
 #pragma unroll
-            for (int s = 7; s > 0; --s) {
-                if (top[s] > top[s - 1]) {
-                    const float tmp = top[s];
-                    top[s] = top[s - 1];
-                    top[s - 1] = tmp;
-                }
+            for (int s = 0; s < 8; ++s) {
+                const float hi = fmaxf(top[s], c);
+                c = fminf(top[s], c);
+                top[s] = hi;
             }
         }
     }
