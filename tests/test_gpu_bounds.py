@@ -109,6 +109,32 @@ def test_cfg3_labels_sampled(ctx):
     _compare(sc, {k: v[sel] for k, v in g.items()}, o, top8=True, label="cfg3")
 
 
+def test_cfg4_128_problems_sampled(ctx):
+    """The 128-problem batch (M, N uniform on [16, 256]) at its search size:
+    16,384 cubes per problem (256 seeded cubes, each repeated 64 times), 2.1 M
+    cubes in one launch of each kernel, under the benchmark's launch shape and
+    one-wave blocks; four cubes per problem are checked against the oracle."""
+    scs = scenes.batch_scenes(128, seed=4000)
+    ctx.set_scenes(scs)
+    uniq, per = 256, 16384
+    rks, tks, want = [], [], []
+    for p, s in enumerate(scs):
+        rk, tk = scenes.random_cubes(s, uniq, 6000 + p, r_levels=(2, 12), t_levels=(1, 10))
+        rks.append(np.tile(rk, per // uniq))
+        tks.append(np.tile(tk, per // uniq))
+        want.append(oracle.OracleProblem(s).bounds(rk[:4], tk[:4]))
+    rk, tk = np.concatenate(rks), np.concatenate(tks)
+    pid = np.repeat(np.arange(128, dtype=np.uint32), per)
+    for tile in [(4, 8192), (1, 8192)]:
+        ctx.set_tiles(s11=tile, s12=tile)
+        g = ctx.bounds(rk, tk, problem_np=pid)
+        for p, s in enumerate(scs):
+            # the sampled cubes and their last copies in the launch
+            for off in (0, per - uniq):
+                m = np.arange(p * per + off, p * per + off + 4)
+                _compare(s, {k: v[m] for k, v in g.items()}, want[p], label=f"cfg4-{p} tile {tile} copy {off}")
+
+
 def test_cubes_around_true_pose(ctx):
     """Deep cubes containing the true pose (the cubes that decide termination)."""
     sc = scenes.cfg2_scene(0)
