@@ -668,6 +668,85 @@ __global__ __launch_bounds__(kBlock) void k_push(Bufs b, const float *prio_overr
     }
 }
 
+// The same pushes with the slots reserved per block: each child takes its
+// place among the block's children of the same target (problem, hot or cold)
+// with an LDS atomic, and one global atomic per target and block reserves
+// the block's run.  For up to kPushAggProblems problems.
+constexpr int kPushAggProblems = 256;
+__global__ __launch_bounds__(kBlock) void k_push_agg(Bufs b, const float *prio_override, int P)
+{
+    __shared__ uint32_t cnt[2 * kPushAggProblems], base[2 * kPushAggProblems];
+    __shared__ unsigned long long mn[2 * kPushAggProblems];
+    const uint32_t n = b.g->nchild;
+    const int T = 2 * P;
+    for (uint32_t start = blockIdx.x * blockDim.x; start < n; start += gridDim.x * blockDim.x) {
+        for (int t = threadIdx.x; t < T; t += blockDim.x) {
+            cnt[t] = 0;
+            mn[t] = ord64(INFINITY);
+        }
+        __syncthreads();
+        const uint32_t i = start + threadIdx.x;
+        bool push = false, hot = false;
+        uint32_t p = 0, local = 0;
+        double lbs = 0.0;
+        float pr = 0.0f;
+        uint8_t fl = 0;
+        if (i < n) {
+            p = b.cpid[i];
+            PState &s = b.st[p];
+            fl = b.cflags[i];
+            if (!((fl & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS)) || b.cskip[i])) {
+                const unsigned long long draw = s.dstar;
+                if (b.cub[i] < INFINITY && ord64(b.cub[i]) == draw) {
+                    s.best_rkey = b.crk[i];
+                    s.best_tkey = b.ctk[i];
+                }
+                lbs = fmax(sane_lb(b.clbs[i]), b.par.lb[b.cpar[i]]);
+                if (lbs < unord64(draw)) {
+                    push = true;
+                    pr = prio_override ? prio_override[i] : (float)lbs;
+                    hot = s.theta == 0xffffffffu || key32(pr) < s.theta;
+                }
+            }
+        }
+        const uint32_t tgt = 2u * p + (hot ? 1u : 0u);
+        if (push) {
+            local = atomicAdd(&cnt[tgt], 1u);
+            atomicMin(&mn[tgt], ord64(lbs));
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < T; t += blockDim.x) {
+            if (!cnt[t]) continue;
+            PState &s = b.st[t >> 1];
+            const bool h = t & 1;
+            base[t] = atomicAdd(h ? &s.nH[s.hcur ^ 1] : &s.nC[s.ccur], cnt[t]);
+            unsigned long long *m = h ? &s.minH : &s.minC;
+            if (mn[t] < __atomic_load_n(m, __ATOMIC_RELAXED)) atomicMin(m, mn[t]);
+        }
+        __syncthreads();
+        if (push) {
+            PState &s = b.st[p];
+            const uint32_t slot = base[tgt] + local;
+            const Queue q = hot ? qoff(b.H[s.hcur ^ 1], (size_t)p * b.hcap) : qoff(b.C[s.ccur], (size_t)p * b.ccap);
+            if (slot >= (hot ? b.hcap : b.ccap)) {
+                s.overflow = 1;
+            } else {
+                q.rkey[slot] = b.crk[i];
+                q.tkey[slot] = b.ctk[i];
+                q.lb[slot] = lbs;
+                q.prio[slot] = pr;
+                q.flags[slot] = fl & GOSMA_FLAG_SPLIT_ROT;
+                if (q.ubn) {
+                    const double S22 = b.prob[p].S22;
+                    q.ubn[slot] = (float)fmin(fmax((b.cub[i] + S22) / S22, -10.0), 10.0);
+                    for (int k = 0; k < 8; ++k) q.t8[8 * slot + k] = b.ctop8[8 * (size_t)i + k];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Features of a cube for the queue-ordering network (layout documented in
 // include/gosma.h): geometry from the keys, normalised bounds, top-8 terms.
 __device__ void cube_features(const ProbDesc &P, uint64_t rk, uint64_t tk, double ubn, double lbn,
@@ -1063,7 +1142,15 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
         T1(ti);
     }
     ti = T0(GOSMA_KERNEL_PUSH);
-    hipLaunchKernelGGL(k_push, dim3(kGridX), dim3(kBlock), 0, st, b, learned ? (const float *)b.cprio : nullptr);
+    {
+        const float *po = learned ? (const float *)b.cprio : nullptr;
+        // blocks for the children of all problems (8 k per problem at most)
+        const int gp = std::max(1, std::min<int>(kGridX, (int)((8 * (size_t)b.k * P + kBlock - 1) / kBlock)));
+        if (P <= kPushAggProblems)
+            hipLaunchKernelGGL(k_push_agg, dim3(gp), dim3(kBlock), 0, st, b, po, P);
+        else
+            hipLaunchKernelGGL(k_push, dim3(kGridX), dim3(kBlock), 0, st, b, po);
+    }
     hipLaunchKernelGGL(k_iter_end, dim3((P + 63) / 64), dim3(64), 0, st, b, P, rb_every);
     T1(ti);
     return hipGetLastError();
