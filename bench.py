@@ -16,7 +16,7 @@ over K steps after W warmup steps of the same search, inputs resident in HBM.
 
 Also reported: the bound kernels alone on a 32,768-cube batch, with the
 roofline of the dominant kernel (GMM-vMF pair sums) from its HIP-event launch
-times and the op model in the design doc; the FP64 CPU oracle's own search rate on
+times and the op model below; the FP64 CPU oracle's own search rate on
 the host's cores; time to eps on the 16 x 16 scene; and time to eps on fresh
 64 x 64 scenes with plain and learned queue order (network trained on records
 logged by the search itself).
@@ -34,10 +34,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Op model of the GMM-vMF pair kernel, counted from its source (the design doc lists
-# the counts).  A plain FP32 or FP64 operation takes one issue slot per lane
-# (the FP64 vector peak, 78.6 TFLOP/s, is one FMA per lane per clock, like
-# unpacked FP32); a transcendental (sqrt, rcp, exp2, log2) issues at half that
+# Op model of the GMM-vMF pair kernel, counted from its source.  A plain FP32
+# or FP64 operation takes one issue slot per lane (the FP64 vector peak,
+# 78.6 TFLOP/s, is one FMA per lane per clock, like unpacked FP32); a transcendental (sqrt, rcp, exp2, log2) issues at half that
 # rate on gfx950 (measured 1.8-1.9 plain-op slots), so it counts 2.
 #   per component and cube (the set-up of Lemmas 2-3 and of the kappa
 #   interval): 54 FP64 + 409 plain FP32 + 17 transcendentals;
@@ -275,8 +274,9 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0, help="only run a plain copy of this size (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; how the search would shard over "
-                                   "several GPUs is described in DESIGN.md", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the search would shard by splitting "
+                                   "each iteration's parents across GPUs, with one all-reduce of d* and the "
+                                   "lowest bound per iteration; that path is not built)", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
