@@ -36,8 +36,9 @@ sys.path.insert(0, ROOT)
 
 # Op model of the GMM-vMF pair kernel, counted from its source.  A plain FP32
 # or FP64 operation takes one issue slot per lane (the FP64 vector peak,
-# 78.6 TFLOP/s, is one FMA per lane per clock, like unpacked FP32); a transcendental (sqrt, rcp, exp2, log2) issues at half that
-# rate on gfx950 (measured 1.8-1.9 plain-op slots), so it counts 2.
+# 78.6 TFLOP/s, is one FMA per lane per clock, like unpacked FP32); a
+# transcendental (sqrt, rcp, exp2, log2) issues at half that rate on gfx950
+# (measured 1.8-1.9 plain-op slots), so it counts 2.
 #   per component and cube (the set-up of Lemmas 2-3 and of the kappa
 #   interval): 54 FP64 + 409 plain FP32 + 17 transcendentals;
 #   per same-class pair screened: 7 plain (a dot product, three threshold
