@@ -357,13 +357,15 @@ constexpr int kBatch = 1, kList = 64 * kBatch + 64;
 // the runs are accumulated in FP64.
 constexpr int kRun = 8;
 
-// LDS record stride in float4: a GMM record holds five float4 (a stride of
-// 20 dwords, so 16-byte reads of consecutive records by consecutive lanes hit
-// distinct banks).  The vMF rows (two float4 per component) are read from the
+// LDS record stride in float4: an S11 GMM record holds five float4 (a stride
+// of 20 dwords, so 16-byte reads of consecutive records by consecutive lanes
+// hit distinct banks).  The pair kernel's GMM record holds four (its pair
+// list is read by row, mostly the same row across a wave) and a separate
+// two-float4 screen record per component is read from one address.  The vMF rows (two float4 per component) are read from the
 // global table when one problem is set (every block reads the same few KB,
 // which stay in L1/L2); with several problems a block's successive cubes
 // belong to different problems, so their rows are staged in LDS per cube.
-constexpr int kG = 5;
+constexpr int kG = 5, kG12 = 4;
 
 // ---------------------------------------------------------------------------
 // S11 over translation cells
@@ -650,14 +652,14 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
 // S12 over rotation x translation cells, and the final bounds
 // ---------------------------------------------------------------------------
 //
-// GMM component record in LDS, five float4 (80 bytes):
+// GMM component record in LDS, four float4 (64 bytes):
 //   [0] w = R_r0 u (rotated unit vector), weight
 //   [1] kappa(t0), G(kappa), cos, sin of Psi / 2 with Psi = psi_t + psi_r (eq. 25)
 //   [2] kappa interval [alo, ahi] over the cell, half-width ha, coth(alo)
 //   [3] G(alo), G(ahi), nu(alo), nu(ahi)
-//   [4] Lam, 1 / alo, -sin Psi, ln(alo) / 2 (pair screen, far-apart cap)
-// Screen row of the component (a separate LDS array, one float4):
-//   {w cos Psi, 1 - sin Psi - Lam / alo}
+// Screen record of the component (a separate LDS array, two float4):
+//   {w cos Psi, 1 - sin Psi - Lam / alo},
+//   {Lam, 1 / alo, -sin Psi, ln(alo) / 2 (the far-apart cap's term)}
 // vMF row, two float4 (32 bytes, global table or LDS):
 //   {dx, dy, dz, kappa}, {weight, G(kappa), coth(kappa), ln(2 kappa) / 2};
 // the screen's column term l = ln(weight G(kappa)) - ln(2 kappa) / 2 - ln thr is
@@ -692,11 +694,11 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
 // evaluated kBatch per lane at a time.
 
 template <bool TOP8>
-__device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, int a_, const float4 v0, const float4 v1,
-                                         float &sub, float &shi, float (&top)[8])
+__device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, const float4 *__restrict__ scr, int a_,
+                                         const float4 v0, const float4 v1, float &sub, float &shi, float (&top)[8])
 {
-    const float4 R0 = rec[kG * a_], R1 = rec[kG * a_ + 1], R2 = rec[kG * a_ + 2], R3 = rec[kG * a_ + 3],
-                 R4 = rec[kG * a_ + 4];
+    const float4 R0 = rec[kG12 * a_], R1 = rec[kG12 * a_ + 1], R2 = rec[kG12 * a_ + 2], R3 = rec[kG12 * a_ + 3];
+    const float hla = scr[2 * a_ + 1].w;   // ln(alo) / 2
     const float b = v0.w;
     const float dx = R0.x - v0.x, dy = R0.y - v0.y, dz = R0.z - v0.z;
     const float q = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
@@ -742,7 +744,7 @@ __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, int a_,
         // far-apart caps: 2 G G e^{-qB cf} and G G e^{-min(qB, 2) cf} / sqrt(2 alo b)
         const float cf = alo * b * frcp(2.0f * (alo + b));
         const float e2 = fmaf(-qB, cf, kLn2);
-        const float eK = fmaf(-fminf(qB, 2.0f), cf, -(R4.w + v1.w));
+        const float eK = fmaf(-fminf(qB, 2.0f), cf, -(hla + v1.w));
         const float far = R3.y * v1.y * fexp2(fminf(e2, eK) * kLog2e);
         shi += ww * fminf(fminf(vT, cap), far);
     }
@@ -817,9 +819,9 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
 {
     extern __shared__ float4 lds4[];
     __shared__ BlockShared sh;
-    float4 *rec = lds4;               // kG per GMM component
-    float4 *scr = lds4 + kG * maxM;   // screen row per GMM component
-    float4 *vrec = scr + maxM;        // vMF rows (VLDS only)
+    float4 *rec = lds4;                 // kG12 per GMM component
+    float4 *scr = lds4 + kG12 * maxM;   // two-float4 screen record per GMM component
+    float4 *vrec = scr + 2 * maxM;      // vMF rows (VLDS only)
     // per wave: pairs that passed the screen
     uint32_t *plist = reinterpret_cast<uint32_t *>(vrec + (VLDS ? 2 * maxN : 0));
     const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, wv = tid >> 6, lane = tid & 63;
@@ -901,13 +903,13 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                 const float lam = fmaxf(__builtin_amdgcn_logf(wi * fh.G) * kLn2 - hla, -100.0f);
                 const float ia = frcp((float)tp.klo);
                 const float r0 = cf >= sf ? 1.0f - sPsi - lam * ia : -1e30f;
-                scr[i] = make_float4((float)w[0] * cPsi, (float)w[1] * cPsi, (float)w[2] * cPsi, r0);
-                rec[kG * i + 4] = make_float4(lam, ia, -sPsi, hla);
+                scr[2 * i] = make_float4((float)w[0] * cPsi, (float)w[1] * cPsi, (float)w[2] * cPsi, r0);
+                scr[2 * i + 1] = make_float4(lam, ia, -sPsi, hla);
             }
-            rec[kG * i] = make_float4((float)w[0], (float)w[1], (float)w[2], wi);
-            rec[kG * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)cP, (float)sP);
-            rec[kG * i + 2] = make_float4((float)tp.klo, (float)ahi, (float)tp.ha, (float)fl.coth);
-            rec[kG * i + 3] = make_float4((float)fl.G, (float)fh.G, (float)fl.nu, (float)fh.nu);
+            rec[kG12 * i] = make_float4((float)w[0], (float)w[1], (float)w[2], wi);
+            rec[kG12 * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)cP, (float)sP);
+            rec[kG12 * i + 2] = make_float4((float)tp.klo, (float)ahi, (float)tp.ha, (float)fl.coth);
+            rec[kG12 * i + 3] = make_float4((float)fl.G, (float)fh.G, (float)fl.nu, (float)fh.nu);
         }
         // the problem's vMF rows {mu, kappa}, {weight, G(kappa), coth kappa, ln(2 kappa) / 2}
         const float4 *__restrict__ vt = mx.vmf + 2 * (int64_t)P.vmf_off;
@@ -980,7 +982,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                 for (int k = 0; k < kBatch; ++k) {
                     if (e[k] != 0xffffffffu) {
                         const int jj = (int)(e[k] & 0xffffu);
-                        s12_pair<TOP8>(rec, (int)(e[k] >> 16), vrow(jj, 0), vrow(jj, 1), sub, shi, top);
+                        s12_pair<TOP8>(rec, scr, (int)(e[k] >> 16), vrow(jj, 0), vrow(jj, 1), sub, shi, top);
                     }
                 }
                 run += kBatch;
@@ -994,8 +996,9 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             // the screen test; vm = {mu_j, l_j c_j}, vc = {c_j = 1 / b_j, l_j}: the
             // lane's vMF screen constants
             auto screened_in = [&](int a_, const float4 &vm, const float2 &vc) __attribute__((always_inline)) {
-                const float4 S0 = scr[a_], S1 = rec[kG * a_ + 4];
-                const float d = fmaxf(fmaf(S0.x, vm.x, fmaf(S0.y, vm.y, S0.z * vm.z)), S1.z);
+                const float4 S0 = scr[2 * a_], S1 = scr[2 * a_ + 1];
+                // max(dot, -sin Psi) as a median with +inf (no operand canonicalisation)
+                const float d = __builtin_amdgcn_fmed3f(fmaf(S0.x, vm.x, fmaf(S0.y, vm.y, S0.z * vm.z)), S1.z, INFINITY);
                 const float rhs = fmaf(-S1.y, vc.y, fmaf(-S1.x, vc.x, S0.w - vm.w));
                 return !(d <= rhs);
             };
@@ -1176,7 +1179,7 @@ size_t s11_lds_bytes(int maxM, int waves)
 }
 size_t s12_lds_bytes(int maxM, int maxN, int waves, bool vlds)
 {
-    return sizeof(float4) * ((kG + 1) * (size_t)maxM + (vlds ? 2 * (size_t)maxN : 0)) +
+    return sizeof(float4) * ((kG12 + 2) * (size_t)maxM + (vlds ? 2 * (size_t)maxN : 0)) +
            sizeof(uint32_t) * kList * (size_t)waves;
 }
 
