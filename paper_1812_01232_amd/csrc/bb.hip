@@ -163,8 +163,17 @@ struct Bufs {
     uint32_t *cpid, *cpar;        // problem and parent slot of each child
     int64_t *ctidx;
     uint8_t *cskip;
+    // translation cells of the iteration's children: a hash table of
+    // 2^tbits slots per problem (key or kEmptyCell), one slot per distinct
+    // cell, so parents that share a translation cell share its S11 sums
     uint64_t *tcells;
-    uint32_t *tpid;
+    uint32_t *tpid;               // problem of each slot (fixed)
+    uint32_t tbits;
+    // the distinct cells of the iteration, compacted (g->ntcell of them):
+    // key, problem and table slot (where their S11 sums are stored)
+    uint64_t *ckey;
+    uint32_t *cpid2;
+    int64_t *cslot;
     double *cub, *clb, *clbs;
     uint8_t *cflags;
     double *s11ub, *s11lo;
@@ -542,6 +551,74 @@ __global__ __launch_bounds__(kBlock) void k_select_compact(Bufs b)
     if (threadIdx.x == 0 && mh < INFINITY) atomicMin(&s.minH, ord64(mh));
 }
 
+// The table slot of translation cell `key` of problem p: linear probing from
+// a multiplicative hash; the first thread to claim an empty slot stores the
+// key, later ones find it.  At most half of a problem's slots are ever used
+// (8 k children), so the probe ends well within the table.
+__device__ __forceinline__ uint32_t cell_slot(const Bufs &b, uint32_t p, uint64_t key, bool &claimed)
+{
+    const uint32_t mask = (1u << b.tbits) - 1u;
+    unsigned long long *tab = (unsigned long long *)(b.tcells + ((size_t)p << b.tbits));
+    uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - b.tbits));
+    claimed = false;
+    for (uint32_t probe = 0; probe <= mask; ++probe, h = (h + 1u) & mask) {
+        const unsigned long long cur = tab[h];
+        if (cur == key) return h;
+        if (cur != kEmptyCell) continue;
+        const unsigned long long prev = atomicCAS(&tab[h], (unsigned long long)kEmptyCell, (unsigned long long)key);
+        claimed = prev == kEmptyCell;
+        if (claimed || prev == key) return h;
+    }
+    return 0xffffffffu;
+}
+
+// Each child's translation cell in the table (one thread per child).
+__global__ __launch_bounds__(kBlock) void k_child_cells(Bufs b)
+{
+    // the thread that claims a slot lists the cell (one atomic per wave)
+    const uint32_t n = b.g->nchild;
+    const int lane = threadIdx.x & 63;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        bool claimed = false;
+        uint32_t p = 0;
+        int64_t at = 0;
+        if (i < n) {
+            p = b.cpid[i];
+            uint32_t slot = cell_slot(b, p, b.ctk[i], claimed);
+            if (slot == 0xffffffffu) {   // cannot happen (see cell_slot); keep the index in range
+                b.st[p].overflow = 1;
+                slot = 0;
+                claimed = false;
+            }
+            at = (int64_t)(((size_t)p << b.tbits) + slot);
+            b.ctidx[i] = at;
+        }
+        const unsigned long long m = __ballot(claimed);
+        if (!m) continue;
+        const int leader = __ffsll((long long)m) - 1;
+        uint32_t first = 0;
+        if (lane == leader) first = atomicAdd(&b.g->ntcell, (uint32_t)__popcll(m));
+        first = __shfl(first, leader, 64);
+        if (claimed) {
+            const uint32_t j = first + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            b.ckey[j] = b.ctk[i];
+            b.cpid2[j] = p;
+            b.cslot[j] = at;
+        }
+    }
+}
+
+// Every slot of the cell table empty, and its problem index (once per solve).
+__global__ void k_cells_init(Bufs b, int P)
+{
+    const size_t n = (size_t)P << b.tbits;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        b.tcells[i] = kEmptyCell;
+        b.tpid[i] = (uint32_t)(i >> b.tbits);
+    }
+}
+
 // 8 children per parent, all problems appended to one list.  A rotation split
 // shares its parent's translation cell among the 8 children.
 __global__ __launch_bounds__(kBlock) void k_branch(Bufs b)
@@ -567,7 +644,6 @@ __global__ __launch_bounds__(kBlock) void k_branch(Bufs b)
         }
         const bool one = rot || skip;
         const uint32_t c0 = block_reserve(&b.g->nchild, valid ? 8u : 0u);
-        const uint32_t t0 = block_reserve(&b.g->ntcell, valid ? (one ? 1u : 8u) : 0u);
         if (!valid) continue;
         b.pchild[(size_t)p * b.k + i] = c0;
         for (int c = 0; c < 8; ++c) {
@@ -578,15 +654,6 @@ __global__ __launch_bounds__(kBlock) void k_branch(Bufs b)
             b.cpid[ci] = (uint32_t)p;
             b.cpar[ci] = (uint32_t)p * b.k + i;
             b.cskip[ci] = skip;
-            b.ctidx[ci] = one ? t0 : t0 + c;
-            if (!one) {
-                b.tcells[t0 + c] = ck;
-                b.tpid[t0 + c] = (uint32_t)p;
-            }
-        }
-        if (one) {
-            b.tcells[t0] = tk;
-            b.tpid[t0] = (uint32_t)p;
         }
     }
 }
@@ -594,8 +661,18 @@ __global__ __launch_bounds__(kBlock) void k_branch(Bufs b)
 // Queue the children whose raised, margined lower bound is below d*.  Slots
 // are reserved per wavefront and target (problem, hot or cold): one atomic
 // per distinct target in the wave instead of one per child.
-__global__ __launch_bounds__(kBlock) void k_push(Bufs b, const float *prio_override)
+// The cell table is emptied here for the next iteration (its S11 sums have
+// been read by the bound kernels).
+__device__ __forceinline__ void clear_cells(const Bufs &b, int P)
 {
+    const size_t n = (size_t)P << b.tbits;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b.tcells[i] = kEmptyCell;
+}
+
+__global__ __launch_bounds__(kBlock) void k_push(Bufs b, const float *prio_override, int P)
+{
+    clear_cells(b, P);
     const uint32_t n = b.g->nchild;
     const int lane = threadIdx.x & 63;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
@@ -677,6 +754,7 @@ __global__ __launch_bounds__(kBlock) void k_push_agg(Bufs b, const float *prio_o
 {
     __shared__ uint32_t cnt[2 * kPushAggProblems], base[2 * kPushAggProblems];
     __shared__ unsigned long long mn[2 * kPushAggProblems];
+    clear_cells(b, P);
     const uint32_t n = b.g->nchild;
     const int T = 2 * P;
     for (uint32_t start = blockIdx.x * blockDim.x; start < n; start += gridDim.x * blockDim.x) {
@@ -994,6 +1072,9 @@ void free_solver(Solver *s)
     dfree(b.cskip);
     dfree(b.tcells);
     dfree(b.tpid);
+    dfree(b.ckey);
+    dfree(b.cpid2);
+    dfree(b.cslot);
     dfree(b.cub);
     dfree(b.clb);
     dfree(b.clbs);
@@ -1044,14 +1125,21 @@ hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap, b
     if (!e) e = dalloc(b.cpar, nc);
     if (!e) e = dalloc(b.ctidx, nc);
     if (!e) e = dalloc(b.cskip, nc);
-    if (!e) e = dalloc(b.tcells, nc);
-    if (!e) e = dalloc(b.tpid, nc);
+    // cell table: 2^tbits >= 16 k slots per problem (at most 8 k used)
+    uint32_t tbits = 4;
+    while (((size_t)1 << tbits) < 16 * k) ++tbits;
+    const size_t nt = (size_t)P << tbits;
+    if (!e) e = dalloc(b.tcells, nt);
+    if (!e) e = dalloc(b.tpid, nt);
+    if (!e) e = dalloc(b.ckey, nc);
+    if (!e) e = dalloc(b.cpid2, nc);
+    if (!e) e = dalloc(b.cslot, nc);
     if (!e) e = dalloc(b.cub, nc);
     if (!e) e = dalloc(b.clb, nc);
     if (!e) e = dalloc(b.clbs, nc);
     if (!e) e = dalloc(b.cflags, nc);
-    if (!e) e = dalloc(b.s11ub, nc);
-    if (!e) e = dalloc(b.s11lo, nc);
+    if (!e) e = dalloc(b.s11ub, std::max(nt, nc));
+    if (!e) e = dalloc(b.s11lo, std::max(nt, nc));
     if (!e) e = dalloc(b.csetup, nc);
     if (!e) e = dalloc(b.hist, (size_t)gosma::kHistBins * P);
     if (!e) e = dalloc(b.st, (size_t)P);
@@ -1066,6 +1154,7 @@ hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap, b
     b.hcap = (uint32_t)hcap;
     b.ccap = (uint32_t)ccap;
     b.k = (uint32_t)k;
+    b.tbits = tbits;
     s->payload = payload;
     s->P = P;
     s->k = k;
@@ -1117,11 +1206,13 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     T1(ti);
     ti = T0(GOSMA_KERNEL_BRANCH);
     hipLaunchKernelGGL(k_branch, dim3(std::max(1, gx / 4), P), dim3(kBlock), 0, st, b);
+    hipLaunchKernelGGL(k_child_cells, dim3((unsigned)std::max<size_t>(1, std::min<size_t>((8 * (size_t)b.k * P + kBlock - 1) / kBlock, 8192))),
+                       dim3(kBlock), 0, st, b);
     T1(ti);
     const int64_t maxc = 8 * (int64_t)S.k * P;
     ti = T0(GOSMA_KERNEL_S11);
-    hipError_t e = launch_s11(mx, b.tcells, b.tpid, maxc, &b.g->ntcell, S11Out{b.s11ub, b.s11lo}, ctx->maxM,
-                              ctx->tile11, st);
+    hipError_t e = launch_s11(mx, b.ckey, b.cpid2, maxc, &b.g->ntcell, S11Out{b.s11ub, b.s11lo}, ctx->maxM,
+                              ctx->tile11, st, b.cslot);
     T1(ti);
     if (e) return e;
     ti = T0(GOSMA_KERNEL_S12);
@@ -1149,7 +1240,7 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
         if (P <= kPushAggProblems)
             hipLaunchKernelGGL(k_push_agg, dim3(gp), dim3(kBlock), 0, st, b, po, P);
         else
-            hipLaunchKernelGGL(k_push, dim3(kGridX), dim3(kBlock), 0, st, b, po);
+            hipLaunchKernelGGL(k_push, dim3(kGridX), dim3(kBlock), 0, st, b, po, P);
     }
     hipLaunchKernelGGL(k_iter_end, dim3((P + 63) / 64), dim3(64), 0, st, b, P, rb_every);
     T1(ti);
@@ -1278,6 +1369,13 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         return fail(GOSMA_E_NOMEM, "allocating solver buffers", e);
     Bufs &b = S.b;
     b.prob = ctx->d_prob;
+    {
+        // an empty cell table (the pushes of every iteration empty it again)
+        const size_t nt = (size_t)P << b.tbits;
+        hipLaunchKernelGGL(k_cells_init, dim3((unsigned)std::min<size_t>((nt + kBlock - 1) / kBlock, 4096)),
+                           dim3(kBlock), 0, S.stream, b, P);
+        if ((e = hipGetLastError())) return fail(GOSMA_E_HIP, "cell table", e);
+    }
     b.rec = ctx->rec_sink;
     b.rec_count = ctx->rec_count;
     b.rec_cap = (uint64_t)ctx->rec_cap;

@@ -436,7 +436,8 @@ __device__ __forceinline__ void s11_pair(const float4 *__restrict__ rec, int a_,
 
 __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_t *__restrict__ tkeys,
                                                          const uint32_t *__restrict__ pids, int64_t nt_host,
-                                                         const uint32_t *__restrict__ nt_dev, S11Out out, int maxM)
+                                                         const uint32_t *__restrict__ nt_dev, S11Out out, int maxM,
+                                                         const int64_t *__restrict__ out_idx)
 {
     extern __shared__ float4 lds4[];
     __shared__ BlockShared sh;
@@ -447,11 +448,12 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
     const int64_t nt = nt_dev ? (int64_t)nt_dev[0] : nt_host;
     for (int64_t cell = blockIdx.x; cell < nt; cell += gridDim.x) {
         __syncthreads();
+        const int64_t o = out_idx ? out_idx[cell] : cell;   // where the cell's sums go
         const uint32_t pid = pids ? pids[cell] : 0u;
         if (pid >= (uint32_t)mx.n_prob) {     // invalid problem index: no bound
             if (tid == 0) {
-                out.ub[cell] = NAN;
-                out.lo[cell] = NAN;
+                out.ub[o] = NAN;
+                out.lo[o] = NAN;
             }
             continue;
         }
@@ -501,8 +503,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
         }
         if (drop) {
             if (tid == 0) {
-                out.ub[cell] = INFINITY;
-                out.lo[cell] = INFINITY;
+                out.ub[o] = INFINITY;
+                out.lo[o] = INFINITY;
             }
             continue;
         }
@@ -642,8 +644,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
                 su += sh.s0[w];
                 sl += sh.s1[w];
             }
-            out.ub[cell] = ubinf ? INFINITY : su;
-            out.lo[cell] = sl;
+            out.ub[o] = ubinf ? INFINITY : su;
+            out.lo[o] = sl;
         }
     }
 }
@@ -1199,13 +1201,13 @@ hipError_t prepare_bound_kernels(int maxM, int maxN)
 static bool tile_ok(const Tile &t) { return t.waves >= 1 && t.waves <= kMaxWaves && t.blocks >= 1; }
 
 hipError_t launch_s11(const DevMix &mx, const uint64_t *tkeys, const uint32_t *pids, int64_t nt, const uint32_t *nt_dev,
-                      S11Out out, int maxM, Tile tile, hipStream_t stream)
+                      S11Out out, int maxM, Tile tile, hipStream_t stream, const int64_t *out_idx)
 {
     if (nt <= 0) return hipSuccess;
     if (!tile_ok(tile)) return hipErrorInvalidValue;
     const unsigned g = (unsigned)std::min<int64_t>(tile.blocks, nt);
     hipLaunchKernelGGL(k_s11, dim3(g), dim3(64 * tile.waves), s11_lds_bytes(maxM, tile.waves), stream, mx, tkeys,
-                       pids, nt, nt_dev, out, maxM);
+                       pids, nt, nt_dev, out, maxM, out_idx);
     return hipGetLastError();
 }
 

@@ -60,6 +60,10 @@ struct BoundOut {
 };
 constexpr int kCountSlots = 64;
 
+// A translation-cell key no cell has (the level field of real keys is at most 19).
+constexpr uint64_t kEmptyCell = ~0ull;
+// launch_s11's out_idx: NULL writes cell c's sums at index c, otherwise at out_idx[c].
+
 struct S11Out {
     double *ub, *lo;   // S11 at the centre and its lower bound, per translation cube
 };
@@ -93,7 +97,7 @@ struct Tile {
 // memory (times n_dev_mul); the host count is then the maximum.  Each launch
 // runs min(tile.blocks, count) blocks of 64 * tile.waves threads.
 hipError_t launch_s11(const DevMix &mx, const uint64_t *tkeys, const uint32_t *pids, int64_t nt, const uint32_t *nt_dev,
-                      S11Out out, int maxM, Tile tile, hipStream_t stream);
+                      S11Out out, int maxM, Tile tile, hipStream_t stream, const int64_t *out_idx = nullptr);
 hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                       const int64_t *tidx, const double *s11ub, const double *s11lo, int64_t n, const uint32_t *n_dev,
                       int n_dev_mul, BoundOut out, double margin_gamma, int maxM, int maxN, bool with_top8, Tile tile,
