@@ -551,64 +551,6 @@ __global__ __launch_bounds__(kBlock) void k_select_compact(Bufs b)
     if (threadIdx.x == 0 && mh < INFINITY) atomicMin(&s.minH, ord64(mh));
 }
 
-// The table slot of translation cell `key` of problem p: linear probing from
-// a multiplicative hash; the first thread to claim an empty slot stores the
-// key, later ones find it.  At most half of a problem's slots are ever used
-// (8 k children), so the probe ends well within the table.
-__device__ __forceinline__ uint32_t cell_slot(const Bufs &b, uint32_t p, uint64_t key, bool &claimed)
-{
-    const uint32_t mask = (1u << b.tbits) - 1u;
-    unsigned long long *tab = (unsigned long long *)(b.tcells + ((size_t)p << b.tbits));
-    uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - b.tbits));
-    claimed = false;
-    for (uint32_t probe = 0; probe <= mask; ++probe, h = (h + 1u) & mask) {
-        const unsigned long long cur = tab[h];
-        if (cur == key) return h;
-        if (cur != kEmptyCell) continue;
-        const unsigned long long prev = atomicCAS(&tab[h], (unsigned long long)kEmptyCell, (unsigned long long)key);
-        claimed = prev == kEmptyCell;
-        if (claimed || prev == key) return h;
-    }
-    return 0xffffffffu;
-}
-
-// Each child's translation cell in the table (one thread per child).
-__global__ __launch_bounds__(kBlock) void k_child_cells(Bufs b)
-{
-    // the thread that claims a slot lists the cell (one atomic per wave)
-    const uint32_t n = b.g->nchild;
-    const int lane = threadIdx.x & 63;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-        const uint32_t i = base + threadIdx.x;
-        bool claimed = false;
-        uint32_t p = 0;
-        int64_t at = 0;
-        if (i < n) {
-            p = b.cpid[i];
-            uint32_t slot = cell_slot(b, p, b.ctk[i], claimed);
-            if (slot == 0xffffffffu) {   // cannot happen (see cell_slot); keep the index in range
-                b.st[p].overflow = 1;
-                slot = 0;
-                claimed = false;
-            }
-            at = (int64_t)(((size_t)p << b.tbits) + slot);
-            b.ctidx[i] = at;
-        }
-        const unsigned long long m = __ballot(claimed);
-        if (!m) continue;
-        const int leader = __ffsll((long long)m) - 1;
-        uint32_t first = 0;
-        if (lane == leader) first = atomicAdd(&b.g->ntcell, (uint32_t)__popcll(m));
-        first = __shfl(first, leader, 64);
-        if (claimed) {
-            const uint32_t j = first + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            b.ckey[j] = b.ctk[i];
-            b.cpid2[j] = p;
-            b.cslot[j] = at;
-        }
-    }
-}
-
 // Every slot of the cell table empty, and its problem index (once per solve).
 __global__ void k_cells_init(Bufs b, int P)
 {
@@ -1206,10 +1148,15 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     T1(ti);
     ti = T0(GOSMA_KERNEL_BRANCH);
     hipLaunchKernelGGL(k_branch, dim3(std::max(1, gx / 4), P), dim3(kBlock), 0, st, b);
-    hipLaunchKernelGGL(k_child_cells, dim3((unsigned)std::max<size_t>(1, std::min<size_t>((8 * (size_t)b.k * P + kBlock - 1) / kBlock, 8192))),
-                       dim3(kBlock), 0, st, b);
-    T1(ti);
     const int64_t maxc = 8 * (int64_t)S.k * P;
+    // the children's set-up records and their translation cells (table slots,
+    // and the list of distinct cells that k_s11 evaluates)
+    {
+        const CellTable cells{b.tcells, b.tbits, b.ctidx, b.ckey, b.cpid2, b.cslot, &b.g->ntcell};
+        hipError_t ce = launch_cube_setup(mx, b.crk, b.ctk, b.cpid, maxc, &b.g->nchild, 1, b.csetup, &cells, st);
+        if (ce) return ce;
+    }
+    T1(ti);
     ti = T0(GOSMA_KERNEL_S11);
     hipError_t e = launch_s11(mx, b.ckey, b.cpid2, maxc, &b.g->ntcell, S11Out{b.s11ub, b.s11lo}, ctx->maxM,
                               ctx->tile11, st, b.cslot);
@@ -1220,7 +1167,7 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     BoundOut bo{b.cub, b.clb, b.clbs, nullptr, b.cflags, top8 ? b.ctop8 : nullptr, nullptr, &b.st->dstar,
                 (int)(sizeof(PState) / sizeof(unsigned long long)), timed ? ctx->d_pairs : nullptr};
     e = launch_s12(mx, b.crk, b.ctk, b.cpid, b.ctidx, b.s11ub, b.s11lo, maxc, &b.g->nchild, 1, bo, kMarginGamma,
-                   ctx->maxM, ctx->maxN, top8, ctx->tile12, b.csetup, st);
+                   ctx->maxM, ctx->maxN, top8, ctx->tile12, b.csetup, st, true);
     T1(ti);
     if (e) return e;
     if (logging) hipLaunchKernelGGL(k_log_records, dim3(std::max(1, gx / 8), P), dim3(kBlock), 0, st, b, P);

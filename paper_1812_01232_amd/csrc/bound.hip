@@ -755,53 +755,101 @@ __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, const f
 // Per-cube set-up of k_s12 (one thread per cube): the two cells, the rotation
 // matrix and, for Lemma 2 per direction (reading in k_s12 below), the left
 // Jacobian applied to four corners of the rotation cell's half-width box.
+// The slot of translation cell `key` in its problem's part of the cell table
+// (2^tbits slots): linear probing from a multiplicative hash; the first
+// thread to claim an empty slot stores the key (claimed), later ones find it.
+// At most half of a problem's slots are ever used, so a free or matching slot
+// is always found within the table.
+__device__ __forceinline__ uint32_t cell_slot(unsigned long long *tab, uint32_t tbits, uint64_t key, bool &claimed)
+{
+    const uint32_t mask = (1u << tbits) - 1u;
+    uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - tbits));
+    claimed = false;
+    for (uint32_t probe = 0; probe <= mask; ++probe, h = (h + 1u) & mask) {
+        const unsigned long long cur = tab[h];
+        if (cur == key) return h;
+        if (cur != kEmptyCell) continue;
+        const unsigned long long prev = atomicCAS(&tab[h], (unsigned long long)kEmptyCell, (unsigned long long)key);
+        claimed = prev == kEmptyCell;
+        if (claimed || prev == key) return h;
+    }
+    return 0;   // not reached (see above)
+}
+
 __global__ __launch_bounds__(256) void k_cube_setup(DevMix mx, const uint64_t *__restrict__ rkeys,
                                                     const uint64_t *__restrict__ tkeys,
                                                     const uint32_t *__restrict__ pids, int64_t n_host,
                                                     const uint32_t *__restrict__ n_dev, int n_dev_mul,
-                                                    CubeSetup *__restrict__ out)
+                                                    CubeSetup *__restrict__ out, CellTable cells)
 {
     const int64_t n = n_dev ? (int64_t)n_dev[0] * n_dev_mul : n_host;
-    for (int64_t cube = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cube < n;
-         cube += (int64_t)gridDim.x * blockDim.x) {
-        CubeSetup cs;
-        const uint32_t pid = pids ? pids[cube] : 0u;
-        if (pid >= (uint32_t)mx.n_prob) {
-            cs = CubeSetup{};
-            cs.flags = kSetupInvalid;
-            out[cube] = cs;
-            continue;
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t cube = base + threadIdx.x;
+        bool claimed = false;
+        uint32_t pid = 0;
+        int64_t at = 0;
+        if (cube < n) {
+            CubeSetup cs;
+            pid = pids ? pids[cube] : 0u;
+            if (pid >= (uint32_t)mx.n_prob) {
+                cs = CubeSetup{};
+                cs.flags = kSetupInvalid;
+                out[cube] = cs;
+            } else {
+                const ProbDesc &P = mx.prob[pid];
+                double r0[3], hr[3];
+                decode_key(rkeys[cube], P.r_lo, P.r_w, r0, hr);
+                decode_key(tkeys[cube], P.t_lo, P.t_w, cs.t0, cs.tau);
+                const double hn = sqrt(hr[0] * hr[0] + hr[1] * hr[1] + hr[2] * hr[2]);
+                cs.hn = (float)hn;
+                cs.cap = fminf(cs.hn, (float)kPi);
+                const double rr = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
+                uint32_t flags = sqrt(rr) + hn <= 5.5 ? kSetupPerDir : 0u;
+                double ja, jb;
+                rotation_matrix(r0, cs.R, &ja, &jb);
+                for (int q = 0; q < 4; ++q) {
+                    const double d[3] = {hr[0], (q & 2) ? -hr[1] : hr[1], (q & 1) ? -hr[2] : hr[2]};
+                    // J d = d + a (r x d) + b (r (r . d) - |r|^2 d)
+                    const double x[3] = {r0[1] * d[2] - r0[2] * d[1], r0[2] * d[0] - r0[0] * d[2],
+                                         r0[0] * d[1] - r0[1] * d[0]};
+                    const double rd = r0[0] * d[0] + r0[1] * d[1] + r0[2] * d[2];
+                    for (int k = 0; k < 3; ++k)
+                        cs.jc[q][k] = (float)(d[k] + ja * x[k] + jb * (r0[k] * rd - rr * d[k]));
+                }
+                // rotation cells with no point in the radius-pi ball hold no rotation
+                double nr2 = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    const double lo = r0[k] - hr[k], hi = r0[k] + hr[k];
+                    const double nk = lo > 0.0 ? lo : (hi < 0.0 ? hi : 0.0);
+                    nr2 += nk * nk;
+                }
+                if (nr2 > kPi * kPi) flags |= GOSMA_FLAG_DROP_ROT;
+                cs.flags = flags;
+                cs.pad = 0;
+                out[cube] = cs;
+                if (cells.keys) {
+                    // the cube's translation cell in the table
+                    unsigned long long *tab = (unsigned long long *)(cells.keys + ((size_t)pid << cells.tbits));
+                    at = (int64_t)(((size_t)pid << cells.tbits) + cell_slot(tab, cells.tbits, tkeys[cube], claimed));
+                    cells.ctidx[cube] = at;
+                }
+            }
         }
-        const ProbDesc &P = mx.prob[pid];
-        double r0[3], hr[3];
-        decode_key(rkeys[cube], P.r_lo, P.r_w, r0, hr);
-        decode_key(tkeys[cube], P.t_lo, P.t_w, cs.t0, cs.tau);
-        const double hn = sqrt(hr[0] * hr[0] + hr[1] * hr[1] + hr[2] * hr[2]);
-        cs.hn = (float)hn;
-        cs.cap = fminf(cs.hn, (float)kPi);
-        const double rr = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
-        uint32_t flags = sqrt(rr) + hn <= 5.5 ? kSetupPerDir : 0u;
-        double ja, jb;
-        rotation_matrix(r0, cs.R, &ja, &jb);
-        for (int q = 0; q < 4; ++q) {
-            const double d[3] = {hr[0], (q & 2) ? -hr[1] : hr[1], (q & 1) ? -hr[2] : hr[2]};
-            // J d = d + a (r x d) + b (r (r . d) - |r|^2 d)
-            const double x[3] = {r0[1] * d[2] - r0[2] * d[1], r0[2] * d[0] - r0[0] * d[2],
-                                 r0[0] * d[1] - r0[1] * d[0]};
-            const double rd = r0[0] * d[0] + r0[1] * d[1] + r0[2] * d[2];
-            for (int k = 0; k < 3; ++k) cs.jc[q][k] = (float)(d[k] + ja * x[k] + jb * (r0[k] * rd - rr * d[k]));
+        if (!cells.keys) continue;
+        // the claiming thread lists the cell (one atomic per wave)
+        const unsigned long long m = __ballot(claimed);
+        if (!m) continue;
+        const int leader = __ffsll((long long)m) - 1;
+        uint32_t first = 0;
+        if (lane == leader) first = atomicAdd(cells.count, (uint32_t)__popcll(m));
+        first = __shfl(first, leader, 64);
+        if (claimed) {
+            const uint32_t j = first + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            cells.list_key[j] = tkeys[cube];
+            cells.list_pid[j] = pid;
+            cells.list_slot[j] = at;
         }
-        // rotation cells with no point in the radius-pi ball hold no rotation
-        double nr2 = 0.0;
-        for (int k = 0; k < 3; ++k) {
-            const double lo = r0[k] - hr[k], hi = r0[k] + hr[k];
-            const double nk = lo > 0.0 ? lo : (hi < 0.0 ? hi : 0.0);
-            nr2 += nk * nk;
-        }
-        if (nr2 > kPi * kPi) flags |= GOSMA_FLAG_DROP_ROT;
-        cs.flags = flags;
-        cs.pad = 0;
-        out[cube] = cs;
     }
 }
 
@@ -1211,17 +1259,27 @@ hipError_t launch_s11(const DevMix &mx, const uint64_t *tkeys, const uint32_t *p
     return hipGetLastError();
 }
 
+hipError_t launch_cube_setup(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
+                             int64_t n, const uint32_t *n_dev, int n_dev_mul, CubeSetup *setup, const CellTable *cells,
+                             hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const unsigned gs = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_cube_setup, dim3(gs), dim3(256), 0, stream, mx, rkeys, tkeys, pids, n, n_dev, n_dev_mul, setup,
+                       cells ? *cells : CellTable{});
+    return hipGetLastError();
+}
+
 hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                       const int64_t *tidx, const double *s11ub, const double *s11lo, int64_t n, const uint32_t *n_dev,
                       int n_dev_mul, BoundOut out, double margin_gamma, int maxM, int maxN, bool with_top8, Tile tile,
-                      CubeSetup *setup, hipStream_t stream)
+                      CubeSetup *setup, hipStream_t stream, bool setup_done)
 {
     if (n <= 0) return hipSuccess;
     if (!tile_ok(tile) || !setup) return hipErrorInvalidValue;
-    {
-        const unsigned gs = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
-        hipLaunchKernelGGL(k_cube_setup, dim3(gs), dim3(256), 0, stream, mx, rkeys, tkeys, pids, n, n_dev, n_dev_mul,
-                           setup);
+    if (!setup_done) {
+        hipError_t e = launch_cube_setup(mx, rkeys, tkeys, pids, n, n_dev, n_dev_mul, setup, nullptr, stream);
+        if (e) return e;
     }
     const bool vlds = mx.n_prob > 1;   // see kG
     const size_t lds = s12_lds_bytes(maxM, maxN, tile.waves, vlds);

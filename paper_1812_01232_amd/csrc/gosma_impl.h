@@ -64,6 +64,20 @@ constexpr int kCountSlots = 64;
 constexpr uint64_t kEmptyCell = ~0ull;
 // launch_s11's out_idx: NULL writes cell c's sums at index c, otherwise at out_idx[c].
 
+// The translation cells of a batch of cubes, deduplicated (the search's cell
+// table): 2^tbits slots per problem holding a cell key or kEmptyCell.  The
+// set-up pass stores each cube's slot (ctidx, global index) and lists every
+// newly claimed cell once (key, problem, slot; count is the list length).
+struct CellTable {
+    uint64_t *keys;
+    uint32_t tbits;
+    int64_t *ctidx;
+    uint64_t *list_key;
+    uint32_t *list_pid;
+    int64_t *list_slot;
+    uint32_t *count;
+};
+
 struct S11Out {
     double *ub, *lo;   // S11 at the centre and its lower bound, per translation cube
 };
@@ -101,7 +115,11 @@ hipError_t launch_s11(const DevMix &mx, const uint64_t *tkeys, const uint32_t *p
 hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                       const int64_t *tidx, const double *s11ub, const double *s11lo, int64_t n, const uint32_t *n_dev,
                       int n_dev_mul, BoundOut out, double margin_gamma, int maxM, int maxN, bool with_top8, Tile tile,
-                      CubeSetup *setup, hipStream_t stream);
+                      CubeSetup *setup, hipStream_t stream, bool setup_done = false);
+// The per-cube set-up pass of k_s12 (and, with cells, the cubes' translation cells).
+hipError_t launch_cube_setup(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
+                             int64_t n, const uint32_t *n_dev, int n_dev_mul, CubeSetup *setup, const CellTable *cells,
+                             hipStream_t stream);
 // Dynamic LDS of the two kernels (the pair kernel's grows with the waves per
 // block), and the per-kernel limit setup for it.
 size_t s11_lds_bytes(int maxM, int waves);
