@@ -364,19 +364,21 @@ static double g_da(double a, double b, double th)
  *   L(K) K_aa <= min(1/3, b^2 sin^2(theta) / K^3)  (as L(K) <= K/3, K >= b sin theta),
  * and the Hessian of log Z(K(a, b)) is positive semi-definite (K is a norm
  * of a linear function of (a, b) and log Z(K) is increasing and convex in
- * K^2), so the Hessian of g is at least -max(L'(a), L'(b)) I. */
+ * K^2).  The other two terms of g are separable, -log Z(a) and -log Z(b), so
+ * the Hessian of g is at least diag(-L'(a), -L'(b)). */
 
 /* S11 summand, i != i' (eq. 21, first sum), at angle A: a lower bound on
- * min over a in [alo, ahi], b in [blo, bhi] of g(a, b, A):
- *   g(c) - |g_a| h_a - |g_b| h_b - (lambda/2)(h_a^2 + h_b^2),
- * lambda = max(min(1/3, 1/alo^2), min(1/3, 1/blo^2)). */
+ * min over a in [alo, ahi], b in [blo, bhi] of g(a, b, A), from the expansion
+ * at the box centre c with the Hessian bound above:
+ *   g(c) - |g_a| h_a - |g_b| h_b - (lambda_a h_a^2 + lambda_b h_b^2)/2,
+ * lambda_a = min(1/3, 1/alo^2) >= L'(a) on the interval, lambda_b likewise. */
 static double s11_lower_log(double alo, double ahi, double blo, double bhi, double A)
 {
     double ac = 0.5 * (alo + ahi), ha = 0.5 * (ahi - alo);
     double bc = 0.5 * (blo + bhi), hb = 0.5 * (bhi - blo);
-    double lam = fmax(fmin(1.0 / 3.0, 1.0 / (alo * alo)), fmin(1.0 / 3.0, 1.0 / (blo * blo)));
+    double lam_a = fmin(1.0 / 3.0, 1.0 / (alo * alo)), lam_b = fmin(1.0 / 3.0, 1.0 / (blo * blo));
     return g_term(ac, bc, A) - fabs(g_da(ac, bc, A)) * ha - fabs(g_da(bc, ac, A)) * hb -
-           0.5 * lam * (ha * ha + hb * hb);
+           0.5 * (lam_a * ha * ha + lam_b * hb * hb);
 }
 
 /* S12 summand (eq. 21, second sum) at angle B with b = kappa_2j fixed: the
