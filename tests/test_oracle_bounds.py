@@ -186,20 +186,6 @@ def test_cube_status_edge_cases():
     assert P.bounds([touching], [0])["status"][0] == 0
 
 
-def test_top8_are_the_largest_pair_terms():
-    sc = scenes.cfg1_scene(0)
-    P = oracle.OracleProblem(sc)
-    rk, tk = scenes.random_cubes(sc, 20, 77)
-    b = P.bounds(rk, tk)
-    for q in range(20):
-        if b["status"][q] != 0 or not math.isfinite(b["ub"][q]):
-            continue
-        top = b["top8"][q]
-        assert np.all(np.diff(top) <= 0)
-        assert top.sum() <= b["s12_ub"][q] * (1 + 1e-12)
-        assert top[0] >= b["s12_ub"][q] / (sc.M * sc.N)
-
-
 def test_pair_screen_inequality_implies_negligible_summand():
     """The GMM-vMF pair screen of the bound kernel, written out on the CPU: a
     pair is dropped when max(d cos Psi, -sin Psi) <= (1 - sin Psi - Lam/alo)
