@@ -14,12 +14,13 @@ branch, bound every child (translation-cell sums, GMM-vMF sums, both bounds
 of Theorem 1), update d*, prune and push.  `value` = cubes bounded per second
 over K steps after W warmup steps of the same search, inputs resident in HBM.
 
-Also reported: the bound kernels alone on a 32,768-cube batch, with the
-roofline of the dominant kernel (GMM-vMF pair sums) from its HIP-event launch
-times and the op model below; the FP64 CPU oracle's own search rate on
-the host's cores; time to eps on the 16 x 16 scene; and time to eps on fresh
-64 x 64 scenes with plain and learned queue order (network trained on records
-logged by the search itself).
+Also reported: the roofline of the dominant kernel (GMM-vMF pair sums and
+bounds) from its HIP-event launch times in the search and the operation
+counts of the bound formulas; the bound kernels alone on a 32,768-cube batch;
+the FP64 CPU oracle's bound rate on a sample of the same batch with all host
+cores and with one; time to eps on the 16 x 16 scene; and time to eps on
+fresh 64 x 64 scenes with plain and learned queue order (network trained on
+records logged by the search itself).
 """
 from __future__ import annotations
 
@@ -34,25 +35,47 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Op model of the GMM-vMF pair kernel, counted from its source.  A plain FP32
-# or FP64 operation takes one issue slot per lane (the FP64 vector peak,
-# 78.6 TFLOP/s, is one FMA per lane per clock, like unpacked FP32); a
-# transcendental (sqrt, rcp, exp2, log2) issues at half that rate on gfx950
-# (measured 1.8-1.9 plain-op slots), so it counts 2.
-#   per component and cube (the set-up of Lemmas 2-3 and of the kappa
-#   interval): 54 FP64 + 409 plain FP32 + 17 transcendentals;
-#   per same-class pair screened: 7 plain (a dot product, three threshold
-#   terms, a compare);
-#   per pair evaluated in full: 125 plain + 14 transcendentals.
-TRANS_SLOTS, FP64_SLOTS = 2, 1
-PREP_SLOTS = 54 * FP64_SLOTS + 409 + 17 * TRANS_SLOTS
-PREP_FLOPS = 54 + 409 + 17
-SCREEN_SLOTS, SCREEN_FLOPS = 7, 7 + 4      # 4 of the screen's operations are FMAs
-S12_PLAIN, S12_TRANS = 125, 14
-S12_SLOTS = S12_PLAIN + TRANS_SLOTS * S12_TRANS
-S12_FLOPS = S12_PLAIN + S12_TRANS + 13      # 13 of the plain operations are FMAs
+# Operation counts of the bound formulas (profiles/opcount.md, checked by
+# tests/test_opcount.py): (plain ops, FMAs among them, transcendentals) per
+# work unit.  FLOPs count an FMA as 2; issue slots count a plain op as one
+# slot per lane and a transcendental as TRANS_SLOTS (measured 1.8-1.9 on
+# gfx950, so 2; the survey's weight of 4 is reported beside).
+OPS = {
+    "PAIR12": (100, 15, 15),     # GMM-vMF pair evaluated: UB term (eq. 12) + upper term over the cube (eq. 25, R3)
+    "SCREEN12": (8, 4, 0),       # GMM-vMF pair screened
+    "PAIR11": (69, 13, 10),      # GMM-GMM pair evaluated: UB term (eq. 11) + lower term (eq. 24, R3)
+    "SCREEN11": (7, 3, 0),       # GMM-GMM pair screened
+    "CUBE": (116, 30, 3),        # per live cube: decode, Rodrigues, Jacobian corners, ball test
+    "ROT_PREP": (72, 22, 5),     # per component and live cube: rotated direction, Lemma 2, screen row
+    "TRANS_PREP": (234, 42, 15), # per component and translation cell: kappa interval, Lemma 3, normalisers
+}
+TRANS_SLOTS = 2
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9            # CUs x SIMDs x lanes x clock
 PEAK_FP32_TFLOPS = 157.3
+
+
+def op_totals(units, trans_slots=TRANS_SLOTS):
+    """(FLOPs, issue slots) of {OPS name: count}."""
+    flops = slots = 0.0
+    for name, n in units.items():
+        plain, fma, trans = OPS[name]
+        flops += n * (plain + fma + trans)
+        slots += n * (plain + trans_slots * trans)
+    return flops, slots
+
+
+def s12_units(w, M):
+    """Algorithmic work of the GMM-vMF kernel for work counts w (one problem of M components)."""
+    return {"CUBE": w["cubes"], "ROT_PREP": w["cubes"] * M, "SCREEN12": w["s12_screened"],
+            "PAIR12": w["s12_evaluated"]}
+
+
+def s11_units(w, M):
+    """Algorithmic work of the GMM-GMM kernel: the translation preparation and the
+    pairs, once per distinct translation cell."""
+    return {"TRANS_PREP": w["cells"] * M, "SCREEN11": w["s11_screened"], "PAIR11": w["s11_evaluated"]}
+
+
 BATCH_PARENTS = 4096
 BATCH = 8 * BATCH_PARENTS
 
@@ -96,10 +119,14 @@ def copy_calibration(mib):
 
 
 def host_cores():
+    """Host cores available to this process: its CPU affinity, capped at the
+    OpenMP thread count the environment sets (the GPU machine's CPU share)."""
     try:
-        return min(16, len(os.sched_getaffinity(0)))
+        n = len(os.sched_getaffinity(0))
     except AttributeError:
-        return min(16, os.cpu_count() or 1)
+        n = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    return min(n, int(omp)) if omp.isdigit() and int(omp) > 0 else n
 
 
 def search_rate(ctx, steps, warmup):
@@ -117,15 +144,15 @@ def search_rate(ctx, steps, warmup):
     dt = b["seconds"] - a["seconds"]
     cubes = b["cubes"] - a["cubes"]
     # per-kernel split of the same iterations (direct launches with HIP events)
-    # and the pair counts of the GMM-vMF sums
+    # and the work counts of the bound kernels
     ctx.get_timing()
-    ctx.get_pair_counts()
+    ctx.get_work_counts()
     ctx.set_timing(True)
     ctx.solve(1e-9, max_iters=total, **kw)
     ctx.set_timing(False)
     kt = ctx.get_timing()
-    pairs = ctx.get_pair_counts()
-    return cubes / dt, dt / steps * 1e3, kt, b, b["max_queue_used"], pairs
+    work = ctx.get_work_counts()
+    return cubes / dt, dt / steps * 1e3, kt, b, b["max_queue_used"], work
 
 
 def other_workload_rates(ctx, warmup=20, steps=40):
@@ -174,7 +201,7 @@ def kernel_rate(ctx, scene, reps):
         ctx.eval_bounds(rk, tk, ub, lb, fl)
     torch.cuda.synchronize()
     ctx.get_timing()
-    ctx.get_pair_counts()
+    ctx.get_work_counts()
     ctx.set_timing(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -185,20 +212,35 @@ def kernel_rate(ctx, scene, reps):
     torch.cuda.synchronize()
     ctx.set_timing(False)
     kt = ctx.get_timing()
-    pairs = ctx.get_pair_counts()
+    work = ctx.get_work_counts()
     live = int(((fl.cpu().numpy() & 6) == 0).sum())
-    return BATCH * reps / (e0.elapsed_time(e1) / 1e3), kt, live, pairs
+    return BATCH * reps / (e0.elapsed_time(e1) / 1e3), kt, live, work, (rk_np, tk_np)
 
 
-def cpu_baseline(scene, budget_s=15.0):
-    """The FP64 oracle's own branch-and-bound on the same scene, bounded in time."""
+def cpu_baseline(scene, rk, tk):
+    """The FP64 oracle's bound evaluation (Theorem 1) on leading cubes of the
+    same 32,768-cube batch the bound-only GPU rate uses: with all host cores,
+    then with one.  Samples are sized for about 10-20 s of CPU work."""
     import oracle
     P = oracle.OracleProblem(scene)
-    cores = host_cores()
-    r = P.solve(1e-9, BATCH_PARENTS, time_limit_s=budget_s, nthreads=cores)
-    return {"value": r["cubes"] / r["seconds"], "unit": "cube-bounds/s", "cores": cores, "kind": "oracle",
-            "sample": f"oracle best-first search on the same 64x64 scene and batch size, stopped after "
-                      f"{r['seconds']:.1f} s ({r['cubes']} cubes, {r['iters']} iterations)"}
+    out = {}
+    for label, cores in (("all", host_cores()), ("one", 1)):
+        # calibrate on a small slice, then time a slice of about 6 s
+        t0 = time.perf_counter()
+        P.bounds(rk[:64], tk[:64], nthreads=cores)
+        per = (time.perf_counter() - t0) / 64
+        n = int(min(len(rk), max(256, 6.0 / max(per, 1e-9))))
+        t0 = time.perf_counter()
+        P.bounds(rk[:n], tk[:n], nthreads=cores)
+        dt = time.perf_counter() - t0
+        out[label] = {"cores": cores, "cubes": n, "seconds": dt, "value": n / dt}
+    a = out["all"]
+    return {"value": a["value"], "unit": "cube-bounds/s", "cores": a["cores"], "kind": "oracle",
+            "sample": f"oracle bounds (FP64, OpenMP over cubes) of the first {a['cubes']} cubes of the 32,768-cube "
+                      f"64x64 batch (rotation levels 2-12, translation levels 1-10) in {a['seconds']:.1f} s on "
+                      f"{a['cores']} cores; one core: {out['one']['value']:.0f} cube-bounds/s over "
+                      f"{out['one']['cubes']} cubes",
+            "one_core": out["one"]}
 
 
 def learned_comparison(ctx, n_eval, eps, records_cap, epochs, time_cap):
@@ -295,21 +337,28 @@ def main():
 
     # whole hot path: the search itself
     torch.cuda.synchronize()
-    value, ms_step, kt_search, r_search, queue, pairs_search = search_rate(ctx, args.steps, args.warmup)
+    value, ms_step, kt_search, r_search, queue, work_search = search_rate(ctx, args.steps, args.warmup)
     torch.cuda.synchronize()
 
     # roofline of the GMM-vMF pair kernel over its launches in the search
-    # (HIP events on its stream), with the algorithmic work from the pair counts
+    # (HIP events on its stream), with the algorithmic work of the formulas
+    # (profiles/opcount.md) times the work counts of the same launches
     s12_ms, s12_n = kt_search["s12"]
-    s12_s = s12_ms / 1e3
-    screened, evaluated = pairs_search
-    comps = screened // N        # live cubes x M (one problem, no classes: M N pairs per live cube)
-    achieved = (comps * PREP_SLOTS + screened * SCREEN_SLOTS + evaluated * S12_SLOTS) / s12_s / 1e12
-    tflops = (comps * PREP_FLOPS + screened * SCREEN_FLOPS + evaluated * S12_FLOPS) / s12_s / 1e12
+    s11_ms, s11_n = kt_search["s11"]
+    w = work_search
+    fl12, sl12 = op_totals(s12_units(w, M))
+    _, sl12_4 = op_totals(s12_units(w, M), trans_slots=4)
+    fl11, sl11 = op_totals(s11_units(w, M))
+    achieved = sl12 / (s12_ms / 1e3) / 1e12
     peak = PEAK_SLOTS / 1e12
+    steps_timed = args.warmup + args.steps
+    # pair terms: two per evaluated pair (upper and lower bound), S11 once per
+    # distinct translation cell with its M diagonal terms; screened-out pairs
+    # are not counted
+    terms_per_step = 2 * (w["s12_evaluated"] + w["s11_evaluated"] + w["cells"] * M) / steps_timed
 
     # bound kernels alone on a fixed batch of cubes across levels
-    krate, kt, live, pairs_k = kernel_rate(ctx, scene, 10)
+    krate, kt, live, work_k, (rk_np, tk_np) = kernel_rate(ctx, scene, 10)
 
     rec = {
         "metric": "sub-cube bounds/s at 64x64 comps; time-to-eps-optimum plain vs learned order",
@@ -327,17 +376,25 @@ def main():
         "config": {"workload": "64x64 paper-like scene (45 noisy inliers + 19 outliers), branch-and-bound with "
                                "4096 parents = 32768 sub-cubes per step",
                    "M": M, "N": N, "batch_cubes": BATCH, "queue_after_steps": queue},
-        "pair_terms_per_s": value * (M * N + M * (M - 1) // 2) * 2,
+        "pair_terms_per_s": terms_per_step / (ms_step / 1e3),
+        "pair_terms_per_step": terms_per_step,
         "search_kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt_search.items() if v[1]},
+        "work_counts_timed_search": dict(w, iterations=steps_timed),
         "bound_kernels_only": {"cube_bounds_per_s": krate, "live_cubes": live,
-                               "pairs_evaluated_frac": pairs_k[1] / max(pairs_k[0], 1),
+                               "pairs_evaluated_frac": work_k["s12_evaluated"] / max(work_k["s12_screened"], 1),
                                "ms_per_launch": {"s12": kt["s12"][0] / kt["s12"][1], "s11": kt["s11"][0] / kt["s11"][1]}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
                      "frac": achieved / peak, "traffic": measured_traffic(), "traffic_unit": "bytes/launch",
-                     "kernel": "k_s12 (GMM-vMF pair sums), its launches in the search",
+                     "kernel": "k_s12 (GMM-vMF pair sums and bounds), its launches in the search",
                      "launches": s12_n, "ms_per_launch": s12_ms / s12_n,
-                     "pairs_screened": screened, "pairs_evaluated": evaluated,
-                     "fp32_tflops": tflops, "fp32_peak_tflops": PEAK_FP32_TFLOPS},
+                     "op_model": "profiles/opcount.md (formula counts x work counts; transcendental = "
+                                 f"{TRANS_SLOTS} slots)",
+                     "frac_trans_weight_4": sl12_4 / (s12_ms / 1e3) / PEAK_SLOTS,
+                     "fp32_tflops": fl12 / (s12_ms / 1e3) / 1e12, "fp32_peak_tflops": PEAK_FP32_TFLOPS,
+                     "fp32_frac": fl12 / (s12_ms / 1e3) / 1e12 / PEAK_FP32_TFLOPS,
+                     "s11": {"ms_per_launch": s11_ms / max(s11_n, 1),
+                             "frac": sl11 / (s11_ms / 1e3) / PEAK_SLOTS if s11_ms > 0 else None,
+                             "fp32_frac": fl11 / (s11_ms / 1e3) / 1e12 / PEAK_FP32_TFLOPS if s11_ms > 0 else None}},
     }
     if not args.no_other:
         rec["other_workloads"] = other_workload_rates(ctx)
@@ -357,7 +414,7 @@ def main():
             rec["time_to_eps_64x64_plain_vs_learned"] = learned_comparison(
                 ctx, args.learned_scenes, 1e-2, args.records, 4, 8.0)
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(scene)
+        rec["cpu_baseline"] = cpu_baseline(scene, rk_np, tk_np)
     ctx.close()
     print(json.dumps(rec), flush=True)
 

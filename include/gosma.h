@@ -312,14 +312,29 @@ int gosma_autotune(gosma_ctx *ctx, int64_t n_cubes, uint64_t seed, double *rows,
 int gosma_set_timing(gosma_ctx *ctx, int enable);
 int gosma_get_timing(gosma_ctx *ctx, double *ms, int64_t *launches);
 
-/* Pair counts of the GMM-vMF sums (Theorem 1, eq. 20-21, second sums) in the
+/* Work counts of the bound kernels (Theorem 1, eqs. 20-21) in the
  * gosma_eval_bounds calls and search iterations run while timing was enabled
- * (searches launch their kernels directly then): *screened receives
- * the number of same-class GMM-vMF pairs of the live cubes, *evaluated the
- * number that passed the screen of negligible pairs and were evaluated in
- * full.  Both host int64; the counts are cleared.  Synchronises the device.
- * Both are 0 if timing was never enabled. */
-int gosma_get_pair_counts(gosma_ctx *ctx, int64_t *screened, int64_t *evaluated);
+ * (searches launch their kernels directly then), for the roofline of the
+ * kernels: counts[GOSMA_N_COUNTS] (host int64) receives
+ *   [GOSMA_COUNT_CUBES]          cubes bounded that were not dropped,
+ *   [GOSMA_COUNT_S12_SCREENED]   same-class GMM-vMF pairs of those cubes,
+ *   [GOSMA_COUNT_S12_EVALUATED]  of those, the pairs that passed the screen of
+ *                                negligible pairs and were evaluated in full,
+ *   [GOSMA_COUNT_CELLS]          translation cells whose GMM-GMM sums were
+ *                                evaluated (searches: once per distinct cell),
+ *   [GOSMA_COUNT_S11_SCREENED]   unordered same-class GMM-GMM pairs i < i' of
+ *                                those cells,
+ *   [GOSMA_COUNT_S11_EVALUATED]  of those, the pairs evaluated in full.
+ * The counts are cleared.  Synchronises the device.  All 0 if timing was
+ * never enabled. */
+#define GOSMA_COUNT_CUBES 0
+#define GOSMA_COUNT_S12_SCREENED 1
+#define GOSMA_COUNT_S12_EVALUATED 2
+#define GOSMA_COUNT_CELLS 3
+#define GOSMA_COUNT_S11_SCREENED 4
+#define GOSMA_COUNT_S11_EVALUATED 5
+#define GOSMA_N_COUNTS 6
+int gosma_get_work_counts(gosma_ctx *ctx, int64_t *counts);
 
 #ifdef __cplusplus
 }

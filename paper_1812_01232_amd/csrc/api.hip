@@ -136,7 +136,7 @@ void gosma_destroy(gosma_ctx *ctx)
     dfree(ctx->d_s11ub);
     dfree(ctx->d_s11lo);
     dfree(ctx->d_setup);
-    dfree(ctx->d_pairs);
+    dfree(ctx->d_counts);
     dfree(ctx->d_stage);
     gosma_release_solver(ctx);
     gosma_release_mlp(ctx);
@@ -470,11 +470,11 @@ int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tke
     }
     gosma::DevMix mx = ctx->mix();
     int ti = ctx->time_begin(GOSMA_KERNEL_S11, s);
-    HIP_TRY(ctx, gosma::launch_s11(mx, tkeys, problem, n, nullptr, gosma::S11Out{ctx->d_s11ub, ctx->d_s11lo},
-                                   ctx->maxM, ctx->tile11, s));
+    gosma::S11Out o11{ctx->d_s11ub, ctx->d_s11lo, ctx->timing ? ctx->d_counts : nullptr};
+    HIP_TRY(ctx, gosma::launch_s11(mx, tkeys, problem, n, nullptr, o11, ctx->maxM, ctx->tile11, s));
     ctx->time_end(ti, s);
     gosma::BoundOut out{ub, lb, nullptr, aux, flags, top8, nullptr, nullptr, 0, nullptr};
-    if (ctx->timing) out.pair_counts = ctx->d_pairs;
+    if (ctx->timing) out.counts = ctx->d_counts;
     ti = ctx->time_begin(GOSMA_KERNEL_S12, s);
     HIP_TRY(ctx, gosma::launch_s12(mx, rkeys, tkeys, problem, nullptr, ctx->d_s11ub, ctx->d_s11lo, n, nullptr, 1, out,
                                    0.0, ctx->maxM, ctx->maxN, top8 != nullptr, ctx->tile12, ctx->d_setup, s));
@@ -507,30 +507,29 @@ int gosma_set_timing(gosma_ctx *ctx, int enable)
 {
     if (!ctx) return GOSMA_E_INVAL;
     ctx->err.clear();
-    if (enable && !ctx->d_pairs) {
+    if (enable && !ctx->d_counts) {
+        const size_t bytes = (size_t)gosma::kCountSlots * gosma::kCounters * sizeof(unsigned long long);
         HIP_TRY(ctx, hipSetDevice(ctx->device));
-        HIP_TRY(ctx, hipMalloc((void **)&ctx->d_pairs, 2 * gosma::kCountSlots * sizeof(unsigned long long)));
-        HIP_TRY(ctx, hipMemset(ctx->d_pairs, 0, 2 * gosma::kCountSlots * sizeof(unsigned long long)));
+        HIP_TRY(ctx, hipMalloc((void **)&ctx->d_counts, bytes));
+        HIP_TRY(ctx, hipMemset(ctx->d_counts, 0, bytes));
     }
     ctx->timing = enable != 0;
     return GOSMA_OK;
 }
 
-int gosma_get_pair_counts(gosma_ctx *ctx, int64_t *screened, int64_t *evaluated)
+int gosma_get_work_counts(gosma_ctx *ctx, int64_t *counts)
 {
-    if (!ctx || !screened || !evaluated) return GOSMA_E_INVAL;
+    if (!ctx || !counts) return GOSMA_E_INVAL;
     ctx->err.clear();
-    *screened = *evaluated = 0;
-    if (!ctx->d_pairs) return GOSMA_OK;
+    for (int c = 0; c < GOSMA_N_COUNTS; ++c) counts[c] = 0;
+    if (!ctx->d_counts) return GOSMA_OK;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipDeviceSynchronize());
-    unsigned long long h[2 * gosma::kCountSlots];
-    HIP_TRY(ctx, hipMemcpy(h, ctx->d_pairs, sizeof h, hipMemcpyDeviceToHost));
-    HIP_TRY(ctx, hipMemset(ctx->d_pairs, 0, sizeof h));
-    for (int k = 0; k < gosma::kCountSlots; ++k) {
-        *screened += (int64_t)h[2 * k];
-        *evaluated += (int64_t)h[2 * k + 1];
-    }
+    unsigned long long h[gosma::kCountSlots * gosma::kCounters];
+    HIP_TRY(ctx, hipMemcpy(h, ctx->d_counts, sizeof h, hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemset(ctx->d_counts, 0, sizeof h));
+    for (int k = 0; k < gosma::kCountSlots; ++k)
+        for (int c = 0; c < GOSMA_N_COUNTS; ++c) counts[c] += (int64_t)h[gosma::kCounters * k + c];
     return GOSMA_OK;
 }
 

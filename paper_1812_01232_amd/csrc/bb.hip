@@ -42,6 +42,7 @@ constexpr int kHistBins = 2048;
 constexpr int kBlock = 256;
 constexpr int kGridX = 2048;            // blocks per grid-stride kernel (divided among problems)
 constexpr int kMaxLevel = 19;
+constexpr uint32_t kNoChildren = 0xffffffffu;   // pchild of a parent that cannot be split
 // Rounding margin of the FP32 bounds, relative to the magnitude S11 + 2 S12 of
 // each bound: over 6x the largest relative error measured against the FP64
 // oracle on every parity set.
@@ -61,6 +62,7 @@ struct PState {
     uint32_t hcur, ccur;
     uint32_t theta;                // hot iff key32(priority) < theta (0xffffffff: all hot)
     uint32_t nsel, rebuild, done, overflow, iters, max_iters;
+    uint32_t nskip;                // selected cubes that cannot be split (no children)
     uint32_t take_all, prefix, need, eq_quota, eq_taken;   // radix select
     uint32_t rb_target;            // hot entries wanted after a re-partition
 };
@@ -162,7 +164,6 @@ struct Bufs {
     uint64_t *crk, *ctk;
     uint32_t *cpid, *cpar;        // problem and parent slot of each child
     int64_t *ctidx;
-    uint8_t *cskip;
     // translation cells of the iteration's children: a hash table of
     // 2^tbits slots per problem (key or kEmptyCell), one slot per distinct
     // cell, so parents that share a translation cell share its S11 sums
@@ -296,6 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_iter_begin(Bufs b, int P, int rb_slo
     for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) h[i] = 0;
     if (threadIdx.x == 0) {
         s.nsel = 0;
+        s.nskip = 0;
         s.take_all = 0;
         s.prefix = 0;
         s.need = 0;
@@ -582,20 +584,23 @@ __global__ __launch_bounds__(kBlock) void k_branch(Bufs b)
             if (rot && rmax) rot = false;
             if (!rot && tmax) rot = !rmax;
             skip = rmax && tmax;
-            if (skip) atomicMin(&s.floor_lb, ord64(par.lb[i]));
+            if (skip) {
+                atomicMin(&s.floor_lb, ord64(par.lb[i]));
+                atomicAdd(&s.nskip, 1u);
+            }
         }
-        const bool one = rot || skip;
-        const uint32_t c0 = block_reserve(&b.g->nchild, valid ? 8u : 0u);
+        // a parent at the finest level in both groups has no children (its
+        // lower bound stays in the queue minimum through floor_lb)
+        const uint32_t c0 = block_reserve(&b.g->nchild, valid && !skip ? 8u : 0u);
         if (!valid) continue;
-        b.pchild[(size_t)p * b.k + i] = c0;
+        b.pchild[(size_t)p * b.k + i] = skip ? kNoChildren : c0;
+        if (skip) continue;
         for (int c = 0; c < 8; ++c) {
             const uint32_t ci = c0 + c;
-            const uint64_t ck = one ? tk : child_key(tk, c);
-            b.crk[ci] = one ? child_key(rk, c) : rk;
-            b.ctk[ci] = ck;
+            b.crk[ci] = rot ? child_key(rk, c) : rk;
+            b.ctk[ci] = rot ? tk : child_key(tk, c);
             b.cpid[ci] = (uint32_t)p;
             b.cpar[ci] = (uint32_t)p * b.k + i;
-            b.cskip[ci] = skip;
         }
     }
 }
@@ -628,7 +633,7 @@ __global__ __launch_bounds__(kBlock) void k_push(Bufs b, const float *prio_overr
             p = b.cpid[i];
             PState &s = b.st[p];
             fl = b.cflags[i];
-            if (!((fl & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS)) || b.cskip[i])) {
+            if (!(fl & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS))) {
                 const unsigned long long draw = s.dstar;
                 if (b.cub[i] < INFINITY && ord64(b.cub[i]) == draw) {
                     s.best_rkey = b.crk[i];
@@ -715,7 +720,7 @@ __global__ __launch_bounds__(kBlock) void k_push_agg(Bufs b, const float *prio_o
             p = b.cpid[i];
             PState &s = b.st[p];
             fl = b.cflags[i];
-            if (!((fl & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS)) || b.cskip[i])) {
+            if (!(fl & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS))) {
                 const unsigned long long draw = s.dstar;
                 if (b.cub[i] < INFINITY && ord64(b.cub[i]) == draw) {
                     s.best_rkey = b.crk[i];
@@ -843,10 +848,11 @@ __global__ __launch_bounds__(kBlock) void k_log_records(Bufs b, int P)
     const Queue par = qoff(b.par, (size_t)p * b.k);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint32_t c0 = b.pchild[(size_t)p * b.k + i];
+        if (c0 == kNoChildren) continue;
         double best = INFINITY;
         for (int c = 0; c < 8; ++c) {
             const uint32_t ci = c0 + c;
-            if ((b.cflags[ci] & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS)) || b.cskip[ci]) continue;
+            if (b.cflags[ci] & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS)) continue;
             best = fmin(best, fmax(sane_lb(b.clbs[ci]), par.lb[i]));
         }
         if (!(best < INFINITY)) continue;
@@ -868,7 +874,7 @@ __global__ void k_iter_end(Bufs b, int P, int rb_every)
     if (p >= P) return;
     PState &s = b.st[p];
     if (s.done) return;
-    s.bounded += 8ull * s.nsel;
+    s.bounded += 8ull * (s.nsel - s.nskip);
     s.hcur ^= 1;
     s.iters += 1;
     const uint32_t nh = s.nH[s.hcur], nc = s.nC[s.ccur];
@@ -1011,7 +1017,6 @@ void free_solver(Solver *s)
     dfree(b.cpid);
     dfree(b.cpar);
     dfree(b.ctidx);
-    dfree(b.cskip);
     dfree(b.tcells);
     dfree(b.tpid);
     dfree(b.ckey);
@@ -1066,7 +1071,6 @@ hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap, b
     if (!e) e = dalloc(b.cpid, nc);
     if (!e) e = dalloc(b.cpar, nc);
     if (!e) e = dalloc(b.ctidx, nc);
-    if (!e) e = dalloc(b.cskip, nc);
     // cell table: 2^tbits >= 16 k slots per problem (at most 8 k used)
     uint32_t tbits = 4;
     while (((size_t)1 << tbits) < 16 * k) ++tbits;
@@ -1158,14 +1162,15 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     }
     T1(ti);
     ti = T0(GOSMA_KERNEL_S11);
-    hipError_t e = launch_s11(mx, b.ckey, b.cpid2, maxc, &b.g->ntcell, S11Out{b.s11ub, b.s11lo}, ctx->maxM,
-                              ctx->tile11, st, b.cslot);
+    hipError_t e = launch_s11(mx, b.ckey, b.cpid2, maxc, &b.g->ntcell,
+                              S11Out{b.s11ub, b.s11lo, timed ? ctx->d_counts : nullptr}, ctx->maxM, ctx->tile11, st,
+                              b.cslot);
     T1(ti);
     if (e) return e;
     ti = T0(GOSMA_KERNEL_S12);
     const bool top8 = learned || logging;
     BoundOut bo{b.cub, b.clb, b.clbs, nullptr, b.cflags, top8 ? b.ctop8 : nullptr, nullptr, &b.st->dstar,
-                (int)(sizeof(PState) / sizeof(unsigned long long)), timed ? ctx->d_pairs : nullptr};
+                (int)(sizeof(PState) / sizeof(unsigned long long)), timed ? ctx->d_counts : nullptr};
     e = launch_s12(mx, b.crk, b.ctk, b.cpid, b.ctidx, b.s11ub, b.s11lo, maxc, &b.g->nchild, 1, bo, kMarginGamma,
                    ctx->maxM, ctx->maxN, top8, ctx->tile12, b.csetup, st, true);
     T1(ti);

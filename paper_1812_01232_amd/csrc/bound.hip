@@ -374,7 +374,7 @@ constexpr int kG = 5, kG12 = 4;
 // Component record in LDS, four float4 (64 bytes, padded to 80):
 //   [0] u (unit vector mu - t0), weight      [1] kappa(t0), G(kappa), cos, sin of psi_t / 2
 //   [2] kappa interval centre ac, half-width ha, G(ac), nu(ac)
-//   [3] lambda = min(1/3, 1/klo^2), Lam (pair screen), 2 / kappa(t0), -
+//   [3] min(1/3, 1/klo^2) (curvature bound), Lam (pair screen), 2 / kappa(t0), -
 //
 // Pair screen.  The summand of a pair at the centre is at most
 // G(k) G(k') exp(-min(q, 2) k k' / (2 (k + k'))) / sqrt(2 k k') (h(K) <= 1/K,
@@ -422,8 +422,10 @@ __device__ __forceinline__ void s11_terms(const float4 &A0, const float4 &A1, co
         const float kb1 = 0.5f * a * qA * (b - a - k.K) * k.r;
         const float ga = ka1 + A2.w - k.nuK * (1.0f + ka1);
         const float gb = kb1 + B2.w - k.nuK * (1.0f + kb1);
-        const float lam = fmaxf(A3.x, B3.x);
-        const float corr = -fabsf(ga) * ha - fabsf(gb) * hb - 0.5f * lam * fmaf(ha, ha, hb * hb);
+        // curvature remainder per axis: the Hessian of g is at least
+        // diag(-L'(a), -L'(b)) (log Z(K) is convex in (a, b)); slot 3.x holds
+        // min(1/3, 1/klo^2) >= L' over the component's interval
+        const float corr = -fabsf(ga) * ha - fabsf(gb) * hb - 0.5f * fmaf(A3.x * ha, ha, B3.x * hb * hb);
         slo += w2 * (fexp2((k.x + corr) * kLog2e) * k.hK * A2.z * B2.z);
     }
 }
@@ -446,6 +448,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
     uint32_t *plist = reinterpret_cast<uint32_t *>(lds4 + kG * maxM);
     const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, wv = tid >> 6, lane = tid & 63;
     const int64_t nt = nt_dev ? (int64_t)nt_dev[0] : nt_host;
+    unsigned ncells = 0, noff_all = 0, nkeep_all = 0;   // per wave, over the block's cells (for out.counts)
     for (int64_t cell = blockIdx.x; cell < nt; cell += gridDim.x) {
         __syncthreads();
         const int64_t o = out_idx ? out_idx[cell] : cell;   // where the cell's sums go
@@ -508,6 +511,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             }
             continue;
         }
+        ncells += 1;
         // threshold of the pair screen, per unordered GMM pair
         const double thr11 = P.M > 1 ? kCullRel * dk / (0.5 * (double)P.M * (double)(P.M - 1)) : 0.0;
         const float lthr11 = thr11 > 0.0 ? __builtin_amdgcn_logf((float)thr11) * kLn2 : -INFINITY;
@@ -538,6 +542,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             }
         };
         auto offer = [&](const float4 &A0, const float4 &A3, int a_, int b_, bool valid) __attribute__((always_inline)) {
+            if (out.counts) noff_all += (unsigned)__popcll(__ballot(valid));
             bool keep = false;
             if (valid) {
                 const float4 B0 = rec[kG * b_], B3 = rec[kG * b_ + 3];
@@ -554,6 +559,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)pc));
                 pl[slot] = ((uint32_t)a_ << 16) | (uint32_t)b_;
             }
+            nkeep_all += (unsigned)__popcll(m);
             pc += __popcll(m);
             if (pc >= 64 * kBatch) {
                 pc -= 64 * kBatch;
@@ -647,6 +653,12 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             out.ub[o] = ubinf ? INFINITY : su;
             out.lo[o] = sl;
         }
+    }
+    if (out.counts && lane == 0) {
+        unsigned long long *c = out.counts + kCounters * (blockIdx.x % kCountSlots);
+        if (wv == 0) atomicAdd(c + kCntCells, (unsigned long long)ncells);
+        atomicAdd(c + kCntS11Screened, (unsigned long long)noff_all);
+        atomicAdd(c + kCntS11Evaluated, (unsigned long long)nkeep_all);
     }
 }
 
@@ -877,6 +889,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
     const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, wv = tid >> 6, lane = tid & 63;
     const int64_t n = n_dev ? (int64_t)n_dev[0] * n_dev_mul : n_host;
     unsigned nscr = 0, ncull_all = 0;   // per wave: pairs screened and dropped, over all cubes of the block
+    unsigned nlive = 0;                 // cubes of the block that were not dropped
     for (int64_t cube = blockIdx.x; cube < n; cube += gridDim.x) {
         __syncthreads();
         const CubeSetup &cs = setup[cube];
@@ -1005,6 +1018,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         if (prsum >= psum) flags |= GOSMA_FLAG_SPLIT_ROT;
 
         const bool dropped = flags & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS);
+        nlive += dropped ? 0u : 1u;
         double acc_ub = 0.0, acc_hi = 0.0;
         float top[8];
 #pragma unroll
@@ -1213,11 +1227,12 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             if (out.psi_gap) out.psi_gap[cube] = prsum - psum;
         }
     }
-    if (out.pair_counts && lane == 0) {
-        // one pair of atomics per wave, spread over kCountSlots addresses
-        unsigned long long *pc2 = out.pair_counts + 2 * (blockIdx.x % kCountSlots);
-        atomicAdd(pc2, (unsigned long long)nscr);
-        atomicAdd(pc2 + 1, (unsigned long long)(nscr - ncull_all));
+    if (out.counts && lane == 0) {
+        // one set of atomics per wave, spread over kCountSlots addresses
+        unsigned long long *c = out.counts + kCounters * (blockIdx.x % kCountSlots);
+        if (wv == 0) atomicAdd(c + kCntCubes, (unsigned long long)nlive);
+        atomicAdd(c + kCntS12Screened, (unsigned long long)nscr);
+        atomicAdd(c + kCntS12Evaluated, (unsigned long long)(nscr - ncull_all));
     }
 }
 

@@ -55,10 +55,15 @@ struct BoundOut {
     float *psi_gap;    // optional: weighted mean psi_r - weighted mean psi_t (branching statistic)
     unsigned long long *dstar_bits;   // optional: atomic minimum of finite upper bounds (ordered bits),
     int dstar_stride;                 // at dstar_bits[problem * dstar_stride]
-    unsigned long long *pair_counts;  // optional: kCountSlots pairs of counters {GMM-vMF pairs screened,
-                                      // evaluated}, added to; the totals are the sums over the slots
+    unsigned long long *counts;       // optional work counters (kCountSlots x kCounters, added to; the
+                                      // totals are the sums over the slots), see kCnt*
 };
+// Work counters of timed launches: per slot {live cubes, GMM-vMF pairs
+// screened, evaluated, live translation cells, GMM-GMM pairs screened,
+// evaluated}; a block adds to slot blockIdx.x % kCountSlots.
 constexpr int kCountSlots = 64;
+constexpr int kCounters = GOSMA_N_COUNTS;
+enum { kCntCubes = 0, kCntS12Screened, kCntS12Evaluated, kCntCells, kCntS11Screened, kCntS11Evaluated };
 
 // A translation-cell key no cell has (the level field of real keys is at most 19).
 constexpr uint64_t kEmptyCell = ~0ull;
@@ -80,6 +85,7 @@ struct CellTable {
 
 struct S11Out {
     double *ub, *lo;   // S11 at the centre and its lower bound, per translation cube
+    unsigned long long *counts = nullptr;   // optional work counters (see BoundOut)
 };
 
 // Per-cube set-up of the GMM-vMF pair kernel: both cells decoded, the rotation
@@ -156,7 +162,7 @@ struct gosma_ctx {
     int64_t s11_cap = 0;
     double *d_s11ub = nullptr, *d_s11lo = nullptr;
     gosma::CubeSetup *d_setup = nullptr;
-    unsigned long long *d_pairs = nullptr;   // pair counts of timed gosma_eval_bounds calls
+    unsigned long long *d_counts = nullptr;  // work counters of timed launches (kCountSlots x kCounters)
     uint8_t *d_stage = nullptr;              // device copies of host arrays given to gosma_eval_bounds
     size_t stage_cap = 0;
 

@@ -25,10 +25,11 @@ EXPORTS = ["gosma_create", "gosma_destroy", "gosma_last_error", "gosma_set_mixtu
            "gosma_set_problems", "gosma_get_S22", "gosma_eval_bounds", "gosma_solve", "gosma_solve_batch",
            "gosma_set_timing", "gosma_get_timing", "gosma_get_trace", "gosma_mlp_init", "gosma_mlp_set_params",
            "gosma_mlp_get_params", "gosma_mlp_predict", "gosma_mlp_loss_grad", "gosma_mlp_train",
-           "gosma_set_record_sink", "gosma_get_tiles", "gosma_set_tiles", "gosma_autotune", "gosma_get_pair_counts",
+           "gosma_set_record_sink", "gosma_get_tiles", "gosma_set_tiles", "gosma_autotune", "gosma_get_work_counts",
            "gosma_snapshot", "gosma_resume"]
 MLP_FEATURES, MLP_RECORD, MLP_PARAMS = 20, 21, 35841
 KERNEL_KINDS = ["s11", "s12", "select", "branch", "push", "mlp"]
+WORK_COUNTS = ["cubes", "s12_screened", "s12_evaluated", "cells", "s11_screened", "s11_evaluated"]
 
 
 class GosmaError(RuntimeError):
@@ -99,7 +100,7 @@ def lib():
         L.gosma_mlp_train.argtypes = [vp, vp, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_uint64, fp]
         L.gosma_set_record_sink.argtypes = [vp, vp, C.c_int64, vp]
         L.gosma_get_timing.argtypes = [vp, dp, C.POINTER(C.c_int64)]
-        L.gosma_get_pair_counts.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.gosma_get_work_counts.argtypes = [vp, C.POINTER(C.c_int64)]
         L.gosma_snapshot.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
         L.gosma_resume.argtypes = [vp, vp, C.c_size_t]
         L.gosma_get_tiles.argtypes = [vp, C.POINTER(Tiles)]
@@ -345,12 +346,19 @@ class Context:
         self._check(lib().gosma_get_timing(self._h, ms, n), "gosma_get_timing")
         return {KERNEL_KINDS[k]: (ms[k], n[k]) for k in range(len(KERNEL_KINDS))}
 
+    def get_work_counts(self):
+        """Work counts of the timed launches since the last call (live cubes,
+        GMM-vMF pairs screened and evaluated, translation cells, GMM-GMM
+        pairs screened and evaluated); synchronises."""
+        c = (C.c_int64 * len(WORK_COUNTS))()
+        self._check(lib().gosma_get_work_counts(self._h, c), "gosma_get_work_counts")
+        return {k: int(c[i]) for i, k in enumerate(WORK_COUNTS)}
+
     def get_pair_counts(self):
-        """(screened, evaluated) GMM-vMF pairs of the timed eval_bounds calls
-        since the last call; synchronises."""
-        a, b = C.c_int64(), C.c_int64()
-        self._check(lib().gosma_get_pair_counts(self._h, C.byref(a), C.byref(b)), "gosma_get_pair_counts")
-        return a.value, b.value
+        """(screened, evaluated) GMM-vMF pairs of the timed launches since the
+        last call; synchronises (and clears every work count)."""
+        w = self.get_work_counts()
+        return w["s12_screened"], w["s12_evaluated"]
 
     # -- branch and bound -------------------------------------------------
     def solve(self, eps, batch_parents=4096, max_queue=1 << 24, max_iters=0, time_limit_s=0.0, order=0,

@@ -109,6 +109,23 @@ def test_cfg3_labels_sampled(ctx):
     _compare(sc, {k: v[sel] for k, v in g.items()}, o, top8=True, label="cfg3")
 
 
+def test_cfg3_full_launch_sampled(ctx):
+    """The 256 x 256 labelled workload at its full batch: 131,072 cubes in one
+    launch of each kernel (every block walks 16 cubes at 8,192 blocks), with
+    400 cubes spread over the batch, its last cubes included, checked
+    against the oracle."""
+    sc = scenes.cfg3_scene(0)
+    n = 131072
+    rk, tk = scenes.random_cubes(sc, n, 3600, r_levels=(2, 12), t_levels=(1, 10))
+    ctx.set_scene(sc)
+    for tile in [(1, 8192), (2, 8192)]:
+        ctx.set_tiles(s11=tile, s12=tile)
+        g = ctx.bounds(rk, tk, want_top8=True)
+        sel = np.concatenate([np.random.default_rng(3).choice(n - 16, 384, replace=False), np.arange(n - 16, n)])
+        o = oracle.OracleProblem(sc).bounds(rk[sel], tk[sel])
+        _compare(sc, {k: v[sel] for k, v in g.items()}, o, top8=True, label=f"cfg3-full tile {tile}")
+
+
 def test_cfg4_128_problems_sampled(ctx):
     """The 128-problem batch (M, N uniform on [16, 256]) at its search size:
     16,384 cubes per problem (256 seeded cubes, each repeated 64 times), 2.1 M
@@ -313,14 +330,20 @@ def test_pair_screen_counts_and_parity(ctx):
     for levels, lo_frac, hi_frac in [((10, 12), 0.0, 0.6), ((0, 0), 1.0, 1.0)]:
         rk, tk = scenes.random_cubes(sc, 2000, 5900, r_levels=levels, t_levels=(levels[0] - 1 if levels[0] else 0,
                                                                               levels[1] - 1 if levels[1] else 0))
-        ctx.get_pair_counts()
+        ctx.get_work_counts()
         ctx.set_timing(True)
         g = ctx.bounds(rk, tk)
         ctx.set_timing(False)
         ctx.get_timing()
-        screened, evaluated = ctx.get_pair_counts()
+        w = ctx.get_work_counts()
+        screened, evaluated = w["s12_screened"], w["s12_evaluated"]
         live = int(((g["flags"] & 6) == 0).sum())
+        assert w["cubes"] == live
         assert screened == live * sc.M * sc.N
+        # every cube's translation cell is its own cell here; those not dropped
+        # for zeta are counted with all their unordered GMM pairs
+        assert w["s11_screened"] == w["cells"] * sc.M * (sc.M - 1) // 2
+        assert w["cells"] >= live and w["s11_evaluated"] <= w["s11_screened"]
         frac = evaluated / screened
         print(f"levels {levels}: {live} live cubes, {frac:.3f} of the pairs evaluated")
         assert lo_frac <= frac <= hi_frac

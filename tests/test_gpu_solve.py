@@ -297,3 +297,53 @@ def test_snapshot_resume_errors(ctx):
     with pytest.raises(GosmaError) as ei:
         ctx.resume(snap)
     assert ei.value.code == -1
+
+
+def _snapshot_with_cubes(snap, rkeys, tkeys, lbs, flags):
+    """Replace the queued cubes of a one-problem snapshot (layout of
+    gosma_snapshot: a 24-byte header, a 176-byte problem record whose last
+    fields are best keys, bounded count, n and iters, then n rkeys, n tkeys,
+    n lower bounds and n flag bytes padded to 8)."""
+    import struct
+    head, prob = bytearray(snap[:24]), bytearray(snap[24:200])
+    n = len(rkeys)
+    struct.pack_into("<Q", prob, 160, n)
+    body = (np.asarray(rkeys, np.uint64).tobytes() + np.asarray(tkeys, np.uint64).tobytes() +
+            np.asarray(lbs, np.float64).tobytes() + np.asarray(flags, np.uint8).tobytes())
+    body += bytes((-len(body)) % 8)
+    struct.pack_into("<Q", head, 16, 24 + 176 + len(body))
+    return bytes(head) + bytes(prob) + body, struct.unpack_from("<Q", prob, 152)[0]
+
+
+def test_finest_level_parents_have_no_children(ctx):
+    """Cubes at octree level 19 in both groups cannot be split (Algorithm 1
+    has no children for them): they add no bounded cubes, a cube at level 19
+    in one group splits the other, and d* keeps the pose it was found at."""
+    sc = scenes.small_scene(4, 4, seed=81)
+    ctx.set_scene(sc)
+    ctx.solve(1e-9, batch_parents=64, max_iters=2)
+    snap = ctx.snapshot()
+
+    def key_at(x, lo, hi, L, shift=0):
+        idx = np.floor((np.asarray(x) - lo) / (hi - lo) * (2 ** L)).astype(int) + shift
+        return int(scenes.pack_key(L, *np.clip(idx, 0, 2 ** L - 1)))
+    rg, tg = sc.r_gt, sc.t_gt
+    rk = [key_at(rg, sc.r_lo, sc.r_hi, 19), key_at(rg, sc.r_lo, sc.r_hi, 19, 1),
+          key_at(rg, sc.r_lo, sc.r_hi, 19), key_at(rg, sc.r_lo, sc.r_hi, 18)]
+    tk = [key_at(tg, sc.t_lo, sc.t_hi, 19), key_at(tg, sc.t_lo, sc.t_hi, 19, 1),
+          key_at(tg, sc.t_lo, sc.t_hi, 18), key_at(tg, sc.t_lo, sc.t_hi, 19)]
+    lbs = [-1e300] * 4
+    flags = [1, 1, 1, 1]          # split flag set: rotation where it can still split
+    crafted, bounded0 = _snapshot_with_cubes(snap, rk, tk, lbs, flags)
+    ctx.resume(crafted)
+    r = ctx.solve(0.0, batch_parents=64, max_iters=4)
+    print(f"level-19 search: status {r['status']} iters {r['iters']} cubes {r['cubes']} (from {bounded0})")
+    # two splittable parents (one in translation, one in rotation) give 16
+    # children at level 19 in both groups, which in turn have none
+    assert r["cubes"] == bounded0 + 16
+    assert r["status"] == 1
+    P = oracle.OracleProblem(sc)
+    f, s11, s12 = P.objective(r["r"], r["t"])
+    assert abs(f - r["f_best"]) <= 1e-5 * (s11 + 2 * s12)
+    # the pose is one of the children: within a level-19 cell of the truth
+    assert np.all(np.abs(np.asarray(r["r"]) - rg) <= 3 * 2 * math.pi / 2 ** 19)
