@@ -51,14 +51,19 @@ class Bound(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("batch_parents", C.c_int64), ("max_iters", C.c_int64),
-                ("time_limit_s", C.c_double), ("nthreads", C.c_int)]
+                ("time_limit_s", C.c_double), ("nthreads", C.c_int), ("sma_iters", C.c_int)]
+
+
+class SmaOpts(C.Structure):
+    _fields_ = [("max_iters", C.c_int), ("memory", C.c_int), ("gtol", C.c_double), ("ftol", C.c_double)]
 
 
 class Result(C.Structure):
     _fields_ = [("f_best", C.c_double), ("lb_global", C.c_double), ("f_norm_best", C.c_double),
                 ("lb_norm", C.c_double), ("S22", C.c_double), ("r", C.c_double * 3),
                 ("t", C.c_double * 3), ("iters", C.c_int64), ("cubes", C.c_int64),
-                ("max_queue", C.c_int64), ("status", C.c_int32), ("seconds", C.c_double)]
+                ("max_queue", C.c_int64), ("status", C.c_int32), ("seconds", C.c_double),
+                ("sma_runs", C.c_int64), ("sma_improved", C.c_int64)]
 
 
 _lib = None
@@ -100,6 +105,10 @@ def lib():
         L.oracle_eval_bounds.argtypes = [C.POINTER(Problem), C.POINTER(Domain), C.POINTER(C.c_uint64),
                                          C.POINTER(C.c_uint64), C.c_int64, C.POINTER(Bound), C.c_int]
         L.oracle_solve.argtypes = [C.POINTER(Problem), C.POINTER(Domain), C.POINTER(Opts), C.POINTER(Result)]
+        L.oracle_objective_grad.restype = C.c_double
+        L.oracle_objective_grad.argtypes = [C.POINTER(Problem), d3, d3, d3]
+        L.oracle_sma.restype = C.c_int
+        L.oracle_sma.argtypes = [C.POINTER(Problem), C.POINTER(Domain), d3, d3, C.POINTER(SmaOpts), d3, d3, d3]
         _lib = L
     return _lib
 
@@ -148,8 +157,25 @@ class OracleProblem:
         arr = np.ctypeslib.as_array(out)[:n]
         return {name: np.array(arr[name]) for name in arr.dtype.names}
 
-    def solve(self, eps, batch_parents, max_iters=0, time_limit_s=0.0, nthreads=0):
-        o = Opts(eps, batch_parents, max_iters, time_limit_s, nthreads)
+    def objective_grad(self, r, t):
+        """Objective and its gradient (6,) with respect to (r, t)."""
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        g = np.zeros(6)
+        f = lib().oracle_objective_grad(C.byref(self.p), _dp(r), _dp(t), _dp(g))
+        return f, g
+
+    def sma(self, r0, t0, max_iters=100, memory=5, gtol=1e-6, ftol=1e-9):
+        """SMA (L-BFGS) from (r0, t0): {r, t, f, iters} (iters -1: start not allowed)."""
+        r0 = np.ascontiguousarray(r0, dtype=np.float64)
+        t0 = np.ascontiguousarray(t0, dtype=np.float64)
+        r, t, f = np.zeros(3), np.zeros(3), np.zeros(1)
+        o = SmaOpts(max_iters, memory, gtol, ftol)
+        it = lib().oracle_sma(C.byref(self.p), C.byref(self.d), _dp(r0), _dp(t0), C.byref(o), _dp(r), _dp(t), _dp(f))
+        return {"r": r, "t": t, "f": float(f[0]), "iters": it}
+
+    def solve(self, eps, batch_parents, max_iters=0, time_limit_s=0.0, nthreads=0, sma_iters=0):
+        o = Opts(eps, batch_parents, max_iters, time_limit_s, nthreads, sma_iters)
         res = Result()
         lib().oracle_solve(C.byref(self.p), C.byref(self.d), C.byref(o), C.byref(res))
         return {name: (list(getattr(res, name)) if name in ("r", "t") else getattr(res, name))

@@ -10,9 +10,10 @@
  * The code follows the paper's notation and order: the objective of Lemma 1
  * (Section 4, eqs. 10-13) written with the Z(.) normaliser of eq. 2 in log
  * space; the bounds of Theorem 1 (Section 5.2, eqs. 20-25) with the
- * uncertainty angles of Lemmas 2-3; and Algorithm 1 (Section 6) without the
- * local optimiser.  Where the paper leaves a step open the reading taken is
- * stated in the comment of that step.
+ * uncertainty angles of Lemmas 2-3; the gradient of the objective and the
+ * SMA local optimiser (Section 6); and Algorithm 1 (Section 6).  Where the
+ * paper leaves a step open the reading taken is stated in the comment of that
+ * step.
  *
  * Parity status:
  *   oracle_log_Z, oracle_vmf_pdf, oracle_pn_pdf, oracle_qpn_kappa  -- pinned
@@ -25,6 +26,11 @@
  *   oracle_bounds_cube: ub pinned (= objective at the centre); lb value is
  *     "parity unpinned" (the paper's proof appendix is missing); its validity
  *     (lb <= sampled minimum) and convergence are pinned by brute force.
+ *   oracle_objective_grad                                          -- pinned
+ *     (central finite differences of oracle_objective).
+ *   oracle_sma: pinned by first-order optimality at its result (finite
+ *     differences), by never raising f, and by reaching the zero-distance
+ *     ground-truth pose from nearby starts.
  *   oracle_solve: pinned on small problems by a dense pose grid with local
  *     polishing, and by recovery of the ground-truth pose.
  */
@@ -604,7 +610,228 @@ int oracle_eval_bounds(const oracle_problem *p, const oracle_domain *d, const ui
 }
 
 /* ------------------------------------------------------------------ */
-/* Algorithm 1 (Section 6) without the local optimiser.               */
+/* Section 6: SMA, the local optimiser of Algorithm 1.                */
+/* ------------------------------------------------------------------ */
+
+/* Gradient of the objective of Lemma 1 (eqs. 10-13, class sum eq. 17) with
+ * respect to the angle-axis rotation r and the camera centre t, by the chain
+ * rule (the paper's appendix, which derives it, is not available).  For a
+ * summand w w' Z(K)/(Z(a) Z(b)) write g = log Z(K) - log Z(a) - log Z(b) and
+ * L(x) = d log Z / dx = coth x - 1/x.  Each GMM component i enters through
+ * d_i = mu_1i - t: kappa_i = |d_i|^2/sigma_i^2 + 1 (eq. 13), u_i = d_i/|d_i|,
+ * and the vector p_i = kappa_i u_i, whose Jacobian is
+ *   P_i = dp_i/dd_i = (rho/sigma^2 + 1/rho) I + (rho/sigma^2 - 1/rho) u u^T,
+ * rho = |d_i|, and d kappa_i / d d_i = 2 d_i / sigma_i^2.
+ *   S11 summand (i, k): v = p_i + p_k, K = |v|,
+ *     dg/dd_i = P_i (L(K) v / K) - L(kappa_i) 2 d_i / sigma_i^2  (and k alike).
+ *   S12 summand (i, j): v = R p_i + kappa_2j mu_2j, K = |v|,
+ *     dg/dd_i = P_i R^T (L(K) v / K) - L(kappa_i) 2 d_i / sigma_i^2,
+ *     and under R -> exp([w]x) R, dg/dw = (L(K)/K) (R p_i) x v.
+ * d/dt = -sum_i d/dd_i, and d/dr = J(r)^T d/dw with J the left Jacobian
+ * (R(r + dr) = exp([J(r) dr]x) R(r) to first order). */
+double oracle_objective_grad(const oracle_problem *p, const double r[3], const double t[3], double grad[6])
+{
+    int M = p->M, N = p->N;
+    double R[9], J[9];
+    oracle_rodrigues(r, R);
+    oracle_left_jacobian(r, J);
+    double *w1 = malloc(sizeof(double) * M), *w2 = malloc(sizeof(double) * N);
+    double *pv = malloc(sizeof(double) * 3 * M), *dv = malloc(sizeof(double) * 3 * M);
+    double *kap = malloc(sizeof(double) * M), *gd = calloc((size_t)(3 * M), sizeof(double));
+    class_weights(p, w1, w2);
+    for (int i = 0; i < M; ++i) {
+        for (int a = 0; a < 3; ++a) dv[3 * i + a] = p->mu[3 * i + a] - t[a];
+        double n = norm3(dv + 3 * i);
+        kap[i] = (n / p->sigma[i]) * (n / p->sigma[i]) + 1.0;
+        for (int a = 0; a < 3; ++a) pv[3 * i + a] = kap[i] * dv[3 * i + a] / n;
+    }
+    /* dg/dd_i of one summand, given c = L(K) v / K seen from component i's frame */
+    #define ADD_DD(i, c, coef)                                                              \
+        do {                                                                                \
+            const double *d_ = dv + 3 * (i);                                                \
+            double rho_ = norm3(d_), s2_ = p->sigma[i] * p->sigma[i];                       \
+            double al_ = rho_ / s2_ + 1.0 / rho_, be_ = rho_ / s2_ - 1.0 / rho_;            \
+            double uc_ = (d_[0] * (c)[0] + d_[1] * (c)[1] + d_[2] * (c)[2]) / rho_;         \
+            double lk_ = langevin(kap[i]);                                                  \
+            for (int a_ = 0; a_ < 3; ++a_)                                                  \
+                gd[3 * (i) + a_] += (coef) * (al_ * (c)[a_] + be_ * uc_ * d_[a_] / rho_ -   \
+                                              lk_ * 2.0 * d_[a_] / s2_);                     \
+        } while (0)
+    double phil = class_weight(p), f = 0.0, gw[3] = {0, 0, 0};
+    for (int i = 0; i < M; ++i) {
+        for (int k = 0; k < M; ++k) {
+            if (label_of(p->label1, i) != label_of(p->label1, k)) continue;
+            double v[3];
+            for (int a = 0; a < 3; ++a) v[a] = pv[3 * i + a] + pv[3 * k + a];
+            double K = norm3(v);
+            double T = phil * w1[i] * w1[k] * exp(oracle_log_Z(K) - oracle_log_Z(kap[i]) - oracle_log_Z(kap[k]));
+            double lk = K < 1e-6 ? 1.0 / 3.0 : langevin(K) / K, c[3];
+            for (int a = 0; a < 3; ++a) c[a] = lk * v[a];
+            f += T;
+            ADD_DD(i, c, T);
+            ADD_DD(k, c, T);
+        }
+        double Rp[3];
+        matvec(R, pv + 3 * i, Rp);
+        for (int j = 0; j < N; ++j) {
+            if (label_of(p->label1, i) != label_of(p->label2, j)) continue;
+            double v[3];
+            for (int a = 0; a < 3; ++a) v[a] = Rp[a] + p->kappa2[j] * p->dir2[3 * j + a];
+            double K = norm3(v);
+            double T = phil * w1[i] * w2[j] *
+                       exp(oracle_log_Z(K) - oracle_log_Z(kap[i]) - oracle_log_Z(p->kappa2[j]));
+            double lk = K < 1e-6 ? 1.0 / 3.0 : langevin(K) / K, cw[3], c[3], x[3];
+            for (int a = 0; a < 3; ++a) cw[a] = lk * v[a];
+            matTvec(R, cw, c);                         /* R^T (L(K) v / K) */
+            f -= 2.0 * T;
+            ADD_DD(i, c, -2.0 * T);
+            cross3(Rp, cw, x);                         /* (R p_i) x (L(K) v / K) */
+            for (int a = 0; a < 3; ++a) gw[a] += -2.0 * T * x[a];
+        }
+    }
+    #undef ADD_DD
+    double gt[3] = {0, 0, 0};
+    for (int i = 0; i < M; ++i)
+        for (int a = 0; a < 3; ++a) gt[a] -= gd[3 * i + a];
+    matTvec(J, gw, grad);                              /* d/dr = J^T d/dw */
+    for (int a = 0; a < 3; ++a) grad[3 + a] = gt[a];
+    free(w1); free(w2); free(pv); free(dv); free(kap); free(gd);
+    return f;
+}
+
+/* The objective where the pose is allowed: +inf if the camera centre lies
+ * within zeta of a Gaussian mean (the restriction of Omega_t, Section 5.1). */
+static double sma_value(const oracle_problem *p, const double x[6], double zeta, double g[6])
+{
+    for (int i = 0; i < p->M; ++i) {
+        double e[3] = {p->mu[3 * i] - x[3], p->mu[3 * i + 1] - x[4], p->mu[3 * i + 2] - x[5]};
+        if (norm3(e) < zeta) return INFINITY;
+    }
+    return oracle_objective_grad(p, x, x + 3, g);
+}
+
+/* SMA (Section 6): minimise the objective from a start pose with L-BFGS over
+ * the six pose parameters x = (r, t), kept in the domain box (rotation box x
+ * translation box; the paper cites the bound-constrained L-BFGS-B).  Reading
+ * taken: the L-BFGS direction (two-loop recursion of Nocedal and Wright,
+ * Numerical Optimization, Algorithm 7.4, with the newest m curvature pairs and
+ * the initial scaling s^T y / y^T y) is followed along the projected path
+ * x+ = clamp(x + s d) onto the box, instead of L-BFGS-B's Cauchy point and
+ * subspace step; trial points within zeta of a mean are infeasible.  Steps:
+ *   1. stop if the projected gradient (components pointing out of the box at
+ *      an active bound dropped) has infinity norm <= gtol * scale, scale =
+ *      S11 + 2 S12 at the start;
+ *   2. d = -H g from the stored pairs (with none stored: d = -g scaled to
+ *      length at most 0.05); if g^T d >= 0, drop the pairs and take that
+ *      steepest-descent step instead;
+ *   3. backtrack s = 1, 1/2, 1/4, ... (at most 40 halvings) until
+ *      f(x+) <= f(x) + 1e-4 g^T (x+ - x); stop if none is accepted;
+ *   4. store (x+ - x, g+ - g) if s^T y > 1e-12 |s| |y|;
+ *   5. stop if f fell by at most ftol (|f| + scale), or after max_iters.
+ * Returns the number of iterations taken, or -1 if the start is not an allowed
+ * pose. */
+int oracle_sma(const oracle_problem *p, const oracle_domain *d, const double r0[3], const double t0[3],
+               const oracle_sma_opts *o, double r_out[3], double t_out[3], double *f_out)
+{
+    enum { MAXM = 16 };
+    const int m = o->memory < 1 ? 1 : (o->memory > MAXM ? MAXM : o->memory);
+    double lo[6], hi[6], x[6], g[6], S[MAXM][6], Y[MAXM][6], rho[MAXM], al[MAXM];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = d->r_lo[a]; hi[a] = d->r_hi[a];
+        lo[3 + a] = d->t_lo[a]; hi[3 + a] = d->t_hi[a];
+        x[a] = r0[a]; x[3 + a] = t0[a];
+    }
+    for (int a = 0; a < 6; ++a)
+        if (!(x[a] >= lo[a] && x[a] <= hi[a])) return -1;
+    double f = sma_value(p, x, d->zeta, g);
+    if (!(f < INFINITY)) return -1;
+    double s11, s12;
+    oracle_objective(p, x, x + 3, &s11, &s12);
+    const double scale = s11 + 2.0 * s12;
+    int nst = 0, head = 0, it = 0;
+    while (it < o->max_iters) {
+        double pg = 0.0;
+        for (int a = 0; a < 6; ++a) {
+            double ga = g[a];
+            if ((x[a] <= lo[a] && ga > 0.0) || (x[a] >= hi[a] && ga < 0.0)) ga = 0.0;
+            pg = fmax(pg, fabs(ga));
+        }
+        if (pg <= o->gtol * scale) break;
+        double q[6], dir[6], gn = 0.0;
+        for (int a = 0; a < 6; ++a) { q[a] = g[a]; gn += g[a] * g[a]; }
+        gn = sqrt(gn);
+        for (int k = 0; k < nst; ++k) {
+            int s = (head - 1 - k + MAXM) % MAXM;
+            double sq = 0.0;
+            for (int a = 0; a < 6; ++a) sq += S[s][a] * q[a];
+            al[s] = rho[s] * sq;
+            for (int a = 0; a < 6; ++a) q[a] -= al[s] * Y[s][a];
+        }
+        double h0 = 1.0;
+        if (nst > 0) {
+            int s = (head - 1 + MAXM) % MAXM;
+            double sy = 0.0, yy = 0.0;
+            for (int a = 0; a < 6; ++a) { sy += S[s][a] * Y[s][a]; yy += Y[s][a] * Y[s][a]; }
+            h0 = sy / yy;
+        } else {
+            h0 = fmin(1.0, 0.05 / gn);
+        }
+        for (int a = 0; a < 6; ++a) q[a] *= h0;
+        for (int k = nst - 1; k >= 0; --k) {
+            int s = (head - 1 - k + MAXM) % MAXM;
+            double yq = 0.0;
+            for (int a = 0; a < 6; ++a) yq += Y[s][a] * q[a];
+            double b = rho[s] * yq;
+            for (int a = 0; a < 6; ++a) q[a] += (al[s] - b) * S[s][a];
+        }
+        double gdir = 0.0;
+        for (int a = 0; a < 6; ++a) { dir[a] = -q[a]; gdir += g[a] * dir[a]; }
+        if (!(gdir < 0.0)) {
+            double h = fmin(1.0, 0.05 / gn);
+            for (int a = 0; a < 6; ++a) dir[a] = -h * g[a];
+            nst = 0;
+        }
+        double step = 1.0, xn[6], gx[6], fn = INFINITY;
+        int accepted = 0;
+        for (int ls = 0; ls <= 40; ++ls, step *= 0.5) {
+            double dec = 0.0;
+            for (int a = 0; a < 6; ++a) {
+                xn[a] = fmin(fmax(x[a] + step * dir[a], lo[a]), hi[a]);
+                dec += g[a] * (xn[a] - x[a]);
+            }
+            fn = sma_value(p, xn, d->zeta, gx);
+            if (fn <= f + 1e-4 * dec) { accepted = 1; break; }
+        }
+        if (!accepted) break;
+        ++it;
+        double sv[6], yv[6], sy = 0.0, ss = 0.0, yy = 0.0;
+        for (int a = 0; a < 6; ++a) {
+            sv[a] = xn[a] - x[a];
+            yv[a] = gx[a] - g[a];
+            sy += sv[a] * yv[a];
+            ss += sv[a] * sv[a];
+            yy += yv[a] * yv[a];
+        }
+        const double fprev = f;
+        memcpy(x, xn, sizeof x);
+        memcpy(g, gx, sizeof g);
+        f = fn;
+        if (sy > 1e-12 * sqrt(ss * yy)) {
+            memcpy(S[head], sv, sizeof sv);
+            memcpy(Y[head], yv, sizeof yv);
+            rho[head] = 1.0 / sy;
+            head = (head + 1) % MAXM;
+            if (nst < m) ++nst;
+        }
+        if (fprev - f <= o->ftol * (fabs(f) + scale)) break;
+    }
+    for (int a = 0; a < 3; ++a) { r_out[a] = x[a]; t_out[a] = x[3 + a]; }
+    *f_out = f;
+    return it;
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 1 (Section 6), with SMA when opts->sma_iters > 0.       */
 /* ------------------------------------------------------------------ */
 
 typedef struct {
@@ -677,6 +904,12 @@ static double now_s(void)
     return ts.tv_sec + 1e-9 * ts.tv_nsec;
 }
 
+/* SMA settings inside the search: 5 curvature pairs; stop at a projected
+ * gradient of 1e-6 of the bound scale or a step gaining under 1e-9 of it. */
+#define ORACLE_SMA_MEMORY 5
+#define ORACLE_SMA_GTOL 1e-6
+#define ORACLE_SMA_FTOL 1e-9
+
 int oracle_solve(const oracle_problem *p, const oracle_domain *d, const oracle_opts *o, oracle_result *res)
 {
     double t_start = now_s();
@@ -738,6 +971,20 @@ int oracle_solve(const oracle_problem *p, const oracle_domain *d, const oracle_o
             double h[3];
             oracle_decode(rk[best], d->r_lo, d->r_hi, best_r, h);
             oracle_decode(tk[best], d->t_lo, d->t_hi, best_t, h);
+            if (o->sma_iters > 0) {
+                /* Algorithm 1's SMA step, from the centre of the child that
+                 * improved d* most in this iteration (all children of an
+                 * iteration are bounded together) */
+                const oracle_sma_opts so = {o->sma_iters, ORACLE_SMA_MEMORY, ORACLE_SMA_GTOL, ORACLE_SMA_FTOL};
+                double rs[3], ts[3], fs;
+                res->sma_runs++;
+                if (oracle_sma(p, d, best_r, best_t, &so, rs, ts, &fs) >= 0 && fs < dstar) {
+                    dstar = fs;
+                    memcpy(best_r, rs, sizeof rs);
+                    memcpy(best_t, ts, sizeof ts);
+                    res->sma_improved++;
+                }
+            }
         }
         for (int64_t q = 0; q < nc; ++q) {
             if (cb[q].status != 0) continue;

@@ -56,6 +56,8 @@ typedef struct {
     int64_t max_iters;
     double time_limit_s;
     int nthreads;          /* 0: OpenMP default */
+    int sma_iters;         /* > 0: run SMA (oracle_sma, at most this many iterations) from the
+                              best child of an iteration whenever it improves d* */
 } oracle_opts;
 
 typedef struct {
@@ -64,7 +66,17 @@ typedef struct {
     int64_t iters, cubes, max_queue;
     int32_t status;        /* 0 eps-optimal, 1 queue exhausted, 2 iteration/time cap */
     double seconds;
+    int64_t sma_runs;      /* SMA runs, and how many of them lowered d* below the cube's bound */
+    int64_t sma_improved;
 } oracle_result;
+
+/* SMA options (Section 6 local optimiser, oracle_sma). */
+typedef struct {
+    int max_iters;         /* L-BFGS iterations */
+    int memory;            /* curvature pairs kept (1..16) */
+    double gtol;           /* stop when |projected gradient|_inf <= gtol * (S11 + 2 S12) at the start */
+    double ftol;           /* stop when a step lowers f by <= ftol * (|f| + S11 + 2 S12) */
+} oracle_sma_opts;
 
 /* Section 3 densities (for the Fig. 3b check). */
 double oracle_log_Z(double x);
@@ -94,6 +106,12 @@ int oracle_bounds_cube(const oracle_problem *p, const oracle_domain *d, uint64_t
                        uint64_t tkey, oracle_bound *out);
 int oracle_eval_bounds(const oracle_problem *p, const oracle_domain *d, const uint64_t *rkeys,
                        const uint64_t *tkeys, int64_t n, oracle_bound *out, int nthreads);
+
+/* Gradient of the objective with respect to (r, t); returns f. */
+double oracle_objective_grad(const oracle_problem *p, const double r[3], const double t[3], double grad[6]);
+/* SMA from (r0, t0) inside the domain; returns iterations or -1 (start not allowed). */
+int oracle_sma(const oracle_problem *p, const oracle_domain *d, const double r0[3], const double t0[3],
+               const oracle_sma_opts *o, double r_out[3], double t_out[3], double *f_out);
 
 int oracle_solve(const oracle_problem *p, const oracle_domain *d, const oracle_opts *o,
                  oracle_result *res);
