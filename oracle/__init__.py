@@ -14,6 +14,7 @@ import numpy as np
 
 HERE = Path(__file__).resolve().parent
 SRC = HERE / "gosma_oracle.c"
+SRC_MIXGEN = HERE / "mixgen_oracle.c"
 LIB = HERE / "libgosma_oracle.so"
 
 
@@ -23,7 +24,7 @@ def build(force=True):
         return LIB
     tmp = LIB.with_suffix(".so.tmp")
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra",
-           "-D_POSIX_C_SOURCE=200809L", str(SRC), "-o", str(tmp), "-lm"]
+           "-D_POSIX_C_SOURCE=200809L", str(SRC), str(SRC_MIXGEN), "-o", str(tmp), "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
@@ -107,6 +108,15 @@ def lib():
         L.oracle_solve.argtypes = [C.POINTER(Problem), C.POINTER(Domain), C.POINTER(Opts), C.POINTER(Result)]
         L.oracle_objective_grad.restype = C.c_double
         L.oracle_objective_grad.argtypes = [C.POINTER(Problem), d3, d3, d3]
+        i32p, i64p = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+        for name in ("oracle_dpmeans", "oracle_dpvmf_means"):
+            getattr(L, name).restype = C.c_int
+            getattr(L, name).argtypes = [d3, C.c_int64, C.c_double, C.c_int, C.c_int, i32p, d3, i64p,
+                                         C.POINTER(C.c_int)]
+        L.oracle_vmf_kappa_ml.restype = C.c_double
+        L.oracle_vmf_kappa_ml.argtypes = [C.c_double]
+        L.oracle_gmm_sigma_ml.restype = None
+        L.oracle_gmm_sigma_ml.argtypes = [d3, C.c_int64, i32p, d3, i64p, C.c_int, d3]
         L.oracle_sma.restype = C.c_int
         L.oracle_sma.argtypes = [C.POINTER(Problem), C.POINTER(Domain), d3, d3, C.POINTER(SmaOpts), d3, d3, d3]
         _lib = L
@@ -246,3 +256,41 @@ def decode(key, lo, hi):
     h = np.zeros(3)
     lib().oracle_decode(C.c_uint64(int(key)), _dp(lo), _dp(hi), _dp(c), _dp(h))
     return c, h
+
+
+def _cluster(fn, x, lam, max_clusters, max_passes):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n = x.shape[0]
+    z = np.zeros(max(n, 1), dtype=np.int32)
+    mu = np.zeros((max_clusters, 3))
+    cnt = np.zeros(max_clusters, dtype=np.int64)
+    passes = C.c_int()
+    K = fn(_dp(x), n, float(lam), int(max_clusters), int(max_passes), z.ctypes.data_as(C.POINTER(C.c_int32)),
+           _dp(mu), cnt.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(passes))
+    return {"K": K, "labels": z[:n], "centres": mu[:K].copy(), "counts": cnt[:K].copy(), "passes": passes.value}
+
+
+def dpmeans(x, lam, max_clusters=1024, max_passes=100):
+    """DP-means (serial batch algorithm): {K, labels, centres, counts, passes}."""
+    return _cluster(lib().oracle_dpmeans, x, lam, max_clusters, max_passes)
+
+
+def dpvmf_means(x, cos_lam, max_clusters=1024, max_passes=100):
+    """DP-vMF-means on unit vectors: {K, labels, centres (unit), counts, passes}."""
+    return _cluster(lib().oracle_dpvmf_means, x, cos_lam, max_clusters, max_passes)
+
+
+def vmf_kappa_ml(rbar):
+    return lib().oracle_vmf_kappa_ml(float(rbar))
+
+
+def gmm_sigma_ml(x, labels, centres, counts):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    z = np.ascontiguousarray(labels, dtype=np.int32)
+    mu = np.ascontiguousarray(centres, dtype=np.float64)
+    cnt = np.ascontiguousarray(counts, dtype=np.int64)
+    K = mu.shape[0]
+    s = np.zeros(max(K, 1))
+    lib().oracle_gmm_sigma_ml(_dp(x), x.shape[0], z.ctypes.data_as(C.POINTER(C.c_int32)), _dp(mu),
+                              cnt.ctypes.data_as(C.POINTER(C.c_int64)), K, _dp(s))
+    return s[:K]

@@ -116,6 +116,16 @@ int oracle_sma(const oracle_problem *p, const oracle_domain *d, const double r0[
 int oracle_solve(const oracle_problem *p, const oracle_domain *d, const oracle_opts *o,
                  oracle_result *res);
 
+/* Mixture generation (Section 7, mixgen_oracle.c): DP-means and DP-vMF-means
+ * clustering and the maximum-likelihood fits. */
+int oracle_dpmeans(const double *x, int64_t n, double lambda, int max_clusters, int max_passes, int32_t *z,
+                   double *mu, int64_t *counts, int *passes);
+int oracle_dpvmf_means(const double *x, int64_t n, double lambda, int max_clusters, int max_passes, int32_t *z,
+                       double *mu, int64_t *counts, int *passes);
+double oracle_vmf_kappa_ml(double rbar);
+void oracle_gmm_sigma_ml(const double *x, int64_t n, const int32_t *z, const double *mu, const int64_t *counts,
+                         int K, double *sigma);
+
 #ifdef __cplusplus
 }
 #endif
