@@ -152,6 +152,10 @@ typedef struct {
                                 bound is clamped to [0, learned_window]; <= 0: to [0, 10].  Cubes
                                 whose lower bound is within eps of d* are ordered after all others
                                 (by lower bound) under either setting */
+    int sma_iters;           /* > 0: Algorithm 1's SMA step (Section 6): after each iteration in
+                                which a bounded cube lowered d*, run SMA (gosma_refine, at most
+                                sma_iters L-BFGS iterations) from the centre of the cube holding
+                                d* and keep its result when it is lower; 0 = off (<= 10000) */
 } gosma_opts;
 
 typedef struct {
@@ -165,6 +169,8 @@ typedef struct {
     double seconds;          /* wall time inside the call */
     int status;              /* 0 eps-optimal, 1 queue exhausted, 2 iteration/time cap, 3 queue
                                 capacity reached (f_best and lb_global still bound the optimum) */
+    int64_t sma_runs;        /* SMA runs of the search, and how many of them lowered d* (r, t is */
+    int64_t sma_improved;    /* then SMA's pose rather than a cube centre) */
 } gosma_result;
 
 /* Solve problem 0 to eps-optimality (Algorithm 1 without local refinement).
@@ -187,6 +193,74 @@ int gosma_get_trace(gosma_ctx *ctx, double *buf, int64_t cap, int64_t *n);
  * status 3 while the others go on; the call then returns
  * GOSMA_E_QUEUE_OVERFLOW with every result filled. */
 int gosma_solve_batch(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *results);
+
+/* SMA, the local optimiser of Algorithm 1 (Section 6): L-BFGS on the
+ * objective of Lemma 1 (eqs. 10-13, eq. 17) over the pose (r, t), with the
+ * gradient by the chain rule.  The L-BFGS direction (5 curvature pairs,
+ * initial scaling s^T y / y^T y) is followed along the path projected on the
+ * problem's domain box (rotation box x translation box), with Armijo
+ * backtracking (sufficient-decrease constant 1e-4, at most 40 halvings from
+ * the unit step; the first direction is -g scaled to length <= 0.05); poses
+ * within zeta of a Gaussian mean are infeasible.  Stops after max_iters
+ * iterations, when the projected gradient's largest component is at most
+ * 1e-6 of S11 + 2 S12 at the start, or when a step lowers f by at most 1e-9 of
+ * |f| + S11 + 2 S12.  Pair terms are FP32 in log space, sums and the pose FP64.
+ *   n          number of starts (one GPU block each)
+ *   problem    host uint32 problem index per start, or NULL (all problem 0)
+ *   r0, t0     host n x 3 start poses (angle-axis rotation, camera centre)
+ *   max_iters  L-BFGS iterations; 0 evaluates f and its gradient at the starts
+ *   r_out, t_out  host n x 3 results; f_out host n objective values there
+ *   grad_out   host n x 6 gradient {d/dr, d/dt} at the result, or NULL
+ *   iters_out  host n iterations taken; -1 if the start lies outside the box
+ *              or within zeta of a mean (f_out = +inf) or the problem index is
+ *              out of range (f_out = NaN)
+ * Synchronous; allocates and frees its own device buffers.  Errors:
+ * GOSMA_E_STATE before mixtures and a domain are set, GOSMA_E_INVAL for n < 0,
+ * max_iters < 0 or a NULL required pointer. */
+int gosma_refine(gosma_ctx *ctx, int64_t n, const uint32_t *problem, const double *r0, const double *t0,
+                 int max_iters, double *r_out, double *t_out, double *f_out, double *grad_out, int32_t *iters_out);
+
+/* Mixture generation (Section 7): the GMM theta_1 from a 3D point set by
+ * DP-means clustering and the vMF mixture theta_2 from bearing vectors by
+ * DP-vMF-means, with a maximum-likelihood component fitted to each cluster.
+ * Both run the serial batch algorithm of their papers (Kulis and Jordan 2012;
+ * Straub et al. 2015): passes over the points in index order, each point
+ * joining the best cluster that exists when it is visited (ties: the cluster
+ * created first) or opening a new cluster at itself when even the best is
+ * beyond lambda; after each pass the centres are recomputed from their
+ * points (DP-vMF-means: the normalised sum) and empty clusters are removed
+ * in order; passes stop when no label changes or after max_passes.  The
+ * first pass starts from one cluster at the mean of all points (DP-vMF-means:
+ * their mean direction).  Scores are FP64, evaluated as |x - mu|^2 (x, y, z in
+ * order) and x . mu without fused multiply-adds; centre sums are FP64
+ * atomics, exact in any order when the inputs lie on a binary grid whose sums
+ * do not exceed 53 bits (e.g. points on a 2^-24 m grid within 64 m, up to
+ * 2^20 of them), which makes the result identical to a serial evaluation.
+ *   points / dirs  device n x 3 FP64 (context's device); dirs unit vectors
+ *   lambda         DP-means: squared distance beyond which a point opens a
+ *                  cluster; cos_lambda: cosine below which a direction does
+ *   max_clusters   1 .. GOSMA_MAX_CLUSTERS; a pass that would open more lets
+ *                  the point join its best cluster and *passes is negated
+ *   sigma_min      the fitted isotropic standard deviation sqrt(sum |x -
+ *                  mu|^2 / (3 n)) is raised to at least this (one-point
+ *                  clusters); kappa_max: the fitted concentration (root of
+ *                  coth k - 1/k = |sum x| / n) is lowered to at most this
+ *   labels         device n int32 out: cluster of each point
+ *   centres, counts, sigma / kappa   host arrays of max_clusters (x 3) out;
+ *                  the first *K entries are set (mixture weights: counts / n)
+ *   K, passes      host out
+ * Synchronous on `stream`; allocates and frees its own device buffers.
+ * Errors: GOSMA_E_INVAL for n outside [1, 2^30], max_clusters outside
+ * [1, GOSMA_MAX_CLUSTERS], max_passes < 1, a non-finite lambda, a clamp <= 0,
+ * NULL pointers or points / labels that are not device memory of the context's
+ * device. */
+#define GOSMA_MAX_CLUSTERS 2048
+int gosma_dpmeans(gosma_ctx *ctx, const double *points, int64_t n, double lambda, int max_clusters, int max_passes,
+                  double sigma_min, int32_t *labels, double *centres, int64_t *counts, double *sigma, int *K,
+                  int *passes, void *stream);
+int gosma_dpvmf_means(gosma_ctx *ctx, const double *dirs, int64_t n, double cos_lambda, int max_clusters,
+                      int max_passes, double kappa_max, int32_t *labels, double *centres, int64_t *counts,
+                      double *kappa, int *K, int *passes, void *stream);
 
 /* Checkpoint of the search (Algorithm 1's state between two iterations: the
  * queued sub-cubes with their lower bounds, d* and its pose, the counters).
@@ -308,6 +382,7 @@ int gosma_autotune(gosma_ctx *ctx, int64_t n_cubes, uint64_t seed, double *rows,
 #define GOSMA_KERNEL_BRANCH 3   /* children of the selected cubes */
 #define GOSMA_KERNEL_PUSH 4     /* best upper bound, pruning and queue insertion */
 #define GOSMA_KERNEL_MLP 5      /* learned-priority network (inference and training) */
+#define GOSMA_KERNEL_SMA 6      /* SMA local refinement inside the search */
 #define GOSMA_N_KERNELS 8
 int gosma_set_timing(gosma_ctx *ctx, int enable);
 int gosma_get_timing(gosma_ctx *ctx, double *ms, int64_t *launches);

@@ -13,12 +13,17 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libgosma.so"
-SOURCES = ["api.hip", "bound.hip", "bb.hip", "mlp.hip", "tune.hip"]
+SOURCES = ["api.hip", "bound.hip", "bb.hip", "mlp.hip", "tune.hip", "sma.hip", "mixgen.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # gfx950 only; packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall"]
+
+
+# Per-file flags: the clustering decisions of mixgen.hip must be the plain
+# left-to-right FP64 expressions (no fused multiply-adds).
+FILE_FLAGS = {"mixgen.hip": ["-ffp-contract=off"]}
 
 
 def build(verbose=False, extra=()):
@@ -27,7 +32,7 @@ def build(verbose=False, extra=()):
     objs = []
     for src in SOURCES:
         obj = build_dir / (src + ".o")
-        cmd = [HIPCC, *DEVICE_FLAGS, *extra, "-I", str(ROOT / "include"), "-I", str(CSRC),
+        cmd = [HIPCC, *DEVICE_FLAGS, *FILE_FLAGS.get(src, []), *extra, "-I", str(ROOT / "include"), "-I", str(CSRC),
                "-c", str(CSRC / src), "-o", str(obj)]
         if verbose:
             print(" ".join(cmd), flush=True)

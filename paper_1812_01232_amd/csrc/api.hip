@@ -488,6 +488,58 @@ int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tke
     return GOSMA_OK;
 }
 
+int gosma_refine(gosma_ctx *ctx, int64_t n, const uint32_t *problem, const double *r0, const double *t0,
+                 int max_iters, double *r_out, double *t_out, double *f_out, double *grad_out, int32_t *iters_out)
+{
+    if (!ctx) return GOSMA_E_INVAL;
+    ctx->err.clear();
+    if (ctx->n_problems < 1 || !ctx->has_domain)
+        return fail(ctx, GOSMA_E_STATE, "set mixtures and a domain before refining poses");
+    if (n < 0 || max_iters < 0) return fail(ctx, GOSMA_E_INVAL, "n and max_iters must be >= 0");
+    if (n == 0) return GOSMA_OK;
+    if (!r0 || !t0 || !r_out || !t_out || !f_out || !iters_out)
+        return fail(ctx, GOSMA_E_INVAL, "a required pointer is NULL");
+    if (!problem && ctx->n_problems != 1)
+        return fail(ctx, GOSMA_E_INVAL, "problem indices are required when several problems are set");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    std::vector<double> x0(6 * (size_t)n);
+    for (int64_t s = 0; s < n; ++s)
+        for (int a = 0; a < 3; ++a) {
+            x0[6 * s + a] = r0[3 * s + a];
+            x0[6 * s + 3 + a] = t0[3 * s + a];
+        }
+    // one device block: starts, problem indices, poses, values, gradients, iterations
+    const size_t b_x = sizeof(double) * 6 * n, b_p = (sizeof(uint32_t) * n + 255) & ~(size_t)255;
+    const size_t b_f = (sizeof(double) * n + 255) & ~(size_t)255, b_i = sizeof(int32_t) * n;
+    const size_t bytes = 3 * ((b_x + 255) & ~(size_t)255) + b_p + b_f + b_i;
+    uint8_t *buf = nullptr;
+    HIP_TRY(ctx, hipMalloc((void **)&buf, bytes));
+    double *d_x0 = (double *)buf, *d_x = (double *)(buf + ((b_x + 255) & ~(size_t)255));
+    double *d_g = (double *)(buf + 2 * ((b_x + 255) & ~(size_t)255));
+    uint32_t *d_p = (uint32_t *)(buf + 3 * ((b_x + 255) & ~(size_t)255));
+    double *d_f = (double *)((uint8_t *)d_p + b_p);
+    int32_t *d_it = (int32_t *)((uint8_t *)d_f + b_f);
+    hipError_t e = hipMemcpy(d_x0, x0.data(), b_x, hipMemcpyHostToDevice);
+    if (e == hipSuccess && problem) e = hipMemcpy(d_p, problem, sizeof(uint32_t) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = gosma::launch_sma(ctx->mix(), ctx->maxM, ctx->maxN, n, problem ? d_p : nullptr, d_x0, max_iters,
+                              gosma::kSmaMemory, gosma::kSmaGtol, gosma::kSmaFtol, d_x, d_f, d_g, d_it, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    std::vector<double> hx(6 * (size_t)n), hg(grad_out ? 6 * (size_t)n : 0);
+    if (e == hipSuccess) e = hipMemcpy(hx.data(), d_x, b_x, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(f_out, d_f, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(iters_out, d_it, sizeof(int32_t) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && grad_out) e = hipMemcpy(grad_out, d_g, b_x, hipMemcpyDeviceToHost);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return hip_fail(ctx, e, "gosma_refine");
+    for (int64_t s = 0; s < n; ++s)
+        for (int a = 0; a < 3; ++a) {
+            r_out[3 * s + a] = hx[6 * s + a];
+            t_out[3 * s + a] = hx[6 * s + 3 + a];
+        }
+    return GOSMA_OK;
+}
+
 int gosma_set_record_sink(gosma_ctx *ctx, float *records, int64_t capacity, unsigned long long *count)
 {
     if (!ctx) return GOSMA_E_INVAL;

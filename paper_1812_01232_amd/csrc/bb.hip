@@ -33,6 +33,7 @@
 #include <cstring>
 
 #include "gosma_impl.h"
+#include "sma_core.h"
 
 namespace gosma {
 
@@ -65,6 +66,11 @@ struct PState {
     uint32_t nskip;                // selected cubes that cannot be split (no children)
     uint32_t take_all, prefix, need, eq_quota, eq_taken;   // radix select
     uint32_t rb_target;            // hot entries wanted after a re-partition
+    // SMA (Section 6): the pose of d* when SMA set it, and the d* it last started from
+    double pose[6];
+    unsigned long long sma_from;   // ordered bits of d* at the last SMA start
+    uint32_t pose_sma;             // 1: d* was found by SMA at `pose` (else: the centre of the best keys)
+    uint32_t sma_runs, sma_gain, pad_sma;
 };
 
 struct GState {
@@ -638,6 +644,7 @@ __global__ __launch_bounds__(kBlock) void k_push(Bufs b, const float *prio_overr
                 if (b.cub[i] < INFINITY && ord64(b.cub[i]) == draw) {
                     s.best_rkey = b.crk[i];
                     s.best_tkey = b.ctk[i];
+                    s.pose_sma = 0;
                 }
                 lbs = fmax(sane_lb(b.clbs[i]), b.par.lb[b.cpar[i]]);
                 if (lbs < unord64(draw)) {
@@ -725,6 +732,7 @@ __global__ __launch_bounds__(kBlock) void k_push_agg(Bufs b, const float *prio_o
                 if (b.cub[i] < INFINITY && ord64(b.cub[i]) == draw) {
                     s.best_rkey = b.crk[i];
                     s.best_tkey = b.ctk[i];
+                    s.pose_sma = 0;
                 }
                 lbs = fmax(sane_lb(b.clbs[i]), b.par.lb[b.cpar[i]]);
                 if (lbs < unord64(draw)) {
@@ -910,6 +918,7 @@ __global__ void k_seed(Bufs b, int P)
     if (b.cub[p] < INFINITY && ord64(b.cub[p]) == s.dstar) {
         s.best_rkey = b.crk[p];
         s.best_tkey = b.ctk[p];
+        s.pose_sma = 0;
     }
     if (fl & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS)) {
         s.done = EXHAUSTED;
@@ -935,6 +944,53 @@ __global__ void k_seed(Bufs b, int P)
     s.minH = ord64(lbs);
 }
 
+// Algorithm 1's SMA step: when a bounded cube has lowered d* since SMA last
+// ran, refine from the centre of that cube (the child holding d*, recorded by
+// the push) and keep the result if it lowers d* further.  One block per
+// problem; a problem whose d* did not move since the last start, or whose d*
+// came from SMA, returns at once.
+__global__ __launch_bounds__(sma::kSmaThreads) void k_sma_search(Bufs b, DevMix mx, int P, int max_iters)
+{
+    extern __shared__ float4 lds[];
+    __shared__ sma::SmaShared sh;
+    __shared__ sma::SmaState sst;
+    const int tid = threadIdx.x;
+    for (int p = blockIdx.x; p < P; p += gridDim.x) {
+        PState &s = b.st[p];
+        const unsigned long long dbits = s.dstar;
+        const bool run = !s.done && !s.pose_sma && dbits != s.sma_from && unord64(dbits) < INFINITY;
+        __syncthreads();
+        if (!run) continue;
+        const ProbDesc D = mx.prob[p];
+        if (tid == 0) {
+            const uint64_t m = (1ull << 19) - 1;
+            const uint64_t rk = s.best_rkey, tk = s.best_tkey;
+            const int Lr = key_level(rk), Lt = key_level(tk);
+            const uint64_t ir[3] = {(rk >> 38) & m, (rk >> 19) & m, rk & m};
+            const uint64_t it[3] = {(tk >> 38) & m, (tk >> 19) & m, tk & m};
+            for (int a = 0; a < 3; ++a) {
+                sh.x[a] = D.r_lo[a] + (2.0 * (double)ir[a] + 1.0) * ldexp(D.r_w[a], -(Lr + 1));
+                sh.x[3 + a] = D.t_lo[a] + (2.0 * (double)it[a] + 1.0) * ldexp(D.t_w[a], -(Lt + 1));
+            }
+        }
+        __syncthreads();
+        double x[6], f, g[6];
+        const int it = sma::sma_run(mx, D, sh, sst, sma::sma_lds(lds, D.M, D.N), max_iters, kSmaMemory, kSmaGtol,
+                                    kSmaFtol, x, f, g);
+        if (tid == 0) {
+            s.sma_from = dbits;
+            s.sma_runs += 1;
+            if (it >= 0 && f < unord64(dbits)) {
+                s.dstar = ord64(f);
+                for (int a = 0; a < 6; ++a) s.pose[a] = x[a];
+                s.pose_sma = 1;
+                s.sma_from = s.dstar;
+                s.sma_gain += 1;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 // Device buffers of a solve, owned by the context and reused while large enough.
@@ -952,6 +1008,7 @@ struct Solver {
     int graph_mode = -1;      // captured mode: learned | logging
     float graph_window = 0.0f;
     int graph_iters = 0;      // iterations per captured graph
+    int graph_sma = 0;        // SMA iterations of the captured graph
 };
 
 }  // namespace gosma
@@ -1119,7 +1176,7 @@ unsigned long long ordh(double x)
 // Launch one iteration (all problems).  Every launch has a fixed shape and
 // reads its work counts from device memory, so the sequence can be captured.
 hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool timed, bool learned, bool logging,
-                            float window, bool rb_slot, int rb_every)
+                            float window, bool rb_slot, int rb_every, int sma_iters)
 {
     using namespace gosma;
     Bufs &b = S.b;
@@ -1194,8 +1251,14 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
         else
             hipLaunchKernelGGL(k_push, dim3(kGridX), dim3(kBlock), 0, st, b, po, P);
     }
-    hipLaunchKernelGGL(k_iter_end, dim3((P + 63) / 64), dim3(64), 0, st, b, P, rb_every);
     T1(ti);
+    if (sma_iters > 0) {
+        ti = T0(GOSMA_KERNEL_SMA);
+        hipLaunchKernelGGL(k_sma_search, dim3(std::min(P, 1024)), dim3(sma::kSmaThreads),
+                           sma_lds_bytes(ctx->maxM, ctx->maxN), st, b, mx, P, sma_iters);
+        T1(ti);
+    }
+    hipLaunchKernelGGL(k_iter_end, dim3((P + 63) / 64), dim3(64), 0, st, b, P, rb_every);
     return hipGetLastError();
 }
 
@@ -1214,10 +1277,11 @@ struct SnapProb {
     double S22, zeta, r_lo[3], r_w[3], t_lo[3], t_w[3];
     double dstar, floor_lb;
     uint64_t best_rkey, best_tkey, bounded, n;
-    uint32_t iters, pad;
+    uint32_t iters, pose_sma;
+    double pose[6];            // the pose of d* when SMA found it (pose_sma = 1)
 };
 constexpr char kSnapMagic[8] = {'G', 'O', 'S', 'M', 'A', 'Q', 'S', '1'};
-constexpr uint32_t kSnapVersion = 1;
+constexpr uint32_t kSnapVersion = 2;
 
 size_t snap_cube_bytes(uint64_t n) { return 24 * (size_t)n + (size_t)((n + 7) & ~7ull); }
 
@@ -1284,6 +1348,8 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
     const bool learned = opts->order == 1, logging = opts->log_records != 0;
     if (opts->order != 0 && opts->order != 1) return fail(GOSMA_E_INVAL, "order must be 0 (best-first) or 1 (learned)");
     if (learned && !ctx->mlp_ready()) return fail(GOSMA_E_STATE, "learned order needs a network (gosma_mlp_init/set_params)");
+    if (opts->sma_iters < 0 || opts->sma_iters > 10000) return fail(GOSMA_E_INVAL, "sma_iters must be in [0, 10000]");
+    const int sma_iters = opts->sma_iters;
     if (logging && !ctx->rec_sink) return fail(GOSMA_E_STATE, "record logging needs gosma_set_record_sink");
     // a pending gosma_resume: the problems may have changed since, so check again
     const bool resuming = !ctx->resume.empty();
@@ -1311,12 +1377,18 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
     const size_t hcap = std::max<size_t>(std::min<size_t>(std::max<size_t>(256 * k, (size_t)1 << 20), ccap),
                                          64 * k + 16);
     const float window = (float)opts->learned_window;
-    const int mode = (learned ? 1 : 0) | (logging ? 2 : 0);
+    const int mode = (learned ? 1 : 0) | (logging ? 2 : 0) | (sma_iters > 0 ? 4 : 0);
     const bool timed = ctx->timing;
     const bool tracing = opts->trace_every > 0 && P == 1;
     const int check = (timed || tracing) ? 1 : 4;   // iterations between status reads
-    if (S.graph_maxM != ctx->maxM || S.graph_mode != mode || S.graph_window != window || S.graph_iters != check)
+    if (S.graph_maxM != ctx->maxM || S.graph_mode != mode || S.graph_window != window || S.graph_iters != check ||
+        S.graph_sma != sma_iters)
         drop_graph(&S);   // the captured launches depend on these
+    if (sma_iters > 0) {
+        e = hipFuncSetAttribute((const void *)k_sma_search, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sma_lds_bytes(ctx->maxM, ctx->maxN));
+        if (e) return fail(GOSMA_E_HIP, "SMA kernel set-up", e);
+    }
     if ((e = ensure_solver(&S, P, k, hcap, ccap, logging)))
         return fail(GOSMA_E_NOMEM, "allocating solver buffers", e);
     Bufs &b = S.b;
@@ -1338,7 +1410,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
     for (int p = 0; p < P; ++p) {
         PState &s = init[p];
         std::memset(&s, 0, sizeof s);
-        s.dstar = s.minH = s.minC = s.floor_lb = ordh(INFINITY);
+        s.dstar = s.minH = s.minC = s.floor_lb = s.sma_from = ordh(INFINITY);
         s.eps_f = opts->eps * ctx->h_prob[p].S22;
         s.theta = 0xffffffffu;
         s.max_iters = (uint32_t)std::min<int64_t>(opts->max_iters, 0xffffffffll);
@@ -1364,6 +1436,9 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
             s.minC = ordh(mn);
             s.best_rkey = q.best_rkey;
             s.best_tkey = q.best_tkey;
+            s.pose_sma = q.pose_sma != 0;
+            for (int a = 0; a < 6; ++a) s.pose[a] = q.pose[a];
+            s.sma_from = s.dstar;   // SMA restarts only once d* moves again
             s.bounded = q.bounded;
             s.iters = q.iters;
             if (opts->max_iters > 0)
@@ -1420,7 +1495,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         if (!e) {
             hipError_t le = hipSuccess;
             for (int r = 0; r < check && !le; ++r)
-                le = launch_iteration(ctx, S, st, false, learned, logging, window, r == 0, check);
+                le = launch_iteration(ctx, S, st, false, learned, logging, window, r == 0, check, sma_iters);
             e = hipStreamEndCapture(st, &S.graph);
             if (!e) e = le;
         }
@@ -1434,6 +1509,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
             S.graph_mode = mode;
             S.graph_window = window;
             S.graph_iters = check;
+            S.graph_sma = sma_iters;
         }
     }
     int rc = GOSMA_OK;
@@ -1460,7 +1536,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
             e = hipGraphLaunch(S.exec, st);
         else
             for (int r = 0; r < check && !e; ++r)
-                e = launch_iteration(ctx, S, st, timed, learned, logging, window, r == 0, check);
+                e = launch_iteration(ctx, S, st, timed, learned, logging, window, r == 0, check, sma_iters);
         if (e) {
             rc = fail(GOSMA_E_HIP, "branch-and-bound iteration", e);
             break;
@@ -1489,8 +1565,17 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
             uint64_t idx[3] = {(key >> 38) & m, (key >> 19) & m, key & m};
             for (int a = 0; a < 3; ++a) c[a] = lo[a] + (2.0 * (double)idx[a] + 1.0) * std::ldexp(w[a], -(L + 1));
         };
-        centre(h.best_rkey, D.r_lo, D.r_w, r.r);
-        centre(h.best_tkey, D.t_lo, D.t_w, r.t);
+        if (h.pose_sma) {
+            for (int a = 0; a < 3; ++a) {
+                r.r[a] = h.pose[a];
+                r.t[a] = h.pose[3 + a];
+            }
+        } else {
+            centre(h.best_rkey, D.r_lo, D.r_w, r.r);
+            centre(h.best_tkey, D.t_lo, D.t_w, r.t);
+        }
+        r.sma_runs = h.sma_runs;
+        r.sma_improved = h.sma_gain;
         if (h.done == OVERFLOW && rc == GOSMA_OK)
             rc = fail(GOSMA_E_QUEUE_OVERFLOW, "branch-and-bound queue capacity exceeded");
     }
@@ -1572,6 +1657,8 @@ int gosma_snapshot(gosma_ctx *ctx, void *buf, size_t *bytes)
         q.floor_lb = unord64(h.floor_lb);
         q.best_rkey = h.best_rkey;
         q.best_tkey = h.best_tkey;
+        q.pose_sma = h.pose_sma;
+        for (int a = 0; a < 6; ++a) q.pose[a] = h.pose[a];
         q.bounded = h.bounded;
         q.iters = h.iters;
         q.n = (uint64_t)h.nH[h.hcur] + h.nC[h.ccur];

@@ -132,6 +132,22 @@ size_t s11_lds_bytes(int maxM, int waves);
 size_t s12_lds_bytes(int maxM, int maxN, int waves, bool vlds);
 hipError_t prepare_bound_kernels(int maxM, int maxN);
 
+// SMA (sma.hip): L-BFGS from n starts x0 (n x 6 doubles {r, t}), one block per
+// start; results x_out (n x 6), f_out (n), g_out (n x 6 or NULL), it_out (n).
+constexpr int kSmaMemory = 5;         // curvature pairs
+constexpr double kSmaGtol = 1e-6;     // projected-gradient stop, relative to S11 + 2 S12 at the start
+constexpr double kSmaFtol = 1e-9;     // per-step gain stop, relative to |f| + S11 + 2 S12
+size_t sma_lds_bytes(int maxM, int maxN);
+hipError_t launch_sma(const DevMix &mx, int maxM, int maxN, int64_t n, const uint32_t *pids, const double *x0,
+                      int max_iters, int memory, double gtol, double ftol, double *x_out, double *f_out,
+                      double *g_out, int32_t *it_out, hipStream_t stream);
+
+// Mixture generation (mixgen.hip): one DP-means (spherical = 0) or
+// DP-vMF-means (spherical = 1) clustering with the ML fit of each cluster.
+hipError_t dp_cluster(const double *x, int64_t n, double lambda, int spherical, int max_clusters, int max_passes,
+                      double clamp, int32_t *z, std::vector<double> &centres, std::vector<int64_t> &counts,
+                      std::vector<double> &spread, int &K_out, int &passes_out, hipStream_t st);
+
 struct Mlp;
 hipError_t mlp_predict(const Mlp &m, const float *X, int64_t n, const uint32_t *n_dev, float *y, int grid,
                        hipStream_t s);

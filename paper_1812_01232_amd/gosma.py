@@ -26,9 +26,9 @@ EXPORTS = ["gosma_create", "gosma_destroy", "gosma_last_error", "gosma_set_mixtu
            "gosma_set_timing", "gosma_get_timing", "gosma_get_trace", "gosma_mlp_init", "gosma_mlp_set_params",
            "gosma_mlp_get_params", "gosma_mlp_predict", "gosma_mlp_loss_grad", "gosma_mlp_train",
            "gosma_set_record_sink", "gosma_get_tiles", "gosma_set_tiles", "gosma_autotune", "gosma_get_work_counts",
-           "gosma_snapshot", "gosma_resume"]
+           "gosma_snapshot", "gosma_resume", "gosma_refine", "gosma_dpmeans", "gosma_dpvmf_means"]
 MLP_FEATURES, MLP_RECORD, MLP_PARAMS = 20, 21, 35841
-KERNEL_KINDS = ["s11", "s12", "select", "branch", "push", "mlp"]
+KERNEL_KINDS = ["s11", "s12", "select", "branch", "push", "mlp", "sma"]
 WORK_COUNTS = ["cubes", "s12_screened", "s12_evaluated", "cells", "s11_screened", "s11_evaluated"]
 
 
@@ -47,7 +47,7 @@ class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("batch_parents", C.c_int64), ("max_queue", C.c_int64),
                 ("max_iters", C.c_int64), ("time_limit_s", C.c_double), ("order", C.c_int),
                 ("log_records", C.c_int), ("trace_every", C.c_int), ("no_graph", C.c_int),
-                ("learned_window", C.c_double)]
+                ("learned_window", C.c_double), ("sma_iters", C.c_int)]
 
 
 class Tile(C.Structure):
@@ -62,7 +62,7 @@ class Result(C.Structure):
     _fields_ = [("f_best", C.c_double), ("lb_global", C.c_double), ("f_norm_best", C.c_double),
                 ("lb_norm", C.c_double), ("r", C.c_double * 3), ("t", C.c_double * 3), ("iters", C.c_int64),
                 ("cubes", C.c_int64), ("max_queue_used", C.c_int64), ("seconds", C.c_double),
-                ("status", C.c_int)]
+                ("status", C.c_int), ("sma_runs", C.c_int64), ("sma_improved", C.c_int64)]
 
 
 _lib = None
@@ -107,6 +107,10 @@ def lib():
         L.gosma_set_tiles.argtypes = [vp, C.POINTER(Tiles)]
         L.gosma_autotune.argtypes = [vp, C.c_int64, C.c_uint64, dp, C.c_int64, C.POINTER(C.c_int64),
                                      C.POINTER(Tiles)]
+        L.gosma_refine.argtypes = [vp, C.c_int64, C.POINTER(C.c_uint32), dp, dp, C.c_int, dp, dp, dp, dp, ip]
+        for name in ("gosma_dpmeans", "gosma_dpvmf_means"):
+            getattr(L, name).argtypes = [vp, vp, C.c_int64, C.c_double, C.c_int, C.c_int, C.c_double, vp, dp,
+                                         C.POINTER(C.c_int64), dp, C.POINTER(C.c_int), C.POINTER(C.c_int), vp]
         _lib = L
     return _lib
 
@@ -259,6 +263,53 @@ class Context:
                     "gosma_eval_bounds")
         return out
 
+    # -- local refinement (SMA) ---------------------------------------------
+    def refine(self, r0, t0, max_iters=100, problem=None, want_grad=True):
+        """SMA from each start (rows of r0, t0): {"r", "t", "f", "grad", "iters"};
+        max_iters = 0 evaluates the objective and its gradient at the starts."""
+        r0 = _f64(np.atleast_2d(r0))
+        t0 = _f64(np.atleast_2d(t0))
+        n = r0.shape[0]
+        r, t, f = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros(n)
+        g = np.zeros((n, 6)) if want_grad else None
+        it = np.zeros(n, dtype=np.int32)
+        pr = None
+        if problem is not None:
+            pr = np.ascontiguousarray(problem, dtype=np.uint32)
+        self._check(lib().gosma_refine(self._h, n, None if pr is None else pr.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                       _d(r0), _d(t0), int(max_iters), _d(r), _d(t), _d(f), _d(g), _i(it)),
+                    "gosma_refine")
+        return {"r": r, "t": t, "f": f, "grad": g, "iters": it}
+
+    # -- mixture generation (clustering + ML fits) ----------------------------
+    def _cluster(self, fn, name, x, lam, max_clusters, max_passes, clamp):
+        import torch
+        dev = torch.device("cuda", self.device)
+        xt = x if isinstance(x, torch.Tensor) else torch.from_numpy(_f64(x))
+        xt = xt.to(dev, dtype=torch.float64).contiguous()
+        n = int(xt.shape[0])
+        lab = torch.empty(n, dtype=torch.int32, device=dev)
+        mu = np.zeros((max_clusters, 3))
+        cnt = np.zeros(max_clusters, dtype=np.int64)
+        sp = np.zeros(max_clusters)
+        K, passes = C.c_int(), C.c_int()
+        torch.cuda.synchronize(dev)
+        self._check(fn(self._h, _ptr(xt), n, float(lam), int(max_clusters), int(max_passes), float(clamp), _ptr(lab),
+                       _d(mu), cnt.ctypes.data_as(C.POINTER(C.c_int64)), _d(sp), C.byref(K), C.byref(passes),
+                       _current_stream()), name)
+        k = K.value
+        return {"K": k, "labels": lab.cpu().numpy(), "centres": mu[:k].copy(), "counts": cnt[:k].copy(),
+                "spread": sp[:k].copy(), "passes": passes.value}
+
+    def dpmeans(self, points, lam, max_clusters=1024, max_passes=100, sigma_min=1e-3):
+        """DP-means + isotropic Gaussian fit: {K, labels, centres, counts, spread (sigma), passes}."""
+        return self._cluster(lib().gosma_dpmeans, "gosma_dpmeans", points, lam, max_clusters, max_passes, sigma_min)
+
+    def dpvmf_means(self, dirs, cos_lam, max_clusters=1024, max_passes=100, kappa_max=1e5):
+        """DP-vMF-means + vMF fit: {K, labels, centres, counts, spread (kappa), passes}."""
+        return self._cluster(lib().gosma_dpvmf_means, "gosma_dpvmf_means", dirs, cos_lam, max_clusters, max_passes,
+                             kappa_max)
+
     # -- queue-ordering network -------------------------------------------
     def mlp_init(self, seed=0):
         self._check(lib().gosma_mlp_init(self._h, int(seed)), "gosma_mlp_init")
@@ -362,10 +413,10 @@ class Context:
 
     # -- branch and bound -------------------------------------------------
     def solve(self, eps, batch_parents=4096, max_queue=1 << 24, max_iters=0, time_limit_s=0.0, order=0,
-              log_records=0, trace_every=0, no_graph=False, learned_window=0.0, allow_overflow=False):
+              log_records=0, trace_every=0, no_graph=False, learned_window=0.0, allow_overflow=False, sma_iters=0):
         """With allow_overflow a full queue returns the result (status 3) instead of raising."""
         o = Opts(eps, batch_parents, max_queue, max_iters, time_limit_s, order, log_records, trace_every,
-                 int(bool(no_graph)), float(learned_window))
+                 int(bool(no_graph)), float(learned_window), int(sma_iters))
         r = Result()
         rc = lib().gosma_solve(self._h, C.byref(o), C.byref(r))
         if not (allow_overflow and rc == QUEUE_OVERFLOW):
@@ -381,10 +432,10 @@ class Context:
         return buf[:n.value]
 
     def solve_batch(self, n_problems, eps, batch_parents=2048, max_queue=1 << 22, max_iters=0, time_limit_s=0.0,
-                    order=0, no_graph=False, learned_window=0.0, allow_overflow=False):
+                    order=0, no_graph=False, learned_window=0.0, allow_overflow=False, sma_iters=0):
         """With allow_overflow problems whose queue filled up come back with status 3 instead of raising."""
         o = Opts(eps, batch_parents, max_queue, max_iters, time_limit_s, order, 0, 0, int(bool(no_graph)),
-                 float(learned_window))
+                 float(learned_window), int(sma_iters))
         rs = (Result * n_problems)()
         rc = lib().gosma_solve_batch(self._h, C.byref(o), rs)
         if not (allow_overflow and rc == QUEUE_OVERFLOW):

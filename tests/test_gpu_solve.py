@@ -301,17 +301,17 @@ def test_snapshot_resume_errors(ctx):
 
 def _snapshot_with_cubes(snap, rkeys, tkeys, lbs, flags):
     """Replace the queued cubes of a one-problem snapshot (layout of
-    gosma_snapshot: a 24-byte header, a 176-byte problem record whose last
-    fields are best keys, bounded count, n and iters, then n rkeys, n tkeys,
-    n lower bounds and n flag bytes padded to 8)."""
+    gosma_snapshot: a 24-byte header, a 224-byte problem record holding at
+    byte 152 the bounded count and at 160 n, then n rkeys, n tkeys, n lower
+    bounds and n flag bytes padded to 8)."""
     import struct
-    head, prob = bytearray(snap[:24]), bytearray(snap[24:200])
+    head, prob = bytearray(snap[:24]), bytearray(snap[24:248])
     n = len(rkeys)
     struct.pack_into("<Q", prob, 160, n)
     body = (np.asarray(rkeys, np.uint64).tobytes() + np.asarray(tkeys, np.uint64).tobytes() +
             np.asarray(lbs, np.float64).tobytes() + np.asarray(flags, np.uint8).tobytes())
     body += bytes((-len(body)) % 8)
-    struct.pack_into("<Q", head, 16, 24 + 176 + len(body))
+    struct.pack_into("<Q", head, 16, 24 + 224 + len(body))
     return bytes(head) + bytes(prob) + body, struct.unpack_from("<Q", prob, 152)[0]
 
 
