@@ -40,7 +40,7 @@ extern "C" {
 #define GOSMA_E_QUEUE_OVERFLOW (-4) /* the branch-and-bound queue exceeded its capacity */
 #define GOSMA_E_STATE (-5)          /* call made before the state it needs was set */
 
-#define GOSMA_MAX_COMPONENTS 1024   /* per mixture, per problem */
+#define GOSMA_MAX_COMPONENTS 4096   /* per mixture, per problem */
 #define GOSMA_MAX_LABELS 64
 
 typedef struct gosma_ctx gosma_ctx;
@@ -80,12 +80,14 @@ const char *gosma_last_error(const gosma_ctx *ctx);
  * both to use one class.  With labels only same-class pairs contribute and
  * the objective is sum_l f_l / n_labels, the weights being renormalised
  * within each class; without labels the weights are renormalised to sum 1.
- * All arrays are host FP64/int32 and are copied.  1 <= M, N <= 1024
- * (GOSMA_E_INVAL otherwise); a bound-kernel block stages 96 bytes per GMM
+ * All arrays are host FP64/int32 and are copied.  1 <= M, N <= 4096
+ * (GOSMA_E_INVAL otherwise).  A bound-kernel block stages 96 bytes per GMM
  * component in LDS plus 512 bytes per wave (and 32 bytes per vMF component
- * when several problems are set), which fits gfx950's 160 KB at M = N =
- * 1024; a device with less LDS per block rejects larger sizes with
- * GOSMA_E_INVAL. */
+ * when several problems are set), an SMA block 44 per GMM and 24 per vMF
+ * component; when that exceeds the device's LDS per block (on gfx950 beyond
+ * about 1,600 components) the records go to a device buffer the context
+ * allocates here (96 bytes per GMM component for each of 512 blocks, 200 MB
+ * at M = N = 4096) and the kernels read them through the caches. */
 int gosma_set_mixtures(gosma_ctx *ctx, int M, const double *mu, const double *sigma, const double *phi1,
                        const int32_t *label1, int N, const double *dir2, const double *kappa2,
                        const double *phi2, const int32_t *label2, int n_labels);

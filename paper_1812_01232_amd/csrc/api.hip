@@ -61,6 +61,8 @@ void free_problems(gosma_ctx *ctx)
     dfree(ctx->d_vmf);
     dfree(ctx->d_cls);
     dfree(ctx->d_prob);
+    dfree(ctx->d_grec);
+    ctx->grec_stride = 0;
     ctx->n_problems = 0;
     ctx->h_prob.clear();
     ctx->gmm_order.clear();
@@ -194,18 +196,21 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
     }
 
     HIP_TRY(ctx, hipSetDevice(ctx->device));
+    // Every cell of a bound kernel (and every SMA start) stages its problem's
+    // components in LDS while they fit; larger mixtures stage them in a global
+    // buffer of kGrecBlocks per-block slices instead.
+    bool use_grec = false;
     {
-        // every cell of a bound kernel stages its problem's components in LDS
         int needM = 0, needN = 0, lds_max = 0;
         for (int p = 0; p < n_problems; ++p) {
             needM = std::max(needM, (int)(gmm_off[p + 1] - gmm_off[p]));
             needN = std::max(needN, (int)(vmf_off[p + 1] - vmf_off[p]));
         }
         HIP_TRY(ctx, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
-        const size_t need = std::max(gosma::s11_lds_bytes(needM, gosma::kMaxWaves), gosma::s12_lds_bytes(needM, needN, gosma::kMaxWaves, n_problems > 1)) + 1024;
-        if (need > (size_t)lds_max)
-            return fail(ctx, GOSMA_E_INVAL, "M = %d, N = %d need %zu bytes of LDS per block; the device has %d", needM,
-                        needN, need, lds_max);
+        const size_t need = std::max({gosma::s11_lds_bytes(needM, gosma::kMaxWaves),
+                                      gosma::s12_lds_bytes(needM, needN, gosma::kMaxWaves, n_problems > 1),
+                                      gosma::sma_lds_bytes(needM, needN)}) + 2048;
+        use_grec = need > (size_t)lds_max;
     }
     gosma_drop_graph(ctx);   // a captured iteration holds the old mixture pointers
     free_problems(ctx);
@@ -305,7 +310,18 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
         ctx->gmm_order[p] = og;
     }
     hipError_t e;
-    if ((e = gosma::prepare_bound_kernels(maxM, maxN)) != hipSuccess) return hip_fail(ctx, e, "bound kernel LDS limit");
+    if (!use_grec && (e = gosma::prepare_bound_kernels(maxM, maxN)) != hipSuccess)
+        return hip_fail(ctx, e, "bound kernel LDS limit");
+    if (use_grec) {
+        const int64_t stride = gosma::grec_stride(maxM, maxN);
+        if ((e = hipMalloc((void **)&ctx->d_grec, sizeof(float4) * stride * gosma::kGrecBlocks)) != hipSuccess) {
+            ctx->d_grec = nullptr;
+            free_problems(ctx);
+            return fail(ctx, GOSMA_E_NOMEM, "global component records (%lld bytes): %s",
+                        (long long)(sizeof(float4) * stride * gosma::kGrecBlocks), hipGetErrorString(e));
+        }
+        ctx->grec_stride = stride;
+    }
     if ((e = upload(ctx->d_mu, h_mu)) != hipSuccess || (e = upload(ctx->d_isig2, h_isig2)) != hipSuccess ||
         (e = upload(ctx->d_w1, h_w1)) != hipSuccess || (e = upload(ctx->d_pbar, h_pbar)) != hipSuccess ||
         (e = upload(ctx->d_vmf, h_vmf)) != hipSuccess ||

@@ -975,7 +975,8 @@ __global__ __launch_bounds__(sma::kSmaThreads) void k_sma_search(Bufs b, DevMix 
         }
         __syncthreads();
         double x[6], f, g[6];
-        const int it = sma::sma_run(mx, D, sh, sst, sma::sma_lds(lds, D.M, D.N), max_iters, kSmaMemory, kSmaGtol,
+        float4 *base = mx.grec ? mx.grec + (int64_t)blockIdx.x * mx.grec_stride : lds;
+        const int it = sma::sma_run(mx, D, sh, sst, sma::sma_lds(base, D.M, D.N), max_iters, kSmaMemory, kSmaGtol,
                                     kSmaFtol, x, f, g);
         if (tid == 0) {
             s.sma_from = dbits;
@@ -1254,8 +1255,8 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     T1(ti);
     if (sma_iters > 0) {
         ti = T0(GOSMA_KERNEL_SMA);
-        hipLaunchKernelGGL(k_sma_search, dim3(std::min(P, 1024)), dim3(sma::kSmaThreads),
-                           sma_lds_bytes(ctx->maxM, ctx->maxN), st, b, mx, P, sma_iters);
+        hipLaunchKernelGGL(k_sma_search, dim3(std::min(P, mx.grec ? mx.grec_blocks : 1024)), dim3(sma::kSmaThreads),
+                           mx.grec ? 0 : sma_lds_bytes(ctx->maxM, ctx->maxN), st, b, mx, P, sma_iters);
         T1(ti);
     }
     hipLaunchKernelGGL(k_iter_end, dim3((P + 63) / 64), dim3(64), 0, st, b, P, rb_every);
@@ -1384,7 +1385,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
     if (S.graph_maxM != ctx->maxM || S.graph_mode != mode || S.graph_window != window || S.graph_iters != check ||
         S.graph_sma != sma_iters)
         drop_graph(&S);   // the captured launches depend on these
-    if (sma_iters > 0) {
+    if (sma_iters > 0 && !ctx->d_grec) {
         e = hipFuncSetAttribute((const void *)k_sma_search, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sma_lds_bytes(ctx->maxM, ctx->maxN));
         if (e) return fail(GOSMA_E_HIP, "SMA kernel set-up", e);

@@ -436,6 +436,7 @@ __device__ __forceinline__ void s11_pair(const float4 *__restrict__ rec, int a_,
               rec[kG * b_ + 2], rec[kG * b_ + 3], sub, slo);
 }
 
+template <bool GREC>
 __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_t *__restrict__ tkeys,
                                                          const uint32_t *__restrict__ pids, int64_t nt_host,
                                                          const uint32_t *__restrict__ nt_dev, S11Out out, int maxM,
@@ -443,9 +444,10 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
 {
     extern __shared__ float4 lds4[];
     __shared__ BlockShared sh;
-    float4 *rec = lds4;
+    // component records: LDS, or the block's slice of the global records
+    float4 *rec = GREC ? mx.grec + (int64_t)blockIdx.x * mx.grec_stride : lds4;
     // per wave: pairs that passed the screen
-    uint32_t *plist = reinterpret_cast<uint32_t *>(lds4 + kG * maxM);
+    uint32_t *plist = reinterpret_cast<uint32_t *>(GREC ? lds4 : lds4 + kG * maxM);
     const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, wv = tid >> 6, lane = tid & 63;
     const int64_t nt = nt_dev ? (int64_t)nt_dev[0] : nt_host;
     unsigned ncells = 0, noff_all = 0, nkeep_all = 0;   // per wave, over the block's cells (for out.counts)
@@ -868,7 +870,7 @@ __global__ __launch_bounds__(256) void k_cube_setup(DevMix mx, const uint64_t *_
 // Five waves per SIMD fit the plain kernel's registers without spills; the
 // variant that also keeps the top-8 terms (learned order, record logging) is
 // held to four.
-template <bool TOP8, bool VLDS>
+template <bool TOP8, bool VLDS, bool GREC>
 __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(TOP8 ? 4 : 5))) void k_s12(DevMix mx, const uint64_t *__restrict__ rkeys,
                                                          const uint64_t *__restrict__ tkeys,
                                                          const uint32_t *__restrict__ pids,
@@ -881,11 +883,13 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
 {
     extern __shared__ float4 lds4[];
     __shared__ BlockShared sh;
-    float4 *rec = lds4;                 // kG12 per GMM component
-    float4 *scr = lds4 + kG12 * maxM;   // two-float4 screen record per GMM component
+    static_assert(!(VLDS && GREC), "with global records the vMF rows are read from the global table");
+    // component records: LDS, or the block's slice of the global records
+    float4 *rec = GREC ? mx.grec + (int64_t)blockIdx.x * mx.grec_stride : lds4;   // kG12 per GMM component
+    float4 *scr = rec + kG12 * maxM;    // two-float4 screen record per GMM component
     float4 *vrec = scr + 2 * maxM;      // vMF rows (VLDS only)
     // per wave: pairs that passed the screen
-    uint32_t *plist = reinterpret_cast<uint32_t *>(vrec + (VLDS ? 2 * maxN : 0));
+    uint32_t *plist = reinterpret_cast<uint32_t *>(GREC ? lds4 : vrec + (VLDS ? 2 * maxN : 0));
     const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, wv = tid >> 6, lane = tid & 63;
     const int64_t n = n_dev ? (int64_t)n_dev[0] * n_dev_mul : n_host;
     unsigned nscr = 0, ncull_all = 0;   // per wave: pairs screened and dropped, over all cubes of the block
@@ -1248,16 +1252,23 @@ size_t s12_lds_bytes(int maxM, int maxN, int waves, bool vlds)
            sizeof(uint32_t) * kList * (size_t)waves;
 }
 
+int64_t grec_stride(int maxM, int maxN)
+{
+    const int64_t s11 = (int64_t)kG * maxM, s12 = (int64_t)(kG12 + 2) * maxM;
+    const int64_t sma = ((int64_t)sma_lds_bytes(maxM, maxN) + 15) / 16;
+    return std::max(s11, std::max(s12, sma));
+}
+
 hipError_t prepare_bound_kernels(int maxM, int maxN)
 {
     // allow dynamic LDS beyond the default limit on devices that have it
-    hipError_t e = hipFuncSetAttribute((const void *)k_s11, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void *)k_s11<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)s11_lds_bytes(maxM, kMaxWaves));
     const int l0 = (int)s12_lds_bytes(maxM, maxN, kMaxWaves, false), l1 = (int)s12_lds_bytes(maxM, maxN, kMaxWaves, true);
-    if (!e) e = hipFuncSetAttribute((const void *)k_s12<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, l0);
-    if (!e) e = hipFuncSetAttribute((const void *)k_s12<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, l0);
-    if (!e) e = hipFuncSetAttribute((const void *)k_s12<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, l1);
-    if (!e) e = hipFuncSetAttribute((const void *)k_s12<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, l1);
+    if (!e) e = hipFuncSetAttribute((const void *)k_s12<false, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, l0);
+    if (!e) e = hipFuncSetAttribute((const void *)k_s12<true, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, l0);
+    if (!e) e = hipFuncSetAttribute((const void *)k_s12<false, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, l1);
+    if (!e) e = hipFuncSetAttribute((const void *)k_s12<true, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, l1);
     return e;
 }
 
@@ -1268,9 +1279,16 @@ hipError_t launch_s11(const DevMix &mx, const uint64_t *tkeys, const uint32_t *p
 {
     if (nt <= 0) return hipSuccess;
     if (!tile_ok(tile)) return hipErrorInvalidValue;
+    if (mx.grec) {
+        // records in global memory: at most mx.grec_blocks blocks, LDS for the pair lists only
+        const unsigned g = (unsigned)std::min<int64_t>(std::min<int64_t>(tile.blocks, nt), mx.grec_blocks);
+        hipLaunchKernelGGL(k_s11<true>, dim3(g), dim3(64 * tile.waves), s11_lds_bytes(0, tile.waves), stream, mx,
+                           tkeys, pids, nt, nt_dev, out, maxM, out_idx);
+        return hipGetLastError();
+    }
     const unsigned g = (unsigned)std::min<int64_t>(tile.blocks, nt);
-    hipLaunchKernelGGL(k_s11, dim3(g), dim3(64 * tile.waves), s11_lds_bytes(maxM, tile.waves), stream, mx, tkeys,
-                       pids, nt, nt_dev, out, maxM, out_idx);
+    hipLaunchKernelGGL(k_s11<false>, dim3(g), dim3(64 * tile.waves), s11_lds_bytes(maxM, tile.waves), stream, mx,
+                       tkeys, pids, nt, nt_dev, out, maxM, out_idx);
     return hipGetLastError();
 }
 
@@ -1296,17 +1314,20 @@ hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *t
         hipError_t e = launch_cube_setup(mx, rkeys, tkeys, pids, n, n_dev, n_dev_mul, setup, nullptr, stream);
         if (e) return e;
     }
-    const bool vlds = mx.n_prob > 1;   // see kG
-    const size_t lds = s12_lds_bytes(maxM, maxN, tile.waves, vlds);
-    const unsigned g = (unsigned)std::min<int64_t>(tile.blocks, n);
+    const bool grec = mx.grec != nullptr;
+    const bool vlds = mx.n_prob > 1 && !grec;   // see kG
+    const size_t lds = grec ? s12_lds_bytes(0, 0, tile.waves, false) : s12_lds_bytes(maxM, maxN, tile.waves, vlds);
+    const unsigned g = (unsigned)std::min<int64_t>(std::min<int64_t>(tile.blocks, n), grec ? mx.grec_blocks : INT32_MAX);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(g), dim3(64 * tile.waves), lds, stream, mx, rkeys, tkeys, pids, tidx, s11ub,
                            s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, maxN, setup);
     };
-    if (with_top8)
-        vlds ? go(k_s12<true, true>) : go(k_s12<true, false>);
+    if (grec)
+        with_top8 ? go(k_s12<true, false, true>) : go(k_s12<false, false, true>);
+    else if (with_top8)
+        vlds ? go(k_s12<true, true, false>) : go(k_s12<true, false, false>);
     else
-        vlds ? go(k_s12<false, true>) : go(k_s12<false, false>);
+        vlds ? go(k_s12<false, true, false>) : go(k_s12<false, false, false>);
     return hipGetLastError();
 }
 

@@ -46,7 +46,18 @@ struct DevMix {
     const ClassRange *cls;
     const ProbDesc *prob;
     int n_prob;
+    // Per-component records of the bound kernels and SMA live in LDS while
+    // they fit; for larger mixtures they go to this buffer instead: grec_stride
+    // float4 per block, for at most grec_blocks blocks (NULL: LDS).
+    float4 *grec;
+    int64_t grec_stride;
+    int grec_blocks;
 };
+// Blocks of a bound or SMA launch that stage their records in global memory.
+constexpr int kGrecBlocks = 512;
+// float4 per block of the global records for mixtures of at most M x N
+// components (the largest of the S11, S12 and SMA records).
+int64_t grec_stride(int maxM, int maxN);
 
 struct BoundOut {
     double *ub, *lb, *lb_safe, *aux;
@@ -169,6 +180,8 @@ struct gosma_ctx {
     float4 *d_vmf = nullptr;
     gosma::ClassRange *d_cls = nullptr;
     gosma::ProbDesc *d_prob = nullptr;
+    float4 *d_grec = nullptr;       // global component records for mixtures too large for LDS
+    int64_t grec_stride = 0;
     std::vector<std::vector<int32_t>> gmm_order;   // original row of each sorted row, per problem
 
     // launch shapes of the two bound kernels (gosma_set_tiles / gosma_autotune)
@@ -200,6 +213,7 @@ struct gosma_ctx {
     void time_end(int idx, hipStream_t s);
 
     gosma::DevMix mix() const {
-        return gosma::DevMix{d_mu, d_isig2, d_w1, d_pbar, d_vmf, d_cls, d_prob, n_problems};
+        return gosma::DevMix{d_mu,   d_isig2,  d_w1,        d_pbar,           d_vmf, d_cls,
+                             d_prob, n_problems, d_grec, grec_stride, gosma::kGrecBlocks};
     }
 };

@@ -36,7 +36,8 @@ __global__ __launch_bounds__(kSmaThreads) void k_sma(DevMix mx, int64_t n, const
             f = NAN;
         } else {
             const ProbDesc P = mx.prob[pid];
-            it = sma_run(mx, P, sh, st, sma_lds(lds, P.M, P.N), max_iters, memory, gtol, ftol, x, f, g);
+            float4 *base = mx.grec ? mx.grec + (int64_t)blockIdx.x * mx.grec_stride : lds;
+            it = sma_run(mx, P, sh, st, sma_lds(base, P.M, P.N), max_iters, memory, gtol, ftol, x, f, g);
         }
         if (tid == 0) {
             for (int a = 0; a < 6; ++a) {
@@ -62,10 +63,14 @@ hipError_t launch_sma(const DevMix &mx, int maxM, int maxN, int64_t n, const uin
                       double *g_out, int32_t *it_out, hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
-    const size_t lds = sma_lds_bytes(maxM, maxN);
-    hipError_t e = hipFuncSetAttribute((const void *)k_sma, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    const int grid = (int)(n < 4096 ? n : 4096);
+    // records in LDS, or (mixtures too large for it) in the global records, one slice per block
+    const size_t lds = mx.grec ? 0 : sma_lds_bytes(maxM, maxN);
+    if (!mx.grec) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_sma, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t gmax = mx.grec ? mx.grec_blocks : 4096;
+    const int grid = (int)(n < gmax ? n : gmax);
     hipLaunchKernelGGL(k_sma, dim3(grid), dim3(kSmaThreads), lds, stream, mx, n, pids, x0, max_iters, memory, gtol,
                        ftol, x_out, f_out, g_out, it_out);
     return hipGetLastError();

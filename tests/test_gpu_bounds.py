@@ -306,17 +306,34 @@ def test_autotune(ctx):
         ctx.set_tiles(s11=(1, 0), s12=(1, 10))
 
 
-def test_max_components(ctx):
-    """The largest problem the library accepts: M = N = 1024 (LDS per block
-    96 M bytes plus 512 per wave), a few cubes checked one by one."""
-    sc = scenes.small_scene(1024, 1024, seed=77, noise_deg=1.0, n_inliers=700, sigma=(0.05, 0.3), t_half=1.0,
-                            room=((-5, -5, -1.5), (5, 5, 1.5)))
-    rk, tk = scenes.random_cubes(sc, 12, 5300, r_levels=(2, 12), t_levels=(1, 10))
+@pytest.mark.parametrize("M,N", [(1024, 1024), (2500, 700), (4096, 4096)])
+def test_max_components(ctx, M, N):
+    """Large mixtures up to the largest the library accepts, M = N = 4096.
+    Up to about 1,600 components the bound kernels stage each cube's records
+    in LDS (96 bytes per GMM component); beyond, in the context's global
+    record buffer.  A few cubes checked one by one, and SMA's objective and
+    gradient at two poses."""
+    sc = scenes.small_scene(M, N, seed=77, noise_deg=1.0, n_inliers=int(0.7 * min(M, N)), sigma=(0.05, 0.3),
+                            t_half=1.0, room=((-5, -5, -1.5), (5, 5, 1.5)))
+    n = 12 if M <= 1024 else 6
+    rk, tk = scenes.random_cubes(sc, n, 5300, r_levels=(2, 12), t_levels=(1, 10))
     ctx.set_scene(sc)
+    P = oracle.OracleProblem(sc)
+    o = P.bounds(rk, tk)
     for t in [(1, 64), (4, 64)]:
         ctx.set_tiles(s11=t, s12=t)
         g = ctx.bounds(rk, tk)
-        _compare(sc, g, oracle.OracleProblem(sc).bounds(rk, tk), label=f"1024x1024 tile {t}")
+        _compare(sc, g, o, label=f"{M}x{N} tile {t}")
+    r0 = np.stack([sc.r_gt, sc.r_gt + 0.1])
+    t0 = np.stack([sc.t_gt, np.clip(sc.t_gt + 0.1, sc.t_lo, sc.t_hi)])
+    out = ctx.refine(r0, t0, max_iters=0)
+    for s in range(2):
+        if out["iters"][s] < 0:
+            continue
+        fo, go = P.objective_grad(r0[s], t0[s])
+        _, s11, s12 = P.objective(r0[s], t0[s])
+        assert abs(out["f"][s] - fo) <= 1e-5 * (s11 + 2 * s12)
+        assert np.max(np.abs(out["grad"][s] - go)) <= 1e-4 * np.max(np.abs(go)) + 1e-5 * (s11 + 2 * s12)
 
 
 def test_pair_screen_counts_and_parity(ctx):
