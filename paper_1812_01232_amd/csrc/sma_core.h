@@ -17,6 +17,22 @@
 // under R -> exp([w]x) R the derivative is -2 sum_i (R p_i) x C_i, and
 // d/dr = J(r)^T d/dw with J the left Jacobian of the angle-axis map.
 //
+// Evaluated without cancellation.  With v split into its part along the
+// component's direction (u_i; w_i = R u_i for S12) and the rest v_perp,
+//   P_i v = (kappa_i / rho) v_perp + 2 ((kappa_i - 1) / rho) (v . u) u,
+// and the radial part of a summand's derivative combines with the kappa term
+// into (2 (kappa_i - 1) / rho) T [L(K) (v . u) / K - L(kappa_i)] u, whose
+// bracket is a small difference of two numbers near 1 (of order 1/kappa).
+// With nu = 1 - L it is written as
+//   nu(kappa_i) - nu(K) - L(K) |v x u|^2 / (K (K + v . u))     (v . u >= 0)
+// (K - v . u = |v x u|^2 / (K + v . u)); for v . u < 0 the plain form has no
+// cancellation.  So per component the sums are U, V (objective), the radial
+// brackets Rr (S11) and Rv (S12), and the tangential vectors
+//   Dt = sum_k T L(K)/K kappa_k (u_k - (u_k . u_i) u_i),
+//   Ct = sum_j T L(K)/K kappa_2j (mu_2j - (mu_2j . w_i) w_i),
+// and df/dd_i = 2 (kappa_i/rho) (Dt - R^T Ct) + 4 ((kappa_i - 1)/rho) (Rr - Rv) u_i,
+// d/dw = -2 sum_i kappa_i w_i x Ct_i.
+//
 // Summands in FP32 log space: log of the summand = -a b q / (K + a + b) +
 // l(K) - l(a) - l(b), l(y) = log((1 - e^{-2y}) / y), q the squared chord
 // between the two directions, K^2 = (a + b)^2 - a b q; sums and the pose in
@@ -63,7 +79,29 @@ __device__ __forceinline__ float langevin_over(float K)
     return (coth - frcp(K)) * frcp(K);
 }
 
-__device__ __forceinline__ double langevin64(double x) { return x < 1e-6 ? x / 3.0 : 1.0 / tanh(x) - 1.0 / x; }
+// L(K) = coth K - 1/K and nu(K) = 1 - L(K) = 1/K - 2 e^{-2K} / (1 - e^{-2K});
+// series L = K/3 - K^3/45 below 1e-2
+__device__ __forceinline__ void langevin_nu(float K, float &L, float &nu)
+{
+    if (K < 1e-2f) {
+        L = K * (1.0f / 3.0f - K * K * (1.0f / 45.0f));
+        nu = 1.0f - L;
+        return;
+    }
+    const float e = fexp(-2.0f * K), ie = frcp(1.0f - e), iK = frcp(K);
+    nu = iK - 2.0f * e * ie;
+    L = 1.0f - nu;
+}
+
+// radial bracket L(K) (v . u) / K - L(a) of a summand (see the header), from
+// nu(a), K, v . u and |v x u|^2
+__device__ __forceinline__ float radial_bracket(float nua, float K, float vu, float s2)
+{
+    float L, nuK;
+    langevin_nu(K, L, nuK);
+    if (vu >= 0.0f) return nua - nuK - L * s2 * frcp(K * (K + vu));
+    return L * vu * frcp(K) - (1.0f - nua);
+}
 
 // Rodrigues' formula R = I + sin(th) [k]x + (1 - cos th) [k]x^2 and the left
 // Jacobian J = I + A [r]x + B [r]x^2, A = (1 - cos th)/th^2, B = (th - sin th)/th^3
@@ -124,7 +162,9 @@ __device__ void eval_pose(const DevMix &mx, const ProbDesc &P, SmaShared &sh, fl
         for (int a = 0; a < 3; ++a) w[a] = R[3 * a] * u[0] + R[3 * a + 1] * u[1] + R[3 * a + 2] * u[2];
         gA[i] = make_float4((float)u[0], (float)u[1], (float)u[2], (float)kap);
         gB[i] = make_float4((float)w[0], (float)w[1], (float)w[2], ell((float)kap));
-        gC[i] = make_float2(mx.w1[g], 0.0f);
+        // nu(kappa_i) = 1/kappa - 2 e / (1 - e), e = e^{-2 kappa} (kappa >= 1)
+        const double e2k = exp(-2.0 * kap);
+        gC[i] = make_float2(mx.w1[g], (float)(1.0 / kap - 2.0 * e2k / (1.0 - e2k)));
         int c = 0;
         while (c + 1 < P.n_cls && !(g < mx.cls[P.cls_off + c].g1)) ++c;
         gcls[i] = c;
@@ -152,9 +192,10 @@ __device__ void eval_pose(const DevMix &mx, const ProbDesc &P, SmaShared &sh, fl
         const float wi = gC[ii].x;
         const ClassRange cr = mx.cls[P.cls_off + gcls[ii]];
         double U = 0.0, V = 0.0;
-        float D[3] = {0, 0, 0}, Cc[3] = {0, 0, 0};
+        float Rr = 0.0f, Rv = 0.0f;
+        float D[3] = {0, 0, 0}, Cc[3] = {0, 0, 0};   // tangential sums Dt, Ct
         if (live) {
-            const float a = Ai.w, la = Bi.w;
+            const float a = Ai.w, la = Bi.w, nua = gC[ii].y;
             for (int k = cr.g0 - P.gmm_off + sub; k < cr.g1 - P.gmm_off; k += S) {
                 const float4 Ak = gA[k];
                 const float b = Ak.w;
@@ -163,11 +204,15 @@ __device__ void eval_pose(const DevMix &mx, const ProbDesc &P, SmaShared &sh, fl
                 const float K = fsqrt(fmaxf((a + b) * (a + b) - a * b * q, 0.0f));
                 const float lg = -a * b * q * frcp(K + a + b) + ell(K) - la - gB[k].w;
                 const float Tk = wi * gC[k].x * fexp(lg);
-                const float c = Tk * langevin_over(K);
+                // v = kappa_i u_i + kappa_k u_k: v . u_i = a + b cos, |v x u_i|^2 = b^2 sin^2
+                const float cs = 1.0f - 0.5f * q;
+                const float vu = a + b * cs, s2 = b * b * q * (1.0f - 0.25f * q);
+                Rr += Tk * radial_bracket(nua, K, vu, s2);
+                const float c = Tk * langevin_over(K) * b;
+                D[0] += c * (Ak.x - cs * Ai.x);
+                D[1] += c * (Ak.y - cs * Ai.y);
+                D[2] += c * (Ak.z - cs * Ai.z);
                 U += (double)Tk;
-                D[0] += c * (a * Ai.x + b * Ak.x);
-                D[1] += c * (a * Ai.y + b * Ak.y);
-                D[2] += c * (a * Ai.z + b * Ak.z);
             }
             for (int j = cr.v0 - P.vmf_off + sub; j < cr.v1 - P.vmf_off; j += S) {
                 const float4 Aj = vA[j];
@@ -178,17 +223,22 @@ __device__ void eval_pose(const DevMix &mx, const ProbDesc &P, SmaShared &sh, fl
                 const float K = fsqrt(fmaxf((a + b) * (a + b) - a * b * q, 0.0f));
                 const float lg = -a * b * q * frcp(K + a + b) + ell(K) - la - Bj.y;
                 const float Tj = wi * Bj.x * fexp(lg);
-                const float c = Tj * langevin_over(K);
+                const float cs = 1.0f - 0.5f * q;
+                const float vu = a + b * cs, s2 = b * b * q * (1.0f - 0.25f * q);
+                Rv += Tj * radial_bracket(nua, K, vu, s2);
+                const float c = Tj * langevin_over(K) * b;
+                Cc[0] += c * (Aj.x - cs * Bi.x);
+                Cc[1] += c * (Aj.y - cs * Bi.y);
+                Cc[2] += c * (Aj.z - cs * Bi.z);
                 V += (double)Tj;
-                Cc[0] += c * (a * Bi.x + b * Aj.x);
-                Cc[1] += c * (a * Bi.y + b * Aj.y);
-                Cc[2] += c * (a * Bi.z + b * Aj.z);
             }
         }
         // combine the S partial sums of the component (lanes sub = 0 .. S-1 are adjacent)
         for (int off = 1; off < S; off <<= 1) {
             U += __shfl_xor(U, off, 64);
             V += __shfl_xor(V, off, 64);
+            Rr += __shfl_xor(Rr, off, 64);
+            Rv += __shfl_xor(Rv, off, 64);
             for (int a = 0; a < 3; ++a) {
                 D[a] += __shfl_xor(D[a], off, 64);
                 Cc[a] += __shfl_xor(Cc[a], off, 64);
@@ -199,21 +249,19 @@ __device__ void eval_pose(const DevMix &mx, const ProbDesc &P, SmaShared &sh, fl
             const double d[3] = {mx.mu[3 * g] - x[3], mx.mu[3 * g + 1] - x[4], mx.mu[3 * g + 2] - x[5]};
             const double rho = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             const double is2 = mx.isig2[g], kap = rho * rho * is2 + 1.0;
-            const double al = rho * is2 + 1.0 / rho, be = rho * is2 - 1.0 / rho;
-            // E = D - R^T C (component frame), and R p_i for the rotation part
-            double E[3], Rp[3];
-            for (int a = 0; a < 3; ++a)
-                E[a] = (double)D[a] - (R[a] * Cc[0] + R[3 + a] * Cc[1] + R[6 + a] * Cc[2]);
-            const double ue = (d[0] * E[0] + d[1] * E[1] + d[2] * E[2]) / rho;
-            const double lk = langevin64(kap), dif = U - V;
+            const double u[3] = {d[0] / rho, d[1] / rho, d[2] / rho};
+            // df/dd_i = 2 (kappa/rho) (Dt - R^T Ct) + 4 ((kappa - 1)/rho) (Rr - Rv) u
+            const double tg = 2.0 * kap / rho, rd = 4.0 * rho * is2 * ((double)Rr - (double)Rv);
+            double w[3];
             for (int a = 0; a < 3; ++a) {
-                const double gda = 2.0 * (al * E[a] + be * ue * d[a] / rho) - 2.0 * lk * 2.0 * d[a] * is2 * dif;
-                acc[2 + a] -= gda;   // d/dt = -d/dd
+                const double E = (double)D[a] - (R[a] * Cc[0] + R[3 + a] * Cc[1] + R[6 + a] * Cc[2]);
+                acc[2 + a] -= tg * E + rd * u[a];   // d/dt = -d/dd
+                w[a] = R[3 * a] * u[0] + R[3 * a + 1] * u[1] + R[3 * a + 2] * u[2];
             }
-            for (int a = 0; a < 3; ++a) Rp[a] = kap * (R[3 * a] * d[0] + R[3 * a + 1] * d[1] + R[3 * a + 2] * d[2]) / rho;
-            acc[5] += -2.0 * (Rp[1] * Cc[2] - Rp[2] * Cc[1]);
-            acc[6] += -2.0 * (Rp[2] * Cc[0] - Rp[0] * Cc[2]);
-            acc[7] += -2.0 * (Rp[0] * Cc[1] - Rp[1] * Cc[0]);
+            // d/dw = -2 kappa_i w_i x Ct_i
+            acc[5] += -2.0 * kap * (w[1] * Cc[2] - w[2] * Cc[1]);
+            acc[6] += -2.0 * kap * (w[2] * Cc[0] - w[0] * Cc[2]);
+            acc[7] += -2.0 * kap * (w[0] * Cc[1] - w[1] * Cc[0]);
             acc[0] += U - 2.0 * V;
             acc[1] += U + 2.0 * V;
         }

@@ -62,7 +62,7 @@ def test_cfg2_size_search_is_eps_optimal(ctx, seed):
     sc = scenes.cfg2_scene(seed=seed)
     ctx.set_scene(sc)
     eps = 1e-2
-    r = ctx.solve(eps, batch_parents=16384, max_queue=1 << 28, time_limit_s=60, allow_overflow=True)
+    r = ctx.solve(eps, batch_parents=16384, max_queue=1 << 29, time_limit_s=60, allow_overflow=True)
     assert r["status"] == 0, r["status"]
     _check(sc, r, eps, f"64x64 seed {seed}")
 

@@ -32,38 +32,41 @@ def _first_within(trace, f_final, eps_f):
 
 def test_learned_order_trained_on_logged_records():
     dev = torch.device("cuda", 0)
-    cap = 400000
+    cap = 1_000_000
     recs = torch.zeros((cap, 21), dtype=torch.float32, device=dev)
     cnt = torch.zeros(1, dtype=torch.int64, device=dev)
     with Context(0) as ctx:
+        # records logged by searches of the 16 x 16 and 64 x 64 workloads (a full
+        # queue ends a search; the records it logged stay valid)
         ctx.set_record_sink(recs, cnt)
-        for seed in (200, 201, 202, 203, 204, 205):
-            ctx.set_scene(scenes.small_scene(8, 8, seed=seed, noise_deg=1.0, n_inliers=6))
-            ctx.solve(EPS, batch_parents=512, log_records=1, max_queue=1 << 24, time_limit_s=20)
+        for sc in (scenes.cfg1_scene(10), scenes.cfg2_scene(10), scenes.cfg1_scene(11), scenes.cfg2_scene(11)):
+            if int(cnt.item()) >= cap:
+                break
+            ctx.set_scene(sc)
+            ctx.solve(EPS, batch_parents=4096, log_records=1, max_queue=1 << 27, time_limit_s=6, allow_overflow=True)
         ctx.set_record_sink(None, None)
         n = min(int(cnt.item()), cap)
-        assert n > 20000
+        assert n > 100000
         perm = torch.randperm(n, device=dev, generator=torch.Generator(device=dev).manual_seed(0))
-        ntr = int(0.9 * n)
+        ntr = int(0.95 * n)
         tr, te = recs[perm[:ntr]].contiguous(), recs[perm[ntr:n]].contiguous()
         ctx.mlp_init(0)
-        ctx.mlp_train(records=tr, epochs=4, batch=2048, lr=1e-3, seed=1)
+        ctx.mlp_train(records=tr, epochs=4, batch=4096, lr=1e-3, seed=1)
         yp = ctx.mlp_predict(te[:, :20].cpu().numpy())
         yt = te[:, 20].cpu().numpy().astype(np.float64)
         mae, mae0 = float(np.mean(np.abs(yp - yt))), float(np.mean(np.abs(yt - yt.mean())))
-        print(f"{n} records; held-out MAE {mae:.4f} (mean predictor {mae0:.4f})")
-        assert mae < 0.8 * mae0
+        print(f"{n} records; held-out MAE {mae:.4f} (mean predictor {mae0:.4f})", flush=True)
+        assert mae < 0.5 * mae0
 
         rows = []
-        for seed in (300, 301, 302):
-            sc = scenes.small_scene(8, 8, seed=seed, noise_deg=1.0, n_inliers=6)
+        for seed in (5003, 5000):
+            sc = scenes.cfg2_scene(seed=seed)
             ctx.set_scene(sc)
             S22 = ctx.S22()
             out = {}
             for name, kw in (("plain", {}), ("learned", {"order": 1, "learned_window": EPS})):
-                r = ctx.solve(EPS, batch_parents=512, max_queue=1 << 25, time_limit_s=60, trace_every=1, **kw)
-                tr_rows = ctx.trace()
-                out[name] = (r, tr_rows)
+                r = ctx.solve(EPS, batch_parents=4096, max_queue=1 << 29, time_limit_s=30, trace_every=1, **kw)
+                out[name] = (r, ctx.trace())
             (rp, tp), (rl, tl) = out["plain"], out["learned"]
             assert rp["status"] == 0 and rl["status"] == 0
             assert abs(rp["f_norm_best"] - rl["f_norm_best"]) <= EPS
@@ -74,4 +77,4 @@ def test_learned_order_trained_on_logged_records():
             rows.append((seed, rl["seconds"] / rp["seconds"], rl["cubes"] / rp["cubes"], ip, il, rp["iters"], rl["iters"]))
         for s, tr_, cr, ip, il, np_, nl in rows:
             print(f"scene {s}: learned/plain time {tr_:.3f}, cubes {cr:.4f}; d* within eps at iteration "
-                  f"{ip} (plain, of {np_}) vs {il} (learned, of {nl})")
+                  f"{ip} (plain, of {np_}) vs {il} (learned, of {nl})", flush=True)

@@ -72,8 +72,10 @@ def test_batched_problems_objective_and_gradient():
         out = ctx.refine(r0, t0, max_iters=0, problem=pids)
     for s, p in enumerate(pids):
         P = oracle.OracleProblem(scs[p])
-        if np.min(np.linalg.norm(scs[p].mu - t0[s], axis=1)) < scs[p].zeta:
-            assert out["iters"][s] == -1
+        # starts within zeta of a mean or outside the rotation box are rejected
+        outside = np.any(np.abs(r0[s]) > math.pi)
+        if outside or np.min(np.linalg.norm(scs[p].mu - t0[s], axis=1)) < scs[p].zeta:
+            assert out["iters"][s] == -1 and out["f"][s] == math.inf
             continue
         fo, go = P.objective_grad(r0[s], t0[s])
         scale = _scale(P, r0[s], t0[s])
