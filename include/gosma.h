@@ -138,6 +138,28 @@ int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tke
                       int64_t n, double *ub, double *lb, uint8_t *flags, double *aux, float *top8,
                       void *stream);
 
+/* gosma_eval_bounds for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results as gosma_eval_bounds, with the
+ * kernels' per-cube scratch (the S11 sums of each cube's translation cell and
+ * the pair kernel's set-up record, 208 bytes per cube) in a fixed array of
+ * the library, sized for GOSMA_NOALLOC_MAX_CUBES cubes (13.6 MB), that each
+ * device holds from its first gosma_create until the process ends.  The call
+ * allocates nothing: no hipMalloc, hipFree or allocating library routine.
+ *   Arguments as for gosma_eval_bounds, except that every array must be
+ *   device memory of the context's device (GOSMA_E_INVAL otherwise; no host
+ *   staging) and n <= GOSMA_NOALLOC_MAX_CUBES (GOSMA_E_INVAL beyond).
+ *   Kernel timing and work counters are not recorded.
+ * Asynchronous on `stream`.  Every call on a device shares that device's
+ * array (it keeps the last call's contents; this call writes every element it
+ * reads before reading it, so nothing needs clearing): calls that overlap on
+ * one device, on different streams or from different contexts, race and must
+ * be serialised by the caller. */
+#define GOSMA_NOALLOC_MAX_CUBES 65536
+int gosma_eval_bounds_noalloc(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *problem,
+                              int64_t n, double *ub, double *lb, uint8_t *flags, double *aux, float *top8,
+                              void *stream);
+
 /* Branch-and-bound options (Algorithm 1, Section 6). */
 typedef struct {
     double eps;              /* tolerance on the normalised objective (f + S22)/S22 */

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "gosma_impl.h"
@@ -105,6 +106,49 @@ void set_domain_desc(ProbDesc &P, const gosma_domain &d)
     P.zeta = d.zeta;
 }
 
+// Scratch of gosma_eval_bounds_noalloc: a fixed device array holding, for
+// up to GOSMA_NOALLOC_MAX_CUBES cubes, the S11 sums of each cube's
+// translation cell and the pair kernel's per-cube set-up record.  Host code
+// never uses the symbol itself as an address: gosma_create looks up the
+// array's device address once per device (hipGetSymbolAddress) and every
+// launch takes that pointer.
+constexpr size_t kScratchAlign = 256;
+constexpr size_t scratch_part(size_t bytes) { return (bytes + kScratchAlign - 1) / kScratchAlign * kScratchAlign; }
+constexpr size_t kScratchBytes = 2 * scratch_part(sizeof(double) * GOSMA_NOALLOC_MAX_CUBES) +
+                                 scratch_part(sizeof(gosma::CubeSetup) * GOSMA_NOALLOC_MAX_CUBES);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+struct ScratchLayout {
+    double *s11ub, *s11lo;
+    gosma::CubeSetup *setup;
+};
+ScratchLayout scratch_layout(unsigned char *base, int64_t n)
+{
+    (void)n;   // the parts are laid out for the maximum, so a call's view does not depend on n
+    const size_t part = scratch_part(sizeof(double) * GOSMA_NOALLOC_MAX_CUBES);
+    return ScratchLayout{(double *)base, (double *)(base + part), (gosma::CubeSetup *)(base + 2 * part)};
+}
+
+// Device address of `scratch` per device, looked up once per device with
+// that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(int device, unsigned char **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = (unsigned char *)p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -119,6 +163,10 @@ int gosma_create(int device, gosma_ctx **out)
     if (!ctx) return GOSMA_E_NOMEM;
     ctx->device = device;
     if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return GOSMA_E_HIP;
+    }
+    if (scratch_address(device, &ctx->d_scratch) != hipSuccess) {
         delete ctx;
         return GOSMA_E_HIP;
     }
@@ -501,6 +549,42 @@ int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tke
                 HIP_TRY(ctx, hipMemcpyAsync(a.user, a.dev, a.bytes, hipMemcpyDeviceToHost, s));
         HIP_TRY(ctx, hipStreamSynchronize(s));
     }
+    return GOSMA_OK;
+}
+
+int gosma_eval_bounds_noalloc(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *problem,
+                              int64_t n, double *ub, double *lb, uint8_t *flags, double *aux, float *top8,
+                              void *stream)
+{
+    if (!ctx) return GOSMA_E_INVAL;
+    ctx->err.clear();
+    if (ctx->n_problems < 1 || !ctx->has_domain)
+        return fail(ctx, GOSMA_E_STATE, "set mixtures and a domain before evaluating bounds");
+    if (n < 0) return fail(ctx, GOSMA_E_INVAL, "n must be >= 0");
+    if (n > GOSMA_NOALLOC_MAX_CUBES)
+        return fail(ctx, GOSMA_E_INVAL, "n = %lld exceeds GOSMA_NOALLOC_MAX_CUBES (%d), the capacity of the "
+                    "library's fixed scratch array", (long long)n, GOSMA_NOALLOC_MAX_CUBES);
+    if (n == 0) return GOSMA_OK;
+    if (!rkeys || !tkeys || !ub || !lb || !flags) return fail(ctx, GOSMA_E_INVAL, "a required pointer is NULL");
+    if (!problem && ctx->n_problems != 1)
+        return fail(ctx, GOSMA_E_INVAL, "problem indices are required when several problems are set");
+    if (!ctx->d_scratch) return fail(ctx, GOSMA_E_STATE, "the scratch array of this device is not available");
+    const void *ptrs[8] = {rkeys, tkeys, problem, ub, lb, flags, aux, top8};
+    for (const void *q : ptrs)
+        if (q && where_is(ctx, q) != Where::device)
+            return fail(ctx, GOSMA_E_INVAL, "every array must be device memory of the context's device");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    // the scratch array's address on this device (from hipGetSymbolAddress at
+    // gosma_create), carved into the per-cube S11 sums and set-up records;
+    // every element used is written by this call's kernels before it is read
+    const ScratchLayout L = scratch_layout(ctx->d_scratch, n);
+    gosma::DevMix mx = ctx->mix();
+    gosma::S11Out o11{L.s11ub, L.s11lo, nullptr};
+    HIP_TRY(ctx, gosma::launch_s11(mx, tkeys, problem, n, nullptr, o11, ctx->maxM, ctx->tile11, s));
+    gosma::BoundOut out{ub, lb, nullptr, aux, flags, top8, nullptr, nullptr, 0, nullptr};
+    HIP_TRY(ctx, gosma::launch_s12(mx, rkeys, tkeys, problem, nullptr, L.s11ub, L.s11lo, n, nullptr, 1, out, 0.0,
+                                   ctx->maxM, ctx->maxN, top8 != nullptr, ctx->tile12, L.setup, s));
     return GOSMA_OK;
 }
 

@@ -193,6 +193,7 @@ struct gosma_ctx {
     gosma::CubeSetup *d_setup = nullptr;
     unsigned long long *d_counts = nullptr;  // work counters of timed launches (kCountSlots x kCounters)
     uint8_t *d_stage = nullptr;              // device copies of host arrays given to gosma_eval_bounds
+    unsigned char *d_scratch = nullptr;      // this device's fixed scratch array (gosma_eval_bounds_noalloc)
     size_t stage_cap = 0;
 
     gosma::Solver *solver = nullptr;

@@ -26,8 +26,10 @@ EXPORTS = ["gosma_create", "gosma_destroy", "gosma_last_error", "gosma_set_mixtu
            "gosma_set_timing", "gosma_get_timing", "gosma_get_trace", "gosma_mlp_init", "gosma_mlp_set_params",
            "gosma_mlp_get_params", "gosma_mlp_predict", "gosma_mlp_loss_grad", "gosma_mlp_train",
            "gosma_set_record_sink", "gosma_get_tiles", "gosma_set_tiles", "gosma_autotune", "gosma_get_work_counts",
-           "gosma_snapshot", "gosma_resume", "gosma_refine", "gosma_dpmeans", "gosma_dpvmf_means"]
+           "gosma_snapshot", "gosma_resume", "gosma_refine", "gosma_dpmeans", "gosma_dpvmf_means",
+           "gosma_eval_bounds_noalloc"]
 MLP_FEATURES, MLP_RECORD, MLP_PARAMS = 20, 21, 35841
+NOALLOC_MAX_CUBES = 65536
 KERNEL_KINDS = ["s11", "s12", "select", "branch", "push", "mlp", "sma"]
 WORK_COUNTS = ["cubes", "s12_screened", "s12_evaluated", "cells", "s11_screened", "s11_evaluated"]
 
@@ -87,6 +89,7 @@ def lib():
                                          dp, dp, dp, ip, C.c_int, C.POINTER(Domain)]
         L.gosma_get_S22.argtypes = [vp, C.c_int, dp]
         L.gosma_eval_bounds.argtypes = [vp, vp, vp, vp, C.c_int64, vp, vp, vp, vp, vp, vp]
+        L.gosma_eval_bounds_noalloc.argtypes = [vp, vp, vp, vp, C.c_int64, vp, vp, vp, vp, vp, vp]
         L.gosma_solve.argtypes = [vp, C.POINTER(Opts), C.POINTER(Result)]
         L.gosma_solve_batch.argtypes = [vp, C.POINTER(Opts), C.POINTER(Result)]
         L.gosma_set_timing.argtypes = [vp, C.c_int]
@@ -220,6 +223,15 @@ class Context:
         s = _current_stream() if stream is None else C.c_void_p(stream)
         self._check(lib().gosma_eval_bounds(self._h, _ptr(rkeys), _ptr(tkeys), _ptr(problem), n, _ptr(ub), _ptr(lb),
                                             _ptr(flags), _ptr(aux), _ptr(top8), s), "gosma_eval_bounds")
+
+    def eval_bounds_noalloc(self, rkeys, tkeys, ub, lb, flags, aux=None, top8=None, problem=None, stream=None):
+        """gosma_eval_bounds_noalloc: device tensors only, at most NOALLOC_MAX_CUBES
+        cubes; the library allocates nothing; runs on the current stream."""
+        n = int(rkeys.numel())
+        s = _current_stream() if stream is None else C.c_void_p(stream)
+        self._check(lib().gosma_eval_bounds_noalloc(self._h, _ptr(rkeys), _ptr(tkeys), _ptr(problem), n, _ptr(ub),
+                                                    _ptr(lb), _ptr(flags), _ptr(aux), _ptr(top8), s),
+                    "gosma_eval_bounds_noalloc")
 
     def bounds(self, rkeys_np, tkeys_np, problem_np=None, want_aux=True, want_top8=False):
         """Convenience: host keys in, host arrays out (copies through torch)."""
