@@ -32,6 +32,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "cube_core.h"
 #include "gosma_impl.h"
 #include "sma_core.h"
 
@@ -74,7 +75,8 @@ struct PState {
 };
 
 struct GState {
-    uint32_t nchild, ntcell, running, pad;
+    uint32_t nchild, ntcell, running;
+    uint32_t nl3;      // Lemma 3 records reserved by this iteration's new cells
 };
 
 struct Queue {
@@ -185,6 +187,12 @@ struct Bufs {
     uint8_t *cflags;
     double *s11ub, *s11lo;
     CubeSetup *csetup;            // per-child set-up of the pair kernel
+    // Lemma 3 records of the iteration's cells (M per cell, reserved by the
+    // claiming thread; kNoL3Record when the capacity is used up) and each
+    // cell's record offset, indexed by table slot
+    float4 *l3rec;
+    uint32_t *l3off;
+    uint32_t l3cap;
     uint32_t *hist;               // kHistBins per problem
     PState *st;
     GState *g;
@@ -294,6 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_iter_begin(Bufs b, int P, int rb_slo
         b.g->nchild = 0;
         b.g->ntcell = 0;
         b.g->running = 0;
+        b.g->nl3 = 0;
     }
     if (s.done) {              // finished problems keep their final state
         if (threadIdx.x == 0) s.nsel = 0;
@@ -440,6 +449,28 @@ __global__ __launch_bounds__(kBlock) void k_scan(Bufs b, int rebuild_pass, int p
     }
 }
 
+// Class of a queued cube in a selection or re-partition: 0 (no longer below
+// d*, dropped), 1 (taken: key below the threshold T, or equal to it within
+// the quota of equal keys) or 2 (kept).  Cubes whose key equals T are ranked
+// with one atomic per wave (children inherit their parent's bound, so many
+// keys can be equal); called by all active lanes of a wave together.
+__device__ __forceinline__ int classify_key(PState &s, double lb, double dstar, uint32_t key, uint32_t T, bool all)
+{
+    const bool live = lb < dstar;
+    const bool tie = live && !all && key == T;
+    int c = !live ? 0 : ((all || key < T) ? 1 : 2);
+    const unsigned long long tm = __ballot(tie);
+    if (tm) {
+        const int lane = threadIdx.x & 63, leader = __ffsll((long long)tm) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&s.eq_taken, (uint32_t)__popcll(tm));
+        base = __shfl(base, leader, 64);
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(tm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)tm, base));
+        if (tie && rank < s.eq_quota) c = 1;
+    }
+    return c;
+}
+
 // Re-partition: hot + cold -> new hot (key below the threshold, ties up to the
 // quota) and new cold, dropping cubes no longer below d*.
 __global__ __launch_bounds__(kBlock) void k_rebuild_compact(Bufs b)
@@ -459,10 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_rebuild_compact(Bufs b)
         const Queue q = part == 0 ? qoff(b.H[s.hcur], (size_t)p * b.hcap) : qoff(b.C[s.ccur], (size_t)p * b.ccap);
         const uint32_t n = part == 0 ? s.nH[s.hcur] : s.nC[s.ccur];
         auto classify = [&](uint32_t i) -> int {
-            const double lb = sane_lb(q.lb[i]);
-            if (!(lb < dstar)) return 0;
-            const uint32_t key = key32(q.prio[i]);
-            return (all || key < T || (key == T && atomicAdd(&s.eq_taken, 1u) < s.eq_quota)) ? 1 : 2;
+            return classify_key(s, sane_lb(q.lb[i]), dstar, key32(q.prio[i]), T, all);
         };
         auto move = [&](const Queue &o, uint32_t cap, uint32_t i, uint32_t slot, double &mn) {
             const double lb = sane_lb(q.lb[i]);
@@ -531,10 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_select_compact(Bufs b)
     const Queue par = qoff(b.par, (size_t)p * b.k);
     double mh = INFINITY;
     auto classify = [&](uint32_t i) -> int {
-        const double lb = sane_lb(q.lb[i]);
-        if (!(lb < dstar)) return 0;
-        const uint32_t key = key32(q.prio[i]);
-        return (all || key < T || (key == T && atomicAdd(&s.eq_taken, 1u) < s.eq_quota)) ? 1 : 2;
+        return classify_key(s, sane_lb(q.lb[i]), dstar, key32(q.prio[i]), T, all);
     };
     partition_tiles(
         s.nH[s.hcur], &s.nsel, &s.nH[s.hcur ^ 1], classify,
@@ -569,17 +594,29 @@ __global__ void k_cells_init(Bufs b, int P)
     }
 }
 
-// 8 children per parent, all problems appended to one list.  A rotation split
-// shares its parent's translation cell among the 8 children.
-__global__ __launch_bounds__(kBlock) void k_branch(Bufs b)
+// Branching and the children's set-up in one pass, one thread per child:
+// the eight consecutive threads of a parent split it (in rotation or
+// translation by the flag its bound evaluation set, Section 5.1), the first
+// of them reserves eight consecutive child slots (reservations aggregated
+// per block), and each thread writes its child's keys, the GMM-vMF kernel's
+// set-up record and the slot of its translation cell in the cell table (a
+// rotation split shares its parent's cell among the eight children); the
+// thread that claims a new cell lists it for the GMM-GMM kernel.  Children of
+// all problems are appended to one list.  A parent at
+// the finest level in both groups has no children (its lower bound stays in
+// the queue minimum through floor_lb).
+__global__ __launch_bounds__(kBlock) void k_branch_setup(Bufs b)
 {
     const int p = blockIdx.y;
     PState &s = b.st[p];
     const uint32_t n = s.done ? 0u : s.nsel;
     const Queue par = qoff(b.par, (size_t)p * b.k);
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-        const uint32_t i = base + threadIdx.x;
-        const bool valid = i < n;
+    const int lane = threadIdx.x & 63;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < 8u * n; base += gridDim.x * blockDim.x) {
+        const uint32_t t = base + threadIdx.x;
+        const uint32_t i = t >> 3;
+        const int c = (int)(t & 7u);
+        const bool valid = t < 8u * n;
         bool rot = false, skip = false;
         uint64_t rk = 0, tk = 0;
         if (valid) {
@@ -590,23 +627,52 @@ __global__ __launch_bounds__(kBlock) void k_branch(Bufs b)
             if (rot && rmax) rot = false;
             if (!rot && tmax) rot = !rmax;
             skip = rmax && tmax;
-            if (skip) {
+            if (skip && c == 0) {
                 atomicMin(&s.floor_lb, ord64(par.lb[i]));
                 atomicAdd(&s.nskip, 1u);
             }
         }
-        // a parent at the finest level in both groups has no children (its
-        // lower bound stays in the queue minimum through floor_lb)
-        const uint32_t c0 = block_reserve(&b.g->nchild, valid && !skip ? 8u : 0u);
-        if (!valid) continue;
-        b.pchild[(size_t)p * b.k + i] = skip ? kNoChildren : c0;
-        if (skip) continue;
-        for (int c = 0; c < 8; ++c) {
-            const uint32_t ci = c0 + c;
-            b.crk[ci] = rot ? child_key(rk, c) : rk;
-            b.ctk[ci] = rot ? tk : child_key(tk, c);
+        // blockDim is a multiple of 8, so lanes 8q .. 8q + 7 hold one parent
+        uint32_t c0 = block_reserve(&b.g->nchild, (valid && !skip && c == 0) ? 8u : 0u);
+        c0 = __shfl(c0, lane & ~7, 64);
+        if (valid && c == 0) b.pchild[(size_t)p * b.k + i] = skip ? kNoChildren : c0;
+        bool claimed = false;
+        int64_t at = 0;
+        uint64_t ctk = 0;
+        if (valid && !skip) {
+            const uint32_t ci = c0 + (uint32_t)c;
+            const uint64_t crk = rot ? child_key(rk, c) : rk;
+            ctk = rot ? tk : child_key(tk, c);
+            b.crk[ci] = crk;
+            b.ctk[ci] = ctk;
             b.cpid[ci] = (uint32_t)p;
             b.cpar[ci] = (uint32_t)p * b.k + i;
+            b.csetup[ci] = make_cube_setup(b.prob[p], crk, ctk);
+            unsigned long long *tab = (unsigned long long *)(b.tcells + ((size_t)p << b.tbits));
+            at = (int64_t)(((size_t)p << b.tbits) + cell_slot(tab, b.tbits, ctk, claimed));
+            b.ctidx[ci] = at;
+        }
+        // the claiming threads list their cells (one atomic per wave)
+        const unsigned long long m = __ballot(claimed);
+        if (m) {
+            const int leader = __ffsll((long long)m) - 1;
+            uint32_t first = 0;
+            if (lane == leader) first = atomicAdd(&b.g->ntcell, (uint32_t)__popcll(m));
+            first = __shfl(first, leader, 64);
+            // and reserve the cells' Lemma 3 records (M of them per cell)
+            const uint32_t M = (uint32_t)b.prob[p].M;
+            uint32_t r0 = 0;
+            if (lane == leader) r0 = atomicAdd(&b.g->nl3, M * (uint32_t)__popcll(m));
+            r0 = __shfl(r0, leader, 64);
+            if (claimed) {
+                const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                const uint32_t j = first + rank;
+                b.ckey[j] = ctk;
+                b.cpid2[j] = (uint32_t)p;
+                b.cslot[j] = at;
+                const uint64_t roff = (uint64_t)r0 + (uint64_t)M * rank;
+                b.l3off[at] = roff + M <= (uint64_t)b.l3cap ? (uint32_t)roff : kNoL3Record;
+            }
         }
     }
 }
@@ -876,10 +942,8 @@ __global__ __launch_bounds__(kBlock) void k_log_records(Bufs b, int P)
 // Per-problem control at the end of an iteration.  Re-partitions run once
 // every rb_every iterations, so one is asked for when the hot part would run
 // low or fill up within that many iterations.
-__global__ void k_iter_end(Bufs b, int P, int rb_every)
+__device__ void iter_end_problem(Bufs &b, int p, int rb_every)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
     PState &s = b.st[p];
     if (s.done) return;
     s.bounded += 8ull * (s.nsel - s.nskip);
@@ -905,6 +969,12 @@ __global__ void k_iter_end(Bufs b, int P, int rb_every)
         const uint32_t total = nh + nc;
         s.rb_target = min(max(total / 16u, 16u * b.k), b.hcap / 2u);
     }
+}
+
+__global__ void k_iter_end(Bufs b, int P, int rb_every)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) iter_end_problem(b, p, rb_every);
 }
 
 // Queue the root cube of each problem (after its bounds were evaluated).
@@ -1006,6 +1076,7 @@ struct Solver {
     hipGraphExec_t exec = nullptr;
     int graph_maxM = 0;
     bool payload = false;     // logging payload buffers present
+    int maxM = 0;             // largest M the Lemma 3 record buffer is sized for
     int graph_mode = -1;      // captured mode: learned | logging
     float graph_window = 0.0f;
     int graph_iters = 0;      // iterations per captured graph
@@ -1087,6 +1158,8 @@ void free_solver(Solver *s)
     dfree(b.s11ub);
     dfree(b.s11lo);
     dfree(b.csetup);
+    dfree(b.l3rec);
+    dfree(b.l3off);
     dfree(b.hist);
     dfree(b.st);
     dfree(b.g);
@@ -1105,9 +1178,10 @@ void free_solver(Solver *s)
     s->k = s->hcap = s->ccap = 0;
 }
 
-hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap, bool payload)
+hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap, bool payload, int maxM)
 {
-    if (s->P == P && s->k == k && s->hcap == hcap && s->ccap == ccap && s->b.st && s->payload == payload)
+    if (s->P == P && s->k == k && s->hcap == hcap && s->ccap == ccap && s->b.st && s->payload == payload &&
+        s->maxM == maxM)
         return hipSuccess;
     free_solver(s);
     Bufs &b = s->b;
@@ -1145,6 +1219,11 @@ hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap, b
     if (!e) e = dalloc(b.s11ub, std::max(nt, nc));
     if (!e) e = dalloc(b.s11lo, std::max(nt, nc));
     if (!e) e = dalloc(b.csetup, nc);
+    // Lemma 3 records: one per GMM component of every new cell of an
+    // iteration, up to 2^26 (1 GB); cells beyond compute them in the pair kernel
+    const size_t l3cap = std::min<size_t>(nc * (size_t)std::max(maxM, 1), (size_t)1 << 26);
+    if (!e) e = dalloc(b.l3rec, l3cap);
+    if (!e) e = dalloc(b.l3off, nt);
     if (!e) e = dalloc(b.hist, (size_t)gosma::kHistBins * P);
     if (!e) e = dalloc(b.st, (size_t)P);
     if (!e) e = dalloc(b.g, 1);
@@ -1159,7 +1238,9 @@ hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap, b
     b.ccap = (uint32_t)ccap;
     b.k = (uint32_t)k;
     b.tbits = tbits;
+    b.l3cap = (uint32_t)l3cap;
     s->payload = payload;
+    s->maxM = maxM;
     s->P = P;
     s->k = k;
     s->hcap = hcap;
@@ -1209,19 +1290,19 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     hipLaunchKernelGGL(k_select_compact, dim3(gx, P), dim3(kBlock), 0, st, b);
     T1(ti);
     ti = T0(GOSMA_KERNEL_BRANCH);
-    hipLaunchKernelGGL(k_branch, dim3(std::max(1, gx / 4), P), dim3(kBlock), 0, st, b);
-    const int64_t maxc = 8 * (int64_t)S.k * P;
-    // the children's set-up records and their translation cells (table slots,
-    // and the list of distinct cells that k_s11 evaluates)
+    // children, their set-up records and their translation cells (table slots,
+    // and the list of distinct cells that k_s11 evaluates): one thread per child
     {
-        const CellTable cells{b.tcells, b.tbits, b.ctidx, b.ckey, b.cpid2, b.cslot, &b.g->ntcell};
-        hipError_t ce = launch_cube_setup(mx, b.crk, b.ctk, b.cpid, maxc, &b.g->nchild, 1, b.csetup, &cells, st);
-        if (ce) return ce;
+        const int per = (int)((8 * S.k + kBlock - 1) / kBlock);
+        const int gb = std::max(1, std::min(per, std::max(1, 8 * kGridX / P)));
+        hipLaunchKernelGGL(k_branch_setup, dim3(gb, P), dim3(kBlock), 0, st, b);
     }
+    const int64_t maxc = 8 * (int64_t)S.k * P;
     T1(ti);
     ti = T0(GOSMA_KERNEL_S11);
     hipError_t e = launch_s11(mx, b.ckey, b.cpid2, maxc, &b.g->ntcell,
-                              S11Out{b.s11ub, b.s11lo, timed ? ctx->d_counts : nullptr}, ctx->maxM, ctx->tile11, st,
+                              S11Out{b.s11ub, b.s11lo, timed ? ctx->d_counts : nullptr, b.l3rec, b.l3off}, ctx->maxM,
+                              ctx->tile11, st,
                               b.cslot);
     T1(ti);
     if (e) return e;
@@ -1230,7 +1311,7 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     BoundOut bo{b.cub, b.clb, b.clbs, nullptr, b.cflags, top8 ? b.ctop8 : nullptr, nullptr, &b.st->dstar,
                 (int)(sizeof(PState) / sizeof(unsigned long long)), timed ? ctx->d_counts : nullptr};
     e = launch_s12(mx, b.crk, b.ctk, b.cpid, b.ctidx, b.s11ub, b.s11lo, maxc, &b.g->nchild, 1, bo, kMarginGamma,
-                   ctx->maxM, ctx->maxN, top8, ctx->tile12, b.csetup, st, true);
+                   ctx->maxM, ctx->maxN, top8, ctx->tile12, b.csetup, st, true, Lemma3Recs{b.l3rec, b.l3off});
     T1(ti);
     if (e) return e;
     if (logging) hipLaunchKernelGGL(k_log_records, dim3(std::max(1, gx / 8), P), dim3(kBlock), 0, st, b, P);
@@ -1390,7 +1471,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
                                 (int)sma_lds_bytes(ctx->maxM, ctx->maxN));
         if (e) return fail(GOSMA_E_HIP, "SMA kernel set-up", e);
     }
-    if ((e = ensure_solver(&S, P, k, hcap, ccap, logging)))
+    if ((e = ensure_solver(&S, P, k, hcap, ccap, logging, ctx->maxM)))
         return fail(GOSMA_E_NOMEM, "allocating solver buffers", e);
     Bufs &b = S.b;
     b.prob = ctx->d_prob;

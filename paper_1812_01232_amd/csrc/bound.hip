@@ -35,6 +35,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "cube_core.h"
 #include "gosma_impl.h"
 
 namespace gosma {
@@ -48,83 +49,6 @@ constexpr double kPi = 3.14159265358979323846;
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
-
-// Decode an octree key of the box with lower corner lo and widths w.
-__device__ __forceinline__ void decode_key(uint64_t key, const double *lo, const double *w, double c[3],
-                                           double h[3])
-{
-    const uint64_t mask = (1ull << 19) - 1;
-    int level = (int)((key >> 57) & 63);
-    double scale = ldexp(1.0, -(level + 1));
-    uint64_t idx[3] = {(key >> 38) & mask, (key >> 19) & mask, key & mask};
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        h[k] = w[k] * scale;
-        c[k] = lo[k] + (double)(2 * idx[k] + 1) * h[k];
-    }
-}
-
-// sin and cos in FP64 for the rotation angles of a cell: the argument is
-// reduced to [-pi, pi] with one multiple of 2 pi (exact enough for the
-// |x| < 1e6 of any finite domain) and both Maclaurin series are summed in
-// nested form through x^27 and x^26 (truncation below 3e-15 on [-pi, pi]).
-// A short fixed sequence keeps the register footprint of the per-cell set-up
-// small next to the library routine.
-// Series factors 1/((2k)(2k+1)) and 1/((2k-1)(2k)), k = 1..13, in constant
-// memory: read with scalar loads, so the unrolled series needs no vector
-// registers for its coefficients.
-__constant__ double kSinF[13] = {1.0 / 6, 1.0 / 20, 1.0 / 42, 1.0 / 72, 1.0 / 110, 1.0 / 156, 1.0 / 210,
-                                 1.0 / 272, 1.0 / 342, 1.0 / 420, 1.0 / 506, 1.0 / 600, 1.0 / 702};
-__constant__ double kCosF[13] = {1.0 / 2, 1.0 / 12, 1.0 / 30, 1.0 / 56, 1.0 / 90, 1.0 / 132, 1.0 / 182,
-                                 1.0 / 240, 1.0 / 306, 1.0 / 380, 1.0 / 462, 1.0 / 552, 1.0 / 650};
-
-__device__ __forceinline__ void sincos_reduced(double x, double *s, double *c)
-{
-    constexpr double kTwoPi = 6.283185307179586476925286766559;
-    x -= kTwoPi * rint(x * (1.0 / kTwoPi));
-    const double x2 = x * x;
-    double ts = 1.0, tc = 1.0;
-#pragma unroll
-    for (int k = 12; k >= 0; --k) {
-        ts = fma(-x2 * kSinF[k], ts, 1.0);
-        tc = fma(-x2 * kCosF[k], tc, 1.0);
-    }
-    *s = x * ts;
-    *c = tc;
-}
-
-// Rotation matrix of the angle-axis vector r (Section 5.1), as
-// I + A [r]x + B [r]x^2 with A = sin|r|/|r|, B = (1 - cos|r|)/|r|^2; also the
-// left Jacobian coefficients of the same map, J(r) = I + a [r]x + b [r]x^2 with
-// a = (1 - cos|r|)/|r|^2 = B and b = (|r| - sin|r|)/|r|^3, so that
-// d/ds R(r + s d) = [J(r) d]x R(r) at s = 0.
-__device__ void rotation_matrix(const double r[3], double R[9], double *ja, double *jb)
-{
-    double th2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-    double A, B;
-    if (th2 < 1e-8) {
-        A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
-        B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
-        *jb = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
-    } else {
-        double th = sqrt(th2), sh, ch;
-        sincos_reduced(0.5 * th, &sh, &ch);
-        A = 2.0 * sh * ch / th;
-        B = 2.0 * sh * sh / th2;
-        *jb = th < 1e-4 ? 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0 : (th - 2.0 * sh * ch) / (th2 * th);
-    }
-    *ja = B;
-    // [r]x^2 = r r^T - |r|^2 I
-    R[0] = 1.0 + B * (r[0] * r[0] - th2);
-    R[4] = 1.0 + B * (r[1] * r[1] - th2);
-    R[8] = 1.0 + B * (r[2] * r[2] - th2);
-    R[1] = -A * r[2] + B * r[0] * r[1];
-    R[3] = A * r[2] + B * r[0] * r[1];
-    R[2] = A * r[1] + B * r[0] * r[2];
-    R[6] = -A * r[1] + B * r[0] * r[2];
-    R[5] = -A * r[0] + B * r[1] * r[2];
-    R[7] = A * r[0] + B * r[1] * r[2];
-}
 
 // sin and cos of x in [0, pi/2] in FP32: Maclaurin series through x^13 and
 // x^14 in nested form (truncation below 1e-9).
@@ -186,8 +110,16 @@ struct TransPrep {
     bool drop, ub_inf;    // cell inside the zeta ball of this mean; centre inside it
 };
 
-__device__ TransPrep trans_prep(const double *mu, double isig2, const double t0[3], const double tau[3],
-                                double zeta)
+// Lemma 3's half-angle record of a component for a translation cell:
+// {cos, sin of psi_t / 2, psi_t, 0}, computed by lemma3_record.  The search
+// computes it once per distinct translation cell (k_s11) and the pair kernel
+// reads it instead of recomputing it per cube.
+__device__ float4 lemma3_record(const double c[3], double rho2, const double tau[3], bool inside);
+
+// The interval part of trans_prep (everything but Lemma 3); *inside: mu lies
+// in the cell (then psi_t = pi).
+__device__ TransPrep trans_interval(const double *mu, double isig2, const double t0[3], const double tau[3],
+                                    double zeta, double c_out[3], double *rho2_out, bool *inside_out)
 {
     TransPrep o;
     double c[3] = {mu[0] - t0[0], mu[1] - t0[1], mu[2] - t0[2]};
@@ -223,6 +155,14 @@ __device__ TransPrep trans_prep(const double *mu, double isig2, const double t0[
     o.ha = 0.5 * width * isig2;
     o.ac = o.klo + o.ha;
 
+    for (int k = 0; k < 3; ++k) c_out[k] = c[k];
+    *rho2_out = rho2;
+    *inside_out = inside;
+    return o;
+}
+
+__device__ float4 lemma3_record(const double c[3], double rho2, const double tau[3], bool inside)
+{
     // psi_t: largest vertex angle between mu - v and mu - t0 (Lemma 3); pi if
     // mu is in the cell or any vertex angle exceeds pi/2.  For angles below
     // pi/2 the largest angle has the largest sine, |c x (s tau)|^2 / (|a|^2 |c|^2)
@@ -250,20 +190,19 @@ __device__ TransPrep trans_prep(const double *mu, double isig2, const double t0[
             bdot = dot;
         }
     }
-    if (guard) {
-        o.cps = 0.0;
-        o.sps = 1.0;
-        o.psi = (float)kPi;
-    } else {
-        // sine and cosine of the angle from |c x s tau|^2 and (a . c)^2 over the same denominator
-        const float nrm = frcp(fsqrt(bn + bdot * bdot));
-        const float sp = fsqrt(bn) * nrm, cp = fabsf(bdot) * nrm;
-        const float cps = fsqrt(0.5f * (1.0f + cp));
-        o.cps = cps;
-        o.sps = sp * frcp(2.0f * cps);
-        o.psi = atan2f(sp, cp);
-    }
-    return o;
+    if (guard) return make_float4(0.0f, 1.0f, (float)kPi, 0.0f);
+    // sine and cosine of the angle from |c x s tau|^2 and (a . c)^2 over the same denominator
+    const float nrm = frcp(fsqrt(bn + bdot * bdot));
+    const float sp = fsqrt(bn) * nrm, cp = fabsf(bdot) * nrm;
+    const float cps = fsqrt(0.5f * (1.0f + cp));
+    return make_float4(cps, sp * frcp(2.0f * cps), atan2f(sp, cp), 0.0f);
+}
+
+__device__ __forceinline__ void apply_lemma3(TransPrep &o, const float4 r)
+{
+    o.cps = r.x;
+    o.sps = r.y;
+    o.psi = r.z;
 }
 
 // Functions of one concentration y >= 1 (every kappa here is at least 1),
@@ -465,6 +404,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
         const ProbDesc P = mx.prob[pid];
         double t0[3], tau[3];
         decode_key(tkeys[cell], P.t_lo, P.t_w, t0, tau);
+        // where this cell's Lemma 3 records go (none without a record buffer)
+        const uint32_t l3base = out.l3rec ? out.l3off[o] : kNoL3Record;
 
         // per-component prep; the diagonal (i = i') summands are added here:
         // Z(2k)/Z(k)^2 = k coth(k) / 2 at the centre, and at the low end of the
@@ -474,7 +415,12 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
         int drop = 0, ubinf = 0;
         for (int i = tid; i < P.M; i += T) {
             const int g = P.gmm_off + i;
-            const TransPrep tp = trans_prep(mx.mu + 3 * g, mx.isig2[g], t0, tau, P.zeta);
+            double cd[3], rho2;
+            bool inside;
+            TransPrep tp = trans_interval(mx.mu + 3 * g, mx.isig2[g], t0, tau, P.zeta, cd, &rho2, &inside);
+            const float4 l3 = lemma3_record(cd, rho2, tau, inside);
+            apply_lemma3(tp, l3);
+            if (l3base != kNoL3Record) out.l3rec[(size_t)l3base + i] = l3;
             drop |= tp.drop;
             ubinf |= tp.ub_inf;
             const double w = mx.w1[g];
@@ -726,9 +672,10 @@ __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, const f
         PairK k = pair_k(R1.x, b, q);
         const float v = ww * (fexp2(k.x * kLog2e) * k.hK * R1.y * v1.y);
         sub += v;
-        if (TOP8) {
+        if (TOP8 && v > top[7]) {
             // insert v into the descending list and drop the smallest: each
             // position keeps the larger value and passes the smaller one on
+            // (a value not above the eighth would leave the list unchanged)
             float c = v;
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
@@ -766,30 +713,8 @@ __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, const f
     }
 }
 
-// Per-cube set-up of k_s12 (one thread per cube): the two cells, the rotation
-// matrix and, for Lemma 2 per direction (reading in k_s12 below), the left
-// Jacobian applied to four corners of the rotation cell's half-width box.
-// The slot of translation cell `key` in its problem's part of the cell table
-// (2^tbits slots): linear probing from a multiplicative hash; the first
-// thread to claim an empty slot stores the key (claimed), later ones find it.
-// At most half of a problem's slots are ever used, so a free or matching slot
-// is always found within the table.
-__device__ __forceinline__ uint32_t cell_slot(unsigned long long *tab, uint32_t tbits, uint64_t key, bool &claimed)
-{
-    const uint32_t mask = (1u << tbits) - 1u;
-    uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - tbits));
-    claimed = false;
-    for (uint32_t probe = 0; probe <= mask; ++probe, h = (h + 1u) & mask) {
-        const unsigned long long cur = tab[h];
-        if (cur == key) return h;
-        if (cur != kEmptyCell) continue;
-        const unsigned long long prev = atomicCAS(&tab[h], (unsigned long long)kEmptyCell, (unsigned long long)key);
-        claimed = prev == kEmptyCell;
-        if (claimed || prev == key) return h;
-    }
-    return 0;   // not reached (see above)
-}
-
+// The per-cube set-up pass (one thread per cube): set-up records and, with a
+// cell table, each cube's translation cell (see cell_slot).
 __global__ __launch_bounds__(256) void k_cube_setup(DevMix mx, const uint64_t *__restrict__ rkeys,
                                                     const uint64_t *__restrict__ tkeys,
                                                     const uint32_t *__restrict__ pids, int64_t n_host,
@@ -811,36 +736,7 @@ __global__ __launch_bounds__(256) void k_cube_setup(DevMix mx, const uint64_t *_
                 cs.flags = kSetupInvalid;
                 out[cube] = cs;
             } else {
-                const ProbDesc &P = mx.prob[pid];
-                double r0[3], hr[3];
-                decode_key(rkeys[cube], P.r_lo, P.r_w, r0, hr);
-                decode_key(tkeys[cube], P.t_lo, P.t_w, cs.t0, cs.tau);
-                const double hn = sqrt(hr[0] * hr[0] + hr[1] * hr[1] + hr[2] * hr[2]);
-                cs.hn = (float)hn;
-                cs.cap = fminf(cs.hn, (float)kPi);
-                const double rr = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
-                uint32_t flags = sqrt(rr) + hn <= 5.5 ? kSetupPerDir : 0u;
-                double ja, jb;
-                rotation_matrix(r0, cs.R, &ja, &jb);
-                for (int q = 0; q < 4; ++q) {
-                    const double d[3] = {hr[0], (q & 2) ? -hr[1] : hr[1], (q & 1) ? -hr[2] : hr[2]};
-                    // J d = d + a (r x d) + b (r (r . d) - |r|^2 d)
-                    const double x[3] = {r0[1] * d[2] - r0[2] * d[1], r0[2] * d[0] - r0[0] * d[2],
-                                         r0[0] * d[1] - r0[1] * d[0]};
-                    const double rd = r0[0] * d[0] + r0[1] * d[1] + r0[2] * d[2];
-                    for (int k = 0; k < 3; ++k)
-                        cs.jc[q][k] = (float)(d[k] + ja * x[k] + jb * (r0[k] * rd - rr * d[k]));
-                }
-                // rotation cells with no point in the radius-pi ball hold no rotation
-                double nr2 = 0.0;
-                for (int k = 0; k < 3; ++k) {
-                    const double lo = r0[k] - hr[k], hi = r0[k] + hr[k];
-                    const double nk = lo > 0.0 ? lo : (hi < 0.0 ? hi : 0.0);
-                    nr2 += nk * nk;
-                }
-                if (nr2 > kPi * kPi) flags |= GOSMA_FLAG_DROP_ROT;
-                cs.flags = flags;
-                cs.pad = 0;
+                cs = make_cube_setup(mx.prob[pid], rkeys[cube], tkeys[cube]);
                 out[cube] = cs;
                 if (cells.keys) {
                     // the cube's translation cell in the table
@@ -879,7 +775,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                                                          const double *__restrict__ s11lo, int64_t n_host,
                                                          const uint32_t *__restrict__ n_dev, int n_dev_mul,
                                                          BoundOut out, double gamma, int maxM, int maxN,
-                                                         const CubeSetup *__restrict__ setup)
+                                                         const CubeSetup *__restrict__ setup, Lemma3Recs l3)
 {
     extern __shared__ float4 lds4[];
     __shared__ BlockShared sh;
@@ -909,6 +805,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         const uint32_t pid = pids ? pids[cube] : 0u;
         const ProbDesc P = mx.prob[pid];
         const double *R = cs.R, *t0 = cs.t0, *tau = cs.tau;
+        // the translation cell's Lemma 3 records, when the caller has them
+        const uint32_t l3base = l3.rec ? l3.off[tidx ? tidx[cube] : cube] : kNoL3Record;
 
         // Lemma 2, per direction.  The angle-axis metric bound
         // angle(R_r p, R_s p) <= |r - s| caps every direction's rotation
@@ -929,7 +827,10 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         double dk = 0.0;
         for (int i = tid; i < P.M; i += T) {
             const int g = P.gmm_off + i;
-            const TransPrep tp = trans_prep(mx.mu + 3 * g, mx.isig2[g], t0, tau, P.zeta);
+            double cd[3], rho2;
+            bool inside;
+            TransPrep tp = trans_interval(mx.mu + 3 * g, mx.isig2[g], t0, tau, P.zeta, cd, &rho2, &inside);
+            apply_lemma3(tp, l3base != kNoL3Record ? l3.rec[(size_t)l3base + i] : lemma3_record(cd, rho2, tau, inside));
             drop |= tp.drop;
             ubinf |= tp.ub_inf;
             psum += mx.pbar[g] * tp.psi;
@@ -1306,7 +1207,7 @@ hipError_t launch_cube_setup(const DevMix &mx, const uint64_t *rkeys, const uint
 hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                       const int64_t *tidx, const double *s11ub, const double *s11lo, int64_t n, const uint32_t *n_dev,
                       int n_dev_mul, BoundOut out, double margin_gamma, int maxM, int maxN, bool with_top8, Tile tile,
-                      CubeSetup *setup, hipStream_t stream, bool setup_done)
+                      CubeSetup *setup, hipStream_t stream, bool setup_done, Lemma3Recs l3)
 {
     if (n <= 0) return hipSuccess;
     if (!tile_ok(tile) || !setup) return hipErrorInvalidValue;
@@ -1320,7 +1221,7 @@ hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *t
     const unsigned g = (unsigned)std::min<int64_t>(std::min<int64_t>(tile.blocks, n), grec ? mx.grec_blocks : INT32_MAX);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(g), dim3(64 * tile.waves), lds, stream, mx, rkeys, tkeys, pids, tidx, s11ub,
-                           s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, maxN, setup);
+                           s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, maxN, setup, l3);
     };
     if (grec)
         with_top8 ? go(k_s12<true, false, true>) : go(k_s12<false, false, true>);

@@ -97,6 +97,18 @@ struct CellTable {
 struct S11Out {
     double *ub, *lo;   // S11 at the centre and its lower bound, per translation cube
     unsigned long long *counts = nullptr;   // optional work counters (see BoundOut)
+    // optional Lemma 3 records of the cells (see Lemma3Recs): written at the
+    // cell's record offset, which is looked up by the cell's output index
+    float4 *l3rec = nullptr;
+    const uint32_t *l3off = nullptr;
+};
+// Lemma 3 records: per translation cell and GMM component a float4 {cos, sin
+// of psi_t / 2, psi_t, 0}, at offset l3off[cell index] + component
+// (kNoL3Record: the cell has none and the pair kernel computes them itself).
+constexpr uint32_t kNoL3Record = 0xffffffffu;
+struct Lemma3Recs {
+    const float4 *rec = nullptr;
+    const uint32_t *off = nullptr;   // indexed like the S11 sums (tidx)
 };
 
 // Per-cube set-up of the GMM-vMF pair kernel: both cells decoded, the rotation
@@ -132,7 +144,7 @@ hipError_t launch_s11(const DevMix &mx, const uint64_t *tkeys, const uint32_t *p
 hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                       const int64_t *tidx, const double *s11ub, const double *s11lo, int64_t n, const uint32_t *n_dev,
                       int n_dev_mul, BoundOut out, double margin_gamma, int maxM, int maxN, bool with_top8, Tile tile,
-                      CubeSetup *setup, hipStream_t stream, bool setup_done = false);
+                      CubeSetup *setup, hipStream_t stream, bool setup_done = false, Lemma3Recs l3 = Lemma3Recs{});
 // The per-cube set-up pass of k_s12 (and, with cells, the cubes' translation cells).
 hipError_t launch_cube_setup(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                              int64_t n, const uint32_t *n_dev, int n_dev_mul, CubeSetup *setup, const CellTable *cells,
