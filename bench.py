@@ -173,7 +173,8 @@ def other_workload_rates(ctx, warmup=20, steps=40):
                                "cubes_per_step": (b["cubes"] - a["cubes"]) / steps, "tiles": tiles}
     scs = scenes.batch_scenes(128, seed=4000)
     ctx.set_scenes(scs)
-    tiles = ctx.autotune(32768, seed=4)["chosen"]
+    tuned = ctx.autotune(32768, seed=4)
+    tiles = {"all": tuned["chosen"], "size_buckets": {str(k): v for k, v in tuned["buckets"].items()}}
     kw = dict(batch_parents=2048, max_queue=1 << 21, allow_overflow=True)
     ctx.solve_batch(128, 1e-9, max_iters=warmup, **kw)
     ra = ctx.solve_batch(128, 1e-9, max_iters=warmup, **kw)
@@ -257,6 +258,7 @@ def learned_comparison(ctx, n_eval, eps, records_cap, epochs, time_cap):
     t0 = time.perf_counter()
     i = 0
     while int(cnt.item()) < records_cap and i < 12:
+        print(f"records logged: {int(cnt.item())}", file=sys.stderr, flush=True)
         for sc in (scenes.cfg1_scene(10 + i), scenes.cfg2_scene(10 + i)):
             ctx.set_scene(sc)
             try:
@@ -283,9 +285,11 @@ def learned_comparison(ctx, n_eval, eps, records_cap, epochs, time_cap):
            "heldout_mae": float(np.mean(np.abs(yp - yt))), "heldout_mae_mean_predictor": float(np.mean(np.abs(yt - yt.mean()))),
            "eps": eps, "scenes": []}
     # plain / learned at the 64 x 64 workload's 4,096 parents per iteration;
-    # plain_16384: the same search with four times the parents per iteration
+    # plain_16384: the same search with four times the parents per iteration;
+    # plain_sma: with Algorithm 1's SMA step (at most 100 L-BFGS iterations per run)
     variants = (("plain", {}), ("learned", {"order": 1, "learned_window": eps}),
-                ("learned_unclamped", {"order": 1}), ("plain_16384", {"batch_parents": 4 * BATCH_PARENTS}))
+                ("learned_unclamped", {"order": 1}), ("plain_16384", {"batch_parents": 4 * BATCH_PARENTS}),
+                ("plain_sma", {"sma_iters": 100}))
     for k in range(n_eval):
         sc = scenes.cfg2_scene(seed=5000 + k)
         ctx.set_scene(sc)
@@ -294,13 +298,23 @@ def learned_comparison(ctx, n_eval, eps, records_cap, epochs, time_cap):
             kw = {"batch_parents": BATCH_PARENTS, **kw}
             r = ctx.solve(eps, max_queue=1 << 29, time_limit_s=time_cap, allow_overflow=True, **kw)
             row[name] = {"status": r["status"], "seconds": r["seconds"], "cubes": r["cubes"],
-                         "f_norm": r["f_norm_best"], "lb_norm": r["lb_norm"]}
+                         "f_norm": r["f_norm_best"], "lb_norm": r["lb_norm"], "iters": r["iters"]}
+            print(f"scene {5000 + k} {name}: status {r['status']} {r['seconds']:.2f} s {r['cubes']} cubes",
+                  file=sys.stderr, flush=True)
+            if kw.get("sma_iters"):
+                row[name].update(sma_runs=r["sma_runs"], sma_improved=r["sma_improved"])
         out["scenes"].append(row)
     # status 0 = eps-certified; 2 = time cap; 3 = queue capacity (both uncertified)
+    q = lambda a: [float(x) for x in np.percentile(a, [25, 50, 75])] if len(a) else None
     for name, _ in variants:
         t = np.array([s[name]["seconds"] for s in out["scenes"] if s[name]["status"] == 0])
         out[f"{name}_certified"] = int(t.size)
         out[f"{name}_median_s_certified"] = float(np.median(t)) if t.size else None
+        if name != "plain":
+            # per scene where both certify: this variant over plain (quartiles)
+            both = [s for s in out["scenes"] if s[name]["status"] == 0 and s["plain"]["status"] == 0]
+            out[f"{name}_over_plain_time_q1_med_q3"] = q([s[name]["seconds"] / s["plain"]["seconds"] for s in both])
+            out[f"{name}_over_plain_cubes_q1_med_q3"] = q([s[name]["cubes"] / s["plain"]["cubes"] for s in both])
     return out
 
 

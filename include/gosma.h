@@ -376,21 +376,38 @@ typedef struct {
     gosma_tile s12;   /* GMM-vMF sums and bounds (GOSMA_KERNEL_S12) */
 } gosma_tiles;
 
+/* Size buckets.  The problems of a batch are grouped by their larger mixture
+ * max(M, N): bucket 0 up to 64 components, 1 up to 128, 2 up to 256, 3
+ * larger.  The search bounds each bucket's cubes with launches of their own,
+ * in that bucket's launch shapes (gosma_get_bucket_tiles) and with LDS sized
+ * for its largest problem; gosma_eval_bounds uses the shapes of
+ * gosma_get_tiles for all problems at once. */
+#define GOSMA_N_BUCKETS 4
+
 /* Current shapes (host struct out).  gosma_set_problems resets them to a
  * default chosen from the largest M and N. */
 int gosma_get_tiles(gosma_ctx *ctx, gosma_tiles *out);
-/* Set the shapes (host struct in).  GOSMA_E_INVAL for waves outside
- * {1, 2, 4} or blocks < 1. */
+/* Set the shapes (host struct in) for all problems and every size bucket.
+ * GOSMA_E_INVAL for waves outside {1, 2, 4} or blocks < 1. */
 int gosma_set_tiles(gosma_ctx *ctx, const gosma_tiles *tiles);
+/* The shapes the search uses for size bucket `bucket` (0 .. GOSMA_N_BUCKETS-1)
+ * and the number of current problems in it (host out; n_problems may be
+ * NULL).  gosma_set_problems resets them to a default chosen from the
+ * bucket's largest M and N. */
+int gosma_get_bucket_tiles(gosma_ctx *ctx, int bucket, gosma_tiles *out, int *n_problems);
 /* Autotuner: draws n_cubes random cubes of the current problems (levels 2-10
  * in rotation, 1-8 in translation, inside the rotation ball; deterministic
  * per seed), times every candidate shape of both kernels on them with HIP
  * events (waves 1, 2, 4 x grids of 2048 to 32768 waves in powers of 2; one
- * warm-up and three timed launches each), and keeps the fastest.  rows:
- * NULL or a host array of cap x 4 doubles receiving {kernel (GOSMA_KERNEL_S11
- * or GOSMA_KERNEL_S12), waves, blocks, ms per launch} per candidate; *n_rows
- * (if not NULL) receives the number of candidates.  chosen: NULL or the
- * shapes kept.  Synchronous; allocates and frees its own device buffers. */
+ * warm-up and three timed launches each), and keeps the fastest; then does
+ * the same for each non-empty size bucket on n_cubes random cubes of that
+ * bucket's problems (the shapes the search uses; with one bucket, the same
+ * cubes and result).  rows: NULL or a host array of cap x 5 doubles
+ * receiving {kernel (GOSMA_KERNEL_S11 or GOSMA_KERNEL_S12), waves, blocks,
+ * ms per launch, bucket (-1: all problems)} per candidate; *n_rows (if not
+ * NULL) receives the number of candidates.  chosen: NULL or the shapes kept
+ * for all problems.  Synchronous; allocates and frees its own device
+ * buffers. */
 int gosma_autotune(gosma_ctx *ctx, int64_t n_cubes, uint64_t seed, double *rows, int64_t cap, int64_t *n_rows,
                    gosma_tiles *chosen);
 

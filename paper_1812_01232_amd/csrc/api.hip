@@ -299,6 +299,7 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
         P.N = N;
         P.cls_off = (int32_t)h_cls.size();
         P.n_cls = L;
+        P.bucket = gosma::size_bucket(M, N);
         set_domain_desc(P, domains[p]);
         // class table
         {
@@ -385,6 +386,17 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
     ctx->has_domain = true;
     ctx->tile11 = default_tile((int64_t)maxM * maxM / 2);
     ctx->tile12 = default_tile((int64_t)maxM * maxN);
+    for (int b = 0; b < gosma::kBuckets; ++b) ctx->bucket_nprob[b] = ctx->bucket_maxM[b] = ctx->bucket_maxN[b] = 0;
+    for (const ProbDesc &P : h_prob) {
+        ++ctx->bucket_nprob[P.bucket];
+        ctx->bucket_maxM[P.bucket] = std::max(ctx->bucket_maxM[P.bucket], (int)P.M);
+        ctx->bucket_maxN[P.bucket] = std::max(ctx->bucket_maxN[P.bucket], (int)P.N);
+    }
+    for (int b = 0; b < gosma::kBuckets; ++b) {
+        const int64_t m = ctx->bucket_maxM[b], n = ctx->bucket_maxN[b];
+        ctx->btile11[b] = default_tile(m * m / 2);
+        ctx->btile12[b] = default_tile(m * n);
+    }
     return GOSMA_OK;
 }
 

@@ -75,8 +75,11 @@ struct PState {
 };
 
 struct GState {
-    uint32_t nchild, ntcell, running;
+    uint32_t nchild, running;
     uint32_t nl3;      // Lemma 3 records reserved by this iteration's new cells
+    uint32_t pad;
+    // per size bucket: children and distinct translation cells of the iteration
+    uint32_t nchild_b[kBuckets], ntcell_b[kBuckets];
 };
 
 struct Queue {
@@ -110,7 +113,7 @@ __device__ __forceinline__ double sane_lb(double x) { return x != x ? -INFINITY 
 // Block-aggregated reservation of cnt consecutive slots per thread: an
 // inclusive scan within each wave (shuffles), wave totals combined in LDS, one
 // atomic per block.
-__device__ __forceinline__ uint32_t block_reserve(uint32_t *counter, uint32_t cnt)
+__device__ __forceinline__ uint32_t block_reserve(uint32_t *counter, uint32_t cnt, uint32_t *block_total = nullptr)
 {
     __shared__ uint32_t wtot[kBlock / 64];
     __shared__ uint32_t base;
@@ -131,6 +134,7 @@ __device__ __forceinline__ uint32_t block_reserve(uint32_t *counter, uint32_t cn
             s += c;
         }
         base = s ? atomicAdd(counter, s) : 0u;
+        if (block_total && s) atomicAdd(block_total, s);
     }
     __syncthreads();
     const uint32_t r = base + wtot[wave] + incl - cnt;
@@ -168,7 +172,10 @@ struct Bufs {
     uint32_t hcap, ccap;
     Queue par;                    // parents, problem p at [p * k, (p + 1) * k)
     uint32_t k;
-    // children (all problems, compacted)
+    // children: size bucket b owns indices [kbase[b], kbase[b] + kcap[b]) and
+    // fills them from the start (g->nchild_b[b]); its distinct translation
+    // cells use the same range of the cell list
+    uint32_t kbase[kBuckets], kcap[kBuckets];
     uint64_t *crk, *ctk;
     uint32_t *cpid, *cpar;        // problem and parent slot of each child
     int64_t *ctidx;
@@ -178,8 +185,9 @@ struct Bufs {
     uint64_t *tcells;
     uint32_t *tpid;               // problem of each slot (fixed)
     uint32_t tbits;
-    // the distinct cells of the iteration, compacted (g->ntcell of them):
-    // key, problem and table slot (where their S11 sums are stored)
+    // the distinct cells of the iteration, per bucket from kbase[b]
+    // (g->ntcell_b[b] of them): key, problem and table slot (where their S11
+    // sums are stored)
     uint64_t *ckey;
     uint32_t *cpid2;
     int64_t *cslot;
@@ -205,6 +213,23 @@ struct Bufs {
     unsigned long long *rec_count;
     uint64_t rec_cap;
 };
+
+// The t-th child of the iteration (t < g->nchild), bucket after bucket, from
+// the per-bucket counts n[] read once by the caller.
+__device__ __forceinline__ uint32_t child_at(const Bufs &b, const uint32_t (&n)[kBuckets], uint32_t t)
+{
+#pragma unroll
+    for (int k = 0; k < kBuckets; ++k) {
+        if (t < n[k]) return b.kbase[k] + t;
+        t -= n[k];
+    }
+    return 0u;   // not reached for t < g->nchild
+}
+__device__ __forceinline__ void child_counts(const Bufs &b, uint32_t (&n)[kBuckets])
+{
+#pragma unroll
+    for (int k = 0; k < kBuckets; ++k) n[k] = b.g->nchild_b[k];
+}
 
 __device__ __forceinline__ Queue qoff(Queue q, size_t off)
 {
@@ -300,9 +325,9 @@ __global__ __launch_bounds__(kBlock) void k_iter_begin(Bufs b, int P, int rb_slo
     PState &s = b.st[p];
     if (p == 0 && threadIdx.x == 0) {
         b.g->nchild = 0;
-        b.g->ntcell = 0;
         b.g->running = 0;
         b.g->nl3 = 0;
+        for (int k = 0; k < kBuckets; ++k) b.g->nchild_b[k] = b.g->ntcell_b[k] = 0;
     }
     if (s.done) {              // finished problems keep their final state
         if (threadIdx.x == 0) s.nsel = 0;
@@ -612,6 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_branch_setup(Bufs b)
     const uint32_t n = s.done ? 0u : s.nsel;
     const Queue par = qoff(b.par, (size_t)p * b.k);
     const int lane = threadIdx.x & 63;
+    const int bk = b.prob[p].bucket;
     for (uint32_t base = blockIdx.x * blockDim.x; base < 8u * n; base += gridDim.x * blockDim.x) {
         const uint32_t t = base + threadIdx.x;
         const uint32_t i = t >> 3;
@@ -632,8 +658,10 @@ __global__ __launch_bounds__(kBlock) void k_branch_setup(Bufs b)
                 atomicAdd(&s.nskip, 1u);
             }
         }
-        // blockDim is a multiple of 8, so lanes 8q .. 8q + 7 hold one parent
-        uint32_t c0 = block_reserve(&b.g->nchild, (valid && !skip && c == 0) ? 8u : 0u);
+        // blockDim is a multiple of 8, so lanes 8q .. 8q + 7 hold one parent;
+        // children go to the problem's size bucket
+        uint32_t c0 = b.kbase[bk] + block_reserve(&b.g->nchild_b[bk], (valid && !skip && c == 0) ? 8u : 0u,
+                                                   &b.g->nchild);
         c0 = __shfl(c0, lane & ~7, 64);
         if (valid && c == 0) b.pchild[(size_t)p * b.k + i] = skip ? kNoChildren : c0;
         bool claimed = false;
@@ -657,7 +685,7 @@ __global__ __launch_bounds__(kBlock) void k_branch_setup(Bufs b)
         if (m) {
             const int leader = __ffsll((long long)m) - 1;
             uint32_t first = 0;
-            if (lane == leader) first = atomicAdd(&b.g->ntcell, (uint32_t)__popcll(m));
+            if (lane == leader) first = b.kbase[bk] + atomicAdd(&b.g->ntcell_b[bk], (uint32_t)__popcll(m));
             first = __shfl(first, leader, 64);
             // and reserve the cells' Lemma 3 records (M of them per cell)
             const uint32_t M = (uint32_t)b.prob[p].M;
@@ -693,15 +721,18 @@ __global__ __launch_bounds__(kBlock) void k_push(Bufs b, const float *prio_overr
 {
     clear_cells(b, P);
     const uint32_t n = b.g->nchild;
+    uint32_t nb[kBuckets];
+    child_counts(b, nb);
     const int lane = threadIdx.x & 63;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-        const uint32_t i = base + threadIdx.x;
+        const uint32_t t = base + threadIdx.x;
+        const uint32_t i = t < n ? child_at(b, nb, t) : 0u;
         bool push = false, hot = false;
         uint32_t p = 0;
         double lbs = 0.0;
         float pr = 0.0f;
         uint8_t fl = 0;
-        if (i < n) {
+        if (t < n) {
             p = b.cpid[i];
             PState &s = b.st[p];
             fl = b.cflags[i];
@@ -776,6 +807,8 @@ __global__ __launch_bounds__(kBlock) void k_push_agg(Bufs b, const float *prio_o
     __shared__ unsigned long long mn[2 * kPushAggProblems];
     clear_cells(b, P);
     const uint32_t n = b.g->nchild;
+    uint32_t nb[kBuckets];
+    child_counts(b, nb);
     const int T = 2 * P;
     for (uint32_t start = blockIdx.x * blockDim.x; start < n; start += gridDim.x * blockDim.x) {
         for (int t = threadIdx.x; t < T; t += blockDim.x) {
@@ -783,13 +816,14 @@ __global__ __launch_bounds__(kBlock) void k_push_agg(Bufs b, const float *prio_o
             mn[t] = ord64(INFINITY);
         }
         __syncthreads();
-        const uint32_t i = start + threadIdx.x;
+        const uint32_t ti = start + threadIdx.x;
+        const uint32_t i = ti < n ? child_at(b, nb, ti) : 0u;
         bool push = false, hot = false;
         uint32_t p = 0, local = 0;
         double lbs = 0.0;
         float pr = 0.0f;
         uint8_t fl = 0;
-        if (i < n) {
+        if (ti < n) {
             p = b.cpid[i];
             PState &s = b.st[p];
             fl = b.cflags[i];
@@ -879,11 +913,15 @@ __device__ void cube_features(const ProbDesc &P, uint64_t rk, uint64_t tk, doubl
 __global__ __launch_bounds__(kBlock) void k_child_features(Bufs b)
 {
     const uint32_t n = b.g->nchild;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    uint32_t nb[kBuckets];
+    child_counts(b, nb);
+    // features of the t-th child at row t (the network runs over rows 0 .. n-1)
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        const uint32_t i = child_at(b, nb, t);
         const ProbDesc &P = b.prob[b.cpid[i]];
         const double lbs = fmax(sane_lb(b.clbs[i]), b.par.lb[b.cpar[i]]);
         cube_features(P, b.crk[i], b.ctk[i], (b.cub[i] + P.S22) / P.S22, (lbs + P.S22) / P.S22,
-                      b.ctop8 + 8 * (size_t)i, b.cfeat + (size_t)GOSMA_MLP_FEATURES * i);
+                      b.ctop8 + 8 * (size_t)i, b.cfeat + (size_t)GOSMA_MLP_FEATURES * t);
     }
 }
 
@@ -897,12 +935,15 @@ constexpr float kMaxRise = 10.0f, kDeferred = 16.0f;
 __global__ __launch_bounds__(kBlock) void k_learned_prio(Bufs b, float window)
 {
     const uint32_t n = b.g->nchild;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    uint32_t nb[kBuckets];
+    child_counts(b, nb);
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        const uint32_t i = child_at(b, nb, t);
         const uint32_t p = b.cpid[i];
         const double S22 = b.prob[p].S22;
         const double dstar_n = (unord64(b.st[p].dstar) + S22) / S22, eps_n = b.st[p].eps_f / S22;
-        const float lbn = b.cfeat[(size_t)GOSMA_MLP_FEATURES * i + 11];
-        const float y = b.cpred[i];
+        const float lbn = b.cfeat[(size_t)GOSMA_MLP_FEATURES * t + 11];
+        const float y = b.cpred[t];
         const float rise = fminf(fmaxf(y, 0.0f), window > 0.0f ? window : kMaxRise);
         float pr = isfinite(y) ? lbn + rise : lbn;
         if ((double)lbn >= dstar_n - eps_n) pr = lbn + kDeferred;
@@ -1077,6 +1118,7 @@ struct Solver {
     int graph_maxM = 0;
     bool payload = false;     // logging payload buffers present
     int maxM = 0;             // largest M the Lemma 3 record buffer is sized for
+    int bucket_nprob[kBuckets] = {};   // problems per size bucket (the children's ranges)
     int graph_mode = -1;      // captured mode: learned | logging
     float graph_window = 0.0f;
     int graph_iters = 0;      // iterations per captured graph
@@ -1178,10 +1220,11 @@ void free_solver(Solver *s)
     s->k = s->hcap = s->ccap = 0;
 }
 
-hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap, bool payload, int maxM)
+hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap, bool payload, int maxM,
+                         const int (&bucket_nprob)[gosma::kBuckets])
 {
     if (s->P == P && s->k == k && s->hcap == hcap && s->ccap == ccap && s->b.st && s->payload == payload &&
-        s->maxM == maxM)
+        s->maxM == maxM && std::equal(bucket_nprob, bucket_nprob + gosma::kBuckets, s->bucket_nprob))
         return hipSuccess;
     free_solver(s);
     Bufs &b = s->b;
@@ -1239,6 +1282,16 @@ hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap, b
     b.k = (uint32_t)k;
     b.tbits = tbits;
     b.l3cap = (uint32_t)l3cap;
+    // children (and cells) of size bucket j: 8 k per problem of the bucket
+    {
+        uint32_t at = 0;
+        for (int j = 0; j < gosma::kBuckets; ++j) {
+            b.kbase[j] = at;
+            b.kcap[j] = (uint32_t)(8 * k * (size_t)bucket_nprob[j]);
+            at += b.kcap[j];
+            s->bucket_nprob[j] = bucket_nprob[j];
+        }
+    }
     s->payload = payload;
     s->maxM = maxM;
     s->P = P;
@@ -1299,19 +1352,30 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     }
     const int64_t maxc = 8 * (int64_t)S.k * P;
     T1(ti);
+    // the bound kernels, one launch per non-empty size bucket over its range
+    // of children and cells, in the bucket's launch shape
+    hipError_t e = hipSuccess;
     ti = T0(GOSMA_KERNEL_S11);
-    hipError_t e = launch_s11(mx, b.ckey, b.cpid2, maxc, &b.g->ntcell,
-                              S11Out{b.s11ub, b.s11lo, timed ? ctx->d_counts : nullptr, b.l3rec, b.l3off}, ctx->maxM,
-                              ctx->tile11, st,
-                              b.cslot);
+    for (int k = 0; k < kBuckets && !e; ++k) {
+        if (!b.kcap[k]) continue;
+        const size_t o = b.kbase[k];
+        e = launch_s11(mx, b.ckey + o, b.cpid2 + o, b.kcap[k], &b.g->ntcell_b[k],
+                       S11Out{b.s11ub, b.s11lo, timed ? ctx->d_counts : nullptr, b.l3rec, b.l3off}, ctx->bucket_maxM[k],
+                       ctx->btile11[k], st, b.cslot + o);
+    }
     T1(ti);
     if (e) return e;
     ti = T0(GOSMA_KERNEL_S12);
     const bool top8 = learned || logging;
-    BoundOut bo{b.cub, b.clb, b.clbs, nullptr, b.cflags, top8 ? b.ctop8 : nullptr, nullptr, &b.st->dstar,
-                (int)(sizeof(PState) / sizeof(unsigned long long)), timed ? ctx->d_counts : nullptr};
-    e = launch_s12(mx, b.crk, b.ctk, b.cpid, b.ctidx, b.s11ub, b.s11lo, maxc, &b.g->nchild, 1, bo, kMarginGamma,
-                   ctx->maxM, ctx->maxN, top8, ctx->tile12, b.csetup, st, true, Lemma3Recs{b.l3rec, b.l3off});
+    for (int k = 0; k < kBuckets && !e; ++k) {
+        if (!b.kcap[k]) continue;
+        const size_t o = b.kbase[k];
+        BoundOut bo{b.cub + o, b.clb + o, b.clbs + o, nullptr, b.cflags + o, top8 ? b.ctop8 + 8 * o : nullptr, nullptr,
+                    &b.st->dstar, (int)(sizeof(PState) / sizeof(unsigned long long)), timed ? ctx->d_counts : nullptr};
+        e = launch_s12(mx, b.crk + o, b.ctk + o, b.cpid + o, b.ctidx + o, b.s11ub, b.s11lo, b.kcap[k],
+                       &b.g->nchild_b[k], 1, bo, kMarginGamma, ctx->bucket_maxM[k], ctx->bucket_maxN[k], top8,
+                       ctx->btile12[k], b.csetup + o, st, true, Lemma3Recs{b.l3rec, b.l3off});
+    }
     T1(ti);
     if (e) return e;
     if (logging) hipLaunchKernelGGL(k_log_records, dim3(std::max(1, gx / 8), P), dim3(kBlock), 0, st, b, P);
@@ -1471,7 +1535,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
                                 (int)sma_lds_bytes(ctx->maxM, ctx->maxN));
         if (e) return fail(GOSMA_E_HIP, "SMA kernel set-up", e);
     }
-    if ((e = ensure_solver(&S, P, k, hcap, ccap, logging, ctx->maxM)))
+    if ((e = ensure_solver(&S, P, k, hcap, ccap, logging, ctx->maxM, ctx->bucket_nprob)))
         return fail(GOSMA_E_NOMEM, "allocating solver buffers", e);
     Bufs &b = S.b;
     b.prob = ctx->d_prob;

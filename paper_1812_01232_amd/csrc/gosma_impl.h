@@ -19,7 +19,7 @@ struct Mlp;      // queue-ordering network (mlp.hip)
 // ranges of each class in both mixtures.
 struct ProbDesc {
     int32_t gmm_off, M, vmf_off, N;
-    int32_t cls_off, n_cls, pad0, pad1;
+    int32_t cls_off, n_cls, bucket, pad1;   // bucket: size bucket of the problem (size_bucket)
     double r_lo[3], r_w[3];     // rotation root box: lo and width
     double t_lo[3], t_w[3];     // translation root box
     double zeta, S22;
@@ -135,6 +135,17 @@ struct Tile {
     int waves, blocks;
 };
 
+// Problems of a batch are grouped by size into GOSMA_N_BUCKETS buckets, by
+// their larger mixture: up to 64, 128, 256 components, and larger.  The
+// search bounds each bucket's cubes with a launch of its own, in the launch
+// shape tuned for that bucket and with LDS sized for its largest problem.
+constexpr int kBuckets = GOSMA_N_BUCKETS;
+inline int size_bucket(int M, int N)
+{
+    const int m = M > N ? M : N;
+    return m <= 64 ? 0 : (m <= 128 ? 1 : (m <= 256 ? 2 : 3));
+}
+
 // Launchers (bound.hip).  All asynchronous on `stream`.  With a device count
 // pointer (nt_dev / n_dev) the kernels read the number of cells from device
 // memory (times n_dev_mul); the host count is then the maximum.  Each launch
@@ -196,8 +207,12 @@ struct gosma_ctx {
     int64_t grec_stride = 0;
     std::vector<std::vector<int32_t>> gmm_order;   // original row of each sorted row, per problem
 
-    // launch shapes of the two bound kernels (gosma_set_tiles / gosma_autotune)
+    // launch shapes of the two bound kernels (gosma_set_tiles / gosma_autotune):
+    // for calls over all problems (gosma_eval_bounds) and per size bucket (the
+    // search), with each bucket's problem count and largest M and N
     gosma::Tile tile11{1, 8192}, tile12{1, 8192};
+    gosma::Tile btile11[gosma::kBuckets] = {}, btile12[gosma::kBuckets] = {};
+    int bucket_nprob[gosma::kBuckets] = {}, bucket_maxM[gosma::kBuckets] = {}, bucket_maxN[gosma::kBuckets] = {};
 
     // scratch for gosma_eval_bounds (grown on demand)
     int64_t s11_cap = 0;

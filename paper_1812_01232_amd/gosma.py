@@ -27,9 +27,10 @@ EXPORTS = ["gosma_create", "gosma_destroy", "gosma_last_error", "gosma_set_mixtu
            "gosma_mlp_get_params", "gosma_mlp_predict", "gosma_mlp_loss_grad", "gosma_mlp_train",
            "gosma_set_record_sink", "gosma_get_tiles", "gosma_set_tiles", "gosma_autotune", "gosma_get_work_counts",
            "gosma_snapshot", "gosma_resume", "gosma_refine", "gosma_dpmeans", "gosma_dpvmf_means",
-           "gosma_eval_bounds_noalloc"]
+           "gosma_eval_bounds_noalloc", "gosma_get_bucket_tiles"]
 MLP_FEATURES, MLP_RECORD, MLP_PARAMS = 20, 21, 35841
 NOALLOC_MAX_CUBES = 65536
+N_BUCKETS = 4
 KERNEL_KINDS = ["s11", "s12", "select", "branch", "push", "mlp", "sma"]
 WORK_COUNTS = ["cubes", "s12_screened", "s12_evaluated", "cells", "s11_screened", "s11_evaluated"]
 
@@ -107,6 +108,7 @@ def lib():
         L.gosma_snapshot.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
         L.gosma_resume.argtypes = [vp, vp, C.c_size_t]
         L.gosma_get_tiles.argtypes = [vp, C.POINTER(Tiles)]
+        L.gosma_get_bucket_tiles.argtypes = [vp, C.c_int, C.POINTER(Tiles), C.POINTER(C.c_int)]
         L.gosma_set_tiles.argtypes = [vp, C.POINTER(Tiles)]
         L.gosma_autotune.argtypes = [vp, C.c_int64, C.c_uint64, dp, C.c_int64, C.POINTER(C.c_int64),
                                      C.POINTER(Tiles)]
@@ -388,15 +390,31 @@ class Context:
         self._check(lib().gosma_set_tiles(self._h, C.byref(t)), "gosma_set_tiles")
 
     def autotune(self, n_cubes=32768, seed=0):
-        """Time the candidate launch shapes on random cubes and keep the fastest.
-        Returns {"chosen": get_tiles(), "table": [(kernel, waves, blocks, ms), ...]}."""
-        rows = np.zeros((64, 4))
+        """Time the candidate launch shapes on random cubes and keep the fastest, for
+        all problems and per size bucket.  Returns {"chosen": get_tiles(), "buckets":
+        {bucket: bucket_tiles(bucket)} for the non-empty buckets, "table": [(kernel,
+        waves, blocks, ms, bucket), ...]} (bucket -1: all problems)."""
+        cap = 30 * (1 + N_BUCKETS)
+        rows = np.zeros((cap, 5))
         n = C.c_int64()
         t = Tiles()
-        self._check(lib().gosma_autotune(self._h, int(n_cubes), int(seed), _d(rows), rows.shape[0], C.byref(n),
+        self._check(lib().gosma_autotune(self._h, int(n_cubes), int(seed), _d(rows), cap, C.byref(n),
                                          C.byref(t)), "gosma_autotune")
-        table = [(KERNEL_KINDS[int(r[0])], int(r[1]), int(r[2]), float(r[3])) for r in rows[:min(n.value, 64)]]
-        return {"chosen": {"s11": (t.s11.waves, t.s11.blocks), "s12": (t.s12.waves, t.s12.blocks)}, "table": table}
+        table = [(KERNEL_KINDS[int(r[0])], int(r[1]), int(r[2]), float(r[3]), int(r[4])) for r in rows[:min(n.value, cap)]]
+        buckets = {}
+        for k in range(N_BUCKETS):
+            bt = self.bucket_tiles(k)
+            if bt["n_problems"]:
+                buckets[k] = bt
+        return {"chosen": {"s11": (t.s11.waves, t.s11.blocks), "s12": (t.s12.waves, t.s12.blocks)}, "buckets": buckets,
+                "table": table}
+
+    def bucket_tiles(self, bucket):
+        """{"s11": (waves, blocks), "s12": (...), "n_problems": n} of a size bucket."""
+        t = Tiles()
+        n = C.c_int()
+        self._check(lib().gosma_get_bucket_tiles(self._h, int(bucket), C.byref(t), C.byref(n)), "gosma_get_bucket_tiles")
+        return {"s11": (t.s11.waves, t.s11.blocks), "s12": (t.s12.waves, t.s12.blocks), "n_problems": n.value}
 
     # -- kernel timing ----------------------------------------------------
     def set_timing(self, enable=True):

@@ -288,13 +288,16 @@ def test_autotune(ctx):
     ctx.set_scene(sc)
     res = ctx.autotune(n_cubes=8192, seed=1)
     table = res["table"]
-    assert len(table) == 30
+    # one problem: one size bucket, whose shapes are the all-problem shapes
+    assert len(table) == 30 and all(r[4] == -1 for r in table)
     for kind in ("s11", "s12"):
         rows = [r for r in table if r[0] == kind]
         assert len(rows) == 15 and all(r[3] > 0 for r in rows)
         best = min(rows, key=lambda r: r[3])
         assert res["chosen"][kind] == (best[1], best[2])
     assert ctx.get_tiles() == res["chosen"]
+    assert list(res["buckets"]) == [0]
+    assert res["buckets"][0]["s11"] == res["chosen"]["s11"] and res["buckets"][0]["s12"] == res["chosen"]["s12"]
     print("autotune chosen", res["chosen"])
     rk, tk = scenes.random_cubes(sc, 1000, 2800, r_levels=(2, 12), t_levels=(1, 10))
     g = ctx.bounds(rk, tk)

@@ -42,8 +42,10 @@ def test_forward_matches_oracle(ctx, n):
     err = np.abs(y - yo)
     scale = np.abs(yo).mean() + 1e-3
     print(f"n={n}: max err {err.max():.3e} median {np.median(err):.3e} scale {scale:.3e}")
-    assert np.median(err) <= 2e-3 * scale
-    assert err.max() <= 3e-2 * scale
+    # measured on MI355X: median 3e-8 of the scale, largest 1.7e-3 (an activation
+    # whose bf16 rounding falls the other way)
+    assert np.median(err) <= 1e-6 * scale
+    assert err.max() <= 5e-3 * scale
 
 
 def test_gradient_matches_oracle(ctx):
@@ -61,7 +63,8 @@ def test_gradient_matches_oracle(ctx):
         rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30)
         cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30))
         print(f"{name}: rel {rel:.3e} cos {cos:.6f}")
-        assert rel <= 2e-2 and cos >= 0.9995, name
+        # measured on MI355X: relative error at most 3.6e-6, cosine 1 - 1e-12
+        assert rel <= 2e-5 and cos >= 0.99999, name
 
 
 def _slices():

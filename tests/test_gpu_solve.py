@@ -198,6 +198,25 @@ def test_autotune_on_a_batch_then_solve(ctx):
     res = ctx.autotune(n_cubes=4096, seed=7)
     assert len(res["table"]) == 30
     tuned = ctx.solve_batch(3, 1e-2, batch_parents=256)
+    # problems in several size buckets: shapes per bucket, each the fastest of its own rows
+    big = scenes.small_scene(100, 90, seed=87, noise_deg=1.0, n_inliers=60)
+    mixed = [scenes.small_scene(8, 8, seed=85), big]
+    ctx.set_scenes(mixed)
+    ref = ctx.solve_batch(2, 1e-1, batch_parents=256, time_limit_s=20, allow_overflow=True)
+    res2 = ctx.autotune(n_cubes=4096, seed=9)
+    assert sorted(res2["buckets"]) == [0, 1] and len(res2["table"]) == 90
+    for bk in (0, 1):
+        for kind in ("s11", "s12"):
+            rows = [r for r in res2["table"] if r[0] == kind and r[4] == bk]
+            best = min(rows, key=lambda r: r[3])
+            assert res2["buckets"][bk][kind] == (best[1], best[2])
+    print("bucket shapes", res2["buckets"])
+    again = ctx.solve_batch(2, 1e-1, batch_parents=256, time_limit_s=20, allow_overflow=True)
+    for a, b in zip(ref, again):
+        # each certified interval [lb, f] brackets the minimum, so they overlap
+        assert a["lb_norm"] <= b["f_norm_best"] + 1e-9 and b["lb_norm"] <= a["f_norm_best"] + 1e-9
+        if a["status"] == 0 and b["status"] == 0:
+            assert abs(a["f_norm_best"] - b["f_norm_best"]) <= 1e-1
     for a, b in zip(base, tuned):
         assert a["status"] == b["status"] == 0
         assert abs(a["f_norm_best"] - b["f_norm_best"]) <= 1e-2
