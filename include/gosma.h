@@ -400,9 +400,10 @@ int gosma_get_bucket_tiles(gosma_ctx *ctx, int bucket, gosma_tiles *out, int *n_
  * per seed), times every candidate shape of both kernels on them with HIP
  * events (waves 1, 2, 4 x grids of 2048 to 32768 waves in powers of 2; one
  * warm-up and three timed launches each), and keeps the fastest; then does
- * the same for each non-empty size bucket on n_cubes random cubes of that
- * bucket's problems (the shapes the search uses; with one bucket, the same
- * cubes and result).  rows: NULL or a host array of cap x 5 doubles
+ * the same for each non-empty size bucket on random cubes of that bucket's
+ * problems (the shapes the search uses: n_cubes cubes for the GMM-vMF kernel,
+ * an eighth as many cells for the GMM-GMM kernel, which the search runs once
+ * per distinct translation cell).  rows: NULL or a host array of cap x 5 doubles
  * receiving {kernel (GOSMA_KERNEL_S11 or GOSMA_KERNEL_S12), waves, blocks,
  * ms per launch, bucket (-1: all problems)} per candidate; *n_rows (if not
  * NULL) receives the number of candidates.  chosen: NULL or the shapes kept

@@ -45,6 +45,17 @@ gosma::Tile default_tile(int64_t pairs)
     const int w = pairs <= 64 * 64 ? 1 : (pairs <= 128 * 128 ? 2 : 4);
     return gosma::Tile{w, 8192 / w};
 }
+// The search's GMM-GMM kernel runs over the iteration's distinct translation
+// cells: from a few dozen (rotation splits share their parent's cell) to
+// several thousand.  Blocks of at least two waves: while there are fewer
+// cells than blocks, the waves of a block share a cell (its latency decides:
+// on the 64x64 search 28 -> 22 us per launch over the first 25 iterations),
+// and with more cells every wave takes a cell of its own.
+gosma::Tile default_search_tile11(int64_t pairs)
+{
+    const gosma::Tile t = default_tile(pairs);
+    return t.waves >= 2 ? t : gosma::Tile{2, 4096};
+}
 
 template <class T>
 void dfree(T *&p)
@@ -394,7 +405,7 @@ int gosma_set_problems(gosma_ctx *ctx, int n_problems, const int64_t *gmm_off, c
     }
     for (int b = 0; b < gosma::kBuckets; ++b) {
         const int64_t m = ctx->bucket_maxM[b], n = ctx->bucket_maxN[b];
-        ctx->btile11[b] = default_tile(m * m / 2);
+        ctx->btile11[b] = default_search_tile11(m * m / 2);
         ctx->btile12[b] = default_tile(m * n);
     }
     return GOSMA_OK;

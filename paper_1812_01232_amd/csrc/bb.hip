@@ -46,8 +46,8 @@ constexpr int kGridX = 2048;            // blocks per grid-stride kernel (divide
 constexpr int kMaxLevel = 19;
 constexpr uint32_t kNoChildren = 0xffffffffu;   // pchild of a parent that cannot be split
 // Rounding margin of the FP32 bounds, relative to the magnitude S11 + 2 S12 of
-// each bound: over 6x the largest relative error measured against the FP64
-// oracle on every parity set.
+// each bound: over 3x the largest relative error measured against the FP64
+// oracle on every parity set (1.2e-6).
 constexpr double kMarginGamma = 4e-6;
 
 enum Done : uint32_t { RUNNING = 0, EPS_OPTIMAL = 1, EXHAUSTED = 2, CAPPED = 3, OVERFLOW = 4 };

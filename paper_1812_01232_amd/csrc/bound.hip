@@ -379,19 +379,34 @@ template <bool GREC>
 __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_t *__restrict__ tkeys,
                                                          const uint32_t *__restrict__ pids, int64_t nt_host,
                                                          const uint32_t *__restrict__ nt_dev, S11Out out, int maxM,
-                                                         const int64_t *__restrict__ out_idx)
+                                                         const int64_t *__restrict__ out_idx, int split_ok)
 {
     extern __shared__ float4 lds4[];
     __shared__ BlockShared sh;
-    // component records: LDS, or the block's slice of the global records
-    float4 *rec = GREC ? mx.grec + (int64_t)blockIdx.x * mx.grec_stride : lds4;
-    // per wave: pairs that passed the screen
-    uint32_t *plist = reinterpret_cast<uint32_t *>(GREC ? lds4 : lds4 + kG * maxM);
-    const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, wv = tid >> 6, lane = tid & 63;
+    const int W = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t nt = nt_dev ? (int64_t)nt_dev[0] : nt_host;
+    // A cell is evaluated by a team: the whole block while there are fewer
+    // cells than blocks (the cell's latency decides), or each wave on its own
+    // once every wave can have a cell (with split_ok: LDS for one record set
+    // per wave).  The choice is uniform over the block.
+    const bool split = split_ok && W > 1 && nt > (int64_t)gridDim.x;
+    const int tid = split ? lane : (int)threadIdx.x, T = split ? 64 : (int)blockDim.x;
+    auto team_sync = [&]() __attribute__((always_inline)) {
+        if (split)
+            wave_lds_sync();
+        else
+            __syncthreads();
+    };
+    // component records: LDS (one set per team), or the block's slice of the
+    // global records
+    float4 *rec = GREC ? mx.grec + (int64_t)blockIdx.x * mx.grec_stride : lds4 + (split ? wv * kG * maxM : 0);
+    // per wave: pairs that passed the screen
+    uint32_t *plist = reinterpret_cast<uint32_t *>(GREC ? lds4 : lds4 + kG * maxM * (split_ok ? W : 1));
     unsigned ncells = 0, noff_all = 0, nkeep_all = 0;   // per wave, over the block's cells (for out.counts)
-    for (int64_t cell = blockIdx.x; cell < nt; cell += gridDim.x) {
-        __syncthreads();
+    const int64_t c_first = split ? (int64_t)blockIdx.x * W + wv : (int64_t)blockIdx.x;
+    const int64_t c_step = split ? (int64_t)gridDim.x * W : (int64_t)gridDim.x;
+    for (int64_t cell = c_first; cell < nt; cell += c_step) {
+        team_sync();
         const int64_t o = out_idx ? out_idx[cell] : cell;   // where the cell's sums go
         const uint32_t pid = pids ? pids[cell] : 0u;
         if (pid >= (uint32_t)mx.n_prob) {     // invalid problem index: no bound
@@ -438,19 +453,23 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
         drop = wave_or(drop);
         ubinf = wave_or(ubinf);
         dk = wave_sum(dk);
-        if (lane == 0) {
-            sh.drop[wv] = drop;
-            sh.ubinf[wv] = ubinf;
-            sh.dk[wv] = dk;
-        }
-        __syncthreads();
-        drop = 0;
-        ubinf = 0;
-        dk = 0.0;
-        for (int w = 0; w < W; ++w) {
-            drop |= sh.drop[w];
-            ubinf |= sh.ubinf[w];
-            dk += sh.dk[w];
+        if (!split) {
+            if (lane == 0) {
+                sh.drop[wv] = drop;
+                sh.ubinf[wv] = ubinf;
+                sh.dk[wv] = dk;
+            }
+            __syncthreads();
+            drop = 0;
+            ubinf = 0;
+            dk = 0.0;
+            for (int w = 0; w < W; ++w) {
+                drop |= sh.drop[w];
+                ubinf |= sh.ubinf[w];
+                dk += sh.dk[w];
+            }
+        } else {
+            wave_lds_sync();   // the team's records are written
         }
         if (drop) {
             if (tid == 0) {
@@ -587,6 +606,13 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
         acc_lo += (double)slo;
         acc_ub = wave_sum(acc_ub);
         acc_lo = wave_sum(acc_lo);
+        if (split) {
+            if (lane == 0) {
+                out.ub[o] = ubinf ? INFINITY : acc_ub;
+                out.lo[o] = acc_lo;
+            }
+            continue;
+        }
         if (lane == 0) {
             sh.s0[wv] = acc_ub;
             sh.s1[wv] = acc_lo;
@@ -604,7 +630,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
     }
     if (out.counts && lane == 0) {
         unsigned long long *c = out.counts + kCounters * (blockIdx.x % kCountSlots);
-        if (wv == 0) atomicAdd(c + kCntCells, (unsigned long long)ncells);
+        if (wv == 0 || split) atomicAdd(c + kCntCells, (unsigned long long)ncells);
         atomicAdd(c + kCntS11Screened, (unsigned long long)noff_all);
         atomicAdd(c + kCntS11Evaluated, (unsigned long long)nkeep_all);
     }
@@ -1147,6 +1173,13 @@ size_t s11_lds_bytes(int maxM, int waves)
 {
     return sizeof(float4) * kG * (size_t)maxM + sizeof(uint32_t) * kList * (size_t)waves;
 }
+// With one record set per wave, so that the waves of a block can take cells
+// of their own (k_s11's split_ok): only where it fits kS11SplitLds.
+constexpr size_t kS11SplitLds = 65536;
+size_t s11_split_lds_bytes(int maxM, int waves)
+{
+    return sizeof(float4) * kG * (size_t)maxM * waves + sizeof(uint32_t) * kList * (size_t)waves;
+}
 size_t s12_lds_bytes(int maxM, int maxN, int waves, bool vlds)
 {
     return sizeof(float4) * ((kG12 + 2) * (size_t)maxM + (vlds ? 2 * (size_t)maxN : 0)) +
@@ -1163,8 +1196,9 @@ int64_t grec_stride(int maxM, int maxN)
 hipError_t prepare_bound_kernels(int maxM, int maxN)
 {
     // allow dynamic LDS beyond the default limit on devices that have it
+    const size_t l11s = s11_split_lds_bytes(maxM, kMaxWaves);
     hipError_t e = hipFuncSetAttribute((const void *)k_s11<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)s11_lds_bytes(maxM, kMaxWaves));
+                                       (int)std::max(s11_lds_bytes(maxM, kMaxWaves), l11s <= kS11SplitLds ? l11s : 0));
     const int l0 = (int)s12_lds_bytes(maxM, maxN, kMaxWaves, false), l1 = (int)s12_lds_bytes(maxM, maxN, kMaxWaves, true);
     if (!e) e = hipFuncSetAttribute((const void *)k_s12<false, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, l0);
     if (!e) e = hipFuncSetAttribute((const void *)k_s12<true, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, l0);
@@ -1184,12 +1218,14 @@ hipError_t launch_s11(const DevMix &mx, const uint64_t *tkeys, const uint32_t *p
         // records in global memory: at most mx.grec_blocks blocks, LDS for the pair lists only
         const unsigned g = (unsigned)std::min<int64_t>(std::min<int64_t>(tile.blocks, nt), mx.grec_blocks);
         hipLaunchKernelGGL(k_s11<true>, dim3(g), dim3(64 * tile.waves), s11_lds_bytes(0, tile.waves), stream, mx,
-                           tkeys, pids, nt, nt_dev, out, maxM, out_idx);
+                           tkeys, pids, nt, nt_dev, out, maxM, out_idx, 0);
         return hipGetLastError();
     }
     const unsigned g = (unsigned)std::min<int64_t>(tile.blocks, nt);
-    hipLaunchKernelGGL(k_s11<false>, dim3(g), dim3(64 * tile.waves), s11_lds_bytes(maxM, tile.waves), stream, mx,
-                       tkeys, pids, nt, nt_dev, out, maxM, out_idx);
+    const size_t ls = s11_split_lds_bytes(maxM, tile.waves);
+    const int split_ok = tile.waves > 1 && ls <= kS11SplitLds;
+    hipLaunchKernelGGL(k_s11<false>, dim3(g), dim3(64 * tile.waves), split_ok ? ls : s11_lds_bytes(maxM, tile.waves),
+                       stream, mx, tkeys, pids, nt, nt_dev, out, maxM, out_idx, split_ok);
     return hipGetLastError();
 }
 

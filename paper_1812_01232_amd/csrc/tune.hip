@@ -110,11 +110,8 @@ int gosma_autotune(gosma_ctx *ctx, int64_t n_cubes, uint64_t seed, double *rows,
 
     // problems drawn from: all of them (bucket -1), then each non-empty size bucket
     std::vector<int> groups{-1};
-    int nonempty = 0;
-    for (int b = 0; b < kBuckets; ++b) nonempty += ctx->bucket_nprob[b] > 0;
-    if (nonempty > 1)
-        for (int b = 0; b < kBuckets; ++b)
-            if (ctx->bucket_nprob[b] > 0) groups.push_back(b);
+    for (int b = 0; b < kBuckets; ++b)
+        if (ctx->bucket_nprob[b] > 0) groups.push_back(b);
     const int64_t n = n_cubes;
     DevBuf d_rk, d_tk, d_pid, d_s11u, d_s11l, d_ub, d_lb, d_fl, d_setup;
     if ((e = hipMalloc(&d_rk.p, 8 * n)) || (e = hipMalloc(&d_tk.p, 8 * n)) || (e = hipMalloc(&d_pid.p, 4 * n)) ||
@@ -175,9 +172,13 @@ int gosma_autotune(gosma_ctx *ctx, int64_t n_cubes, uint64_t seed, double *rows,
             (e = hipMemcpy(d_tk.p, tk.data(), 8 * n, hipMemcpyHostToDevice)) ||
             (e = hipMemcpy(d_pid.p, pid.data(), 4 * n, hipMemcpyHostToDevice)))
             break;
+        // for the search's shapes the GMM-GMM kernel is timed on an eighth as many
+        // cells as cubes: the search evaluates it once per distinct translation
+        // cell of an iteration (about one per four to eight children)
+        const int64_t n11 = grp < 0 ? n : std::max<int64_t>(64, n / 8);
         auto run = [&](int kernel, Tile t) -> hipError_t {
             if (kernel == GOSMA_KERNEL_S11)
-                return launch_s11(mx, (const uint64_t *)d_tk.p, (const uint32_t *)d_pid.p, n, nullptr, s11, gM, t,
+                return launch_s11(mx, (const uint64_t *)d_tk.p, (const uint32_t *)d_pid.p, n11, nullptr, s11, gM, t,
                                   nullptr);
             return launch_s12(mx, (const uint64_t *)d_rk.p, (const uint64_t *)d_tk.p, (const uint32_t *)d_pid.p,
                               nullptr, s11.ub, s11.lo, n, nullptr, 1, bo, 0.0, gM, gN, false, t, (CubeSetup *)d_setup.p,
@@ -185,8 +186,8 @@ int gosma_autotune(gosma_ctx *ctx, int64_t n_cubes, uint64_t seed, double *rows,
         };
         Tile *best = grp < 0 ? best_all : best_b[grp];
         double best_ms[2] = {INFINITY, INFINITY};
-        // S11 results feed the S12 launches; compute them once with the current shape
-        e = run(GOSMA_KERNEL_S11, best[0]);
+        // S11 results of every cube feed the S12 launches; compute them once
+        e = launch_s11(mx, (const uint64_t *)d_tk.p, (const uint32_t *)d_pid.p, n, nullptr, s11, gM, best[0], nullptr);
         for (int kernel = GOSMA_KERNEL_S11; kernel <= GOSMA_KERNEL_S12 && !e; ++kernel)
             for (int wi = 0; wi < 3 && !e; ++wi)
                 for (int gj = 0; gj < 5 && !e; ++gj) {
@@ -220,9 +221,8 @@ int gosma_autotune(gosma_ctx *ctx, int64_t n_cubes, uint64_t seed, double *rows,
     ctx->tile11 = best_all[0];
     ctx->tile12 = best_all[1];
     for (int b = 0; b < kBuckets; ++b) {
-        // with one bucket its shapes are the all-problem shapes
-        ctx->btile11[b] = nonempty > 1 ? best_b[b][0] : best_all[0];
-        ctx->btile12[b] = nonempty > 1 ? best_b[b][1] : best_all[1];
+        ctx->btile11[b] = best_b[b][0];
+        ctx->btile12[b] = best_b[b][1];
     }
     if (n_rows) *n_rows = row;
     if (chosen) gosma_get_tiles(ctx, chosen);

@@ -252,7 +252,7 @@ def test_deterministic(ctx):
     assert np.array_equal(a["ub"], b["ub"]) and np.array_equal(a["lb"], b["lb"])
 
 
-TILES = [(1, 8192), (2, 2048), (4, 1024), (4, 7), (1, 3)]
+TILES = [(1, 8192), (2, 2048), (4, 1024), (4, 7), (2, 5), (1, 3)]
 
 
 @pytest.mark.parametrize("M,N", [(64, 64), (40, 32), (70, 128), (33, 45), (100, 256)])
@@ -288,16 +288,17 @@ def test_autotune(ctx):
     ctx.set_scene(sc)
     res = ctx.autotune(n_cubes=8192, seed=1)
     table = res["table"]
-    # one problem: one size bucket, whose shapes are the all-problem shapes
-    assert len(table) == 30 and all(r[4] == -1 for r in table)
+    # all problems (bucket -1), then the one size bucket of the 64x64 problem
+    assert len(table) == 60 and sorted({r[4] for r in table}) == [-1, 0]
     for kind in ("s11", "s12"):
-        rows = [r for r in table if r[0] == kind]
-        assert len(rows) == 15 and all(r[3] > 0 for r in rows)
-        best = min(rows, key=lambda r: r[3])
-        assert res["chosen"][kind] == (best[1], best[2])
+        for bk in (-1, 0):
+            rows = [r for r in table if r[0] == kind and r[4] == bk]
+            assert len(rows) == 15 and all(r[3] > 0 for r in rows)
+            best = min(rows, key=lambda r: r[3])
+            got = res["chosen"][kind] if bk < 0 else res["buckets"][0][kind]
+            assert got == (best[1], best[2])
     assert ctx.get_tiles() == res["chosen"]
     assert list(res["buckets"]) == [0]
-    assert res["buckets"][0]["s11"] == res["chosen"]["s11"] and res["buckets"][0]["s12"] == res["chosen"]["s12"]
     print("autotune chosen", res["chosen"])
     rk, tk = scenes.random_cubes(sc, 1000, 2800, r_levels=(2, 12), t_levels=(1, 10))
     g = ctx.bounds(rk, tk)

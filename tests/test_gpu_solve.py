@@ -196,7 +196,7 @@ def test_autotune_on_a_batch_then_solve(ctx):
     ctx.set_scenes(scs)
     base = ctx.solve_batch(3, 1e-2, batch_parents=256)
     res = ctx.autotune(n_cubes=4096, seed=7)
-    assert len(res["table"]) == 30
+    assert len(res["table"]) == 60      # all problems, then their one size bucket
     tuned = ctx.solve_batch(3, 1e-2, batch_parents=256)
     # problems in several size buckets: shapes per bucket, each the fastest of its own rows
     big = scenes.small_scene(100, 90, seed=87, noise_deg=1.0, n_inliers=60)
