@@ -76,7 +76,7 @@ struct PState {
 
 struct GState {
     uint32_t nchild, running;
-    uint32_t nl3;      // Lemma 3 records reserved by this iteration's new cells
+    uint32_t ntrec;    // translation records reserved by this iteration's new cells
     uint32_t pad;
     // per size bucket: children and distinct translation cells of the iteration
     uint32_t nchild_b[kBuckets], ntcell_b[kBuckets];
@@ -195,12 +195,13 @@ struct Bufs {
     uint8_t *cflags;
     double *s11ub, *s11lo;
     CubeSetup *csetup;            // per-child set-up of the pair kernel
-    // Lemma 3 records of the iteration's cells (M per cell, reserved by the
-    // claiming thread; kNoL3Record when the capacity is used up) and each
-    // cell's record offset, indexed by table slot
-    float4 *l3rec;
-    uint32_t *l3off;
-    uint32_t l3cap;
+    // translation records of the iteration's cells for the pair kernel (M
+    // per cell, reserved by the claiming thread; kNoTRec when the capacity is
+    // used up) and each cell's offset and sums, indexed by table slot
+    TransRec *trec;
+    uint32_t *toff;
+    CellSums *csum;
+    uint32_t tcap;
     uint32_t *hist;               // kHistBins per problem
     PState *st;
     GState *g;
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_iter_begin(Bufs b, int P, int rb_slo
     if (p == 0 && threadIdx.x == 0) {
         b.g->nchild = 0;
         b.g->running = 0;
-        b.g->nl3 = 0;
+        b.g->ntrec = 0;
         for (int k = 0; k < kBuckets; ++k) b.g->nchild_b[k] = b.g->ntcell_b[k] = 0;
     }
     if (s.done) {              // finished problems keep their final state
@@ -687,10 +688,10 @@ __global__ __launch_bounds__(kBlock) void k_branch_setup(Bufs b)
             uint32_t first = 0;
             if (lane == leader) first = b.kbase[bk] + atomicAdd(&b.g->ntcell_b[bk], (uint32_t)__popcll(m));
             first = __shfl(first, leader, 64);
-            // and reserve the cells' Lemma 3 records (M of them per cell)
+            // and reserve the cells' translation records (M of them per cell)
             const uint32_t M = (uint32_t)b.prob[p].M;
             uint32_t r0 = 0;
-            if (lane == leader) r0 = atomicAdd(&b.g->nl3, M * (uint32_t)__popcll(m));
+            if (lane == leader) r0 = atomicAdd(&b.g->ntrec, M * (uint32_t)__popcll(m));
             r0 = __shfl(r0, leader, 64);
             if (claimed) {
                 const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
@@ -699,7 +700,7 @@ __global__ __launch_bounds__(kBlock) void k_branch_setup(Bufs b)
                 b.cpid2[j] = (uint32_t)p;
                 b.cslot[j] = at;
                 const uint64_t roff = (uint64_t)r0 + (uint64_t)M * rank;
-                b.l3off[at] = roff + M <= (uint64_t)b.l3cap ? (uint32_t)roff : kNoL3Record;
+                b.toff[at] = roff + M <= (uint64_t)b.tcap ? (uint32_t)roff : kNoTRec;
             }
         }
     }
@@ -1200,8 +1201,9 @@ void free_solver(Solver *s)
     dfree(b.s11ub);
     dfree(b.s11lo);
     dfree(b.csetup);
-    dfree(b.l3rec);
-    dfree(b.l3off);
+    dfree(b.trec);
+    dfree(b.toff);
+    dfree(b.csum);
     dfree(b.hist);
     dfree(b.st);
     dfree(b.g);
@@ -1262,11 +1264,12 @@ hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap, b
     if (!e) e = dalloc(b.s11ub, std::max(nt, nc));
     if (!e) e = dalloc(b.s11lo, std::max(nt, nc));
     if (!e) e = dalloc(b.csetup, nc);
-    // Lemma 3 records: one per GMM component of every new cell of an
-    // iteration, up to 2^26 (1 GB); cells beyond compute them in the pair kernel
-    const size_t l3cap = std::min<size_t>(nc * (size_t)std::max(maxM, 1), (size_t)1 << 26);
-    if (!e) e = dalloc(b.l3rec, l3cap);
-    if (!e) e = dalloc(b.l3off, nt);
+    // translation records: one per GMM component of every new cell of an
+    // iteration, up to 1 GB; cells beyond compute them in the pair kernel
+    const size_t tcap = std::min<size_t>(nc * (size_t)std::max(maxM, 1), ((size_t)1 << 30) / sizeof(gosma::TransRec));
+    if (!e) e = dalloc(b.trec, tcap);
+    if (!e) e = dalloc(b.toff, nt);
+    if (!e) e = dalloc(b.csum, nt);
     if (!e) e = dalloc(b.hist, (size_t)gosma::kHistBins * P);
     if (!e) e = dalloc(b.st, (size_t)P);
     if (!e) e = dalloc(b.g, 1);
@@ -1281,7 +1284,7 @@ hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap, b
     b.ccap = (uint32_t)ccap;
     b.k = (uint32_t)k;
     b.tbits = tbits;
-    b.l3cap = (uint32_t)l3cap;
+    b.tcap = (uint32_t)tcap;
     // children (and cells) of size bucket j: 8 k per problem of the bucket
     {
         uint32_t at = 0;
@@ -1360,7 +1363,9 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
         if (!b.kcap[k]) continue;
         const size_t o = b.kbase[k];
         e = launch_s11(mx, b.ckey + o, b.cpid2 + o, b.kcap[k], &b.g->ntcell_b[k],
-                       S11Out{b.s11ub, b.s11lo, timed ? ctx->d_counts : nullptr, b.l3rec, b.l3off}, ctx->bucket_maxM[k],
+                       S11Out{b.s11ub, b.s11lo, timed ? ctx->d_counts : nullptr, b.trec, b.toff, b.csum,
+                              &b.g->nchild_b[k]},
+                       ctx->bucket_maxM[k],
                        ctx->btile11[k], st, b.cslot + o);
     }
     T1(ti);
@@ -1374,7 +1379,7 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
                     &b.st->dstar, (int)(sizeof(PState) / sizeof(unsigned long long)), timed ? ctx->d_counts : nullptr};
         e = launch_s12(mx, b.crk + o, b.ctk + o, b.cpid + o, b.ctidx + o, b.s11ub, b.s11lo, b.kcap[k],
                        &b.g->nchild_b[k], 1, bo, kMarginGamma, ctx->bucket_maxM[k], ctx->bucket_maxN[k], top8,
-                       ctx->btile12[k], b.csetup + o, st, true, Lemma3Recs{b.l3rec, b.l3off});
+                       ctx->btile12[k], b.csetup + o, st, true, TransRecs{b.trec, b.toff, b.csum});
     }
     T1(ti);
     if (e) return e;

@@ -226,6 +226,37 @@ __device__ __forceinline__ YFun yfun(double y64)
     return o;
 }
 
+// The record of a component for a translation cell (see TransRec), from its
+// interval set-up tp, its weight w and the functions of kappa and klo; the
+// values are the ones the pair kernel computes from the same inputs.
+__device__ __forceinline__ TransRec trans_record(const TransPrep &tp, float w, const YFun &fk, const YFun &fl)
+{
+    TransRec r;
+    r.u[0] = tp.u[0];
+    r.u[1] = tp.u[1];
+    r.u[2] = tp.u[2];
+    const double ahi = tp.klo + 2.0 * tp.ha;
+    const YFun fh = yfun(ahi);
+    r.kap = (float)tp.kap;
+    r.klo = (float)tp.klo;
+    r.ahi = (float)ahi;
+    r.ha = (float)tp.ha;
+    r.cps = (float)tp.cps;
+    r.sps = (float)tp.sps;
+    r.psi = tp.psi;
+    r.Gk = fk.G;
+    r.cothl = fl.coth;
+    r.Gl = fl.G;
+    r.Gh = fh.G;
+    r.nul = fl.nu;
+    r.nuh = fh.nu;
+    r.hla = 0.5f * kLn2 * __builtin_amdgcn_logf((float)tp.klo);
+    r.lam = fmaxf(__builtin_amdgcn_logf(w * fh.G) * kLn2 - r.hla, -100.0f);
+    r.ia = frcp((float)tp.klo);
+    r.pad = 0.0f;
+    return r;
+}
+
 // Pair kernel pieces for concentrations a, b and squared chord q.
 struct PairK {
     float ks;     // K^2
@@ -403,6 +434,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
     // per wave: pairs that passed the screen
     uint32_t *plist = reinterpret_cast<uint32_t *>(GREC ? lds4 : lds4 + kG * maxM * (split_ok ? W : 1));
     unsigned ncells = 0, noff_all = 0, nkeep_all = 0;   // per wave, over the block's cells (for out.counts)
+    const bool recs = out.trec && (!out.ncubes || (int64_t)out.ncubes[0] >= (int64_t)kTRecMinCubes * nt);
     const int64_t c_first = split ? (int64_t)blockIdx.x * W + wv : (int64_t)blockIdx.x;
     const int64_t c_step = split ? (int64_t)gridDim.x * W : (int64_t)gridDim.x;
     for (int64_t cell = c_first; cell < nt; cell += c_step) {
@@ -419,14 +451,24 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
         const ProbDesc P = mx.prob[pid];
         double t0[3], tau[3];
         decode_key(tkeys[cell], P.t_lo, P.t_w, t0, tau);
-        // where this cell's Lemma 3 records go (none without a record buffer)
-        const uint32_t l3base = out.l3rec ? out.l3off[o] : kNoL3Record;
+        // where this cell's records for the pair kernel go (none without a
+        // record buffer or when the buffer is used up); with too few cubes
+        // per cell to pay for the full records, Lemma 3's records only
+        const uint32_t toff = out.trec ? out.toff[o] : kNoTRec;
+        // (another wave of the team may already have flagged the offset)
+        const uint32_t tbase = toff == kNoTRec ? kNoTRec : toff & ~kTRecLemma3;
+        float4 *l3rec = nullptr;
+        if (tbase != kNoTRec && !recs) {
+            l3rec = reinterpret_cast<float4 *>(out.trec + tbase);
+            if (tid == 0) out.toff[o] = tbase | kTRecLemma3;
+        }
 
         // per-component prep; the diagonal (i = i') summands are added here:
         // Z(2k)/Z(k)^2 = k coth(k) / 2 at the centre, and at the low end of the
         // kappa interval for the lower bound (the angle is exactly 0 and the
         // summand increases with kappa).
         double dub = 0.0, dlo = 0.0, dk = 0.0;
+        float psum = 0.0f;
         int drop = 0, ubinf = 0;
         for (int i = tid; i < P.M; i += T) {
             const int g = P.gmm_off + i;
@@ -435,11 +477,15 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
             TransPrep tp = trans_interval(mx.mu + 3 * g, mx.isig2[g], t0, tau, P.zeta, cd, &rho2, &inside);
             const float4 l3 = lemma3_record(cd, rho2, tau, inside);
             apply_lemma3(tp, l3);
-            if (l3base != kNoL3Record) out.l3rec[(size_t)l3base + i] = l3;
             drop |= tp.drop;
             ubinf |= tp.ub_inf;
+            psum += mx.pbar[g] * tp.psi;
             const double w = mx.w1[g];
             const YFun fk = yfun(tp.kap), fa = yfun(tp.ac), fl = yfun(tp.klo);
+            if (l3rec)
+                l3rec[i] = l3;
+            else if (tbase != kNoTRec)
+                out.trec[(size_t)tbase + i] = trans_record(tp, (float)w, fk, fl);
             dub += w * w * 0.5 * tp.kap * (double)fk.coth;
             dlo += w * w * 0.5 * tp.klo * (double)fl.coth;
             rec[kG * i] = make_float4((float)tp.u[0], (float)tp.u[1], (float)tp.u[2], (float)w);
@@ -453,24 +499,30 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
         drop = wave_or(drop);
         ubinf = wave_or(ubinf);
         dk = wave_sum(dk);
+        psum = wave_sumf(psum);
         if (!split) {
             if (lane == 0) {
                 sh.drop[wv] = drop;
                 sh.ubinf[wv] = ubinf;
                 sh.dk[wv] = dk;
+                sh.psum[wv] = psum;
             }
             __syncthreads();
             drop = 0;
             ubinf = 0;
             dk = 0.0;
+            psum = 0.0f;
             for (int w = 0; w < W; ++w) {
                 drop |= sh.drop[w];
                 ubinf |= sh.ubinf[w];
                 dk += sh.dk[w];
+                psum += sh.psum[w];
             }
         } else {
             wave_lds_sync();   // the team's records are written
         }
+        if (out.csum && tid == 0)
+            out.csum[o] = CellSums{dk, psum, (drop ? kCellDrop : 0u) | (ubinf ? kCellUbInf : 0u)};
         if (drop) {
             if (tid == 0) {
                 out.ub[o] = INFINITY;
@@ -801,7 +853,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                                                          const double *__restrict__ s11lo, int64_t n_host,
                                                          const uint32_t *__restrict__ n_dev, int n_dev_mul,
                                                          BoundOut out, double gamma, int maxM, int maxN,
-                                                         const CubeSetup *__restrict__ setup, Lemma3Recs l3)
+                                                         const CubeSetup *__restrict__ setup, TransRecs tr)
 {
     extern __shared__ float4 lds4[];
     __shared__ BlockShared sh;
@@ -831,8 +883,13 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         const uint32_t pid = pids ? pids[cube] : 0u;
         const ProbDesc P = mx.prob[pid];
         const double *R = cs.R, *t0 = cs.t0, *tau = cs.tau;
-        // the translation cell's Lemma 3 records, when the caller has them
-        const uint32_t l3base = l3.rec ? l3.off[tidx ? tidx[cube] : cube] : kNoL3Record;
+        // the translation cell's records, when the caller has them: the full
+        // records, or Lemma 3's only (kTRecLemma3)
+        const int64_t ti = tidx ? tidx[cube] : cube;
+        const uint32_t toff = tr.rec ? tr.off[ti] : kNoTRec;
+        const bool full = toff != kNoTRec && !(toff & kTRecLemma3);
+        const float4 *l3rec = toff != kNoTRec && !full ? reinterpret_cast<const float4 *>(tr.rec + (toff & ~kTRecLemma3))
+                                                       : nullptr;
 
         // Lemma 2, per direction.  The angle-axis metric bound
         // angle(R_r p, R_s p) <= |r - s| caps every direction's rotation
@@ -853,15 +910,24 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         double dk = 0.0;
         for (int i = tid; i < P.M; i += T) {
             const int g = P.gmm_off + i;
-            double cd[3], rho2;
-            bool inside;
-            TransPrep tp = trans_interval(mx.mu + 3 * g, mx.isig2[g], t0, tau, P.zeta, cd, &rho2, &inside);
-            apply_lemma3(tp, l3base != kNoL3Record ? l3.rec[(size_t)l3base + i] : lemma3_record(cd, rho2, tau, inside));
-            drop |= tp.drop;
-            ubinf |= tp.ub_inf;
-            psum += mx.pbar[g] * tp.psi;
+            const float wi = mx.w1[g];
+            // the translation part: the cell's record, or computed here
+            TransRec r;
+            if (full) {
+                r = tr.rec[(size_t)toff + i];
+            } else {
+                double cd[3], rho2;
+                bool inside;
+                TransPrep tp = trans_interval(mx.mu + 3 * g, mx.isig2[g], t0, tau, P.zeta, cd, &rho2, &inside);
+                apply_lemma3(tp, l3rec ? l3rec[i] : lemma3_record(cd, rho2, tau, inside));
+                drop |= tp.drop;
+                ubinf |= tp.ub_inf;
+                psum += mx.pbar[g] * tp.psi;
+                dk += 0.5 * (double)wi * (double)wi * tp.klo;
+                r = trans_record(tp, wi, yfun(tp.kap), yfun(tp.klo));
+            }
             double w[3];
-            for (int a = 0; a < 3; ++a) w[a] = R[3 * a] * tp.u[0] + R[3 * a + 1] * tp.u[1] + R[3 * a + 2] * tp.u[2];
+            for (int a = 0; a < 3; ++a) w[a] = R[3 * a] * r.u[0] + R[3 * a + 1] * r.u[1] + R[3 * a + 2] * r.u[2];
             // the rotation uncertainty of this direction (FP32: it enters the
             // bound through FP32 records)
             float psir = cap;
@@ -875,35 +941,29 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                                 z = wf[0] * v[1] - wf[1] * v[0];
                     m2 = fmaxf(m2, fmaf(x, x, fmaf(y, y, z * z)));
                 }
-                psir = fminf(fsqrt(m2) + 2.0f * (float)tp.sps * hnf + 1.3f * hnf * hnf, cap);
+                psir = fminf(fsqrt(m2) + 2.0f * r.sps * hnf + 1.3f * hnf * hnf, cap);
             }
             prsum += mx.pbar[g] * psir;
             float crf, srf;
             sincos_half(0.5f * psir, &srf, &crf);
             const double crh = crf, srh = srf;
             // half of Psi = psi_t + psi_r (eq. 25), as cos/sin
-            const double cP = tp.cps * crh - tp.sps * srh, sP = tp.sps * crh + tp.cps * srh;
-            const double ahi = tp.klo + 2.0 * tp.ha;
-            const YFun fk = yfun(tp.kap), fl = yfun(tp.klo), fh = yfun(ahi);
-            const float wi = mx.w1[g];
-            dk += 0.5 * (double)wi * (double)wi * tp.klo;
+            const double cps = r.cps, sps = r.sps;
+            const double cP = cps * crh - sps * srh, sP = sps * crh + cps * srh;
             // pair screen rows: none dropped for Psi > pi/2 (where the bound on
             // cos B fails); Lam clamped below at -100 (a smaller threshold term
             // only screens out fewer pairs)
             {
                 const float cf = (float)cP, sf = (float)sP;
                 const float cPsi = cf * cf - sf * sf, sPsi = 2.0f * cf * sf;
-                const float hla = 0.5f * kLn2 * __builtin_amdgcn_logf((float)tp.klo);   // ln(alo) / 2
-                const float lam = fmaxf(__builtin_amdgcn_logf(wi * fh.G) * kLn2 - hla, -100.0f);
-                const float ia = frcp((float)tp.klo);
-                const float r0 = cf >= sf ? 1.0f - sPsi - lam * ia : -1e30f;
+                const float r0 = cf >= sf ? 1.0f - sPsi - r.lam * r.ia : -1e30f;
                 scr[2 * i] = make_float4((float)w[0] * cPsi, (float)w[1] * cPsi, (float)w[2] * cPsi, r0);
-                scr[2 * i + 1] = make_float4(lam, ia, -sPsi, hla);
+                scr[2 * i + 1] = make_float4(r.lam, r.ia, -sPsi, r.hla);
             }
             rec[kG12 * i] = make_float4((float)w[0], (float)w[1], (float)w[2], wi);
-            rec[kG12 * i + 1] = make_float4((float)tp.kap, (float)fk.G, (float)cP, (float)sP);
-            rec[kG12 * i + 2] = make_float4((float)tp.klo, (float)ahi, (float)tp.ha, (float)fl.coth);
-            rec[kG12 * i + 3] = make_float4((float)fl.G, (float)fh.G, (float)fl.nu, (float)fh.nu);
+            rec[kG12 * i + 1] = make_float4(r.kap, r.Gk, (float)cP, (float)sP);
+            rec[kG12 * i + 2] = make_float4(r.klo, r.ahi, r.ha, r.cothl);
+            rec[kG12 * i + 3] = make_float4(r.Gl, r.Gh, r.nul, r.nuh);
         }
         // the problem's vMF rows {mu, kappa}, {weight, G(kappa), coth kappa, ln(2 kappa) / 2}
         const float4 *__restrict__ vt = mx.vmf + 2 * (int64_t)P.vmf_off;
@@ -915,30 +975,45 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             else
                 return vt[2 * j + h];
         };
-        drop = wave_or(drop);
-        ubinf = wave_or(ubinf);
-        psum = wave_sumf(psum);
+        // the sums over the components: the rotation part here, the
+        // translation part from the cell's sums when it has records
+        const bool own = !full;
         prsum = wave_sumf(prsum);
-        dk = wave_sum(dk);
+        if (own) {
+            drop = wave_or(drop);
+            ubinf = wave_or(ubinf);
+            psum = wave_sumf(psum);
+            dk = wave_sum(dk);
+        }
         if (lane == 0) {
-            sh.drop[wv] = drop;
-            sh.ubinf[wv] = ubinf;
-            sh.psum[wv] = psum;
             sh.prsum[wv] = prsum;
-            sh.dk[wv] = dk;
+            if (own) {
+                sh.drop[wv] = drop;
+                sh.ubinf[wv] = ubinf;
+                sh.psum[wv] = psum;
+                sh.dk[wv] = dk;
+            }
         }
         __syncthreads();
-        drop = 0;
-        ubinf = 0;
-        psum = 0.0f;
         prsum = 0.0f;
-        dk = 0.0;
-        for (int w = 0; w < W; ++w) {
-            drop |= sh.drop[w];
-            ubinf |= sh.ubinf[w];
-            psum += sh.psum[w];
-            prsum += sh.prsum[w];
-            dk += sh.dk[w];
+        for (int w = 0; w < W; ++w) prsum += sh.prsum[w];
+        if (own) {
+            drop = 0;
+            ubinf = 0;
+            psum = 0.0f;
+            dk = 0.0;
+            for (int w = 0; w < W; ++w) {
+                drop |= sh.drop[w];
+                ubinf |= sh.ubinf[w];
+                psum += sh.psum[w];
+                dk += sh.dk[w];
+            }
+        } else {
+            const CellSums c = tr.csum[ti];
+            drop = (c.flags & kCellDrop) != 0;
+            ubinf = (c.flags & kCellUbInf) != 0;
+            psum = c.psum;
+            dk = c.dk;
         }
         // threshold of the pair screen, per GMM-vMF pair
         const double thr = kCullRel * dk / ((double)P.M * (double)P.N);
@@ -1243,7 +1318,7 @@ hipError_t launch_cube_setup(const DevMix &mx, const uint64_t *rkeys, const uint
 hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                       const int64_t *tidx, const double *s11ub, const double *s11lo, int64_t n, const uint32_t *n_dev,
                       int n_dev_mul, BoundOut out, double margin_gamma, int maxM, int maxN, bool with_top8, Tile tile,
-                      CubeSetup *setup, hipStream_t stream, bool setup_done, Lemma3Recs l3)
+                      CubeSetup *setup, hipStream_t stream, bool setup_done, TransRecs tr)
 {
     if (n <= 0) return hipSuccess;
     if (!tile_ok(tile) || !setup) return hipErrorInvalidValue;
@@ -1257,7 +1332,7 @@ hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *t
     const unsigned g = (unsigned)std::min<int64_t>(std::min<int64_t>(tile.blocks, n), grec ? mx.grec_blocks : INT32_MAX);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(g), dim3(64 * tile.waves), lds, stream, mx, rkeys, tkeys, pids, tidx, s11ub,
-                           s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, maxN, setup, l3);
+                           s11lo, n, n_dev, n_dev_mul, out, margin_gamma, maxM, maxN, setup, tr);
     };
     if (grec)
         with_top8 ? go(k_s12<true, false, true>) : go(k_s12<false, false, true>);

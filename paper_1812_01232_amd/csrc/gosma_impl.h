@@ -94,21 +94,57 @@ struct CellTable {
     uint32_t *count;
 };
 
+// Per translation cell and GMM component: the component's quantities that
+// depend on the cell alone (the translation part of the per-component set-up
+// of the pair kernel).  The GMM-GMM kernel computes them for every distinct
+// translation cell of a search iteration and writes them here; the pair
+// kernel reads them for each of the cell's cubes instead of recomputing them.
+struct alignas(16) TransRec {
+    double u[3];                    // (mu - t0) / |mu - t0|
+    float kap, klo, ahi, ha;        // kappa at the centre; the interval [klo, ahi], half its width
+    float cps, sps, psi;            // cos, sin of psi_t / 2; psi_t (Lemma 3)
+    float Gk, cothl, Gl, Gh;        // G(kappa), coth(klo), G(klo), G(ahi)
+    float nul, nuh;                 // nu(klo), nu(ahi)
+    float lam, ia, hla;             // pair-screen row: ln(w G(ahi)) - ln(klo) / 2, 1 / klo, ln(klo) / 2
+    float pad;
+};
+// The cell's sums over its components: w^2 klo / 2 (the pair screen's
+// threshold), the weighted psi_t (branching rule), and its drop flags.
+struct alignas(16) CellSums {
+    double dk;
+    float psum;
+    uint32_t flags;   // kCellDrop, kCellUbInf
+};
+constexpr uint32_t kCellDrop = 1u, kCellUbInf = 2u;
+// No record for the cell: the pair kernel computes the values itself.
+constexpr uint32_t kNoTRec = 0xffffffffu;
+// Offset flag: the cell's record space holds only Lemma 3's half-angle record
+// of each component, a float4 {cos, sin of psi_t / 2, psi_t, 0} (written when
+// too few cubes share the cells to pay for the full records).
+constexpr uint32_t kTRecLemma3 = 0x80000000u;
+
 struct S11Out {
     double *ub, *lo;   // S11 at the centre and its lower bound, per translation cube
     unsigned long long *counts = nullptr;   // optional work counters (see BoundOut)
-    // optional Lemma 3 records of the cells (see Lemma3Recs): written at the
-    // cell's record offset, which is looked up by the cell's output index
-    float4 *l3rec = nullptr;
-    const uint32_t *l3off = nullptr;
+    // optional per-cell records for the pair kernel (see TransRecs): written
+    // at the cell's record offset, which is looked up by its output index
+    TransRec *trec = nullptr;
+    uint32_t *toff = nullptr;
+    CellSums *csum = nullptr;
+    // the number of cubes whose pair kernel will read the records: the full
+    // records are written only while there are at least kTRecMinCubes cubes
+    // per cell, Lemma 3's records otherwise (offsets flagged kTRecLemma3);
+    // NULL: always the full records
+    const uint32_t *ncubes = nullptr;
 };
-// Lemma 3 records: per translation cell and GMM component a float4 {cos, sin
-// of psi_t / 2, psi_t, 0}, at offset l3off[cell index] + component
-// (kNoL3Record: the cell has none and the pair kernel computes them itself).
-constexpr uint32_t kNoL3Record = 0xffffffffu;
-struct Lemma3Recs {
-    const float4 *rec = nullptr;
-    const uint32_t *off = nullptr;   // indexed like the S11 sums (tidx)
+constexpr int kTRecMinCubes = 8;
+// The records of the cells as the pair kernel reads them: the component
+// records of a cell at rec[off[cell] + component] (off = kNoTRec: none), its
+// sums at csum[cell]; cell indexed like the S11 sums (tidx).
+struct TransRecs {
+    const TransRec *rec = nullptr;
+    const uint32_t *off = nullptr;
+    const CellSums *csum = nullptr;
 };
 
 // Per-cube set-up of the GMM-vMF pair kernel: both cells decoded, the rotation
@@ -155,7 +191,7 @@ hipError_t launch_s11(const DevMix &mx, const uint64_t *tkeys, const uint32_t *p
 hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                       const int64_t *tidx, const double *s11ub, const double *s11lo, int64_t n, const uint32_t *n_dev,
                       int n_dev_mul, BoundOut out, double margin_gamma, int maxM, int maxN, bool with_top8, Tile tile,
-                      CubeSetup *setup, hipStream_t stream, bool setup_done = false, Lemma3Recs l3 = Lemma3Recs{});
+                      CubeSetup *setup, hipStream_t stream, bool setup_done = false, TransRecs tr = TransRecs{});
 // The per-cube set-up pass of k_s12 (and, with cells, the cubes' translation cells).
 hipError_t launch_cube_setup(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                              int64_t n, const uint32_t *n_dev, int n_dev_mul, CubeSetup *setup, const CellTable *cells,
