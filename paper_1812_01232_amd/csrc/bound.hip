@@ -14,10 +14,13 @@
 // k_s12 evaluates the GMM-vMF sums and combines.
 //
 // Work mapping: one block of 64 x W threads per cell (W = 1, 2 or 4, the
-// launch shape chosen by the autotuner).  The per-component quantities of the
-// cell (kappa, its interval over the cell, uncertainty half-angles, rotated
-// directions, normaliser factors) are computed in FP64, one component per
-// thread, and staged in LDS as one FP32 record per component (four float4,
+// launch shape chosen by the autotuner; k_s11 lets each wave take a cell of
+// its own once there are more cells than blocks).  The per-component
+// quantities of the cell (kappa, its interval over the cell, uncertainty
+// half-angles, rotated directions, normaliser factors) are computed in FP64,
+// one component per thread (in the search, k_s12 reads the translation part
+// from records that k_s11 writes once per distinct translation cell), and
+// staged in LDS as one FP32 record per component (four float4,
 // padded to 80 bytes so that neighbouring records fall on distinct banks),
 // read back with 16-byte loads.  The pair sums then run over the (i, j) rectangle
 // of each class: when the class's vMF count divides the block or is a
