@@ -102,6 +102,12 @@ def lib():
         L.oracle_s11_lower_log.argtypes = [C.c_double] * 5
         L.oracle_s12_upper_term.restype = C.c_double
         L.oracle_s12_upper_term.argtypes = [C.c_double] * 4
+        L.oracle_s12_upper_term_pieces.restype = C.c_double
+        L.oracle_s12_upper_term_pieces.argtypes = [C.c_double] * 4 + [C.c_int]
+        L.oracle_s12_expansion_log.restype = C.c_double
+        L.oracle_s12_expansion_log.argtypes = [C.c_double] * 4
+        L.oracle_set_kappa_pieces.restype = C.c_int
+        L.oracle_set_kappa_pieces.argtypes = [C.c_int]
         L.oracle_decode.argtypes = [C.c_uint64, d3, d3, d3, d3]
         L.oracle_eval_bounds.argtypes = [C.POINTER(Problem), C.POINTER(Domain), C.POINTER(C.c_uint64),
                                          C.POINTER(C.c_uint64), C.c_int64, C.POINTER(Bound), C.c_int]
@@ -247,6 +253,21 @@ def s11_lower_log(alo, ahi, blo, bhi, A):
 
 def s12_upper_term(alo, ahi, b, B):
     return lib().oracle_s12_upper_term(alo, ahi, b, B)
+
+
+def s12_upper_term_pieces(alo, ahi, b, B, m):
+    return lib().oracle_s12_upper_term_pieces(alo, ahi, b, B, int(m))
+
+
+def s12_expansion_log(e0, e1, b, B):
+    return lib().oracle_s12_expansion_log(e0, e1, b, B)
+
+
+def set_kappa_pieces(m):
+    """Pieces of the kappa interval of the S12 upper term in every later cube
+    bound of the oracle (1 to 64; 1 is the default reading)."""
+    if lib().oracle_set_kappa_pieces(int(m)) != 0:
+        raise ValueError("kappa pieces must be in 1..64")
 
 
 def decode(key, lo, hi):

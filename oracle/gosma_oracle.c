@@ -415,25 +415,44 @@ static double s11_lower_log(double alo, double ahi, double blo, double bhi, doub
  * The term is the smallest of these bounds. */
 static double ell(double y) { return oracle_log_Z(y) - y; }
 
-static double s12_upper_term(double alo, double ahi, double b, double B)
+/* The expansion bound above over a piece [e0, e1] of the kappa interval, as
+ * a log: the smaller of the two end expansions. */
+static double s12_expansion_log(double e0, double e1, double b, double B)
 {
-    const double h = 0.5 * (ahi - alo), c = cos(B);
-    const double K1 = Kab(alo, b, B), K2 = Kab(ahi, b, B);
+    const double h = 0.5 * (e1 - e0), c = cos(B);
+    const double K1 = Kab(e0, b, B), K2 = Kab(e1, b, B);
     /* K - a - b = (K^2 - (a + b)^2) / (K + a + b), with 1 - cos B = 2 sin^2(B/2) */
     const double sh = sin(0.5 * B), chord2 = 4.0 * sh * sh;
-    const double x1 = -alo * b * chord2 / (K1 + alo + b), x2 = -ahi * b * chord2 / (K2 + ahi + b);
-    const double phi1 = ell(K1) - ell(alo) - ell(b), phi2 = ell(K2) - ell(ahi) - ell(b);
+    const double x1 = -e0 * b * chord2 / (K1 + e0 + b), x2 = -e1 * b * chord2 / (K2 + e1 + b);
+    const double phi1 = ell(K1) - ell(e0) - ell(b), phi2 = ell(K2) - ell(e1) - ell(b);
     /* phi'(a) = (L(K) - 1) K_a - (L(a) - 1), K_a = (a + b cos B) / K */
-    const double Ka1 = K1 > 0.0 ? (alo + b * c) / K1 : 0.0, Ka2 = K2 > 0.0 ? (ahi + b * c) / K2 : 0.0;
-    const double d1 = (langevin(K1) - 1.0) * Ka1 - (langevin(alo) - 1.0);
-    const double d2 = (langevin(K2) - 1.0) * Ka2 - (langevin(ahi) - 1.0);
+    const double Ka1 = K1 > 0.0 ? (e0 + b * c) / K1 : 0.0, Ka2 = K2 > 0.0 ? (e1 + b * c) / K2 : 0.0;
+    const double d1 = (langevin(K1) - 1.0) * Ka1 - (langevin(e0) - 1.0);
+    const double d2 = (langevin(K2) - 1.0) * Ka2 - (langevin(e1) - 1.0);
     const double astar = -b * c;
-    const double Kmin = (astar > alo && astar < ahi) ? b * sin(B) : fmin(K1, K2);
+    const double Kmin = (astar > e0 && astar < e1) ? b * sin(B) : fmin(K1, K2);
     const double G = Kmin > 0.0 ? fmin(1.0 / 3.0, 1.0 / (Kmin * Kmin)) : 1.0 / 3.0;
     const double q = 2.0 * G * h * h;    /* G (a - e)^2 / 2 at the far end, a - e = 2h */
     const double from_lo = phi1 + fmax(x1, x2 + 2.0 * d1 * h + q);
     const double from_hi = phi2 + fmax(x2, x1 - 2.0 * d2 * h + q);
-    const double expansion = exp(fmin(from_lo, from_hi));
+    return fmin(from_lo, from_hi);
+}
+
+/* The term with the kappa interval split into m equal pieces: the largest of
+ * the pieces' expansion bounds (each bounds the ratio on its piece, so their
+ * largest bounds it on the whole interval, and it tends to the ratio's
+ * maximum over the interval as the pieces shrink), capped by the aligned and
+ * far-apart bounds of the whole interval.  m = 1 is the reading above. */
+static double s12_upper_pieces(double alo, double ahi, double b, double B, int m)
+{
+    double elog = -INFINITY;
+    for (int k = 0; k < m; ++k) {
+        const double e0 = k == 0 ? alo : alo + (ahi - alo) * k / m;
+        const double e1 = k == m - 1 ? ahi : alo + (ahi - alo) * (k + 1) / m;
+        elog = fmax(elog, s12_expansion_log(e0, e1, b, B));
+    }
+    const double expansion = exp(elog);
+    const double sh = sin(0.5 * B), chord2 = 4.0 * sh * sh;
     const double aligned = 0.5 * fmin(ahi, b) * (1.0 / tanh(alo) + 1.0 / tanh(b));
     /* log G(y) = y - log Z(y) = -ell(y) */
     const double cf = alo * b / (2.0 * (alo + b));
@@ -441,6 +460,13 @@ static double s12_upper_term(double alo, double ahi, double b, double B)
     const double farK = exp(-ell(ahi) - ell(b) - fmin(chord2, 2.0) * cf - 0.5 * log(2.0 * alo * b));
     return fmin(fmin(expansion, aligned), fmin(far2, farK));
 }
+
+static double s12_upper_term(double alo, double ahi, double b, double B) { return s12_upper_pieces(alo, ahi, b, B, 1); }
+
+/* Pieces of the kappa interval of the S12 upper term in the cube bounds (1:
+ * the reading above; set by oracle_set_kappa_pieces, read by every bound
+ * evaluation). */
+static int g_kappa_pieces = 1;
 
 /* Test hooks for the two summand bounds above. */
 double oracle_s11_lower_log(double alo, double ahi, double blo, double bhi, double A)
@@ -450,6 +476,20 @@ double oracle_s11_lower_log(double alo, double ahi, double blo, double bhi, doub
 double oracle_s12_upper_term(double alo, double ahi, double b, double B)
 {
     return s12_upper_term(alo, ahi, b, B);
+}
+double oracle_s12_expansion_log(double e0, double e1, double b, double B)
+{
+    return s12_expansion_log(e0, e1, b, B);
+}
+double oracle_s12_upper_term_pieces(double alo, double ahi, double b, double B, int m)
+{
+    return s12_upper_pieces(alo, ahi, b, B, m < 1 ? 1 : m);
+}
+int oracle_set_kappa_pieces(int m)
+{
+    if (m < 1 || m > 64) return -1;
+    g_kappa_pieces = m;
+    return 0;
 }
 
 static int cmp_desc(const void *a, const void *b)
@@ -586,7 +626,7 @@ int oracle_bounds_cube(const oracle_problem *p, const oracle_domain *d, uint64_t
             matTvec(R0, p->dir2 + 3 * j, Rinv_mu);                     /* R_{r0}^{-1} mu_2j */
             double B = angle3(c + 3 * i, Rinv_mu) - psit[i] - psir[i];
             if (B < 0) B = 0;
-            s12hi += w1[i] * w2[j] * s12_upper_term(klo[i], khi[i], p->kappa2[j], B);
+            s12hi += w1[i] * w2[j] * s12_upper_pieces(klo[i], khi[i], p->kappa2[j], B, g_kappa_pieces);
         }
     }
     out->s11_lo = phil * s11lo;

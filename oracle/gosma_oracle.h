@@ -98,6 +98,14 @@ double oracle_psi_r_dir(const double r0[3], const double half[3], const double w
 
 double oracle_s11_lower_log(double alo, double ahi, double blo, double bhi, double A);
 double oracle_s12_upper_term(double alo, double ahi, double b, double B);
+/* The same with the kappa interval split into m equal pieces (the largest of
+ * the pieces' expansion bounds, capped as above); m = 1 is the term above. */
+double oracle_s12_upper_term_pieces(double alo, double ahi, double b, double B, int m);
+/* The expansion bound of the S12 upper term on [e0, e1] alone, as a log. */
+double oracle_s12_expansion_log(double e0, double e1, double b, double B);
+/* Pieces of the kappa interval used by the cube bounds from now on (1 to 64;
+ * default 1).  Returns 0, or -1 for m out of range. */
+int oracle_set_kappa_pieces(int m);
 
 void oracle_decode(uint64_t key, const double lo[3], const double hi[3], double centre[3],
                    double half[3]);

@@ -45,6 +45,38 @@ def test_s12_upper_term_bounds_interval_maximum():
             assert bound <= exact * (1 + 1e-2)   # tight for small intervals
 
 
+def test_s12_upper_term_in_pieces():
+    """The S12 upper term with the kappa interval split into m pieces (the
+    tighter reading of the kappa dependence): one piece is the default term
+    bit for bit; the largest of the pieces' expansion bounds lies above the
+    ratio's maximum over the interval (dense grid) for every m, and approaches
+    it as the pieces shrink (the expansion's error is second order in the
+    piece width); the capped term stays above the maximum."""
+    rng = np.random.default_rng(11)
+    for _ in range(1500):
+        a = math.exp(rng.uniform(0, math.log(3e4)))
+        b = math.exp(rng.uniform(0, math.log(3e4)))
+        w = 10 ** rng.uniform(-4, 0.5)
+        B = rng.uniform(0, math.pi) * rng.uniform() ** 3
+        ahi = a * (1 + w)
+        grid = np.linspace(a, ahi, 2049)
+        gmax = _g(grid, b, B).max()
+        tol = 1e-13 * (1 + abs(gmax))
+        assert oracle.s12_upper_term_pieces(a, ahi, b, B, 1) == oracle.s12_upper_term(a, ahi, b, B)
+        gaps = []
+        for m in (1, 2, 4, 16, 64):
+            e = np.linspace(a, ahi, m + 1)
+            e[0], e[-1] = a, ahi
+            elog = max(oracle.s12_expansion_log(e[k], e[k + 1], b, B) for k in range(m))
+            assert elog >= gmax - tol
+            gaps.append(elog - gmax)
+            term = oracle.s12_upper_term_pieces(a, ahi, b, B, m)
+            assert term >= math.exp(gmax) * (1 - tol)
+        # second-order convergence of the expansion (the grid resolves the
+        # maximum to (width / 2048)^2 times the curvature bound)
+        assert gaps[-1] <= gaps[0] * 0.05 + 1e-9 * (1 + abs(gmax)) + (ahi - a) ** 2 / 3e5
+
+
 def test_s12_far_apart_bound():
     """For directions far apart the S12 summand bound is at most the smaller of
     2 G(ahi) G(b) exp(-q c) and G(ahi) G(b) exp(-min(q, 2) c) / sqrt(2 alo b)
@@ -147,6 +179,32 @@ def test_lower_bound_below_sampled_minimum(seed, M, N, noise):
             assert b["lb"][q] <= b["ub"][q]
         checked += 1
     assert checked >= 8
+
+
+def test_lower_bound_with_kappa_pieces_stays_valid():
+    """With the kappa interval of the S12 upper term in 4 pieces the lower
+    bound stays below the objective sampled in each cube, and it is at least
+    the one-piece bound on most cubes (its sum can only drop where the
+    piecewise expansion replaced a cap)."""
+    sc = scenes.small_scene(6, 8, seed=32, noise_deg=1.0, n_inliers=5)
+    P = oracle.OracleProblem(sc)
+    rng = np.random.default_rng(40)
+    rk, tk = scenes.random_cubes(sc, 10, 540, r_levels=(3, 8), t_levels=(1, 6))
+    b1 = P.bounds(rk, tk)
+    try:
+        oracle.set_kappa_pieces(4)
+        b4 = P.bounds(rk, tk)
+    finally:
+        oracle.set_kappa_pieces(1)
+    with pytest.raises(ValueError):
+        oracle.set_kappa_pieces(0)
+    ok = b1["status"] == 0
+    assert np.array_equal(b1["ub"][ok], b4["ub"][ok])
+    assert np.mean(b4["lb"][ok] >= b1["lb"][ok] - 1e-12 * np.abs(b1["lb"][ok])) >= 0.8
+    for q in np.flatnonzero(ok):
+        smin = _sampled_min(P, sc, int(rk[q]), int(tk[q]), 4096, rng)
+        if math.isfinite(smin):
+            assert b4["lb"][q] <= smin + 1e-12 * abs(smin)
 
 
 def test_bounds_converge_as_cubes_shrink():
