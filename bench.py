@@ -329,6 +329,8 @@ def main():
     ap.add_argument("--learned-scenes", type=int, default=4)
     ap.add_argument("--records", type=int, default=1_000_000)
     ap.add_argument("--copy-mib", type=int, default=0, help="only run a plain copy of this size (counter scaling)")
+    ap.add_argument("--kappa-pieces", action="store_true",
+                    help="also time the searches with the kappa interval of the S12 upper term in 1, 2 and 4 pieces")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only (the search would shard by splitting "
@@ -427,6 +429,25 @@ def main():
         if args.learned_scenes > 0:
             rec["time_to_eps_64x64_plain_vs_learned"] = learned_comparison(
                 ctx, args.learned_scenes, 1e-2, args.records, 4, 8.0)
+    if args.kappa_pieces:
+        # the tighter reading of the kappa dependence: cubes and time to eps
+        # with the S12 upper term's kappa interval in 1, 2 and 4 pieces
+        study = {}
+        for name, scn, eps, bp in (("16x16", scenes.cfg1_scene(0), 1e-3, 65536),
+                                   ("64x64_5003", scenes.cfg2_scene(seed=5003), 1e-2, BATCH_PARENTS),
+                                   ("64x64_5000", scenes.cfg2_scene(seed=5000), 1e-2, BATCH_PARENTS)):
+            ctx.set_scene(scn)
+            study[name] = {}
+            for m in (1, 2, 4):
+                ctx.set_kappa_pieces(m)
+                r = ctx.solve(eps, batch_parents=bp, max_queue=1 << 28, time_limit_s=60)
+                study[name][f"pieces_{m}"] = {"eps": eps, "status": r["status"], "seconds": r["seconds"],
+                                              "cubes": r["cubes"], "f_norm": r["f_norm_best"],
+                                              "lb_norm": r["lb_norm"]}
+                print(f"kappa pieces {m} on {name}: {r['seconds']:.2f} s, {r['cubes']} cubes", file=sys.stderr,
+                      flush=True)
+            ctx.set_kappa_pieces(1)
+        rec["kappa_pieces_study"] = study
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(scene, rk_np, tk_np)
     ctx.close()

@@ -359,6 +359,27 @@ int gosma_mlp_train(gosma_ctx *ctx, const float *records, int64_t n, int epochs,
 int gosma_set_record_sink(gosma_ctx *ctx, float *records, int64_t capacity, unsigned long long *count);
 
 /* ------------------------------------------------------------------ */
+/* Reading of the kappa dependence of the lower bound.                  */
+/* ------------------------------------------------------------------ */
+/* The lower bound (eq. 21) needs, for each GMM-vMF pair, the largest value
+ * of its summand over the concentrations kappa_1i(t) that the translation
+ * cell allows (Theorem 1; the proof leaves this maximisation to a separate
+ * step).  The default bounds it over the whole kappa interval with the
+ * smaller of two second-order expansions at its ends, capped by the
+ * aligned-directions and far-apart bounds.  With m pieces the interval is
+ * split into m equal parts, the expansions are applied to each part and the
+ * largest part bound is used (capped as before): still a valid upper bound,
+ * and closer to the exact maximum over the interval as m grows.  m is 1, 2
+ * or 4 (GOSMA_E_INVAL otherwise); it applies to gosma_eval_bounds,
+ * gosma_eval_bounds_noalloc and the search from the next call on.  m > 1
+ * needs no top-8 terms (top8 == NULL; in the search: the plain order and no
+ * record logging) and mixtures whose records fit LDS (GOSMA_E_INVAL
+ * otherwise).  gosma_get_kappa_pieces returns the current m (or
+ * GOSMA_E_INVAL for a NULL context). */
+int gosma_set_kappa_pieces(gosma_ctx *ctx, int m);
+int gosma_get_kappa_pieces(const gosma_ctx *ctx);
+
+/* ------------------------------------------------------------------ */
 /* Launch shapes of the bound kernels.                                  */
 /* ------------------------------------------------------------------ */
 /* Each bound kernel gives one cell (a translation cell for the GMM-GMM sums,

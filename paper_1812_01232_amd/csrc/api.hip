@@ -495,6 +495,8 @@ int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tke
     if (n > (int64_t)0x7fffffff) return fail(ctx, GOSMA_E_INVAL, "n exceeds the launch limit");
     if (!problem && ctx->n_problems != 1)
         return fail(ctx, GOSMA_E_INVAL, "problem indices are required when several problems are set");
+    if (ctx->kpieces > 1 && (top8 || ctx->d_grec))
+        return fail(ctx, GOSMA_E_INVAL, "kappa pieces > 1 need top8 == NULL and mixtures whose records fit LDS");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
 
@@ -564,7 +566,8 @@ int gosma_eval_bounds(gosma_ctx *ctx, const uint64_t *rkeys, const uint64_t *tke
     if (ctx->timing) out.counts = ctx->d_counts;
     ti = ctx->time_begin(GOSMA_KERNEL_S12, s);
     HIP_TRY(ctx, gosma::launch_s12(mx, rkeys, tkeys, problem, nullptr, ctx->d_s11ub, ctx->d_s11lo, n, nullptr, 1, out,
-                                   0.0, ctx->maxM, ctx->maxN, top8 != nullptr, ctx->tile12, ctx->d_setup, s));
+                                   0.0, ctx->maxM, ctx->maxN, top8 != nullptr, ctx->tile12, ctx->d_setup, s, false,
+                                   gosma::TransRecs{}, ctx->kpieces));
     ctx->time_end(ti, s);
     if (stage) {
         for (const Arg &a : args)
@@ -592,6 +595,8 @@ int gosma_eval_bounds_noalloc(gosma_ctx *ctx, const uint64_t *rkeys, const uint6
     if (!problem && ctx->n_problems != 1)
         return fail(ctx, GOSMA_E_INVAL, "problem indices are required when several problems are set");
     if (!ctx->d_scratch) return fail(ctx, GOSMA_E_STATE, "the scratch array of this device is not available");
+    if (ctx->kpieces > 1 && (top8 || ctx->d_grec))
+        return fail(ctx, GOSMA_E_INVAL, "kappa pieces > 1 need top8 == NULL and mixtures whose records fit LDS");
     const void *ptrs[8] = {rkeys, tkeys, problem, ub, lb, flags, aux, top8};
     for (const void *q : ptrs)
         if (q && where_is(ctx, q) != Where::device)
@@ -607,8 +612,24 @@ int gosma_eval_bounds_noalloc(gosma_ctx *ctx, const uint64_t *rkeys, const uint6
     HIP_TRY(ctx, gosma::launch_s11(mx, tkeys, problem, n, nullptr, o11, ctx->maxM, ctx->tile11, s));
     gosma::BoundOut out{ub, lb, nullptr, aux, flags, top8, nullptr, nullptr, 0, nullptr};
     HIP_TRY(ctx, gosma::launch_s12(mx, rkeys, tkeys, problem, nullptr, L.s11ub, L.s11lo, n, nullptr, 1, out, 0.0,
-                                   ctx->maxM, ctx->maxN, top8 != nullptr, ctx->tile12, L.setup, s));
+                                   ctx->maxM, ctx->maxN, top8 != nullptr, ctx->tile12, L.setup, s, false,
+                                   gosma::TransRecs{}, ctx->kpieces));
     return GOSMA_OK;
+}
+
+int gosma_set_kappa_pieces(gosma_ctx *ctx, int m)
+{
+    if (!ctx) return GOSMA_E_INVAL;
+    ctx->err.clear();
+    if (m != 1 && m != 2 && m != 4) return fail(ctx, GOSMA_E_INVAL, "kappa pieces must be 1, 2 or 4 (got %d)", m);
+    ctx->kpieces = m;
+    gosma_drop_graph(ctx);   // a captured search iteration holds the old kernels
+    return GOSMA_OK;
+}
+
+int gosma_get_kappa_pieces(const gosma_ctx *ctx)
+{
+    return ctx ? ctx->kpieces : GOSMA_E_INVAL;
 }
 
 int gosma_refine(gosma_ctx *ctx, int64_t n, const uint32_t *problem, const double *r0, const double *t0,

@@ -1379,7 +1379,7 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
                     &b.st->dstar, (int)(sizeof(PState) / sizeof(unsigned long long)), timed ? ctx->d_counts : nullptr};
         e = launch_s12(mx, b.crk + o, b.ctk + o, b.cpid + o, b.ctidx + o, b.s11ub, b.s11lo, b.kcap[k],
                        &b.g->nchild_b[k], 1, bo, kMarginGamma, ctx->bucket_maxM[k], ctx->bucket_maxN[k], top8,
-                       ctx->btile12[k], b.csetup + o, st, true, TransRecs{b.trec, b.toff, b.csum});
+                       ctx->btile12[k], b.csetup + o, st, true, TransRecs{b.trec, b.toff, b.csum}, ctx->kpieces);
     }
     T1(ti);
     if (e) return e;
@@ -1499,6 +1499,9 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
     const bool learned = opts->order == 1, logging = opts->log_records != 0;
     if (opts->order != 0 && opts->order != 1) return fail(GOSMA_E_INVAL, "order must be 0 (best-first) or 1 (learned)");
     if (learned && !ctx->mlp_ready()) return fail(GOSMA_E_STATE, "learned order needs a network (gosma_mlp_init/set_params)");
+    if (ctx->kpieces > 1 && (learned || logging || ctx->d_grec))
+        return fail(GOSMA_E_INVAL, "kappa pieces > 1 need the plain order, no record logging and mixtures whose "
+                                   "records fit LDS");
     if (opts->sma_iters < 0 || opts->sma_iters > 10000) return fail(GOSMA_E_INVAL, "sma_iters must be in [0, 10000]");
     const int sma_iters = opts->sma_iters;
     if (logging && !ctx->rec_sink) return fail(GOSMA_E_STATE, "record logging needs gosma_set_record_sink");
@@ -1632,7 +1635,8 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         e = launch_s11(mx, b.ctk, b.cpid, P, nullptr, S11Out{b.s11ub, b.s11lo}, ctx->maxM, ctx->tile11, st);
         if (!e)
             e = launch_s12(mx, b.crk, b.ctk, b.cpid, nullptr, b.s11ub, b.s11lo, P, nullptr, 1, bo, kMarginGamma,
-                           ctx->maxM, ctx->maxN, true, ctx->tile12, b.csetup, st);
+                           ctx->maxM, ctx->maxN, learned || logging, ctx->tile12, b.csetup, st, false, TransRecs{},
+                           ctx->kpieces);
         if (!e) {
             hipLaunchKernelGGL(k_seed, dim3((P + 63) / 64), dim3(64), 0, st, b, P);
             e = hipGetLastError();

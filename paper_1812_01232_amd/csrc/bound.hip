@@ -260,6 +260,15 @@ __device__ __forceinline__ TransRec trans_record(const TransPrep &tp, float w, c
     return r;
 }
 
+// yfun for an FP32 concentration (interior points of a kappa interval).
+__device__ __forceinline__ void yfun_f(float y, float *G, float *nu)
+{
+    const float e = fexp2(-2.0f * kLog2e * y);
+    const float id = frcp(1.0f - e);
+    *G = y * id;
+    *nu = frcp(y) - 2.0f * e * id;
+}
+
 // Pair kernel pieces for concentrations a, b and squared chord q.
 struct PairK {
     float ks;     // K^2
@@ -736,7 +745,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
 // upper bound).  The pairs that remain are collected per wave in LDS and
 // evaluated kBatch per lane at a time.
 
-template <bool TOP8>
+template <bool TOP8, int KP>
 __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, const float4 *__restrict__ scr, int a_,
                                          const float4 v0, const float4 v1, float &sub, float &shi, float (&top)[8])
 {
@@ -772,18 +781,63 @@ __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, const f
         const float sB = fmaxf(st * R1.z - ct * R1.w, 0.0f);
         const float qB = 4.0f * sB * sB;
         const float alo = R2.x, ahi = R2.y, ha = R2.z;
-        const PairK k1 = pair_k(alo, b, qB), k2 = pair_k(ahi, b, qB);
         const float bc = b * fmaf(-0.5f, qB, 1.0f);             // b cos B
-        const float d1 = R3.z - k1.nuK * (alo + bc) * k1.invK;  // phi'(alo)
-        const float d2 = R3.w - k2.nuK * (ahi + bc) * k2.invK;  // phi'(ahi)
-        const float km2 = (-bc > alo && -bc < ahi) ? b * b * qB * fmaf(-0.25f, qB, 1.0f) : fminf(k1.ks, k2.ks);
-        const float G = fminf(1.0f / 3.0f, frcp(km2));
-        const float q2 = 2.0f * G * ha * ha;
-        const float eA = fmaxf(k1.x, fmaf(2.0f * d1, ha, k2.x + q2));
-        const float eB = fmaxf(k2.x, fmaf(-2.0f * d2, ha, k1.x + q2));
-        const float vA = fexp2(eA * kLog2e) * k1.hK * R3.x;
-        const float vB = fexp2(eB * kLog2e) * k2.hK * R3.y;
-        const float vT = fminf(vA, vB) * v1.y;
+        float vT;
+        if constexpr (KP == 1) {
+            const PairK k1 = pair_k(alo, b, qB), k2 = pair_k(ahi, b, qB);
+            const float d1 = R3.z - k1.nuK * (alo + bc) * k1.invK;  // phi'(alo)
+            const float d2 = R3.w - k2.nuK * (ahi + bc) * k2.invK;  // phi'(ahi)
+            const float km2 = (-bc > alo && -bc < ahi) ? b * b * qB * fmaf(-0.25f, qB, 1.0f) : fminf(k1.ks, k2.ks);
+            const float G = fminf(1.0f / 3.0f, frcp(km2));
+            const float q2 = 2.0f * G * ha * ha;
+            const float eA = fmaxf(k1.x, fmaf(2.0f * d1, ha, k2.x + q2));
+            const float eB = fmaxf(k2.x, fmaf(-2.0f * d2, ha, k1.x + q2));
+            const float vA = fexp2(eA * kLog2e) * k1.hK * R3.x;
+            const float vB = fexp2(eB * kLog2e) * k2.hK * R3.y;
+            vT = fminf(vA, vB) * v1.y;
+        } else {
+            // the kappa interval in KP equal pieces: the same two expansions on
+            // each piece, the largest piece bound (G and nu at the inner ends
+            // computed here, at the outer ends from the record)
+            const float wdt = (ahi - alo) * (1.0f / KP), hp = 0.5f * wdt;
+            const float kmi = b * b * qB * fmaf(-0.25f, qB, 1.0f);   // K^2 where a = -b cos B
+            float ks[KP + 1], xs[KP + 1], d[KP + 1], hk[KP + 1], ge[KP + 1];
+#pragma unroll
+            for (int p = 0; p <= KP; ++p) {
+                const float e = p == 0 ? alo : (p == KP ? ahi : fmaf((float)p, wdt, alo));
+                const PairK k = pair_k(e, b, qB);
+                float Ge, nue;
+                if (p == 0) {
+                    Ge = R3.x;
+                    nue = R3.z;
+                } else if (p == KP) {
+                    Ge = R3.y;
+                    nue = R3.w;
+                } else {
+                    yfun_f(e, &Ge, &nue);
+                }
+                ks[p] = k.ks;
+                xs[p] = k.x;
+                hk[p] = k.hK;
+                ge[p] = Ge;
+                d[p] = nue - k.nuK * (e + bc) * k.invK;
+            }
+            float best = 0.0f;
+#pragma unroll
+            for (int p = 0; p < KP; ++p) {
+                const float e0 = p == 0 ? alo : fmaf((float)p, wdt, alo);
+                const float e1 = p == KP - 1 ? ahi : fmaf((float)(p + 1), wdt, alo);
+                const float km2 = (-bc > e0 && -bc < e1) ? kmi : fminf(ks[p], ks[p + 1]);
+                const float G = fminf(1.0f / 3.0f, frcp(km2));
+                const float q2 = 2.0f * G * hp * hp;
+                const float eA = fmaxf(xs[p], fmaf(2.0f * d[p], hp, xs[p + 1] + q2));
+                const float eB = fmaxf(xs[p + 1], fmaf(-2.0f * d[p + 1], hp, xs[p] + q2));
+                const float vA = fexp2(eA * kLog2e) * hk[p] * ge[p];
+                const float vB = fexp2(eB * kLog2e) * hk[p + 1] * ge[p + 1];
+                best = fmaxf(best, fminf(vA, vB));
+            }
+            vT = best * v1.y;
+        }
         const float cap = 0.5f * fminf(ahi, b) * (R2.w + v1.z);
         // far-apart caps: 2 G G e^{-qB cf} and G G e^{-min(qB, 2) cf} / sqrt(2 alo b)
         const float cf = alo * b * frcp(2.0f * (alo + b));
@@ -847,8 +901,8 @@ __global__ __launch_bounds__(256) void k_cube_setup(DevMix mx, const uint64_t *_
 // Five waves per SIMD fit the plain kernel's registers without spills; the
 // variant that also keeps the top-8 terms (learned order, record logging) is
 // held to four.
-template <bool TOP8, bool VLDS, bool GREC>
-__global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(TOP8 ? 4 : 5))) void k_s12(DevMix mx, const uint64_t *__restrict__ rkeys,
+template <bool TOP8, bool VLDS, bool GREC, int KP = 1>
+__global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu((TOP8 || KP > 1) ? 4 : 5))) void k_s12(DevMix mx, const uint64_t *__restrict__ rkeys,
                                                          const uint64_t *__restrict__ tkeys,
                                                          const uint32_t *__restrict__ pids,
                                                          const int64_t *__restrict__ tidx,
@@ -1055,7 +1109,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                 for (int k = 0; k < kBatch; ++k) {
                     if (e[k] != 0xffffffffu) {
                         const int jj = (int)(e[k] & 0xffffu);
-                        s12_pair<TOP8>(rec, scr, (int)(e[k] >> 16), vrow(jj, 0), vrow(jj, 1), sub, shi, top);
+                        s12_pair<TOP8, KP>(rec, scr, (int)(e[k] >> 16), vrow(jj, 0), vrow(jj, 1), sub, shi, top);
                     }
                 }
                 run += kBatch;
@@ -1282,6 +1336,10 @@ hipError_t prepare_bound_kernels(int maxM, int maxN)
     if (!e) e = hipFuncSetAttribute((const void *)k_s12<true, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, l0);
     if (!e) e = hipFuncSetAttribute((const void *)k_s12<false, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, l1);
     if (!e) e = hipFuncSetAttribute((const void *)k_s12<true, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, l1);
+    if (!e) e = hipFuncSetAttribute((const void *)k_s12<false, false, false, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, l0);
+    if (!e) e = hipFuncSetAttribute((const void *)k_s12<false, false, false, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, l0);
+    if (!e) e = hipFuncSetAttribute((const void *)k_s12<false, true, false, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, l1);
+    if (!e) e = hipFuncSetAttribute((const void *)k_s12<false, true, false, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, l1);
     return e;
 }
 
@@ -1321,10 +1379,13 @@ hipError_t launch_cube_setup(const DevMix &mx, const uint64_t *rkeys, const uint
 hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                       const int64_t *tidx, const double *s11ub, const double *s11lo, int64_t n, const uint32_t *n_dev,
                       int n_dev_mul, BoundOut out, double margin_gamma, int maxM, int maxN, bool with_top8, Tile tile,
-                      CubeSetup *setup, hipStream_t stream, bool setup_done, TransRecs tr)
+                      CubeSetup *setup, hipStream_t stream, bool setup_done, TransRecs tr, int kpieces)
 {
     if (n <= 0) return hipSuccess;
     if (!tile_ok(tile) || !setup) return hipErrorInvalidValue;
+    // pieces of the kappa interval: 1, or 2 and 4 without the top-8 terms and
+    // with the component records in LDS
+    if (kpieces != 1 && ((kpieces != 2 && kpieces != 4) || with_top8 || mx.grec)) return hipErrorInvalidValue;
     if (!setup_done) {
         hipError_t e = launch_cube_setup(mx, rkeys, tkeys, pids, n, n_dev, n_dev_mul, setup, nullptr, stream);
         if (e) return e;
@@ -1341,6 +1402,10 @@ hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *t
         with_top8 ? go(k_s12<true, false, true>) : go(k_s12<false, false, true>);
     else if (with_top8)
         vlds ? go(k_s12<true, true, false>) : go(k_s12<true, false, false>);
+    else if (kpieces == 2)
+        vlds ? go(k_s12<false, true, false, 2>) : go(k_s12<false, false, false, 2>);
+    else if (kpieces == 4)
+        vlds ? go(k_s12<false, true, false, 4>) : go(k_s12<false, false, false, 4>);
     else
         vlds ? go(k_s12<false, true, false>) : go(k_s12<false, false, false>);
     return hipGetLastError();

@@ -191,7 +191,8 @@ hipError_t launch_s11(const DevMix &mx, const uint64_t *tkeys, const uint32_t *p
 hipError_t launch_s12(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                       const int64_t *tidx, const double *s11ub, const double *s11lo, int64_t n, const uint32_t *n_dev,
                       int n_dev_mul, BoundOut out, double margin_gamma, int maxM, int maxN, bool with_top8, Tile tile,
-                      CubeSetup *setup, hipStream_t stream, bool setup_done = false, TransRecs tr = TransRecs{});
+                      CubeSetup *setup, hipStream_t stream, bool setup_done = false, TransRecs tr = TransRecs{},
+                      int kpieces = 1);
 // The per-cube set-up pass of k_s12 (and, with cells, the cubes' translation cells).
 hipError_t launch_cube_setup(const DevMix &mx, const uint64_t *rkeys, const uint64_t *tkeys, const uint32_t *pids,
                              int64_t n, const uint32_t *n_dev, int n_dev_mul, CubeSetup *setup, const CellTable *cells,
@@ -247,6 +248,7 @@ struct gosma_ctx {
     // for calls over all problems (gosma_eval_bounds) and per size bucket (the
     // search), with each bucket's problem count and largest M and N
     gosma::Tile tile11{1, 8192}, tile12{1, 8192};
+    int kpieces = 1;   // pieces of the kappa interval of the S12 upper term (1, 2 or 4)
     gosma::Tile btile11[gosma::kBuckets] = {}, btile12[gosma::kBuckets] = {};
     int bucket_nprob[gosma::kBuckets] = {}, bucket_maxM[gosma::kBuckets] = {}, bucket_maxN[gosma::kBuckets] = {};
 

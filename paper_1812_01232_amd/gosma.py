@@ -27,7 +27,8 @@ EXPORTS = ["gosma_create", "gosma_destroy", "gosma_last_error", "gosma_set_mixtu
            "gosma_mlp_get_params", "gosma_mlp_predict", "gosma_mlp_loss_grad", "gosma_mlp_train",
            "gosma_set_record_sink", "gosma_get_tiles", "gosma_set_tiles", "gosma_autotune", "gosma_get_work_counts",
            "gosma_snapshot", "gosma_resume", "gosma_refine", "gosma_dpmeans", "gosma_dpvmf_means",
-           "gosma_eval_bounds_noalloc", "gosma_get_bucket_tiles"]
+           "gosma_eval_bounds_noalloc", "gosma_get_bucket_tiles", "gosma_set_kappa_pieces",
+           "gosma_get_kappa_pieces"]
 MLP_FEATURES, MLP_RECORD, MLP_PARAMS = 20, 21, 35841
 NOALLOC_MAX_CUBES = 65536
 N_BUCKETS = 4
@@ -110,6 +111,8 @@ def lib():
         L.gosma_get_tiles.argtypes = [vp, C.POINTER(Tiles)]
         L.gosma_get_bucket_tiles.argtypes = [vp, C.c_int, C.POINTER(Tiles), C.POINTER(C.c_int)]
         L.gosma_set_tiles.argtypes = [vp, C.POINTER(Tiles)]
+        L.gosma_set_kappa_pieces.argtypes = [vp, C.c_int]
+        L.gosma_get_kappa_pieces.argtypes = [vp]
         L.gosma_autotune.argtypes = [vp, C.c_int64, C.c_uint64, dp, C.c_int64, C.POINTER(C.c_int64),
                                      C.POINTER(Tiles)]
         L.gosma_refine.argtypes = [vp, C.c_int64, C.POINTER(C.c_uint32), dp, dp, C.c_int, dp, dp, dp, dp, ip]
@@ -377,6 +380,14 @@ class Context:
         """records: device float32 tensor [capacity, 21]; count: device int64 tensor [1] (zeroed)."""
         cap = 0 if records is None else int(records.shape[0])
         self._check(lib().gosma_set_record_sink(self._h, _ptr(records), cap, _ptr(count)), "gosma_set_record_sink")
+
+    # -- reading of the kappa dependence of the lower bound -----------------
+    def set_kappa_pieces(self, m):
+        """Pieces of the kappa interval in the S12 upper term (1, 2 or 4; see gosma.h)."""
+        self._check(lib().gosma_set_kappa_pieces(self._h, int(m)), "gosma_set_kappa_pieces")
+
+    def get_kappa_pieces(self):
+        return int(lib().gosma_get_kappa_pieces(self._h))
 
     # -- launch shapes of the bound kernels ---------------------------------
     def get_tiles(self):

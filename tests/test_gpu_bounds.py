@@ -398,3 +398,44 @@ def test_host_arrays_through_the_abi(ctx):
     torch.cuda.synchronize()
     assert np.array_equal(ub.cpu().numpy(), ref["ub"]) and np.array_equal(lb.cpu().numpy(), ref["lb"])
     assert np.array_equal(fl.cpu().numpy(), ref["flags"])
+
+
+@pytest.mark.parametrize("m", [2, 4])
+def test_kappa_pieces_match_oracle(ctx, m):
+    """The tighter reading of the kappa dependence (the S12 upper term's kappa
+    interval in m pieces) against the oracle's same reading, on one problem
+    and on a batch of problems (vMF rows staged in LDS); the upper bounds do
+    not change, and the lower bounds are at least the one-piece ones on most
+    cubes."""
+    sc = scenes.cfg2_scene(0)
+    rk, tk = scenes.random_cubes(sc, 800, 7700 + m, r_levels=(2, 12), t_levels=(1, 10))
+    ctx.set_scene(sc)
+    P = oracle.OracleProblem(sc)
+    g1 = ctx.bounds(rk, tk)
+    try:
+        ctx.set_kappa_pieces(m)
+        oracle.set_kappa_pieces(m)
+        assert ctx.get_kappa_pieces() == m
+        g = ctx.bounds(rk, tk)
+        o = P.bounds(rk, tk)
+        _compare(sc, g, o, label=f"cfg2 kappa pieces {m}")
+        fin = np.isfinite(g1["ub"])
+        assert np.array_equal(g["ub"][fin], g1["ub"][fin])
+        ok = (g1["flags"] & 6) == 0
+        assert np.mean(g["lb"][ok] >= g1["lb"][ok] - 1e-6 * np.abs(g1["lb"][ok])) >= 0.8
+        with pytest.raises(RuntimeError, match="kappa pieces"):
+            ctx.bounds(rk[:8], tk[:8], want_top8=True)   # the pieces need no top-8 terms
+        scs = scenes.batch_scenes(3, seed=4300 + m, lo=16, hi=80)
+        ctx.set_scenes(scs)
+        ctx.set_kappa_pieces(m)
+        for p, s in enumerate(scs):
+            rkp, tkp = scenes.random_cubes(s, 64, 7800 + p, r_levels=(2, 10), t_levels=(1, 8))
+            gp = ctx.bounds(np.concatenate([rkp, rkp]), np.concatenate([tkp, tkp]),
+                            problem_np=np.full(128, p, np.uint32))
+            op = oracle.OracleProblem(s).bounds(rkp, tkp)
+            _compare(s, {k: v[:64] for k, v in gp.items()}, op, label=f"batch {p} kappa pieces {m}")
+    finally:
+        ctx.set_kappa_pieces(1)
+        oracle.set_kappa_pieces(1)
+    with pytest.raises(RuntimeError, match="kappa pieces"):
+        ctx.set_kappa_pieces(3)

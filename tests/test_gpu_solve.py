@@ -366,3 +366,31 @@ def test_finest_level_parents_have_no_children(ctx):
     assert abs(f - r["f_best"]) <= 1e-5 * (s11 + 2 * s12)
     # the pose is one of the children: within a level-19 cell of the truth
     assert np.all(np.abs(np.asarray(r["r"]) - rg) <= 3 * 2 * math.pi / 2 ** 19)
+
+
+@pytest.mark.parametrize("m", [2, 4])
+def test_search_with_kappa_pieces_matches_oracle(ctx, m):
+    """The search with the kappa interval of the S12 upper term in m pieces
+    certifies the oracle's optimum (the oracle searching with the same
+    reading), and bounds no more cubes than with one piece."""
+    sc = scenes.small_scene(5, 6, seed=90, noise_deg=2.0, n_inliers=4)
+    eps = 1e-2
+    ctx.set_scene(sc)
+    g1 = ctx.solve(eps, batch_parents=256)
+    P = oracle.OracleProblem(sc)
+    try:
+        ctx.set_kappa_pieces(m)
+        oracle.set_kappa_pieces(m)
+        g = ctx.solve(eps, batch_parents=256)
+        o = P.solve(eps, 256, time_limit_s=120)
+        with pytest.raises(RuntimeError, match="kappa pieces"):
+            ctx.solve(eps, batch_parents=256, log_records=True)   # needs the top-8 terms
+    finally:
+        ctx.set_kappa_pieces(1)
+        oracle.set_kappa_pieces(1)
+    print(f"pieces {m}: gpu cubes {g['cubes']} (one piece {g1['cubes']}), oracle cubes {o['cubes']}")
+    assert g["status"] == 0 and o["status"] == 0
+    assert g["lb_norm"] <= o["f_norm_best"] + MARGIN
+    assert o["lb_norm"] <= g["f_norm_best"] + 1e-9
+    assert abs(g["f_norm_best"] - o["f_norm_best"]) <= eps
+    assert g["cubes"] <= 1.1 * o["cubes"] and g["cubes"] <= 1.02 * g1["cubes"]
