@@ -39,7 +39,7 @@ sys.path.insert(0, ROOT)
 # tests/test_opcount.py): (plain ops, FMAs among them, transcendentals) per
 # work unit.  FLOPs count an FMA as 2; issue slots count a plain op as one
 # slot per lane and a transcendental as TRANS_SLOTS (measured 1.8-1.9 on
-# gfx950, so 2; the survey's weight of 4 is reported beside).
+# gfx950, so 2; a weight of 4, the quarter-rate figure, is reported beside).
 OPS = {
     "PAIR12": (100, 15, 15),     # GMM-vMF pair evaluated: UB term (eq. 12) + upper term over the cube (eq. 25, R3)
     "SCREEN12": (8, 4, 0),       # GMM-vMF pair screened
@@ -120,7 +120,7 @@ def copy_calibration(mib):
 
 def host_cores():
     """Host cores available to this process: its CPU affinity, capped at the
-    OpenMP thread count the environment sets (the GPU machine's CPU share)."""
+    OpenMP thread count the environment sets (the host's CPU share for the GPU)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
