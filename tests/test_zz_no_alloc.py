@@ -126,3 +126,29 @@ def test_noalloc_rejects_oversize_and_host_arrays(ctx):
     hp = lambda a: ctypes.c_void_p(a.ctypes.data)
     rc = L.gosma_eval_bounds_noalloc(ctx._h, hp(h), hp(h), None, 4, hp(hu), hp(hu), hp(h), None, None, None)
     assert rc == -1 and b"device memory" in L.gosma_last_error(ctx._h)
+
+
+@pytest.mark.parametrize("m", [2, 4])
+def test_noalloc_with_kappa_pieces(ctx, m):
+    # the kappa-pieces reading goes through the allocation-free entry point too
+    sc = scenes.cfg2_scene(0)
+    ctx.set_scene(sc)
+    rk, tk = scenes.random_cubes(sc, 3000, 1900 + m)
+    print(f"no-alloc: 64x64 scene, kappa pieces {m}, 3000 then 1000 cubes", flush=True)
+    try:
+        ctx.set_kappa_pieces(m)
+        a = _run(ctx, rk, tk, None, True, top8=False)
+        b = _run(ctx, rk, tk, None, False, top8=False)
+        _same(a, b, f"kappa pieces {m}")
+        a = _run(ctx, rk[500:1500], tk[500:1500], None, True, top8=False)
+        b = _run(ctx, rk[500:1500], tk[500:1500], None, False, top8=False)
+        _same(a, b, f"kappa pieces {m}, smaller second call")
+        # the top-8 output is defined for the one-piece term only
+        with pytest.raises(RuntimeError, match="kappa pieces"):
+            _run(ctx, rk[:64], tk[:64], None, True, top8=True)
+    finally:
+        ctx.set_kappa_pieces(1)
+    # the pieces change the lower bound only: flags and upper bounds as with one piece
+    one = _run(ctx, rk[500:1500], tk[500:1500], None, True, top8=False)
+    assert np.array_equal(a["flags"], one["flags"])
+    assert np.array_equal(a["ub"], one["ub"], equal_nan=True)
