@@ -40,7 +40,7 @@ namespace gosma {
 
 namespace {
 
-constexpr int kHistBins = 2048;
+constexpr int kHistBins = 4096;
 constexpr int kBlock = 256;
 constexpr int kGridX = 2048;            // blocks per grid-stride kernel (divided among problems)
 constexpr int kMaxLevel = 19;
@@ -66,6 +66,9 @@ struct PState {
     uint32_t nsel, rebuild, done, overflow, iters, max_iters;
     uint32_t nskip;                // selected cubes that cannot be split (no children)
     uint32_t take_all, prefix, need, eq_quota, eq_taken;   // radix select
+    // range of the keys in each hot buffer (indexed like nH; empty: kmin > kmax)
+    uint32_t kmin[2], kmax[2];
+    uint32_t tshift;               // the selection threshold compares key >> tshift with prefix
     uint32_t rb_target;            // hot entries wanted after a re-partition
     // SMA (Section 6): the pose of d* when SMA set it, and the d* it last started from
     double pose[6];
@@ -152,6 +155,38 @@ __device__ __forceinline__ double block_min(double v)
     for (int k = 1; k < kBlock / 64; ++k) m = fmin(m, w[k]);
     __syncthreads();
     return m;
+}
+
+// Block-wide lowest and highest key (every thread gets them).
+__device__ __forceinline__ void block_key_range(uint32_t &lo, uint32_t &hi)
+{
+    __shared__ uint32_t wl[kBlock / 64], wh[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, (uint32_t)__shfl_xor(lo, off, 64));
+        hi = max(hi, (uint32_t)__shfl_xor(hi, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        wl[threadIdx.x >> 6] = lo;
+        wh[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    lo = wl[0];
+    hi = wh[0];
+    for (int k = 1; k < kBlock / 64; ++k) {
+        lo = min(lo, wl[k]);
+        hi = max(hi, wh[k]);
+    }
+    __syncthreads();
+}
+
+// Widen the key range of hot buffer `buf` to [lo, hi] (nothing when lo > hi).
+// The atomics are skipped when the range already covers the keys, as it
+// does for most callers once a few have widened it.
+__device__ __forceinline__ void widen_key_range(PState &s, uint32_t buf, uint32_t lo, uint32_t hi)
+{
+    if (lo > hi) return;
+    if (lo < __atomic_load_n(&s.kmin[buf], __ATOMIC_RELAXED)) atomicMin(&s.kmin[buf], lo);
+    if (hi > __atomic_load_n(&s.kmax[buf], __ATOMIC_RELAXED)) atomicMax(&s.kmax[buf], hi);
 }
 
 __device__ __forceinline__ int key_level(uint64_t k) { return (int)((k >> 57) & 63); }
@@ -344,7 +379,10 @@ __global__ __launch_bounds__(kBlock) void k_iter_begin(Bufs b, int P, int rb_slo
         s.need = 0;
         s.eq_quota = 0;
         s.eq_taken = 0;
+        s.tshift = 0;
         s.nH[s.hcur ^ 1] = 0;
+        s.kmin[s.hcur ^ 1] = 0xffffffffu;
+        s.kmax[s.hcur ^ 1] = 0u;
         s.minH = ord64(INFINITY);
         if (rb_slot && s.rebuild) {
             s.nC[s.ccur ^ 1] = 0;
@@ -353,18 +391,40 @@ __global__ __launch_bounds__(kBlock) void k_iter_begin(Bufs b, int P, int rb_slo
     }
 }
 
-// Radix select over the ordered 32-bit key of the priority, in passes of 11,
-// 11 and 10 bits: the k-th lowest key is found exactly, and cubes whose key
-// equals it are taken in arbitrary order up to the quota.  (Stopping at a
-// coarser bucket is not enough: children inherit their parent's lower bound,
-// so a bucket that straddles d* - eps keeps refilling itself with cubes that
-// best-first order would never split.)
+// Radix select over the ordered 32-bit key of the priority: the k-th lowest
+// key is found exactly, and cubes whose key equals it are taken in arbitrary
+// order up to the quota.  (Stopping at a coarser bucket is not enough:
+// children inherit their parent's lower bound, so a bucket that straddles
+// d* - eps keeps refilling itself with cubes that best-first order would
+// never split.)  A re-partition (hot and cold parts) takes three passes over
+// the whole key, of 11, 11 and 10 bits.
 constexpr int kRadixPasses = 3;
 constexpr uint32_t kHistPer = 16;   // keys per thread of a histogram pass (at least)
 
+// The selection takes two passes of 12 bits over the hot part, on the key's
+// offset from the lowest key: the keys lie in [kmin, kmax] (kept up to date by
+// every kernel that writes a hot buffer), so the offsets have D = bit length
+// of kmax - kmin bits, and the passes resolve offset bits D-1 .. D-24.  That
+// is every bit when kmax - kmin < 2^24 (priorities of one sign within a
+// factor of four of each other); otherwise the lowest D - 24 bits are left
+// out, and keys whose offsets agree above them (values at most 2^(D-24) - 1
+// units in the last place apart) rank as ties of the threshold.
+constexpr int kSelPasses = 2;
+constexpr int kSelBits = 12;
+struct SelDigits {
+    int s0, s1;   // lowest offset bit of the first and of the second digit
+};
+__device__ __forceinline__ SelDigits sel_digits(const PState &s)
+{
+    const uint32_t lo = s.kmin[s.hcur], hi = s.kmax[s.hcur];
+    const uint32_t w = hi >= lo ? hi - lo : 0xffffffffu;
+    const int D = w ? 32 - __clz((int)w) : 0;
+    const int s0 = max(D - kSelBits, 0);
+    return {s0, max(s0 - kSelBits, 0)};
+}
+
 // One radix pass over a problem's hot part (selection) or hot + cold parts
-// (re-partition): histogram of the next 11-bit digit below the prefix fixed
-// so far.
+// (re-partition): histogram of the next digit below the prefix fixed so far.
 __global__ __launch_bounds__(kBlock) void k_hist(Bufs b, int rebuild_pass, int pass)
 {
     __shared__ uint32_t h[kHistBins];
@@ -379,9 +439,23 @@ __global__ __launch_bounds__(kBlock) void k_hist(Bufs b, int rebuild_pass, int p
     if (blockIdx.x >= nb) return;
     for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) h[i] = 0;
     __syncthreads();
-    const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
-    const uint32_t mask = pass == 2 ? 0x3ffu : 0x7ffu;
-    const int pshift = pass == 1 ? 21 : 10;
+    // digit of this pass: ((key - kbase) >> shift) & mask; a key takes part in
+    // a later pass when (((key - kbase) >> pshift) & pmask) equals the prefix
+    int shift, pshift;
+    uint32_t mask, pmask, kbase = 0u;
+    if (rebuild_pass) {
+        shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
+        mask = pass == 2 ? 0x3ffu : 0x7ffu;
+        pshift = pass == 1 ? 21 : 10;
+        pmask = 0xffffffffu;
+    } else {
+        const SelDigits d = sel_digits(s);
+        shift = pass == 0 ? d.s0 : d.s1;
+        mask = pass == 0 ? (1u << kSelBits) - 1u : (1u << (d.s0 - d.s1)) - 1u;
+        pshift = d.s0;
+        pmask = (1u << kSelBits) - 1u;
+        kbase = s.kmin[s.hcur];
+    }
     const uint32_t prefix = s.prefix;
     const int lane = threadIdx.x & 63;
     for (int part = 0; part < nparts; ++part) {
@@ -392,8 +466,8 @@ __global__ __launch_bounds__(kBlock) void k_hist(Bufs b, int rebuild_pass, int p
             uint32_t bin = 0;
             bool m = false;
             if (i < n) {
-                const uint32_t key = key32(q.prio[i]);
-                m = pass == 0 || (key >> pshift) == prefix;
+                const uint32_t key = key32(q.prio[i]) - kbase;
+                m = pass == 0 || ((key >> pshift) & pmask) == prefix;
                 bin = (key >> shift) & mask;
             }
             // keys cluster: when every counted lane of the wave hits one bin,
@@ -469,9 +543,18 @@ __global__ __launch_bounds__(kBlock) void k_scan(Bufs b, int rebuild_pass, int p
     __syncthreads();
     for (int j = 0; j < per; ++j) gh[t * per + j] = 0;
     if (t == 0) {
-        s.prefix = (pass == 0 ? 0u : s.prefix << (pass == 2 ? 10 : 11)) | found;
+        if (rebuild_pass) {
+            s.prefix = (pass == 0 ? 0u : s.prefix << (pass == 2 ? 10 : 11)) | found;
+        } else if (pass == 0) {
+            s.prefix = found;
+        } else {
+            // the threshold on (key - kmin) >> s1: both digits
+            const SelDigits d = sel_digits(s);
+            s.prefix = (s.prefix << (d.s0 - d.s1)) | found;
+            s.tshift = (uint32_t)d.s1;
+        }
         s.need = left;
-        if (pass == kRadixPasses - 1) s.eq_quota = left;
+        if (pass == (rebuild_pass ? kRadixPasses : kSelPasses) - 1) s.eq_quota = left;
     }
 }
 
@@ -512,6 +595,7 @@ __global__ __launch_bounds__(kBlock) void k_rebuild_compact(Bufs b)
     const Queue Cout = qoff(b.C[s.ccur ^ 1], (size_t)p * b.ccap);
     const uint32_t hcap = b.hcap, ccap = b.ccap;
     double mh = INFINITY, mc = INFINITY;
+    uint32_t klo = 0xffffffffu, khi = 0u;   // keys moved to the new hot part
     for (int part = 0; part < 2; ++part) {
         const Queue q = part == 0 ? qoff(b.H[s.hcur], (size_t)p * b.hcap) : qoff(b.C[s.ccur], (size_t)p * b.ccap);
         const uint32_t n = part == 0 ? s.nH[s.hcur] : s.nC[s.ccur];
@@ -533,14 +617,21 @@ __global__ __launch_bounds__(kBlock) void k_rebuild_compact(Bufs b)
             copy_payload(o, slot, q, i);
         };
         partition_tiles(n, &s.nH[s.hcur ^ 1], &s.nC[s.ccur ^ 1], classify,
-                        [&](uint32_t i, uint32_t slot) { move(Hout, hcap, i, slot, mh); },
+                        [&](uint32_t i, uint32_t slot) {
+                            const uint32_t key = key32(q.prio[i]);
+                            klo = min(klo, key);
+                            khi = max(khi, key);
+                            move(Hout, hcap, i, slot, mh);
+                        },
                         [&](uint32_t i, uint32_t slot) { move(Cout, ccap, i, slot, mc); });
     }
     mh = block_min(mh);
     mc = block_min(mc);
+    block_key_range(klo, khi);
     if (threadIdx.x == 0) {
         if (mh < INFINITY) atomicMin(&s.minH, ord64(mh));
         if (mc < INFINITY) atomicMin(&s.minC, ord64(mc));
+        widen_key_range(s, s.hcur ^ 1, klo, khi);
     }
 }
 
@@ -566,8 +657,11 @@ __global__ void k_rebuild_finish(Bufs b, int P)
     s.need = 0;
     s.eq_quota = 0;
     s.eq_taken = 0;
+    s.tshift = 0;
     s.nH[s.hcur ^ 1] = 0;
     s.nC[s.ccur ^ 1] = 0;
+    s.kmin[s.hcur ^ 1] = 0xffffffffu;
+    s.kmax[s.hcur ^ 1] = 0u;
 }
 
 // Selection: the k lowest keys of the hot part -> parents; the rest stays hot.
@@ -583,13 +677,19 @@ __global__ __launch_bounds__(kBlock) void k_select_compact(Bufs b)
     const Queue q = qoff(b.H[s.hcur], (size_t)p * b.hcap);
     const Queue Hout = qoff(b.H[s.hcur ^ 1], (size_t)p * b.hcap);
     const Queue par = qoff(b.par, (size_t)p * b.k);
+    const uint32_t kb = s.kmin[s.hcur], ts = s.tshift;   // the threshold is on (key - kb) >> ts
     double mh = INFINITY;
+    uint32_t klo = 0xffffffffu, khi = 0u;                 // keys that stay hot
     auto classify = [&](uint32_t i) -> int {
-        return classify_key(s, sane_lb(q.lb[i]), dstar, key32(q.prio[i]), T, all);
+        return classify_key(s, sane_lb(q.lb[i]), dstar, (key32(q.prio[i]) - kb) >> ts, T, all);
     };
     partition_tiles(
         s.nH[s.hcur], &s.nsel, &s.nH[s.hcur ^ 1], classify,
         [&](uint32_t i, uint32_t slot) {
+            if (slot >= b.k) {   // the threshold admits at most k keys; stop loudly if not
+                s.overflow = 1;
+                return;
+            }
             par.rkey[slot] = q.rkey[i];
             par.tkey[slot] = q.tkey[i];
             par.lb[slot] = sane_lb(q.lb[i]);
@@ -601,12 +701,17 @@ __global__ __launch_bounds__(kBlock) void k_select_compact(Bufs b)
             Hout.rkey[slot] = q.rkey[i];
             Hout.tkey[slot] = q.tkey[i];
             Hout.lb[slot] = lb;
-            Hout.prio[slot] = q.prio[i];
+            const float pr = q.prio[i];
+            Hout.prio[slot] = pr;
             Hout.flags[slot] = q.flags[i];
             copy_payload(Hout, slot, q, i);
             mh = fmin(mh, lb);
+            klo = min(klo, key32(pr));
+            khi = max(khi, key32(pr));
         });
     mh = block_min(mh);
+    block_key_range(klo, khi);
+    if (threadIdx.x == 0) widen_key_range(s, s.hcur ^ 1, klo, khi);
     if (threadIdx.x == 0 && mh < INFINITY) atomicMin(&s.minH, ord64(mh));
 }
 
@@ -635,7 +740,7 @@ __global__ __launch_bounds__(kBlock) void k_branch_setup(Bufs b)
 {
     const int p = blockIdx.y;
     PState &s = b.st[p];
-    const uint32_t n = s.done ? 0u : s.nsel;
+    const uint32_t n = s.done ? 0u : min(s.nsel, b.k);   // more than k only on overflow
     const Queue par = qoff(b.par, (size_t)p * b.k);
     const int lane = threadIdx.x & 63;
     const int bk = b.prob[p].bucket;
@@ -761,8 +866,14 @@ __global__ __launch_bounds__(kBlock) void k_push(Bufs b, const float *prio_overr
             const uint32_t lt = __shfl(tgt, leader, 64);
             const unsigned long long grp = __ballot(push && tgt == lt) & todo;
             const uint32_t rank = (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
-            double m = (push && tgt == lt) ? lbs : INFINITY;
-            for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
+            const bool in = push && tgt == lt;
+            double m = in ? lbs : INFINITY;
+            uint32_t klo = in ? key32(pr) : 0xffffffffu, khi = in ? key32(pr) : 0u;
+            for (int off = 32; off > 0; off >>= 1) {
+                m = fmin(m, __shfl_xor(m, off, 64));
+                klo = min(klo, (uint32_t)__shfl_xor(klo, off, 64));
+                khi = max(khi, (uint32_t)__shfl_xor(khi, off, 64));
+            }
             uint32_t first = 0;
             if (lane == leader) {
                 PState &s = b.st[lt >> 1];
@@ -772,6 +883,7 @@ __global__ __launch_bounds__(kBlock) void k_push(Bufs b, const float *prio_overr
                 unsigned long long *mn = h ? &s.minH : &s.minC;
                 const unsigned long long om = ord64(m);
                 if (om < __atomic_load_n(mn, __ATOMIC_RELAXED)) atomicMin(mn, om);
+                if (h) widen_key_range(s, s.hcur ^ 1, klo, khi);
             }
             first = __shfl(first, leader, 64);
             if (push && tgt == lt) slot = first + rank;
@@ -806,6 +918,7 @@ __global__ __launch_bounds__(kBlock) void k_push_agg(Bufs b, const float *prio_o
 {
     __shared__ uint32_t cnt[2 * kPushAggProblems], base[2 * kPushAggProblems];
     __shared__ unsigned long long mn[2 * kPushAggProblems];
+    __shared__ uint32_t kmn[kPushAggProblems], kmx[kPushAggProblems];   // hot keys per problem
     clear_cells(b, P);
     const uint32_t n = b.g->nchild;
     uint32_t nb[kBuckets];
@@ -815,6 +928,10 @@ __global__ __launch_bounds__(kBlock) void k_push_agg(Bufs b, const float *prio_o
         for (int t = threadIdx.x; t < T; t += blockDim.x) {
             cnt[t] = 0;
             mn[t] = ord64(INFINITY);
+        }
+        for (int t = threadIdx.x; t < P; t += blockDim.x) {
+            kmn[t] = 0xffffffffu;
+            kmx[t] = 0u;
         }
         __syncthreads();
         const uint32_t ti = start + threadIdx.x;
@@ -848,6 +965,30 @@ __global__ __launch_bounds__(kBlock) void k_push_agg(Bufs b, const float *prio_o
             local = atomicAdd(&cnt[tgt], 1u);
             atomicMin(&mn[tgt], ord64(lbs));
         }
+        // key range of the hot pushes: reduced over the wave when all of its
+        // hot lanes push to one problem (the usual case), else per lane
+        {
+            const bool hp = push && hot;
+            const unsigned long long hm = __ballot(hp);
+            if (hm) {
+                const int leader = __ffsll((long long)hm) - 1;
+                const uint32_t lp = __shfl(p, leader, 64);
+                uint32_t klo = hp ? key32(pr) : 0xffffffffu, khi = hp ? key32(pr) : 0u;
+                if (__ballot(hp && p == lp) == hm) {
+                    for (int off = 32; off > 0; off >>= 1) {
+                        klo = min(klo, (uint32_t)__shfl_xor(klo, off, 64));
+                        khi = max(khi, (uint32_t)__shfl_xor(khi, off, 64));
+                    }
+                    if ((int)(threadIdx.x & 63) == leader) {
+                        atomicMin(&kmn[lp], klo);
+                        atomicMax(&kmx[lp], khi);
+                    }
+                } else if (hp) {
+                    atomicMin(&kmn[p], klo);
+                    atomicMax(&kmx[p], khi);
+                }
+            }
+        }
         __syncthreads();
         for (int t = threadIdx.x; t < T; t += blockDim.x) {
             if (!cnt[t]) continue;
@@ -856,6 +997,7 @@ __global__ __launch_bounds__(kBlock) void k_push_agg(Bufs b, const float *prio_o
             base[t] = atomicAdd(h ? &s.nH[s.hcur ^ 1] : &s.nC[s.ccur], cnt[t]);
             unsigned long long *m = h ? &s.minH : &s.minC;
             if (mn[t] < __atomic_load_n(m, __ATOMIC_RELAXED)) atomicMin(m, mn[t]);
+            if (h) widen_key_range(s, s.hcur ^ 1, kmn[t >> 1], kmx[t >> 1]);
         }
         __syncthreads();
         if (push) {
@@ -959,7 +1101,7 @@ __global__ __launch_bounds__(kBlock) void k_log_records(Bufs b, int P)
     const int p = blockIdx.y;
     if (p >= P) return;
     const PState &s = b.st[p];
-    const uint32_t n = s.done ? 0u : s.nsel;
+    const uint32_t n = s.done ? 0u : min(s.nsel, b.k);   // more than k only on overflow
     const ProbDesc &D = b.prob[p];
     const Queue par = qoff(b.par, (size_t)p * b.k);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -1054,6 +1196,7 @@ __global__ void k_seed(Bufs b, int P)
     }
     s.nH[s.hcur] = 1;
     s.minH = ord64(lbs);
+    s.kmin[s.hcur] = s.kmax[s.hcur] = key32((float)lbs);
 }
 
 // Algorithm 1's SMA step: when a bounded cube has lowered d* since SMA last
@@ -1339,7 +1482,7 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     // selection of the k lowest hot cubes
     // the hot part holds at most hcap keys: blocks for kHistPer keys per thread
     const int gh = std::max(1, std::min<int>(gx, (int)((b.hcap + kBlock * kHistPer - 1) / (kBlock * kHistPer))));
-    for (int pass = 0; pass < kRadixPasses; ++pass) {
+    for (int pass = 0; pass < kSelPasses; ++pass) {
         hipLaunchKernelGGL(k_hist, dim3(gh, P), dim3(kBlock), 0, st, b, 0, pass);
         hipLaunchKernelGGL(k_scan, dim3(P), dim3(kBlock), 0, st, b, 0, pass);
     }
@@ -1570,6 +1713,7 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         s.dstar = s.minH = s.minC = s.floor_lb = s.sma_from = ordh(INFINITY);
         s.eps_f = opts->eps * ctx->h_prob[p].S22;
         s.theta = 0xffffffffu;
+        s.kmin[0] = s.kmin[1] = 0xffffffffu;   // both hot buffers empty
         s.max_iters = (uint32_t)std::min<int64_t>(opts->max_iters, 0xffffffffll);
     }
     if (resuming) {
