@@ -66,9 +66,9 @@ struct PState {
     uint32_t nsel, rebuild, done, overflow, iters, max_iters;
     uint32_t nskip;                // selected cubes that cannot be split (no children)
     uint32_t take_all, prefix, need, eq_quota, eq_taken;   // radix select
-    // range of the keys in each hot buffer (indexed like nH; empty: kmin > kmax)
+    // a range holding the keys of each hot buffer (indexed like nH; empty: kmin > kmax)
     uint32_t kmin[2], kmax[2];
-    uint32_t tshift;               // the selection threshold compares key >> tshift with prefix
+    uint32_t tshift;               // the selection compares (key - kmin) >> tshift with prefix
     uint32_t rb_target;            // hot entries wanted after a re-partition
     // SMA (Section 6): the pose of d* when SMA set it, and the d* it last started from
     double pose[6];
@@ -187,6 +187,18 @@ __device__ __forceinline__ void widen_key_range(PState &s, uint32_t buf, uint32_
     if (lo > hi) return;
     if (lo < __atomic_load_n(&s.kmin[buf], __ATOMIC_RELAXED)) atomicMin(&s.kmin[buf], lo);
     if (hi > __atomic_load_n(&s.kmax[buf], __ATOMIC_RELAXED)) atomicMax(&s.kmax[buf], hi);
+}
+
+// Key range of the next hot buffer at the start of an iteration: the cubes
+// that stay hot keep their keys, which lie in the current buffer's range;
+// children's keys are at least their parent's (their bound is at least the
+// parent's); and no hot key exceeds theta (keys below it go hot, and a
+// re-partition's ties equal it).  So the pushes widen the range only for
+// priorities that do not follow the bound, or while theta is open.
+__device__ __forceinline__ void start_key_range(PState &s)
+{
+    s.kmin[s.hcur ^ 1] = s.kmin[s.hcur];
+    s.kmax[s.hcur ^ 1] = s.theta != 0xffffffffu ? s.theta : s.kmax[s.hcur];
 }
 
 __device__ __forceinline__ int key_level(uint64_t k) { return (int)((k >> 57) & 63); }
@@ -381,8 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_iter_begin(Bufs b, int P, int rb_slo
         s.eq_taken = 0;
         s.tshift = 0;
         s.nH[s.hcur ^ 1] = 0;
-        s.kmin[s.hcur ^ 1] = 0xffffffffu;
-        s.kmax[s.hcur ^ 1] = 0u;
+        start_key_range(s);
         s.minH = ord64(INFINITY);
         if (rb_slot && s.rebuild) {
             s.nC[s.ccur ^ 1] = 0;
@@ -402,13 +413,15 @@ constexpr int kRadixPasses = 3;
 constexpr uint32_t kHistPer = 16;   // keys per thread of a histogram pass (at least)
 
 // The selection takes two passes of 12 bits over the hot part, on the key's
-// offset from the lowest key: the keys lie in [kmin, kmax] (kept up to date by
-// every kernel that writes a hot buffer), so the offsets have D = bit length
-// of kmax - kmin bits, and the passes resolve offset bits D-1 .. D-24.  That
-// is every bit when kmax - kmin < 2^24 (priorities of one sign within a
-// factor of four of each other); otherwise the lowest D - 24 bits are left
-// out, and keys whose offsets agree above them (values at most 2^(D-24) - 1
-// units in the last place apart) rank as ties of the threshold.
+// offset from kmin.  The keys lie in [kmin, kmax]: a re-partition sets the
+// range from its histogram and threshold, each iteration starts the next
+// buffer's range from the current one, and pushes widen it where needed.  So
+// the offsets have D = bit length of kmax - kmin bits, and the passes resolve
+// offset bits D-1 .. D-24: every bit when kmax - kmin < 2^24 (priorities of
+// one sign within a factor of four of each other); otherwise the lowest
+// D - 24 bits are left out, and keys whose offsets agree above them (values
+// at most 2^(D-24) - 1 units in the last place apart) rank as ties of the
+// threshold.
 constexpr int kSelPasses = 2;
 constexpr int kSelBits = 12;
 struct SelDigits {
@@ -499,17 +512,8 @@ __global__ __launch_bounds__(kBlock) void k_scan(Bufs b, int rebuild_pass, int p
     if (s.done || s.take_all || (rebuild_pass && !s.rebuild)) return;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const uint32_t want = rebuild_pass ? s.rb_target : b.k;
-    if (pass == 0) {
-        const uint32_t total = rebuild_pass ? s.nH[s.hcur] + s.nC[s.ccur] : s.nH[s.hcur];
-        if (total <= want) {
-            __syncthreads();
-            if (t == 0) {
-                s.take_all = 1;
-                s.prefix = 0xffffffffu;
-            }
-            return;
-        }
-    }
+    const uint32_t total = rebuild_pass ? s.nH[s.hcur] + s.nC[s.ccur] : s.nH[s.hcur];
+    const bool all_in = pass == 0 && total <= want;   // every key is taken
     const uint32_t need = pass == 0 ? want : s.need;
     constexpr int per = kHistBins / kBlock;
     uint32_t *gh = b.hist + (size_t)p * kHistBins;
@@ -517,6 +521,32 @@ __global__ __launch_bounds__(kBlock) void k_scan(Bufs b, int rebuild_pass, int p
     for (int j = 0; j < per; ++j) {
         loc[j] = gh[t * per + j];
         sum += loc[j];
+    }
+    if (rebuild_pass && pass == 0) {
+        // key range of the new hot part: from the start of the lowest
+        // non-empty bin of the first digit (key >> 21) to the threshold (set
+        // by the last pass), or to the end of the highest non-empty bin when
+        // every key goes hot; an empty histogram leaves an empty range
+        uint32_t lo = 0xffffffffu, hi = 0u;
+        for (int j = 0; j < per; ++j)
+            if (loc[j]) {
+                lo = min(lo, (uint32_t)(t * per + j));
+                hi = max(hi, (uint32_t)(t * per + j));
+            }
+        block_key_range(lo, hi);
+        if (t == 0) {
+            s.kmin[s.hcur ^ 1] = lo << 21;
+            if (all_in) s.kmax[s.hcur ^ 1] = (hi << 21) | 0x1fffffu;
+        }
+    }
+    if (all_in) {
+        __syncthreads();
+        for (int j = 0; j < per; ++j) gh[t * per + j] = 0;   // the next select starts from zero
+        if (t == 0) {
+            s.take_all = 1;
+            s.prefix = 0xffffffffu;
+        }
+        return;
     }
     // exclusive prefix of the per-thread sums: wave scan, then wave totals
     uint32_t incl = sum;
@@ -545,6 +575,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(Bufs b, int rebuild_pass, int p
     if (t == 0) {
         if (rebuild_pass) {
             s.prefix = (pass == 0 ? 0u : s.prefix << (pass == 2 ? 10 : 11)) | found;
+            if (pass == kRadixPasses - 1) s.kmax[s.hcur ^ 1] = s.prefix;
         } else if (pass == 0) {
             s.prefix = found;
         } else {
@@ -595,7 +626,6 @@ __global__ __launch_bounds__(kBlock) void k_rebuild_compact(Bufs b)
     const Queue Cout = qoff(b.C[s.ccur ^ 1], (size_t)p * b.ccap);
     const uint32_t hcap = b.hcap, ccap = b.ccap;
     double mh = INFINITY, mc = INFINITY;
-    uint32_t klo = 0xffffffffu, khi = 0u;   // keys moved to the new hot part
     for (int part = 0; part < 2; ++part) {
         const Queue q = part == 0 ? qoff(b.H[s.hcur], (size_t)p * b.hcap) : qoff(b.C[s.ccur], (size_t)p * b.ccap);
         const uint32_t n = part == 0 ? s.nH[s.hcur] : s.nC[s.ccur];
@@ -617,21 +647,14 @@ __global__ __launch_bounds__(kBlock) void k_rebuild_compact(Bufs b)
             copy_payload(o, slot, q, i);
         };
         partition_tiles(n, &s.nH[s.hcur ^ 1], &s.nC[s.ccur ^ 1], classify,
-                        [&](uint32_t i, uint32_t slot) {
-                            const uint32_t key = key32(q.prio[i]);
-                            klo = min(klo, key);
-                            khi = max(khi, key);
-                            move(Hout, hcap, i, slot, mh);
-                        },
+                        [&](uint32_t i, uint32_t slot) { move(Hout, hcap, i, slot, mh); },
                         [&](uint32_t i, uint32_t slot) { move(Cout, ccap, i, slot, mc); });
     }
     mh = block_min(mh);
     mc = block_min(mc);
-    block_key_range(klo, khi);
     if (threadIdx.x == 0) {
         if (mh < INFINITY) atomicMin(&s.minH, ord64(mh));
         if (mc < INFINITY) atomicMin(&s.minC, ord64(mc));
-        widen_key_range(s, s.hcur ^ 1, klo, khi);
     }
 }
 
@@ -660,8 +683,7 @@ __global__ void k_rebuild_finish(Bufs b, int P)
     s.tshift = 0;
     s.nH[s.hcur ^ 1] = 0;
     s.nC[s.ccur ^ 1] = 0;
-    s.kmin[s.hcur ^ 1] = 0xffffffffu;
-    s.kmax[s.hcur ^ 1] = 0u;
+    start_key_range(s);
 }
 
 // Selection: the k lowest keys of the hot part -> parents; the rest stays hot.
@@ -679,7 +701,6 @@ __global__ __launch_bounds__(kBlock) void k_select_compact(Bufs b)
     const Queue par = qoff(b.par, (size_t)p * b.k);
     const uint32_t kb = s.kmin[s.hcur], ts = s.tshift;   // the threshold is on (key - kb) >> ts
     double mh = INFINITY;
-    uint32_t klo = 0xffffffffu, khi = 0u;                 // keys that stay hot
     auto classify = [&](uint32_t i) -> int {
         return classify_key(s, sane_lb(q.lb[i]), dstar, (key32(q.prio[i]) - kb) >> ts, T, all);
     };
@@ -701,17 +722,12 @@ __global__ __launch_bounds__(kBlock) void k_select_compact(Bufs b)
             Hout.rkey[slot] = q.rkey[i];
             Hout.tkey[slot] = q.tkey[i];
             Hout.lb[slot] = lb;
-            const float pr = q.prio[i];
-            Hout.prio[slot] = pr;
+            Hout.prio[slot] = q.prio[i];
             Hout.flags[slot] = q.flags[i];
             copy_payload(Hout, slot, q, i);
             mh = fmin(mh, lb);
-            klo = min(klo, key32(pr));
-            khi = max(khi, key32(pr));
         });
     mh = block_min(mh);
-    block_key_range(klo, khi);
-    if (threadIdx.x == 0) widen_key_range(s, s.hcur ^ 1, klo, khi);
     if (threadIdx.x == 0 && mh < INFINITY) atomicMin(&s.minH, ord64(mh));
 }
 
