@@ -1273,8 +1273,10 @@ struct Solver {
     PState *h_st = nullptr;   // pinned host copies
     GState *h_g = nullptr;
     hipStream_t stream = nullptr;
-    hipGraph_t graph = nullptr;
+    hipGraph_t graph = nullptr;         // `check` iterations, re-partitions in the first
     hipGraphExec_t exec = nullptr;
+    hipGraph_t graph_nr = nullptr;      // the same iterations without the re-partition launches
+    hipGraphExec_t exec_nr = nullptr;
     int graph_maxM = 0;
     bool payload = false;     // logging payload buffers present
     int maxM = 0;             // largest M the Lemma 3 record buffer is sized for
@@ -1330,8 +1332,10 @@ void drop_graph(Solver *s)
 {
     if (s->exec) (void)hipGraphExecDestroy(s->exec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
-    s->exec = nullptr;
-    s->graph = nullptr;
+    if (s->exec_nr) (void)hipGraphExecDestroy(s->exec_nr);
+    if (s->graph_nr) (void)hipGraphDestroy(s->graph_nr);
+    s->exec = s->exec_nr = nullptr;
+    s->graph = s->graph_nr = nullptr;
 }
 
 void free_solver(Solver *s)
@@ -1804,20 +1808,26 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         if (e) return fail(GOSMA_E_HIP, "root cubes", e);
     }
 
-    // iterations: replay a captured graph of one iteration, reading the
-    // status every `check` iterations (every iteration when tracing or timing)
+    // iterations: replay a captured graph of `check` iterations, reading the
+    // status after each replay (every iteration when tracing or timing)
     bool use_graph = !timed && !opts->no_graph;
-    // The graph holds `check` iterations; re-partitions run in the first.
+    // Re-partitions run in the first iteration of a replay.  Two graphs: with
+    // the re-partition launches, for replays that start while a problem has
+    // asked for one (the status read before the replay says so), and without
+    // them (their eight launches cost about 4 us each even when no problem
+    // re-partitions).
     if (use_graph && !S.exec) {
-        e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-        if (!e) {
+        for (int g = 0; g < 2 && !e; ++g) {
+            e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e) break;
             hipError_t le = hipSuccess;
             for (int r = 0; r < check && !le; ++r)
-                le = launch_iteration(ctx, S, st, false, learned, logging, window, r == 0, check, sma_iters);
-            e = hipStreamEndCapture(st, &S.graph);
+                le = launch_iteration(ctx, S, st, false, learned, logging, window, g == 0 && r == 0, check, sma_iters);
+            e = hipStreamEndCapture(st, g == 0 ? &S.graph : &S.graph_nr);
             if (!e) e = le;
+            if (!e) e = hipGraphInstantiate(g == 0 ? &S.exec : &S.exec_nr, g == 0 ? S.graph : S.graph_nr, nullptr,
+                                            nullptr, 0);
         }
-        if (!e) e = hipGraphInstantiate(&S.exec, S.graph, nullptr, nullptr, 0);
         if (e) {
             drop_graph(&S);
             (void)hipGetLastError();
@@ -1850,11 +1860,13 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
         }
         if (running == 0) break;
         if (opts->time_limit_s > 0 && el > opts->time_limit_s) break;
+        bool rebuild = false;   // a running problem asked for a re-partition
+        for (int p = 0; p < P; ++p) rebuild |= S.h_st[p].rebuild && S.h_st[p].done == RUNNING;
         if (use_graph)
-            e = hipGraphLaunch(S.exec, st);
+            e = hipGraphLaunch(rebuild ? S.exec : S.exec_nr, st);
         else
             for (int r = 0; r < check && !e; ++r)
-                e = launch_iteration(ctx, S, st, timed, learned, logging, window, r == 0, check, sma_iters);
+                e = launch_iteration(ctx, S, st, timed, learned, logging, window, rebuild && r == 0, check, sma_iters);
         if (e) {
             rc = fail(GOSMA_E_HIP, "branch-and-bound iteration", e);
             break;
