@@ -279,7 +279,21 @@ struct PairK {
     float nuK;    // 1 + 1/K - coth K
 };
 
-__device__ __forceinline__ PairK pair_k(float a, float b, float q)
+// min(a, b) as the median of a, b and -infinity (v_med3_f32), with the
+// infinity passed in a kernel argument so that the compiler keeps the median:
+// the same value as fminf(a, b) for operands that are not NaN, in one
+// instruction where fminf spends up to two more quieting operands it cannot
+// prove canonical (values read from memory, or merged across branches).
+__device__ __forceinline__ float fmin_med3(float a, float b, float inf)
+{
+    return __builtin_amdgcn_fmed3f(a, b, -inf);
+}
+
+// Below this K, e^{-2K} is not negligible next to 1 in FP32.
+constexpr float kSmallK = 9.0f;
+
+// The PairK terms that hold for K >= kSmallK (h(K) / K and nu(K) taken as 1 / K).
+__device__ __forceinline__ PairK pair_k_large(float a, float b, float q)
 {
     PairK o;
     const float s = a + b;
@@ -295,8 +309,14 @@ __device__ __forceinline__ PairK pair_k(float a, float b, float q)
     o.invK = iK;
     o.hK = iK;
     o.nuK = iK;
-    if (__builtin_expect(K < 9.0f, 0)) {
-        // e^{-2K} is not negligible next to 1 in FP32 below K = 9.
+    return o;
+}
+
+// The terms with e^{-2K} for K < kSmallK.
+__device__ __forceinline__ void pair_k_small(PairK &o)
+{
+    const float K = o.K;
+    if (__builtin_expect(K < kSmallK, 0)) {
         float e = fexp2(-2.0f * kLog2e * K);
         if (K < 0.05f)
             o.hK = 2.0f + K * (-2.0f + K * (4.0f / 3.0f + K * (-2.0f / 3.0f + K * (4.0f / 15.0f))));
@@ -309,6 +329,12 @@ __device__ __forceinline__ PairK pair_k(float a, float b, float q)
             o.nuK = o.invK - 2.0f * e * frcp(1.0f - e);
         }
     }
+}
+
+__device__ __forceinline__ PairK pair_k(float a, float b, float q)
+{
+    PairK o = pair_k_large(a, b, q);
+    pair_k_small(o);
     return o;
 }
 
@@ -380,23 +406,19 @@ __device__ __forceinline__ void s11_terms(const float4 &A0, const float4 &A1, co
     const float px = A0.x + B0.x, py = A0.y + B0.y, pz = A0.z + B0.z;
     const float pp = fmaf(px, px, fmaf(py, py, pz * pz));
     const float w2 = 2.0f * A0.w * B0.w;
-    // upper bound summand at the centre
-    {
-        PairK k = pair_k(A1.x, B1.x, q);
-        sub += w2 * (fexp2(k.x * kLog2e) * k.hK * A1.y * B1.y);
-    }
     // lower bound summand: angle A = min(pi, theta + psi_i + psi_i') (eq. 24)
-    // via half angles: A/2 = theta/2 + (psi_i + psi_i')/2, clamped at pi/2.
-    {
-        // half-angle sine and cosine from the two chords |u - v|, |u + v|
-        const float st = 0.5f * fsqrt(q), ct = 0.5f * fsqrt(pp);
-        const float ca = A1.z * B1.z - A1.w * B1.w, sa = A1.w * B1.z + A1.z * B1.w;
-        const float cA = ct * ca - st * sa;
-        float sA = st * ca + ct * sa;
-        sA = cA <= 0.0f ? 1.0f : sA;
-        const float qA = 4.0f * sA * sA;
-        const float a = A2.x, b = B2.x, ha = A2.y, hb = B2.y;
-        PairK k = pair_k(a, b, qA);
+    // via half angles: A/2 = theta/2 + (psi_i + psi_i')/2, clamped at pi/2;
+    // half-angle sine and cosine from the two chords |u - v|, |u + v|
+    const float st = 0.5f * fsqrt(q), ct = 0.5f * fsqrt(pp);
+    const float ca = A1.z * B1.z - A1.w * B1.w, sa = A1.w * B1.z + A1.z * B1.w;
+    const float cA = ct * ca - st * sa;
+    float sA = st * ca + ct * sa;
+    sA = cA <= 0.0f ? 1.0f : sA;
+    const float qA = 4.0f * sA * sA;
+    const float a = A2.x, b = B2.x, ha = A2.y, hb = B2.y;
+    auto terms = [&](const PairK &k0, const PairK &k) __attribute__((always_inline)) {
+        // upper bound summand at the centre
+        sub += w2 * (fexp2(k0.x * kLog2e) * k0.hK * A1.y * B1.y);
         // gradient of g = log Z(K) - log Z(a) - log Z(b) at the box centre:
         // g_a = (K_a - 1) + nu(a) - nu(K) K_a with
         // K_a - 1 = b qA (a - b - K) / (2 K (K + a + b)).
@@ -409,6 +431,16 @@ __device__ __forceinline__ void s11_terms(const float4 &A0, const float4 &A1, co
         // min(1/3, 1/klo^2) >= L' over the component's interval
         const float corr = -fabsf(ga) * ha - fabsf(gb) * hb - 0.5f * fmaf(A3.x * ha, ha, B3.x * hb * hb);
         slo += w2 * (fexp2((k.x + corr) * kLog2e) * k.hK * A2.z * B2.z);
+    };
+    // the small-K corrections in one rarely taken branch (as in s12_pair)
+    PairK k0 = pair_k_large(A1.x, B1.x, q), k = pair_k_large(a, b, qA);
+    if (__builtin_expect(fminf(k0.K, k.K) < kSmallK, 0)) {
+        pair_k_small(k0);
+        pair_k_small(k);
+        terms(k0, k);
+        asm volatile("");   // the two copies of terms stay apart
+    } else {
+        terms(k0, k);
     }
 }
 
@@ -747,7 +779,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_s11(DevMix mx, const uint64_
 
 template <bool TOP8, int KP>
 __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, const float4 *__restrict__ scr, int a_,
-                                         const float4 v0, const float4 v1, float &sub, float &shi, float (&top)[8])
+                                         const float4 v0, const float4 v1, float inf, float &sub, float &shi,
+                                         float (&top)[8])
 {
     const float4 R0 = rec[kG12 * a_], R1 = rec[kG12 * a_ + 1], R2 = rec[kG12 * a_ + 2], R3 = rec[kG12 * a_ + 3];
     const float hla = scr[2 * a_ + 1].w;   // ln(alo) / 2
@@ -757,10 +790,15 @@ __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, const f
     const float px = R0.x + v0.x, py = R0.y + v0.y, pz = R0.z + v0.z;
     const float pp = fmaf(px, px, fmaf(py, py, pz * pz));
     const float ww = R0.w * v1.x;
-    // upper bound summand at the centre (eq. 12)
-    {
-        PairK k = pair_k(R1.x, b, q);
-        const float v = ww * (fexp2(k.x * kLog2e) * k.hK * R1.y * v1.y);
+    // the smallest angle over the cube: B = max(0, theta - Psi) (eq. 25)
+    const float st = 0.5f * fsqrt(q), ct = 0.5f * fsqrt(pp);
+    const float sB = fmaxf(st * R1.z - ct * R1.w, 0.0f);
+    const float qB = 4.0f * sB * sB;
+    const float alo = R2.x, ahi = R2.y, ha = R2.z;
+    const float bc = b * fmaf(-0.5f, qB, 1.0f);             // b cos B
+    // upper bound summand at the centre (eq. 12), from k0
+    auto centre = [&](const PairK &k0) __attribute__((always_inline)) {
+        const float v = ww * (fexp2(k0.x * kLog2e) * k0.hK * R1.y * v1.y);
         sub += v;
         if (TOP8 && v > top[7]) {
             // insert v into the descending list and drop the smallest: each
@@ -769,82 +807,97 @@ __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, const f
             float c = v;
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
-                const float hi = fmaxf(top[s], c);
-                c = fminf(top[s], c);
+                const float hi = __builtin_amdgcn_fmed3f(top[s], c, inf);
+                c = fmin_med3(top[s], c, inf);
                 top[s] = hi;
             }
         }
-    }
-    // upper bound on the summand over the cube: B = max(0, theta - Psi) (eq. 25)
-    {
-        const float st = 0.5f * fsqrt(q), ct = 0.5f * fsqrt(pp);
-        const float sB = fmaxf(st * R1.z - ct * R1.w, 0.0f);
-        const float qB = 4.0f * sB * sB;
-        const float alo = R2.x, ahi = R2.y, ha = R2.z;
-        const float bc = b * fmaf(-0.5f, qB, 1.0f);             // b cos B
-        float vT;
-        if constexpr (KP == 1) {
-            const PairK k1 = pair_k(alo, b, qB), k2 = pair_k(ahi, b, qB);
+    };
+    // upper bound on the summand over the cube, from the majorant vT of the
+    // kappa dependence: capped by the aligned and far-apart values
+    auto upper = [&](float vT) __attribute__((always_inline)) {
+        const float cap = 0.5f * fmin_med3(ahi, b, inf) * (R2.w + v1.z);
+        // far-apart caps: 2 G G e^{-qB cf} and G G e^{-min(qB, 2) cf} / sqrt(2 alo b)
+        const float cf = alo * b * frcp(2.0f * (alo + b));
+        const float e2 = fmaf(-qB, cf, kLn2);
+        const float eK = fmaf(-fmin_med3(qB, 2.0f, inf), cf, -(hla + v1.w));
+        const float far = R3.y * v1.y * fexp2(fminf(e2, eK) * kLog2e);
+        shi += ww * fminf(fminf(vT, cap), far);
+    };
+    if constexpr (KP == 1) {
+        // the two expansions at the ends of [alo, ahi]: from k1 and k2
+        auto terms = [&](const PairK &k0, const PairK &k1, const PairK &k2) __attribute__((always_inline)) {
+            centre(k0);
             const float d1 = R3.z - k1.nuK * (alo + bc) * k1.invK;  // phi'(alo)
             const float d2 = R3.w - k2.nuK * (ahi + bc) * k2.invK;  // phi'(ahi)
-            const float km2 = (-bc > alo && -bc < ahi) ? b * b * qB * fmaf(-0.25f, qB, 1.0f) : fminf(k1.ks, k2.ks);
+            const float km2 =
+                (-bc > alo && -bc < ahi) ? b * b * qB * fmaf(-0.25f, qB, 1.0f) : fmin_med3(k1.ks, k2.ks, inf);
             const float G = fminf(1.0f / 3.0f, frcp(km2));
             const float q2 = 2.0f * G * ha * ha;
             const float eA = fmaxf(k1.x, fmaf(2.0f * d1, ha, k2.x + q2));
             const float eB = fmaxf(k2.x, fmaf(-2.0f * d2, ha, k1.x + q2));
             const float vA = fexp2(eA * kLog2e) * k1.hK * R3.x;
             const float vB = fexp2(eB * kLog2e) * k2.hK * R3.y;
-            vT = fminf(vA, vB) * v1.y;
+            upper(fminf(vA, vB) * v1.y);
+        };
+        // the three K of the pair; the corrections for small K (pair_k_small)
+        // are rare, so they sit in one branch for all three, and the common
+        // path has none of their branches and register copies
+        PairK k0 = pair_k_large(R1.x, b, q), k1 = pair_k_large(alo, b, qB), k2 = pair_k_large(ahi, b, qB);
+        if (__builtin_expect(fminf(fminf(k0.K, k1.K), k2.K) < kSmallK, 0)) {
+            pair_k_small(k0);
+            pair_k_small(k1);
+            pair_k_small(k2);
+            terms(k0, k1, k2);
+            // keeps the compiler from merging the two copies of terms (which
+            // would bring back the register copies of the merged values)
+            asm volatile("");
         } else {
-            // the kappa interval in KP equal pieces: the same two expansions on
-            // each piece, the largest piece bound (G and nu at the inner ends
-            // computed here, at the outer ends from the record)
-            const float wdt = (ahi - alo) * (1.0f / KP), hp = 0.5f * wdt;
-            const float kmi = b * b * qB * fmaf(-0.25f, qB, 1.0f);   // K^2 where a = -b cos B
-            float ks[KP + 1], xs[KP + 1], d[KP + 1], hk[KP + 1], ge[KP + 1];
-#pragma unroll
-            for (int p = 0; p <= KP; ++p) {
-                const float e = p == 0 ? alo : (p == KP ? ahi : fmaf((float)p, wdt, alo));
-                const PairK k = pair_k(e, b, qB);
-                float Ge, nue;
-                if (p == 0) {
-                    Ge = R3.x;
-                    nue = R3.z;
-                } else if (p == KP) {
-                    Ge = R3.y;
-                    nue = R3.w;
-                } else {
-                    yfun_f(e, &Ge, &nue);
-                }
-                ks[p] = k.ks;
-                xs[p] = k.x;
-                hk[p] = k.hK;
-                ge[p] = Ge;
-                d[p] = nue - k.nuK * (e + bc) * k.invK;
-            }
-            float best = 0.0f;
-#pragma unroll
-            for (int p = 0; p < KP; ++p) {
-                const float e0 = p == 0 ? alo : fmaf((float)p, wdt, alo);
-                const float e1 = p == KP - 1 ? ahi : fmaf((float)(p + 1), wdt, alo);
-                const float km2 = (-bc > e0 && -bc < e1) ? kmi : fminf(ks[p], ks[p + 1]);
-                const float G = fminf(1.0f / 3.0f, frcp(km2));
-                const float q2 = 2.0f * G * hp * hp;
-                const float eA = fmaxf(xs[p], fmaf(2.0f * d[p], hp, xs[p + 1] + q2));
-                const float eB = fmaxf(xs[p + 1], fmaf(-2.0f * d[p + 1], hp, xs[p] + q2));
-                const float vA = fexp2(eA * kLog2e) * hk[p] * ge[p];
-                const float vB = fexp2(eB * kLog2e) * hk[p + 1] * ge[p + 1];
-                best = fmaxf(best, fminf(vA, vB));
-            }
-            vT = best * v1.y;
+            terms(k0, k1, k2);
         }
-        const float cap = 0.5f * fminf(ahi, b) * (R2.w + v1.z);
-        // far-apart caps: 2 G G e^{-qB cf} and G G e^{-min(qB, 2) cf} / sqrt(2 alo b)
-        const float cf = alo * b * frcp(2.0f * (alo + b));
-        const float e2 = fmaf(-qB, cf, kLn2);
-        const float eK = fmaf(-fminf(qB, 2.0f), cf, -(hla + v1.w));
-        const float far = R3.y * v1.y * fexp2(fminf(e2, eK) * kLog2e);
-        shi += ww * fminf(fminf(vT, cap), far);
+    } else {
+        centre(pair_k(R1.x, b, q));
+        // the kappa interval in KP equal pieces: the same two expansions on
+        // each piece, the largest piece bound (G and nu at the inner ends
+        // computed here, at the outer ends from the record)
+        const float wdt = (ahi - alo) * (1.0f / KP), hp = 0.5f * wdt;
+        const float kmi = b * b * qB * fmaf(-0.25f, qB, 1.0f);   // K^2 where a = -b cos B
+        float ks[KP + 1], xs[KP + 1], d[KP + 1], hk[KP + 1], ge[KP + 1];
+#pragma unroll
+        for (int p = 0; p <= KP; ++p) {
+            const float e = p == 0 ? alo : (p == KP ? ahi : fmaf((float)p, wdt, alo));
+            const PairK k = pair_k(e, b, qB);
+            float Ge, nue;
+            if (p == 0) {
+                Ge = R3.x;
+                nue = R3.z;
+            } else if (p == KP) {
+                Ge = R3.y;
+                nue = R3.w;
+            } else {
+                yfun_f(e, &Ge, &nue);
+            }
+            ks[p] = k.ks;
+            xs[p] = k.x;
+            hk[p] = k.hK;
+            ge[p] = Ge;
+            d[p] = nue - k.nuK * (e + bc) * k.invK;
+        }
+        float best = 0.0f;
+#pragma unroll
+        for (int p = 0; p < KP; ++p) {
+            const float e0 = p == 0 ? alo : fmaf((float)p, wdt, alo);
+            const float e1 = p == KP - 1 ? ahi : fmaf((float)(p + 1), wdt, alo);
+            const float km2 = (-bc > e0 && -bc < e1) ? kmi : fmin_med3(ks[p], ks[p + 1], inf);
+            const float G = fminf(1.0f / 3.0f, frcp(km2));
+            const float q2 = 2.0f * G * hp * hp;
+            const float eA = fmaxf(xs[p], fmaf(2.0f * d[p], hp, xs[p + 1] + q2));
+            const float eB = fmaxf(xs[p + 1], fmaf(-2.0f * d[p + 1], hp, xs[p] + q2));
+            const float vA = fexp2(eA * kLog2e) * hk[p] * ge[p];
+            const float vB = fexp2(eB * kLog2e) * hk[p + 1] * ge[p + 1];
+            best = fmaxf(best, fminf(vA, vB));
+        }
+        upper(best * v1.y);
     }
 }
 
@@ -1109,7 +1162,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                 for (int k = 0; k < kBatch; ++k) {
                     if (e[k] != 0xffffffffu) {
                         const int jj = (int)(e[k] & 0xffffu);
-                        s12_pair<TOP8, KP>(rec, scr, (int)(e[k] >> 16), vrow(jj, 0), vrow(jj, 1), sub, shi, top);
+                        s12_pair<TOP8, KP>(rec, scr, (int)(e[k] >> 16), vrow(jj, 0), vrow(jj, 1), mx.inf, sub, shi,
+                                           top);
                     }
                 }
                 run += kBatch;
@@ -1125,7 +1179,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
             auto screened_in = [&](int a_, const float4 &vm, const float2 &vc) __attribute__((always_inline)) {
                 const float4 S0 = scr[2 * a_], S1 = scr[2 * a_ + 1];
                 // max(dot, -sin Psi) as a median with +inf (no operand canonicalisation)
-                const float d = __builtin_amdgcn_fmed3f(fmaf(S0.x, vm.x, fmaf(S0.y, vm.y, S0.z * vm.z)), S1.z, INFINITY);
+                const float d = __builtin_amdgcn_fmed3f(fmaf(S0.x, vm.x, fmaf(S0.y, vm.y, S0.z * vm.z)), S1.z, mx.inf);
                 const float rhs = fmaf(-S1.y, vc.y, fmaf(-S1.x, vc.x, S0.w - vm.w));
                 return !(d <= rhs);
             };
@@ -1225,7 +1279,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
                     if (s == head) mine = top[s];
                 float m = mine;
 #pragma unroll
-                for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+                for (int off = 32; off > 0; off >>= 1) m = __builtin_amdgcn_fmed3f(m, __shfl_xor(m, off, 64), mx.inf);
                 // the lowest lane holding the maximum advances its list
                 const unsigned long long ballot = __ballot(mine == m);
                 const int winner = __ffsll((long long)ballot) - 1;

@@ -52,6 +52,8 @@ struct DevMix {
     float4 *grec;
     int64_t grec_stride;
     int grec_blocks;
+    // +infinity, as an argument the compiler cannot fold (see fmin_med3)
+    float inf;
 };
 // Blocks of a bound or SMA launch that stage their records in global memory.
 constexpr int kGrecBlocks = 512;
@@ -280,6 +282,6 @@ struct gosma_ctx {
 
     gosma::DevMix mix() const {
         return gosma::DevMix{d_mu,   d_isig2,  d_w1,        d_pbar,           d_vmf, d_cls,
-                             d_prob, n_problems, d_grec, grec_stride, gosma::kGrecBlocks};
+                             d_prob, n_problems, d_grec, grec_stride, gosma::kGrecBlocks, INFINITY};
     }
 };

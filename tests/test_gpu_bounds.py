@@ -419,8 +419,11 @@ def test_kappa_pieces_match_oracle(ctx, m):
         g = ctx.bounds(rk, tk)
         o = P.bounds(rk, tk)
         _compare(sc, g, o, label=f"cfg2 kappa pieces {m}")
+        # the same upper-bound formula in both kernels; their FP32 pair terms
+        # may round apart where the compiler fuses multiply-adds differently
         fin = np.isfinite(g1["ub"])
-        assert np.array_equal(g["ub"][fin], g1["ub"][fin])
+        assert np.array_equal(np.isfinite(g["ub"]), fin)
+        assert np.all(np.abs(g["ub"][fin] - g1["ub"][fin]) <= 1e-6 * np.abs(g1["ub"][fin]))
         ok = (g1["flags"] & 6) == 0
         assert np.mean(g["lb"][ok] >= g1["lb"][ok] - 1e-6 * np.abs(g1["lb"][ok])) >= 0.8
         with pytest.raises(RuntimeError, match="kappa pieces"):

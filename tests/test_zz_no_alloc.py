@@ -148,7 +148,10 @@ def test_noalloc_with_kappa_pieces(ctx, m):
             _run(ctx, rk[:64], tk[:64], None, True, top8=True)
     finally:
         ctx.set_kappa_pieces(1)
-    # the pieces change the lower bound only: flags and upper bounds as with one piece
+    # the pieces change the lower bound only: flags as with one piece, upper
+    # bounds to FP32 rounding (the two kernels may fuse multiply-adds apart)
     one = _run(ctx, rk[500:1500], tk[500:1500], None, True, top8=False)
     assert np.array_equal(a["flags"], one["flags"])
-    assert np.array_equal(a["ub"], one["ub"], equal_nan=True)
+    fin = np.isfinite(one["ub"])
+    assert np.array_equal(np.isfinite(a["ub"]), fin)
+    assert np.all(np.abs(a["ub"][fin] - one["ub"][fin]) <= 1e-6 * np.abs(one["ub"][fin]))
