@@ -80,7 +80,7 @@ struct PState {
 struct GState {
     uint32_t nchild, running;
     uint32_t ntrec;    // translation records reserved by this iteration's new cells
-    uint32_t pad;
+    uint32_t nrows;    // learned order: children queued this iteration (rows of the network input)
     // per size bucket: children and distinct translation cells of the iteration
     uint32_t nchild_b[kBuckets], ntcell_b[kBuckets];
 };
@@ -254,7 +254,8 @@ struct Bufs {
     GState *g;
     // learned order / record logging
     float *ctop8;                 // children: 8 largest S12 pair terms
-    float *cfeat, *cpred, *cprio; // children: features, network output, priority
+    float *cfeat, *cpred, *cprio; // network rows: features, output; children: priority
+    uint32_t *crow;               // network row -> child
     uint32_t *pchild;             // first child of each parent slot
     const ProbDesc *prob;
     float *rec;                   // record sink
@@ -375,6 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_iter_begin(Bufs b, int P, int rb_slo
         b.g->nchild = 0;
         b.g->running = 0;
         b.g->ntrec = 0;
+        b.g->nrows = 0;
         for (int k = 0; k < kBuckets; ++k) b.g->nchild_b[k] = b.g->ntcell_b[k] = 0;
     }
     if (s.done) {              // finished problems keep their final state
@@ -1068,19 +1070,35 @@ __device__ void cube_features(const ProbDesc &P, uint64_t rk, uint64_t tk, doubl
     for (int k = 0; k < 8; ++k) f[12 + k] = (float)(t8[k] / P.S22);
 }
 
-// Features of every bounded child (input of the learned priority).
+// Features of the children that the push will queue (input of the learned
+// priority): those not dropped whose raised lower bound is below d*, the test
+// the push applies (d* does not change in between).  The others need no
+// priority.  Their rows are packed, one atomic per wave; crow maps each row
+// to its child.
 __global__ __launch_bounds__(kBlock) void k_child_features(Bufs b)
 {
     const uint32_t n = b.g->nchild;
     uint32_t nb[kBuckets];
     child_counts(b, nb);
-    // features of the t-th child at row t (the network runs over rows 0 .. n-1)
+    const int lane = threadIdx.x & 63;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
         const uint32_t i = child_at(b, nb, t);
-        const ProbDesc &P = b.prob[b.cpid[i]];
+        const uint32_t p = b.cpid[i];
         const double lbs = fmax(sane_lb(b.clbs[i]), b.par.lb[b.cpar[i]]);
+        const bool keep = !(b.cflags[i] & (GOSMA_FLAG_DROP_ROT | GOSMA_FLAG_DROP_TRANS)) &&
+                          lbs < unord64(b.st[p].dstar);
+        const unsigned long long m = __ballot(keep);
+        if (!m) continue;
+        const int leader = __ffsll((long long)m) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&b.g->nrows, (uint32_t)__popcll(m));
+        base = __shfl(base, leader, 64);
+        if (!keep) continue;
+        const uint32_t row = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        b.crow[row] = i;
+        const ProbDesc &P = b.prob[p];
         cube_features(P, b.crk[i], b.ctk[i], (b.cub[i] + P.S22) / P.S22, (lbs + P.S22) / P.S22,
-                      b.ctop8 + 8 * (size_t)i, b.cfeat + (size_t)GOSMA_MLP_FEATURES * t);
+                      b.ctop8 + 8 * (size_t)i, b.cfeat + (size_t)GOSMA_MLP_FEATURES * row);
     }
 }
 
@@ -1093,11 +1111,9 @@ __global__ __launch_bounds__(kBlock) void k_child_features(Bufs b)
 constexpr float kMaxRise = 10.0f, kDeferred = 16.0f;
 __global__ __launch_bounds__(kBlock) void k_learned_prio(Bufs b, float window)
 {
-    const uint32_t n = b.g->nchild;
-    uint32_t nb[kBuckets];
-    child_counts(b, nb);
+    const uint32_t n = b.g->nrows;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-        const uint32_t i = child_at(b, nb, t);
+        const uint32_t i = b.crow[t];
         const uint32_t p = b.cpid[i];
         const double S22 = b.prob[p].S22;
         const double dstar_n = (unord64(b.st[p].dstar) + S22) / S22, eps_n = b.st[p].eps_f / S22;
@@ -1374,6 +1390,7 @@ void free_solver(Solver *s)
     dfree(b.cfeat);
     dfree(b.cpred);
     dfree(b.cprio);
+    dfree(b.crow);
     dfree(b.pchild);
     if (s->h_st) (void)hipHostFree(s->h_st);
     if (s->h_g) (void)hipHostFree(s->h_g);
@@ -1405,6 +1422,7 @@ hipError_t ensure_solver(Solver *s, int P, size_t k, size_t hcap, size_t ccap, b
     if (!e) e = dalloc(b.cfeat, (size_t)GOSMA_MLP_FEATURES * nc);
     if (!e) e = dalloc(b.cpred, nc);
     if (!e) e = dalloc(b.cprio, nc);
+    if (!e) e = dalloc(b.crow, nc);
     if (!e) e = dalloc(b.pchild, k * P);
     if (!e) e = dalloc(b.crk, nc);
     if (!e) e = dalloc(b.ctk, nc);
@@ -1550,7 +1568,7 @@ hipError_t launch_iteration(gosma_ctx *ctx, Solver &S, hipStream_t st, bool time
     if (learned) {
         ti = T0(GOSMA_KERNEL_MLP);
         hipLaunchKernelGGL(k_child_features, dim3(kGridX / 2), dim3(kBlock), 0, st, b);
-        e = mlp_predict(*ctx->mlp, b.cfeat, maxc, &b.g->nchild, b.cpred, 512, st);
+        e = mlp_predict(*ctx->mlp, b.cfeat, maxc, &b.g->nrows, b.cpred, 0, st);
         if (e) return e;
         hipLaunchKernelGGL(k_learned_prio, dim3(kGridX / 2), dim3(kBlock), 0, st, b, window);
         T1(ti);

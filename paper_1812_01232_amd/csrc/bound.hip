@@ -955,7 +955,7 @@ __global__ __launch_bounds__(256) void k_cube_setup(DevMix mx, const uint64_t *_
 // variant that also keeps the top-8 terms (learned order, record logging) is
 // held to four.
 template <bool TOP8, bool VLDS, bool GREC, int KP = 1>
-__global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu((TOP8 || KP > 1) ? 4 : 5))) void k_s12(DevMix mx, const uint64_t *__restrict__ rkeys,
+__global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(KP > 1 ? 4 : 5))) void k_s12(DevMix mx, const uint64_t *__restrict__ rkeys,
                                                          const uint64_t *__restrict__ tkeys,
                                                          const uint32_t *__restrict__ pids,
                                                          const int64_t *__restrict__ tidx,
@@ -1270,20 +1270,21 @@ __global__ __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(
         acc_ub = wave_sum(acc_ub);
         acc_hi = wave_sum(acc_hi);
         if (TOP8 && out.top8) {
-            // merge the per-lane sorted lists: 8 rounds of a wave maximum
-            int head = 0;
+            // merge the per-lane sorted lists: 8 rounds of a wave maximum of the
+            // list heads (the terms are >= 0 and an emptied slot holds -1, so the
+            // signed integer order of the bit patterns is the float order); the
+            // lowest lane holding the maximum drops its head
+#pragma unroll
             for (int k = 0; k < 8; ++k) {
-                float mine = -1.0f;
-#pragma unroll
-                for (int s = 0; s < 8; ++s)
-                    if (s == head) mine = top[s];
-                float m = mine;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) m = __builtin_amdgcn_fmed3f(m, __shfl_xor(m, off, 64), mx.inf);
-                // the lowest lane holding the maximum advances its list
+                const float mine = top[0];
+                const float m = __int_as_float(__ockl_wfred_max_i32(__float_as_int(mine)));
                 const unsigned long long ballot = __ballot(mine == m);
                 const int winner = __ffsll((long long)ballot) - 1;
-                if (lane == winner) head++;
+                if (lane == winner) {
+#pragma unroll
+                    for (int s = 0; s < 7; ++s) top[s] = top[s + 1];
+                    top[7] = -1.0f;
+                }
                 if (lane == 0) sh.top[wv][k] = fmaxf(m, 0.0f);
             }
         }

@@ -88,13 +88,14 @@ struct Save {          // per-minibatch activations for the backward pass (B = s
 
 // One dense layer on a 16-row activation tile held in LDS:
 // out[16][N] = act(in[16][K] W^T + bias), W given as rows [N][K] (global).
-template <int K, int N, bool GELU_>
-__device__ inline void layer16(const uint16_t *in, int ldi, const uint16_t *W, int ldw, const float *bias,
+// The calling wave computes the output columns of tiles [nt0, nt0 + NT).
+template <int K, int NT, bool GELU_>
+__device__ inline void layer16(int nt0, const uint16_t *in, int ldi, const uint16_t *W, int ldw, const float *bias,
                                uint16_t *out, int ldo, float *zsave, uint16_t *hfm, int B, int rec0, int nrec)
 {
     const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
 #pragma unroll
-    for (int nt = 0; nt < N / 16; ++nt) {
+    for (int nt = nt0; nt < nt0 + NT; ++nt) {
         f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int ks = 0; ks < K / 16; ++ks)
@@ -118,51 +119,46 @@ __device__ inline void layer16(const uint16_t *in, int ldi, const uint16_t *W, i
 
 // Forward pass.  X: n x IN FP32 features (record-major).  y: n outputs.  With
 // a Save, also stores the pre-activations and feature-major activations
-// (training).  n may be read from device memory (n_dev) times n_mul.
+// (training).  n may be read from device memory (n_dev).  A block of four
+// waves takes one 16-record tile at a time, each wave a quarter of every
+// layer's output columns (the dependent chain of one tile is a quarter as
+// long as with one wave per tile, and a launch has four times the waves).
 __global__ __launch_bounds__(kThreads) void k_forward(Weights w, const float *__restrict__ X, int64_t n_host,
                                                       const uint32_t *n_dev, float *__restrict__ y, Save sv)
 {
     extern __shared__ uint16_t lds[];
     // weights are read straight from global memory (72 KB, cache-resident);
-    // LDS holds the activation tiles, per wave 2 x [16][S_H]
-    uint16_t *act = lds;
+    // LDS holds the tile's activations, 2 x [16][S_H]
+    uint16_t *a0 = lds, *a1 = lds + 16 * S_H;
     const uint16_t *W1 = w.W1, *W2 = w.W2, *W3 = w.W3, *W4 = w.W4;
     const int64_t n = n_dev ? (int64_t)n_dev[0] : n_host;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint16_t *a0 = act + wave * 2 * 16 * S_H, *a1 = a0 + 16 * S_H;
+    constexpr int NT = HID / 16 / (kThreads / 64);   // column tiles per wave
     const int64_t ntiles = (n + 15) / 16;
     const bool train = sv.z1 != nullptr;
-    for (int64_t t0 = (int64_t)blockIdx.x * 4; t0 < ntiles; t0 += (int64_t)gridDim.x * 4) {
-        const int64_t t = t0 + wave;
-        const bool valid = t < ntiles;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t rec0 = t * 16;
-        const int nrec = valid ? (int)std::min<int64_t>(16, n - rec0) : 0;
+        const int nrec = (int)std::min<int64_t>(16, n - rec0);
         // input tile -> bf16 [16][INP] (features beyond IN and rows beyond n are zero)
-        for (int i = lane; i < 16 * INP; i += 64) {
+        for (int i = threadIdx.x; i < 16 * INP; i += kThreads) {
             const int row = i / INP, col = i % INP;
             float v = 0.0f;
             if (row < nrec && col < IN) v = X[(rec0 + row) * IN + col];
             const uint16_t hb = f2bf(v);
             a0[row * S_H + col] = hb;
-            if (train && valid) sv.h0fm[(size_t)col * sv.B + rec0 + row] = hb;
+            if (train) sv.h0fm[(size_t)col * sv.B + rec0 + row] = hb;
         }
         __syncthreads();
-        if (valid) {
-            layer16<INP, HID, true>(a0, S_H, W1, INP, w.b + ob1, a1, S_H, train ? sv.z1 : nullptr, sv.h1fm, sv.B,
-                                    (int)rec0, nrec);
-        }
+        layer16<INP, NT, true>(NT * wave, a0, S_H, W1, INP, w.b + ob1, a1, S_H, train ? sv.z1 : nullptr, sv.h1fm,
+                               sv.B, (int)rec0, nrec);
         __syncthreads();
-        if (valid) {
-            layer16<HID, HID, true>(a1, S_H, W2, HID, w.b + ob2, a0, S_H, train ? sv.z2 : nullptr, sv.h2fm, sv.B,
-                                    (int)rec0, nrec);
-        }
+        layer16<HID, NT, true>(NT * wave, a1, S_H, W2, HID, w.b + ob2, a0, S_H, train ? sv.z2 : nullptr, sv.h2fm,
+                               sv.B, (int)rec0, nrec);
         __syncthreads();
-        if (valid) {
-            layer16<HID, HID, true>(a0, S_H, W3, HID, w.b + ob3, a1, S_H, train ? sv.z3 : nullptr, sv.h3fm, sv.B,
-                                    (int)rec0, nrec);
-        }
+        layer16<HID, NT, true>(NT * wave, a0, S_H, W3, HID, w.b + ob3, a1, S_H, train ? sv.z3 : nullptr, sv.h3fm,
+                               sv.B, (int)rec0, nrec);
         __syncthreads();
-        if (valid) {
+        if (wave == 0) {
             const int r = lane & 15, g = lane >> 4;
             f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -376,14 +372,15 @@ struct Mlp {
     Weights w() const { return Weights{W1, W2, W3, W4, W2t, W3t, W4t, p}; }
 };
 
-size_t mlp_forward_lds() { return sizeof(uint16_t) * (size_t)4 * 2 * 16 * S_H; }
+size_t mlp_forward_lds() { return sizeof(uint16_t) * (size_t)2 * 16 * S_H; }
 size_t mlp_backward_lds() { return sizeof(uint16_t) * (size_t)4 * 2 * 16 * S_H; }
 
 hipError_t mlp_predict(const Mlp &m, const float *X, int64_t n, const uint32_t *n_dev, float *y, int grid,
                        hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    const int g = grid > 0 ? grid : (int)std::min<int64_t>((n + 63) / 64, 1024);
+    // one block per 16-record tile, up to 4,096 (then each block loops)
+    const int g = grid > 0 ? grid : (int)std::min<int64_t>((n + 15) / 16, 4096);
     hipLaunchKernelGGL(k_forward, dim3(g), dim3(kThreads), mlp_forward_lds(), s, m.w(), X, n, n_dev, y,
                        Save{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0});
     return hipGetLastError();
@@ -475,8 +472,8 @@ hipError_t minibatch_grad(Mlp *m, const float *X, const float *t, int n, hipStre
             m->hfm + (size_t)(32 + 128) * B, m->hfm + (size_t)(32 + 256) * B, B};
     const int tiles = (n + 15) / 16;
     const int g = std::max(1, std::min(1024, (tiles + 3) / 4));
-    hipLaunchKernelGGL(k_forward, dim3(g), dim3(kThreads), mlp_forward_lds(), s, m->w(), X, (int64_t)n,
-                       (const uint32_t *)nullptr, m->y, sv);
+    hipLaunchKernelGGL(k_forward, dim3(std::max(1, std::min(4096, tiles))), dim3(kThreads), mlp_forward_lds(), s,
+                       m->w(), X, (int64_t)n, (const uint32_t *)nullptr, m->y, sv);
     hipLaunchKernelGGL(k_loss, dim3(std::max(1, std::min(256, (B + 255) / 256))), dim3(256), 0, s, m->y, t, n, B,
                        m->dy, m->dzfm, m->loss);
     uint16_t *dz3 = m->dzfm + (size_t)16 * B, *dz2 = dz3 + (size_t)128 * B, *dz1 = dz2 + (size_t)128 * B;
