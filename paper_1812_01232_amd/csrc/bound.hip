@@ -800,17 +800,14 @@ __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, const f
     auto centre = [&](const PairK &k0) __attribute__((always_inline)) {
         const float v = ww * (fexp2(k0.x * kLog2e) * k0.hK * R1.y * v1.y);
         sub += v;
-        if (TOP8 && v > top[7]) {
-            // insert v into the descending list and drop the smallest: each
-            // position keeps the larger value and passes the smaller one on
-            // (a value not above the eighth would leave the list unchanged)
-            float c = v;
+        if (TOP8) {
+            // insert v into the descending list and drop the smallest: slot s
+            // takes the median of its old value, v and the old value of slot
+            // s - 1 (eight independent operations; a v not above the eighth
+            // leaves the list unchanged)
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const float hi = __builtin_amdgcn_fmed3f(top[s], c, inf);
-                c = fmin_med3(top[s], c, inf);
-                top[s] = hi;
-            }
+            for (int s = 7; s > 0; --s) top[s] = __builtin_amdgcn_fmed3f(top[s - 1], v, top[s]);
+            top[0] = __builtin_amdgcn_fmed3f(top[0], v, inf);
         }
     };
     // upper bound on the summand over the cube, from the majorant vT of the

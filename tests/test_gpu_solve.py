@@ -141,6 +141,28 @@ def test_batch_solve_matches_single(ctx):
         assert many["lb_norm"] <= one["f_norm_best"] and one["lb_norm"] <= many["f_norm_best"]
 
 
+def test_batch_learned_order_keeps_certificates(ctx):
+    """Several problems searched together in the learned order (the network
+    scores only the children each problem queues, rows of all problems packed
+    together) still end eps-certified and agree with each problem's plain
+    solve."""
+    scs = [scenes.small_scene(4, 4, seed=81), scenes.small_scene(5, 5, seed=86),
+           scenes.small_scene(6, 5, seed=91, noise_deg=1.0, n_inliers=4)]
+    singles = []
+    for s in scs:
+        ctx.set_scene(s)
+        singles.append(ctx.solve(1e-2, batch_parents=256))
+    ctx.set_scenes(scs)
+    ctx.mlp_init(0)   # an untrained network: any order must keep the certificate
+    batch = ctx.solve_batch(len(scs), 1e-2, batch_parents=256, order=1, learned_window=1e-2, max_queue=1 << 24,
+                            time_limit_s=120)
+    for one, many in zip(singles, batch):
+        assert many["status"] == one["status"] == 0
+        assert many["f_norm_best"] - many["lb_norm"] <= 1e-2
+        assert abs(many["f_norm_best"] - one["f_norm_best"]) <= 1e-2
+        assert many["lb_norm"] <= one["f_norm_best"] and one["lb_norm"] <= many["f_norm_best"]
+
+
 def test_learned_order_keeps_certificate_and_logs_records(ctx):
     """With the learned queue order the result is still eps-certified; record
     logging writes finite features and non-negative targets."""
