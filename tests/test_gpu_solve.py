@@ -390,6 +390,60 @@ def test_finest_level_parents_have_no_children(ctx):
     assert np.all(np.abs(np.asarray(r["r"]) - rg) <= 3 * 2 * math.pi / 2 ** 19)
 
 
+def _snapshot_cubes(snap):
+    """The queued cubes of a one-problem snapshot (layout as in _snapshot_with_cubes)."""
+    import struct
+    n = struct.unpack_from("<Q", snap, 24 + 160)[0]
+    o = 24 + 224
+    rk = np.frombuffer(snap, np.uint64, n, o)
+    tk = np.frombuffer(snap, np.uint64, n, o + 8 * n)
+    lb = np.frombuffer(snap, np.float64, n, o + 16 * n)
+    return rk, tk, lb
+
+
+def _priority_keys(lbs):
+    """The ordered 32-bit key of each cube's FP32 priority (its lower bound)."""
+    u = np.asarray(lbs, np.float64).astype(np.float32).view(np.uint32).astype(np.int64)
+    return np.where(u >> 31, (~u) & 0xffffffff, u | 0x80000000)
+
+
+@pytest.mark.parametrize("n, spread", [(3000, 1e-3), (20000, 1e-3), (3000, 3.0), (20000, 3.0)])
+def test_selection_takes_the_lowest_keys(ctx, n, spread):
+    """One iteration resumed from n planted cubes (lower bounds far below d*,
+    so none is pruned) splits the k cubes of lowest priority key.  With the
+    keys within 2^24 units of each other (spread 1e-3) that is exact, ties
+    aside; over ten binades (spread 3) the two selection passes leave the
+    lowest bits of the key's offset unresolved, so the split cubes are the k
+    lowest to within 2^8 key units.  n = 20000 also re-partitions the queue
+    (its 4,096 lowest go hot) before selecting; n = 3000 puts all of it hot."""
+    sc = scenes.small_scene(4, 4, seed=81)
+    ctx.set_scene(sc)
+    ctx.solve(1e-9, batch_parents=64, max_iters=2)
+    snap = ctx.snapshot()
+    rng = np.random.default_rng(n + int(spread))
+    L = 7
+    cells = rng.choice(2 ** (3 * L), size=n, replace=False).astype(np.int64)
+    rk = scenes.pack_key(L, cells >> (2 * L), (cells >> L) & (2 ** L - 1), cells & (2 ** L - 1))
+    tk = np.full(n, int(scenes.pack_key(2, 1, 1, 1)), np.uint64)
+    lbs = -1e6 * 10.0 ** (spread * rng.random(n))
+    crafted, _ = _snapshot_with_cubes(snap, rk, tk, lbs, np.zeros(n, np.uint8))
+    ctx.resume(crafted)
+    k = 256
+    r = ctx.solve(1e-9, batch_parents=k, max_iters=1, max_queue=1 << 22)
+    assert r["iters"] == 3
+    rk2, tk2, _ = _snapshot_cubes(ctx.snapshot())
+    left = set(zip(rk2.tolist(), tk2.tolist()))
+    taken = np.array([(a, b) not in left for a, b in zip(rk.tolist(), tk.tolist())])
+    key = _priority_keys(lbs)
+    print(f"n={n} spread={spread}: {taken.sum()} split, highest split key {key[taken].max()}, "
+          f"lowest kept {key[~taken].min()}")
+    assert taken.sum() == k
+    if spread < 1:
+        assert key[taken].max() <= key[~taken].min()
+    else:
+        assert key[taken].max() <= key[~taken].min() + 2 ** 8
+
+
 @pytest.mark.parametrize("m", [2, 4])
 def test_search_with_kappa_pieces_matches_oracle(ctx, m):
     """The search with the kappa interval of the S12 upper term in m pieces
