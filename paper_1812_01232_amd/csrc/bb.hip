@@ -1709,11 +1709,14 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
     const size_t ccap = (size_t)opts->max_queue;
     // hot part: room for a re-partition's target (at most half of it) plus the
     // children of the iterations until the next re-partition (7 k net each).
-    // Kept small: every iteration's selection passes over all of it, while a
-    // re-partition (over the whole queue) runs at most every few iterations;
-    // on the 64x64 search 64 k entries select about 1% faster per step than
-    // 256 k (or 2^20), and the batch of 128 problems needs 8x less memory.
-    const size_t hcap = 64 * k + 16;
+    // Every selection passes over the hot part, and every re-partition over the
+    // whole queue; the target grows with the queue (a sixteenth of it) up to
+    // half this capacity, so a long search with a queue of 10^8 cubes and more
+    // re-partitions every ~128 iterations (64 entries per parent instead:
+    // every ~32, and 64x64 searches of 10^4 iterations took 14-18% longer;
+    // the first 25 iterations reach neither cap, and over iterations 100-500
+    // the two capacities are within about 1% of each other).
+    const size_t hcap = 256 * k + 16;
     const float window = (float)opts->learned_window;
     const int mode = (learned ? 1 : 0) | (logging ? 2 : 0) | (sma_iters > 0 ? 4 : 0);
     const bool timed = ctx->timing;
