@@ -1178,12 +1178,18 @@ __device__ void iter_end_problem(Bufs &b, int p, int rb_every)
         s.done = CAPPED;
     if (s.done) return;
     atomicAdd(&b.g->running, 1u);
-    // re-partition when the hot part runs low (and cold cubes exist) or fills up
+    // re-partition when the hot part runs low (and cold cubes exist) or fills
+    // up.  The target is a sixteenth of the queue, between 16 k and half the
+    // capacity; the hot part may grow to twice the target (at least 64 k), so
+    // that it stays as small as selections want while the queue is small and
+    // grows, with the target, once re-partitions of a large queue dominate
     const uint32_t span = b.k * (uint32_t)rb_every;
-    if ((nh < span && nc > 0) || nh + 8u * span > b.hcap) {
+    const uint32_t total = nh + nc;
+    const uint32_t target = min(max(total / 16u, 16u * b.k), b.hcap / 2u);
+    const uint32_t cap = min(b.hcap, max(64u * b.k, 2u * target));
+    if ((nh < span && nc > 0) || nh + 8u * span > cap) {
         s.rebuild = 1;
-        const uint32_t total = nh + nc;
-        s.rb_target = min(max(total / 16u, 16u * b.k), b.hcap / 2u);
+        s.rb_target = target;
     }
 }
 
@@ -1712,10 +1718,10 @@ int solve_problems(gosma_ctx *ctx, const gosma_opts *opts, gosma_result *res, in
     // Every selection passes over the hot part, and every re-partition over the
     // whole queue; the target grows with the queue (a sixteenth of it) up to
     // half this capacity, so a long search with a queue of 10^8 cubes and more
-    // re-partitions every ~128 iterations (64 entries per parent instead:
-    // every ~32, and 64x64 searches of 10^4 iterations took 14-18% longer;
-    // the first 25 iterations reach neither cap, and over iterations 100-500
-    // the two capacities are within about 1% of each other).
+    // re-partitions every ~128 iterations (with 64 entries per parent: every
+    // ~32, and 64x64 searches of 10^4 iterations took 14-18% longer).  While
+    // the queue is small the hot part is held to 64 entries per parent (see
+    // iter_end_problem).
     const size_t hcap = 256 * k + 16;
     const float window = (float)opts->learned_window;
     const int mode = (learned ? 1 : 0) | (logging ? 2 : 0) | (sma_iters > 0 ? 4 : 0);
