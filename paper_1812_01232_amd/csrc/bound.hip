@@ -837,21 +837,10 @@ __device__ __forceinline__ void s12_pair(const float4 *__restrict__ rec, const f
             const float vB = fexp2(eB * kLog2e) * k2.hK * R3.y;
             upper(fminf(vA, vB) * v1.y);
         };
-        // the three K of the pair; the corrections for small K (pair_k_small)
-        // are rare, so they sit in one branch for all three, and the common
-        // path has none of their branches and register copies
-        PairK k0 = pair_k_large(R1.x, b, q), k1 = pair_k_large(alo, b, qB), k2 = pair_k_large(ahi, b, qB);
-        if (__builtin_expect(fminf(fminf(k0.K, k1.K), k2.K) < kSmallK, 0)) {
-            pair_k_small(k0);
-            pair_k_small(k1);
-            pair_k_small(k2);
-            terms(k0, k1, k2);
-            // keeps the compiler from merging the two copies of terms (which
-            // would bring back the register copies of the merged values)
-            asm volatile("");
-        } else {
-            terms(k0, k1, k2);
-        }
+        // each K with its own branch for the small-K terms: one branch for all
+        // three made the whole wave run both copies of the terms whenever one
+        // lane had a small K, which late in a search costs more than it saves
+        terms(pair_k(R1.x, b, q), pair_k(alo, b, qB), pair_k(ahi, b, qB));
     } else {
         centre(pair_k(R1.x, b, q));
         // the kappa interval in KP equal pieces: the same two expansions on
