@@ -432,7 +432,8 @@ __device__ __forceinline__ void s11_terms(const float4 &A0, const float4 &A1, co
         const float corr = -fabsf(ga) * ha - fabsf(gb) * hb - 0.5f * fmaf(A3.x * ha, ha, B3.x * hb * hb);
         slo += w2 * (fexp2((k.x + corr) * kLog2e) * k.hK * A2.z * B2.z);
     };
-    // the small-K corrections in one rarely taken branch (as in s12_pair)
+    // the small-K corrections of both K in one rarely taken branch (the wave
+    // runs both copies of the terms only when one of its lanes has a small K)
     PairK k0 = pair_k_large(A1.x, B1.x, q), k = pair_k_large(a, b, qA);
     if (__builtin_expect(fminf(k0.K, k.K) < kSmallK, 0)) {
         pair_k_small(k0);
